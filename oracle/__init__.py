@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the echo-simulation hot path (ctypes wrapper over oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Imported by tests/, the smoke check and the CPU-baseline leg
+of the benchmark; the product library never imports it and shares no code with it.
+The C source is plain brute force in IEEE double (see oracle.c); this module only
+marshals numpy arrays.
+
+Pins (tests/test_oracle_*.py): single-wall image source, box-room unfolding, reciprocity
+of the single-point path, the sphere and flat-plane curvature values, the SplitMix64
+published outputs, chi-square of the diffraction sampler, finite differences of the
+adjoint.  Parts with no external pin ("parity unpinned"): the area weighting w(A) and
+scale eta of the curvature metric, the eligibility threshold tau, the dither of the
+CDF, the visibility target x_ref, the air-absorption constants.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+KAPPA = 32.0      # margin bound in units of FP32 unit roundoff (2^-24)
+MU_G = 1e-3       # grazing threshold on |d . n| at an accepted hit
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = C.CDLL(_LIB_PATH)
+        _lib.orc_splitmix.restype = C.c_uint64
+        _lib.orc_splitmix.argtypes = [C.c_uint64, C.c_uint64]
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def trace(scene: dict, sim: dict, dirs=None, certify: bool = True, kappa: float = KAPPA, mu_g: float = MU_G) -> dict:
+    """Algorithm 1 by brute force in FP64.  Returns records in (ray, bounce) order plus the
+    per-ray certification flag and closest-hit segment count."""
+    L = lib()
+    dirs = _f32(sim["ray_dirs"] if dirs is None else dirs)
+    N = len(dirs)
+    B = int(sim["max_bounces"])
+    cap = max(1, N * B)
+    out = {
+        "ray": np.zeros(cap, np.int32), "bounce": np.zeros(cap, np.int32), "tri": np.zeros(cap, np.int32),
+        "mat": np.zeros(cap, np.int32), "p": np.zeros((cap, 3)), "din": np.zeros((cap, 3)),
+        "dout": np.zeros((cap, 3)), "rtot": np.zeros(cap), "vis": np.zeros(cap, np.uint8),
+    }
+    cert = np.zeros(max(N, 1), np.uint8)
+    nseg = np.zeros(max(N, 1), np.int32)
+    n = C.c_int64(0)
+    v = _f32(scene["vertices"]); t = _i32(scene["tris"]); m = _i32(scene["tri_material"])
+    ep = _f64(sim["emitter_pos"]); er = _f64(sim["emitter_rot"]); xr = _f64(sim["x_ref"])
+    rc = L.orc_trace(C.c_int64(len(v)), C.c_int64(len(t)), _p(v), _p(t), _p(m), _p(ep), _p(er), C.c_int64(N), _p(dirs),
+                     C.c_int32(B), C.c_double(sim["max_distance"]), _p(xr), C.c_double(sim["t_eps"]),
+                     C.c_double(kappa if certify else 0.0), C.c_double(mu_g), C.c_int64(cap), C.byref(n),
+                     _p(out["ray"]), _p(out["bounce"]), _p(out["tri"]), _p(out["mat"]), _p(out["p"]), _p(out["din"]),
+                     _p(out["dout"]), _p(out["rtot"]), _p(out["vis"]), _p(cert), _p(nseg))
+    if rc != 0:
+        raise ValueError(f"orc_trace failed ({rc})")
+    k = n.value
+    res = {key: val[:k].copy() for key, val in out.items()}
+    res["kind"] = np.zeros(k, np.uint8)
+    res["certified"] = cert[:N].astype(bool)
+    res["nseg"] = nseg[:N].copy()
+    return res
+
+
+def synth(rec: dict, sim: dict, bins=None, M_subset=None) -> np.ndarray:
+    """Eqs. (2)-(4) and (7)-(8): complex spectra [M, nk] (complex128) by direct summation.
+    `bins` selects frequency indices (default all F); `M_subset` selects receivers."""
+    L = lib()
+    F = int(sim["F"])
+    k_list = np.arange(F, dtype=np.int32) if bins is None else _i32(bins)
+    rx = _f64(sim["rx_pos"]); rr = _f64(sim["rx_rot"])
+    D = sim.get("directivity")
+    if M_subset is not None:
+        rx = _f64(rx[M_subset]); rr = _f64(rr[M_subset])
+        if D is not None:
+            D = D[M_subset]
+    M = len(rx)
+    Bd = El = Az = 0
+    if D is not None:
+        D = _f32(D)
+        _, Bd, El, Az = D.shape
+    n = len(rec["rtot"])
+    p = _f64(rec["p"]) if n else np.zeros((1, 3))
+    dout = _f64(rec.get("dout", np.zeros((n, 3)))) if n else np.zeros((1, 3))
+    rt = _f64(rec["rtot"]) if n else np.zeros(1)
+    mat = _i32(rec["mat"]) if n else np.zeros(1, np.int32)
+    kind = np.ascontiguousarray(rec.get("kind", np.zeros(n, np.uint8)), np.uint8) if n else np.zeros(1, np.uint8)
+    vis = np.ascontiguousarray(rec.get("vis", np.ones(n, np.uint8)), np.uint8) if n else np.zeros(1, np.uint8)
+    k = _f32(sim["refl_k"]); b = _f32(sim["lobe_beta"]); dc = _f32(sim["diff_coef"])
+    Q, Bk = k.shape
+    out = np.zeros((M, len(k_list), 2))
+    rc = L.orc_synth(C.c_int64(n), _p(p), _p(dout), _p(rt), _p(mat), _p(kind), _p(vis), C.c_int32(M), _p(rx), _p(rr),
+                     C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]), C.c_int32(F), C.c_int32(len(k_list)), _p(k_list),
+                     C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
+                     C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
+                     _p(k), _p(b), _p(dc), C.c_int32(Bd), C.c_int32(El), C.c_int32(Az), _p(D), _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_synth failed ({rc})")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def grad(rec: dict, sim: dict, g: np.ndarray):
+    """Analytic gradient of L = sum |H - H*|^2 with g = H - H* (complex [M, F]):
+    returns (dL/d refl_k [Q, Bk], dL/d rx_pos [M, 3])."""
+    L = lib()
+    if sim.get("directivity") is not None:
+        raise ValueError("gradient with directivity is not defined here")
+    F = int(sim["F"])
+    rx = _f64(sim["rx_pos"])
+    M = len(rx)
+    n = len(rec["rtot"])
+    gg = np.ascontiguousarray(np.stack([g.real, g.imag], -1), np.float64)
+    k = _f32(sim["refl_k"]); b = _f32(sim["lobe_beta"]); dc = _f32(sim["diff_coef"])
+    Q, Bk = k.shape
+    gk = np.zeros((Q, Bk)); gx = np.zeros((M, 3))
+    kind = np.ascontiguousarray(rec.get("kind", np.zeros(n, np.uint8)), np.uint8)
+    vis = np.ascontiguousarray(rec.get("vis", np.ones(n, np.uint8)), np.uint8)
+    rc = L.orc_grad(C.c_int64(n), _p(_f64(rec["p"])), _p(_f64(rec["dout"])), _p(_f64(rec["rtot"])), _p(_i32(rec["mat"])),
+                    _p(kind), _p(vis), C.c_int32(M), _p(rx), C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]),
+                    C.c_int32(F), C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
+                    C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
+                    _p(k), _p(b), _p(dc), _p(gg), _p(gk), _p(gx))
+    if rc != 0:
+        raise ValueError(f"orc_grad failed ({rc})")
+    return gk, gx
+
+
+def curvature(scene: dict, a_ref: float):
+    """Eq. (1): per-vertex G_v and per-triangle C_i (FP64)."""
+    L = lib()
+    v = _f32(scene["vertices"]); t = _i32(scene["tris"])
+    G = np.zeros(len(v)); Ci = np.zeros(len(t))
+    rc = L.orc_curvature(C.c_int64(len(v)), C.c_int64(len(t)), _p(v), _p(t), C.c_double(a_ref), _p(G), _p(Ci))
+    if rc != 0:
+        raise ValueError("orc_curvature failed")
+    return G, Ci
+
+
+def splitmix(key: int, counter: int) -> int:
+    return int(lib().orc_splitmix(C.c_uint64(key), C.c_uint64(counter)))
+
+
+def diffraction(scene: dict, sim: dict, Ci: np.ndarray, certify: bool = True, kappa: float = KAPPA) -> dict:
+    """Section III-D sampler: K candidates drawn from the dithered integer CDF of C_i,
+    filtered by incidence angle and line of sight to the emitter."""
+    L = lib()
+    v = _f32(scene["vertices"]); t = _i32(scene["tris"]); o = _i32(scene["tri_object"])
+    K = int(sim["diff_K"])
+    T = len(t)
+    q = np.zeros(max(T, 1), np.uint64)
+    ne = C.c_int64(0)
+    st = np.zeros(max(K, 1), np.int32); so = np.zeros((max(K, 1), 3)); sr = np.zeros(max(K, 1))
+    sk = np.zeros(max(K, 1), np.uint8); sc = np.zeros(max(K, 1), np.uint8)
+    Ci = _f64(Ci)
+    rc = L.orc_diffraction(C.c_int64(len(v)), C.c_int64(T), _p(v), _p(t), _p(o), C.c_int32(int(scene["n_objects"])),
+                           _p(Ci), _p(_f64(sim["emitter_pos"])), _p(_f64(sim["emitter_rot"])),
+                           C.c_double(math.radians(sim["diff_cone_half_angle_deg"])), C.c_double(sim["diff_tau"]),
+                           C.c_uint64(sim["diff_seed"]), C.c_int64(K),
+                           C.c_double(math.radians(sim["diff_max_incidence_deg"])), C.c_double(sim["t_eps"]),
+                           C.c_double(kappa if certify else 0.0), _p(q), C.byref(ne), _p(st), _p(so), _p(sr), _p(sk), _p(sc))
+    if rc != 0:
+        raise ValueError("orc_diffraction failed")
+    return {"q": q[:T], "n_elig": ne.value, "tri": st[:K], "o": so[:K], "r_src": sr[:K], "keep": sk[:K].astype(bool),
+            "certified": sc[:K].astype(bool)}
+
+
+def diffraction_records(scene: dict, samples: dict) -> dict:
+    """Kept diffraction samples as synthesis records (kind 1: omnidirectional secondary source)."""
+    keep = samples["keep"]
+    tri = samples["tri"][keep]
+    n = int(keep.sum())
+    return {"p": samples["o"][keep].copy(), "dout": np.zeros((n, 3)), "rtot": samples["r_src"][keep].copy(),
+            "mat": scene["tri_material"][tri].astype(np.int32), "kind": np.ones(n, np.uint8),
+            "vis": np.ones(n, np.uint8), "tri": tri.astype(np.int32)}
+
+
+def concat_records(a: dict, b: dict) -> dict:
+    keys = ["p", "dout", "rtot", "mat", "kind", "vis"]
+    return {k: np.concatenate([np.asarray(a[k]), np.asarray(b[k])]) for k in keys}

@@ -1,0 +1,442 @@
+"""Pins of the FP64 oracle against facts fixed by geometry, the paper's definitions and
+published algorithms -- never against the oracle itself or the GPU path.
+
+Each test names what pins it: the image-source construction of a planar wall, the
+unfolding of an empty box room, the reciprocity of a single reflection point, the pure
+delay of a unit-amplitude path, the textbook mean curvature of a sphere and of a plane,
+the published SplitMix64 outputs, sampling statistics, and finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _sim(**kw):
+    base = dict(emitter_pos=[0, 0, 0], emitter_rot=np.eye(3), rx_pos=[[0, 0, 0]], ray_dirs=[[1, 0, 0]],
+                max_bounces=1, f_lo=20e3, f_hi=100e3, F=257, refl_k=np.full((1, 8), 0.9),
+                lobe_beta=np.full((1, 8), 0.1), diff_coef=np.full((1, 8), 0.1))
+    base.update(kw)
+    return W.make_sim(**base)
+
+
+def wall_scene(d=3.0, h=5.0):
+    """Planar wall x = d; its diagonal does not pass through (d, 0, 0)."""
+    mb = W.MeshBuilder()
+    mb.add(np.array([[d, -h, -2 * h], [d, h, -2 * h], [d, h, h], [d, -h, h]], float), np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    return mb.build()
+
+
+def box_room(L=(5.0, 4.0, 3.0)):
+    mb = W.MeshBuilder()
+    v, t = W.quad_grid_box([0, 0, 0], list(L), 1)
+    mb.add(v, t, 0)
+    return mb.build()
+
+
+# ---------------------------------------------------------------------------------------- IS-1
+
+@pytest.mark.parametrize("p_s", [1.0, 2.0])
+def test_image_source_single_wall(p_s):
+    """On-axis ray at a planar wall x = d, receiver at the emitter: the echo is the image
+    source at 2d -- delay 2d/c, spreading (2d)^-p, absorption over 2d, no lobe loss."""
+    d = 3.0
+    scene = wall_scene(d)
+    sim = _sim(spreading_p=p_s)
+    rec = O.trace(scene, sim)
+    assert len(rec["rtot"]) == 1 and rec["vis"][0] == 1
+    np.testing.assert_allclose(rec["p"][0], [d, 0, 0], atol=1e-12)
+    np.testing.assert_allclose(rec["dout"][0], [-1, 0, 0], atol=1e-12)
+    H = O.synth(rec, sim)[0]
+    f = np.linspace(20e3, 100e3, 257)
+    r = 2 * d
+    atten = 10 ** (-(3.5e-5 * f) * r / 20)
+    k32 = float(np.float32(0.9))   # the tables are FP32 inputs
+    expect = k32 * r ** (-p_s) * atten * np.exp(1j * 2 * np.pi * f * r / 343.0)
+    np.testing.assert_allclose(H, expect, rtol=1e-11, atol=1e-14)
+    # the delay is 2d/c: the phase advances by 2 pi df (2d/c) per bin
+    ratio = H[1:] / H[:-1]
+    np.testing.assert_allclose(np.angle(ratio), np.angle(np.exp(1j * 2 * np.pi * (f[1] - f[0]) * r / 343.0)), atol=1e-9)
+
+
+def test_single_wall_offset_receiver():
+    """Receiver off axis: the method's path is emitter -> hit (d) -> receiver (sqrt(d^2+y^2)),
+    deviation angle atan(y/d) between the mirror direction (-1,0,0) and the receiver."""
+    d, y = 2.0, 0.3
+    scene = wall_scene(d)
+    sim = _sim(rx_pos=[[0, y, 0]])
+    rec = O.trace(scene, sim)
+    H = O.synth(rec, sim)[0]
+    f = np.linspace(20e3, 100e3, 257)
+    r = d + math.hypot(d, y)
+    gam = math.atan2(y, d)
+    k32, b32 = float(np.float32(0.9)), float(np.float32(0.1))
+    expect = k32 * r ** -2 * 10 ** (-(3.5e-5 * f) * r / 20) * math.exp(-gam ** 2 / (2 * b32 ** 2)) * np.exp(
+        1j * 2 * np.pi * f * r / 343.0)
+    np.testing.assert_allclose(H, expect, rtol=1e-11, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------------------- IS-2
+
+def test_single_wall_many_rays_geometry():
+    """Every ray of a cone hitting the wall x = d lands at s + (d / cos theta) d, with
+    path d / cos theta and the mirror direction (-dx, dy, dz)."""
+    d = 3.0
+    scene = wall_scene(d, h=20.0)
+    g = W.rng(5)
+    dirs = W.cone_directions(g, 500, math.radians(40))
+    sim = _sim(ray_dirs=dirs)
+    rec = O.trace(scene, sim)
+    assert len(rec["rtot"]) == 500
+    dd = dirs.astype(np.float64)
+    dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+    tt = d / dd[:, 0]
+    np.testing.assert_allclose(rec["rtot"], tt, rtol=1e-13)
+    np.testing.assert_allclose(rec["p"], dd * tt[:, None], atol=1e-12)
+    np.testing.assert_allclose(rec["dout"], dd * np.array([-1, 1, 1]), atol=1e-13)
+
+
+# ---------------------------------------------------------------------------------------- IS-4
+
+def _unfold(s, d, L, n):
+    """First n wall crossings of the straight line s + t d in the unfolded box lattice."""
+    cross = []
+    for a in range(3):
+        if d[a] == 0:
+            continue
+        if d[a] > 0:
+            ks = np.arange(1, n + 2)
+        else:
+            ks = -np.arange(0, n + 1)
+        for k in ks:
+            cross.append(((k * L[a] - s[a]) / d[a], a))
+    cross.sort()
+    cross = cross[:n]
+    out = []
+    flips = np.zeros(3, int)
+    for t, a in cross:
+        q = s + t * d
+        p = np.empty(3)
+        for b in range(3):
+            m = np.mod(q[b], 2 * L[b])
+            p[b] = m if m <= L[b] else 2 * L[b] - m
+        din = d * (-1.0) ** flips
+        flips[a] += 1
+        out.append((t, a, p, din))
+    return out, cross
+
+
+def test_box_room_unfolding():
+    """In an empty axis-aligned box, the n-th hit is the n-th lattice-plane crossing of the
+    unfolded straight line: path t_n, point fold(s + t_n d), incoming direction with one
+    sign flip per earlier crossing of that axis."""
+    L = np.array([5.0, 4.0, 3.0])
+    scene = box_room(tuple(L))
+    s = np.array([1.3, 1.7, 1.1])
+    g = W.rng(7)
+    v = g.normal(size=(200, 3))
+    dirs = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    B = 6
+    sim = _sim(emitter_pos=s, ray_dirs=dirs, max_bounces=B, rx_pos=[s + [0, 0.02, 0]])
+    rec = O.trace(scene, sim)
+    checked = 0
+    for i in range(len(dirs)):
+        d = dirs[i].astype(np.float64)
+        d /= np.linalg.norm(d)
+        exp, cr = _unfold(s, d, L, B)
+        ts = [c[0] for c in cr]
+        if min(np.diff(ts)) < 1e-6:
+            continue                                   # corner / edge crossing: ambiguous order
+        sel = rec["ray"] == i
+        assert sel.sum() == B
+        for j, (t, a, p, din) in enumerate(exp):
+            k = np.nonzero(sel)[0][j]
+            assert rec["bounce"][k] == j
+            np.testing.assert_allclose(rec["rtot"][k], t, rtol=1e-12)
+            np.testing.assert_allclose(rec["p"][k], p, atol=1e-10)
+            np.testing.assert_allclose(rec["din"][k], din, atol=1e-12)
+            # the hit triangle lies in the crossed wall plane
+            tri = scene["tris"][rec["tri"][k]]
+            wall = scene["vertices"][tri][:, a]
+            assert np.all(np.abs(wall - p[a]) < 1e-9)
+        checked += 1
+    assert checked > 180
+
+
+# ---------------------------------------------------------------------------------------- reciprocity
+
+def test_reciprocity_single_point():
+    """Swapping emitter and receiver about one reflection point leaves the path length and
+    the deviation angle unchanged, hence the spectrum (R(a).b = a.R(b) for a mirror R)."""
+    scene = wall_scene(2.0)
+    A = np.array([0.0, 0.0, 0.0])
+    Bp = np.array([0.0, 2.0, 0.5])
+    p = np.array([2.0, 1.0, 0.25])
+    # exact FP32 directions (the oracle normalises in FP64): toward p from A and from B
+    simAB = _sim(emitter_pos=A, rx_pos=[Bp], ray_dirs=[[2.0, 1.0, 0.25]], x_ref=Bp)
+    simBA = _sim(emitter_pos=Bp, rx_pos=[A], ray_dirs=[[2.0, -1.0, -0.25]], x_ref=A)
+    rAB = O.trace(scene, simAB)
+    rBA = O.trace(scene, simBA)
+    np.testing.assert_allclose(rAB["p"][0], p, atol=1e-13)
+    np.testing.assert_allclose(rBA["p"][0], p, atol=1e-13)
+    HAB = O.synth(rAB, simAB)
+    HBA = O.synth(rBA, simBA)
+    np.testing.assert_allclose(HAB, HBA, rtol=1e-12, atol=0)
+    # the off-specular case: same point, different receiver heights still reciprocal
+    C2 = np.array([0.0, 2.3, -0.4])
+    s1 = _sim(emitter_pos=A, rx_pos=[C2], ray_dirs=[[2.0, 1.0, 0.25]], x_ref=C2)
+    r1 = O.trace(scene, s1)
+    dC = (p - C2).astype(np.float32)
+    s2 = _sim(emitter_pos=C2, rx_pos=[A], ray_dirs=[dC], x_ref=A)
+    r2 = O.trace(scene, s2)
+    assert np.linalg.norm(r2["p"][0] - p) < 1e-6            # FP32 direction from C2 is rounded
+    H1, H2 = O.synth(r1, s1), O.synth(r2, s2)
+    np.testing.assert_allclose(np.abs(H1), np.abs(H2), rtol=1e-5)
+
+
+# ---------------------------------------------------------------------------------------- synthesis
+
+def test_pure_delay_special_case():
+    """alpha = 0, beta -> inf, p = 0, k = 1: each bin is exp(j 2 pi f r / c); the spectrum is a
+    geometric sequence in k and its forward DFT peaks at bin F df r / c (delay r / c)."""
+    F = 1024
+    sim = _sim(F=F, atm_a1=0.0, spreading_p=0.0, refl_k=np.ones((1, 8)), lobe_beta=np.full((1, 8), 1e6))
+    r_tot, ell = 1.5, 1.0
+    rec = {"p": np.array([[1.0, 0, 0]]), "dout": np.array([[-1.0, 0, 0]]), "rtot": np.array([r_tot]),
+           "mat": np.array([0], np.int32)}
+    H = O.synth(rec, sim)[0]
+    r = r_tot + ell
+    np.testing.assert_allclose(np.abs(H), 1.0, atol=1e-12)
+    df = (100e3 - 20e3) / (F - 1)
+    ratio = H[1:] / H[:-1]
+    np.testing.assert_allclose(ratio, np.exp(1j * 2 * np.pi * df * r / 343.0), atol=1e-10)
+    h = np.fft.fft(H)
+    assert np.argmax(np.abs(h)) == int(round(F * df * r / 343.0)) % F
+
+
+def test_spectrum_is_linear_in_records():
+    """Eq. (6): the total response is the sum of per-point responses."""
+    scene, sim = W.tiny_scene(n_rays=64, F=64)
+    rec = O.trace(scene, sim)
+    H = O.synth(rec, sim)
+    parts = sum(O.synth({k: v[i:i + 1] for k, v in rec.items() if k not in ("certified", "nseg")}, sim)
+                for i in range(len(rec["rtot"])))
+    np.testing.assert_allclose(H, parts, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------- curvature
+
+def test_curvature_sphere():
+    """Mean curvature of a sphere of radius r is 1/r: the Meyer operator on an icosphere
+    (subdivision 3) reproduces it within its O(h^2) discretisation error."""
+    v, t = W.icosphere(3, 0.5)
+    scene = {"vertices": v.astype(np.float32), "tris": t.astype(np.int32)}
+    G, C = O.curvature(scene, 1.0)
+    np.testing.assert_allclose(G, 2.0, rtol=2e-3)
+    # scaling by s divides curvature by s
+    scene2 = {"vertices": (2 * v).astype(np.float32), "tris": t.astype(np.int32)}
+    G2, _ = O.curvature(scene2, 1.0)
+    np.testing.assert_allclose(G2, G / 2, rtol=1e-6)
+
+
+def test_curvature_flat_plane():
+    """The cotangent Laplacian reproduces linear functions: interior vertices of a flat
+    mesh have K = 0; so does every triangle with only interior vertices."""
+    n = 8
+    xs, ys = np.meshgrid(np.linspace(0, 1, n + 1), np.linspace(0, 1, n + 1) ** 1.3, indexing="ij")
+    v = np.stack([xs.ravel(), ys.ravel(), np.zeros(xs.size)], 1).astype(np.float32)
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = i * (n + 1) + j, (i + 1) * (n + 1) + j, (i + 1) * (n + 1) + j + 1, i * (n + 1) + j + 1
+            tris += [(a, b, c), (a, c, d)]
+    t = np.array(tris, np.int32)
+    G, C = O.curvature({"vertices": v, "tris": t}, 1.0)
+    interior = np.ones((n + 1, n + 1), bool)
+    interior[0, :] = interior[-1, :] = interior[:, 0] = interior[:, -1] = False
+    interior = interior.ravel()
+    assert np.all(np.abs(G[interior]) < 1e-12)
+    assert np.all(G[~interior] > 1e-3)                    # open boundary: one-sided cotangents
+    inner_tri = interior[t].all(1)
+    assert np.all(C[inner_tri] == 0)
+
+
+def test_curvature_box_edges():
+    """A subdivided box is flat except along its edges: C_i > 0 exactly on triangles that
+    touch an edge or corner of the box."""
+    v, t = W.quad_grid_box([0, 0, 0], [1.0, 0.7, 0.4], 5)
+    G, C = O.curvature({"vertices": v.astype(np.float32), "tris": t.astype(np.int32)}, 1.0)
+    lo, hi = v.min(0), v.max(0)
+    on_edge = ((np.abs(v - lo) < 1e-9) | (np.abs(v - hi) < 1e-9)).sum(1) >= 2
+    assert np.all(G[~on_edge] < 1e-9)
+    assert np.all(G[on_edge] > 1e-3)
+    touches = on_edge[t].any(1)
+    # triangles whose vertices all sit on edges can still have dG = 0 (equal G); never the reverse
+    assert np.all(C[~touches] < 1e-12)              # rounding noise of a flat one-ring only
+    assert (C[touches] > 0).mean() > 0.5
+
+
+# ---------------------------------------------------------------------------------------- RNG
+
+def test_splitmix_published_outputs():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) if l.strip() and not l.startswith("#")]
+    for c, hexv in rows:
+        assert O.splitmix(0, int(c)) == int(hexv, 16)
+
+
+# ---------------------------------------------------------------------------------------- diffraction
+
+def _boxes_scene():
+    mb = W.MeshBuilder()
+    g = W.rng(11)
+    for i in range(6):
+        v, t = W.quad_grid_box([0, 0, 0], list(g.uniform(0.3, 0.8, 3)), 4)
+        mb.add(v + np.array([2.0 + i * 0.9, g.uniform(-1, 1), g.uniform(-0.5, 0.5)]), t, i % 3)
+    return mb.build()
+
+
+def test_diffraction_sampler_statistics():
+    """Samples are drawn with probability q_i / sum(q): chi-square of the triangle histogram;
+    every sample lies on its triangle; only edge triangles of the boxes carry weight."""
+    from scipy.stats import chisquare
+    scene = _boxes_scene()
+    G, C = O.curvature(scene, W.median_triangle_area(scene))
+    sim = _sim(diff_K=200000, diff_seed=99, diff_tau=0.0, diff_cone_half_angle_deg=90.0)
+    s = O.diffraction(scene, sim, C, certify=False)
+    q = s["q"].astype(np.float64)
+    assert s["n_elig"] == int((q > 0).sum())
+    assert np.all(C[q > 0] > 0)
+    # dithered weights: q = floor(x) or floor(x) + 1 with x = C / Cmax * 2^32
+    x = C / C.max() * 2.0 ** 32
+    sel = q > 0
+    assert np.all((q[sel] == np.floor(x[sel])) | (q[sel] == np.floor(x[sel]) + 1))
+    tri = s["tri"]
+    assert np.all(q[tri] > 0)
+    counts = np.bincount(tri, minlength=len(q))[sel]
+    expect = q[sel] / q[sel].sum() * len(tri)
+    big = expect >= 5
+    obs, exp = counts[big], expect[big]
+    if (~big).any():
+        obs, exp = np.append(obs, counts[~big].sum()), np.append(exp, expect[~big].sum())
+    assert chisquare(obs, exp).pvalue > 1e-3
+    # each sample point lies on its triangle (barycentric coordinates in [0, 1])
+    V = scene["vertices"].astype(np.float64)
+    T = scene["tris"][tri]
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    o = s["o"]
+    n = np.cross(b - a, c - a)
+    area = np.linalg.norm(n, axis=1)
+    wa = np.einsum("ij,ij->i", np.cross(b - o, c - o), n) / area ** 2
+    wb = np.einsum("ij,ij->i", np.cross(c - o, a - o), n) / area ** 2
+    assert np.all(wa > -1e-9) and np.all(wb > -1e-9) and np.all(wa + wb < 1 + 1e-9)
+    assert np.all(np.abs(np.einsum("ij,ij->i", o - a, n / area[:, None])) < 1e-12)
+
+
+def test_diffraction_filters():
+    """Kept samples satisfy the incidence constraint and see the source; the field-of-view
+    test removes objects behind the emitter."""
+    scene = _boxes_scene()
+    G, C = O.curvature(scene, W.median_triangle_area(scene))
+    sim = _sim(diff_K=4000, diff_seed=5, diff_tau=0.1, diff_max_incidence_deg=60.0, diff_cone_half_angle_deg=90.0)
+    s = O.diffraction(scene, sim, C, certify=False)
+    V = scene["vertices"].astype(np.float64)
+    T = scene["tris"][s["tri"]]
+    n = np.cross(V[T[:, 1]] - V[T[:, 0]], V[T[:, 2]] - V[T[:, 0]])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    w = -s["o"]
+    cosi = np.abs(np.einsum("ij,ij->i", n, w)) / np.linalg.norm(w, axis=1)
+    assert np.all(cosi[s["keep"]] >= math.cos(math.radians(60)) - 1e-12)
+    np.testing.assert_allclose(s["r_src"], np.linalg.norm(s["o"], axis=1), rtol=1e-14)
+    # rear-facing emitter: boxes sit at x > 1.5, a cone about -x with half-angle 30 deg sees none
+    sim_back = _sim(diff_K=100, diff_seed=5, emitter_rot=np.diag([-1.0, -1.0, 1.0]), diff_cone_half_angle_deg=30.0)
+    s2 = O.diffraction(scene, sim_back, C, certify=False)
+    assert s2["n_elig"] == 0 and not s2["keep"].any()
+
+
+# ---------------------------------------------------------------------------------------- adjoint
+
+def _loss(rec, sim, Hstar):
+    H = O.synth(rec, sim)
+    return float(np.sum(np.abs(H - Hstar) ** 2))
+
+
+def test_adjoint_matches_finite_differences():
+    """Central differences (h = 1e-6, FP64) of L = sum |H - H*|^2 with respect to every band
+    coefficient and every receiver coordinate match the analytic adjoint."""
+    scene, sim = W.tiny_scene(n_rays=48, F=64)
+    g = W.rng(3)
+    sim["refl_k"] = np.ascontiguousarray(g.uniform(0.3, 0.99, (1, 8)).astype(np.float32))
+    sim["lobe_beta"] = np.ascontiguousarray(g.uniform(0.1, 0.3, (1, 8)).astype(np.float32))
+    rec = O.trace(scene, sim)
+    assert len(rec["rtot"]) > 20
+    hidden = dict(sim)
+    hidden["refl_k"] = np.ascontiguousarray(g.uniform(0.3, 0.99, (1, 8)).astype(np.float32))
+    Hstar = O.synth(rec, hidden)
+    H = O.synth(rec, sim)
+    gk, gx = O.grad(rec, sim, H - Hstar)
+    # k is FP32 in the ABI; differentiate in FP64 through a float64 table (the oracle promotes exactly)
+    h = 1e-6
+    for b in range(8):
+        kp = sim["refl_k"].astype(np.float64).copy(); kp[0, b] += h
+        km = sim["refl_k"].astype(np.float64).copy(); km[0, b] -= h
+        # H is linear in k: evaluate with unit tables to stay in FP64
+        e = np.zeros((1, 8), np.float32); e[0, b] = 1.0
+        Hb = O.synth(rec, dict(sim, refl_k=e))
+        Lp = np.sum(np.abs(H + h * Hb - Hstar) ** 2)
+        Lm = np.sum(np.abs(H - h * Hb - Hstar) ** 2)
+        np.testing.assert_allclose(gk[0, b], (Lp - Lm) / (2 * h), rtol=1e-6, atol=1e-12 * abs(Lp))
+    for m in range(2):
+        for a in range(3):
+            sp = dict(sim); sp["rx_pos"] = sim["rx_pos"].copy(); sp["rx_pos"][m, a] += h
+            sm = dict(sim); sm["rx_pos"] = sim["rx_pos"].copy(); sm["rx_pos"][m, a] -= h
+            fd = (_loss(rec, sp, Hstar) - _loss(rec, sm, Hstar)) / (2 * h)
+            np.testing.assert_allclose(gx[m, a], fd, rtol=1e-5, atol=1e-9 * max(1.0, abs(fd)))
+
+
+def test_spectrum_linear_in_band_coefficients():
+    """With the reflection coefficient of the hit triangle only, H is linear in k:
+    H(k) = sum_{q,b} k_qb H(e_qb)."""
+    scene, sim = W.tiny_scene(n_rays=64, F=32)
+    rec = O.trace(scene, sim)
+    g = W.rng(4)
+    k = g.uniform(0.3, 0.99, (1, 8)).astype(np.float32)
+    H = O.synth(rec, dict(sim, refl_k=k))
+    acc = 0
+    for b in range(8):
+        e = np.zeros((1, 8), np.float32); e[0, b] = 1
+        acc = acc + float(k[0, b]) * O.synth(rec, dict(sim, refl_k=e))
+    np.testing.assert_allclose(H, acc, rtol=1e-12, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------------------- invariants
+
+def test_closed_sphere_never_missed_from_inside():
+    """Rays from the centre of a closed icosphere all hit it (brute force, FP64)."""
+    v, t = W.icosphere(3, 0.5)
+    mb = W.MeshBuilder(); mb.add(v, t, 0)
+    scene = mb.build()
+    g = W.rng(9)
+    d = g.normal(size=(2000, 3)).astype(np.float32)
+    sim = _sim(ray_dirs=d, max_bounces=1, rx_pos=[[0.01, 0, 0]])
+    rec = O.trace(scene, sim)
+    assert len(rec["rtot"]) == 2000
+    np.testing.assert_allclose(np.linalg.norm(rec["p"], axis=1), 0.5, rtol=0.01)
+
+
+def test_margin_predicate_flags_edge_hits():
+    """Rays aimed exactly at the shared diagonal of a two-triangle wall are marginal;
+    rays through triangle interiors are certified."""
+    d = 3.0
+    mb = W.MeshBuilder()
+    mb.add(np.array([[d, -2, -2], [d, 2, -2], [d, 2, 2], [d, -2, 2]], float), np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    scene = mb.build()
+    dirs = np.array([[3, 0, 0], [3, 1, 1], [3, 0.5, -1.2], [3, -1, 0.9]], np.float32)
+    sim = _sim(ray_dirs=dirs, rx_pos=[[0, 0.01, 0]])
+    rec = O.trace(scene, sim)
+    assert list(rec["certified"]) == [False, False, True, True]
