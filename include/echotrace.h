@@ -1,0 +1,229 @@
+/*
+ * echotrace.h -- C ABI of the MI355X (gfx950) echo-simulation hot path.
+ *
+ * Computes what the SonoTraceUE paper (Jansen & Steckel, arXiv 2602.19652) computes per
+ * frame: rays emitted from a sensor pose are traced through a triangle-mesh scene with
+ * specular bounces (Sec. III-C, Algorithm 1), curvature-importance Monte Carlo
+ * diffraction points are drawn (Sec. III-D), and every path becomes a complex
+ * contribution to each receiver's transfer function (Eqs. 2-4 specular, Eqs. 7-8
+ * diffraction).  Scene in, per-receiver spectra out.
+ *
+ * Conventions
+ *  - Every call returns an int status (et_status); no exception crosses the ABI.
+ *    et_last_error() gives a message for the last failing call on a context.
+ *  - Pointers documented as "device" are HIP device pointers (e.g. torch CUDA tensors on
+ *    ROCm); "host" pointers are read during the call only.  The caller owns every buffer:
+ *    scene blob, scratch, workspace, inputs and outputs.  The library allocates no
+ *    device memory.
+ *  - Calls enqueue work on the context's stream and return; outputs are valid once the
+ *    stream has completed the work (the Python binding uses torch's current stream).
+ *    et_get_stats() synchronises the stream.
+ *  - A context is used by one host thread at a time.  Scenes are immutable after build
+ *    and may be shared by contexts on the same device.
+ *  - Host-side validation (shapes, null pointers, ranges of scalar parameters) runs
+ *    before any launch; array contents on the device are trusted, except that index
+ *    arrays are range-checked on the device during scene build (ET_E_INVALID reported
+ *    by et_get_stats via the error word).
+ *  - Angles are radians, lengths metres, frequencies Hz.  Rotation matrices are 3x3
+ *    row-major, their columns are the local axes expressed in world coordinates
+ *    (world = R * local).
+ */
+#ifndef ECHOTRACE_H
+#define ECHOTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ET_ABI_VERSION 1
+
+typedef enum {
+  ET_OK = 0,
+  ET_E_INVALID = -1,     /* bad argument: null pointer, shape, range, NaN pose */
+  ET_E_WORKSPACE = -2,   /* caller buffer smaller than the queried size */
+  ET_E_CAPACITY = -3,    /* path buffer too small for the records produced (true count in stats) */
+  ET_E_DEVICE = -4,      /* HIP runtime error */
+  ET_E_UNSUPPORTED = -5, /* valid request outside what this build implements */
+  ET_E_INTERNAL = -6     /* device-side invariant broken (e.g. traversal stack overflow) */
+} et_status;
+
+typedef struct et_ctx et_ctx;
+typedef struct et_scene et_scene;
+
+int et_abi_version(void);
+const char* et_status_string(int status);
+
+/* Context bound to a HIP device and stream (stream may be NULL: the null stream). */
+int et_create(int device, void* hip_stream, et_ctx** out);
+int et_destroy(et_ctx* ctx);
+int et_set_stream(et_ctx* ctx, void* hip_stream);
+const char* et_last_error(const et_ctx* ctx);
+
+/* ------------------------------------------------------------------ scene (Sec. III-B)
+ * Scene mesh: world-space triangles welded per object, with a material (acoustic
+ * profile) per triangle (per-object granularity, Sec. III-B) and an object id used by
+ * the emitter field-of-view test of the diffraction sampler (Sec. III-D). */
+typedef struct {
+  int64_t V, T;
+  const float* vertices;        /* device [V][3] */
+  const int32_t* tris;          /* device [T][3], indices in [0, V) */
+  const int32_t* tri_material;  /* device [T], in [0, Q) of the simulation tables */
+  const int32_t* tri_object;    /* device [T], in [0, n_objects) */
+  int32_t n_objects;
+  double area_ref;              /* reference area of the curvature metric's area weight
+                                   w(A) = min(1, A / area_ref), Eq. (1); <= 0 gives w = 1 */
+} et_mesh_desc;
+
+/* Byte sizes of the scene blob (kept for the scene's lifetime: BVH nodes, repacked
+ * triangles, curvature C_i, object boxes) and of the build scratch (free after build). */
+int et_scene_size(et_ctx* ctx, const et_mesh_desc* mesh, size_t* blob_bytes, size_t* scratch_bytes);
+
+/* Builds the device acceleration structure (surface-area-driven agglomerative BVH over
+ * Morton-sorted triangles) and the per-triangle curvature metric C_i of Eq. (1) (Meyer
+ * et al. cotangent operator).  The handle borrows `blob` and copies the mesh pointers
+ * (the mesh arrays must outlive the scene). */
+int et_scene_build(et_ctx* ctx, const et_mesh_desc* mesh, void* blob, size_t blob_bytes, void* scratch,
+                   size_t scratch_bytes, et_scene** out);
+int et_scene_free(et_scene* scene);
+
+typedef struct {
+  int64_t T, V, n_nodes;
+  int32_t depth;          /* BVH depth (root = 1) */
+  double sah_cost;        /* SAH cost with C_node = 1, C_tri = 1, normalised by the root area */
+  double build_ms;        /* device time of the build (event-timed) */
+} et_scene_info;
+int et_scene_get_info(et_ctx* ctx, const et_scene* scene, et_scene_info* info);   /* synchronises */
+
+/* Device copies of the curvature outputs of the build: C [T] (Eq. 1) and G_v [V]
+ * (half the norm of the mean-curvature normal).  Either pointer may be NULL. */
+int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double* G_out);
+
+/* ------------------------------------------------------------------ one pose (one emitter) */
+enum {
+  ET_SPECULAR = 1u << 0,      /* trace rays (Algorithm 1) and synthesise their records */
+  ET_DIFFRACTION = 1u << 1,   /* draw diff_K curvature-importance samples (Sec. III-D) */
+  ET_SYNTH_DIRECT = 1u << 2   /* force the per-term synthesis kernel (no factorised MFMA path) */
+};
+
+typedef struct {
+  double emitter_pos[3];
+  double emitter_rot[9];
+  int32_t M;                    /* receivers */
+  const double* rx_pos;         /* device [M][3] */
+  const double* rx_rot;         /* device [M][9] or NULL (identity frames) */
+  double x_ref[3];              /* target of the per-hit line-of-sight ray (Algorithm 1) */
+  int64_t N;                    /* rays */
+  const float* ray_dirs;        /* device [N][3], emitter frame (normalised in FP64) */
+  int32_t max_bounces;          /* reflection points (hit records) per ray, >= 1 */
+  double max_distance;          /* stop a ray once its path reaches this (after recording) */
+  double t_eps;                 /* self-intersection threshold: hits need t > t_eps */
+  double f_lo, f_hi;            /* inclusive linear frequency grid of F bins */
+  int32_t F;
+  double c;                     /* speed of sound (343 m/s in the paper) */
+  double atm_a0, atm_a1;        /* air absorption A(f) = a0 + a1 f in dB/m: L_atm = 10^(-A r / 20) */
+  double spreading_p;           /* spreading L_geo = r^-p (p = 2 in the paper) */
+  int32_t phase_sign;           /* +1: exp(+j 2 pi f r / c) as printed in Eq. (4); -1 conjugates */
+  int32_t Q, Bk;                /* materials x frequency bands; band of bin k is floor(k Bk / F) */
+  const float* refl_k;          /* device [Q][Bk] reflection magnitude k (Eq. 2) */
+  const float* lobe_beta;       /* device [Q][Bk] lobe opening angle beta, radians (Eq. 2) */
+  const float* diff_coef;       /* device [Q][Bk] diffraction coefficient I_d (Eq. 7) */
+  int32_t Bd, El, Az;           /* directivity bands, elevation and azimuth cells */
+  const float* directivity;     /* device [M][Bd][El][Az] real gain or NULL */
+  int64_t diff_K;               /* diffraction samples */
+  uint64_t diff_seed;
+  double diff_tau;              /* eligibility: C_i >= tau * max C */
+  double diff_max_incidence;    /* incidence limit between normal and source direction */
+  double diff_cone_half_angle;  /* emitter field of view for object eligibility */
+  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT */
+} et_sim_desc;
+
+/* Path records (hit buffer B of Algorithm 1 plus diffraction points), caller-owned
+ * device SoA arrays of `capacity` entries.  Order: specular records bounce-major (all
+ * bounce-0 hits in ray order, then bounce 1, ...), then kept diffraction samples in
+ * sample order.  count (device int64[4]) = {records, specular, diffraction, segments}. */
+typedef struct {
+  int64_t capacity;
+  double* p;          /* [cap][3] hit / diffraction point */
+  float* dout;        /* [cap][3] reflected direction (specular) */
+  double* rtot;       /* [cap] path length emitter -> point */
+  int32_t* tri;       /* [cap] original triangle index */
+  int32_t* mat;       /* [cap] material of the triangle */
+  int32_t* ray;       /* [cap] ray index (specular) or sample index (diffraction) */
+  uint8_t* bounce;    /* [cap] reflection index within the ray */
+  uint8_t* flags;     /* [cap] bit0 visible (line of sight), bit1 diffraction record */
+  int64_t* count;     /* device int64[4] */
+} et_paths;
+
+/* Workspace bytes for et_trace / et_synthesize / et_simulate with this descriptor. */
+int et_workspace_size(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, size_t* bytes);
+
+/* Algorithm 1 (+ diffraction sampling if ET_DIFFRACTION): fills `paths`.  Records beyond
+ * capacity are dropped and the call reports ET_E_CAPACITY at the next et_get_stats. */
+int et_trace(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, void* ws, size_t ws_bytes,
+             const et_paths* paths);
+
+/* Eqs. (2)-(4), (7)-(8): spectra[m][k] = sum over visible records of M(f_k) e^{j sigma 2 pi f_k r / c}
+ * with r = rtot + |p - x_m|.  Output device float [M][F][2] (complex64), overwritten.
+ * Reads the record count from paths->count[0]. */
+int et_synthesize(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void* ws, size_t ws_bytes,
+                  float* spectra);
+
+/* et_trace followed by et_synthesize. */
+int et_simulate(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, const et_paths* paths, void* ws,
+                size_t ws_bytes, float* spectra);
+
+/* Adjoint of et_synthesize over fixed records: given grad_spectra = dL/dH* as complex64
+ * [M][F][2] (for L = sum |H - H_target|^2 this is H - H_target), writes dL/d refl_k as
+ * double [Q][Bk] and dL/d rx_pos as double [M][3] (device, overwritten).  Records keep
+ * their hit points and visibility ("fixed ray paths").  Directivity must be NULL. */
+int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra,
+                           void* ws, size_t ws_bytes, double* grad_k, double* grad_rx);
+
+/* ------------------------------------------------------------------ batches of poses */
+typedef struct {
+  const et_scene* scene;
+  const et_sim_desc* sim;       /* per-job descriptor (M, F, B, Q, Bk equal across jobs) */
+} et_job;
+
+/* Workspace for a batch (all jobs' rays and records) and per-job record capacity. */
+int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes);
+
+/* Traces and synthesises J jobs with one launch sequence per phase: all jobs' rays share
+ * the bounce kernels, all records share the synthesis kernels.  spectra is device
+ * float [J][M][F][2].  grad_spectra (optional, same shape) adds the adjoint of every
+ * job into grad_k [J][Q][Bk] and grad_rx [J][M][3] (device double). */
+int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                      const float* grad_spectra, double* grad_k, double* grad_rx);
+
+/* Captures et_simulate_batch into a HIP graph owned by the context and replays it
+ * (the first call captures; later calls with the same arguments replay). */
+int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes,
+                            float* spectra, const float* grad_spectra, double* grad_k, double* grad_rx);
+int et_graph_reset(et_ctx* ctx);
+
+/* ------------------------------------------------------------------ statistics */
+typedef struct {
+  int64_t records, specular, diffraction, segments;  /* of the last trace */
+  int64_t shadow_rays;                               /* visibility / line-of-sight rays */
+  int64_t diff_eligible;                             /* triangles in the diffraction CDF */
+  int64_t stack_overflows;                           /* traversal stack overflows (must be 0) */
+  int64_t dropped;                                   /* records beyond capacity */
+  int32_t synth_kernel;                              /* 1 factorised MFMA, 2 direct per-term */
+  int32_t status;                                    /* deferred device-side status */
+  double ms_trace, ms_diffraction, ms_synth;         /* event-timed phases of the last calls */
+} et_stats;
+int et_get_stats(et_ctx* ctx, et_stats* out);   /* synchronises the context stream */
+
+/* Traversal work counters (node and triangle fetches of closest-hit and any-hit queries)
+ * for the roofline's algorithmic bytes: enables counting in the next et_trace.  0/1. */
+int et_set_counting(et_ctx* ctx, int enable);
+typedef struct { int64_t nodes_closest, tris_closest, nodes_any, tris_any, rays_closest, rays_any; } et_counters;
+int et_get_counters(et_ctx* ctx, et_counters* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,553 @@
+// C ABI entry points (include/echotrace.h): argument validation, workspace planning,
+// launch sequencing on the context stream, statistics and graph capture.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace et;
+
+struct et_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  Ctl* ctl = nullptr;                 // device control block (the only library allocation)
+  bool counting = false;
+  hipEvent_t ev[8] = {};
+  bool timed_trace = false, timed_diff = false, timed_synth = false;
+  int synth_kernel = 0;
+  const int64_t* last_count = nullptr;   // device count array of the last traced paths
+  // graph replay of a batch
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
+};
+
+namespace {
+
+int fail(et_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(et_ctx* ctx, F&& f) {
+  if (!ctx) return ET_E_INVALID;
+  try {
+    ET_HIP(hipSetDevice(ctx->device));
+    f();
+    ctx->last_error.clear();
+    return ET_OK;
+  } catch (const Error& e) {
+    return fail(ctx, e.code, e.msg);
+  } catch (const std::exception& e) {
+    return fail(ctx, ET_E_INTERNAL, e.what());
+  }
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+void validate_mesh(const et_mesh_desc* m) {
+  ET_CHECK(m, ET_E_INVALID, "mesh descriptor is NULL");
+  ET_CHECK(m->T >= 0 && m->V >= 0, ET_E_INVALID, "negative mesh sizes");
+  ET_CHECK(m->T < (int64_t)1 << 31 && m->V < (int64_t)1 << 31, ET_E_UNSUPPORTED, "mesh larger than 2^31 elements");
+  ET_CHECK(m->T == 0 || (m->vertices && m->tris && m->tri_material && m->tri_object), ET_E_INVALID,
+           "mesh array pointer is NULL");
+  ET_CHECK(m->n_objects >= 1, ET_E_INVALID, "n_objects must be >= 1");
+  ET_CHECK(std::isfinite(m->area_ref), ET_E_INVALID, "area_ref is not finite");
+}
+
+void validate_sim(const et_sim_desc* s, bool need_rays) {
+  ET_CHECK(s, ET_E_INVALID, "simulation descriptor is NULL");
+  ET_CHECK(finite3(s->emitter_pos) && finite3(s->x_ref), ET_E_INVALID, "emitter position or x_ref not finite");
+  for (int i = 0; i < 9; ++i) ET_CHECK(std::isfinite(s->emitter_rot[i]), ET_E_INVALID, "emitter rotation not finite");
+  ET_CHECK(s->M >= 1 && s->rx_pos, ET_E_INVALID, "need M >= 1 receivers and rx_pos");
+  ET_CHECK(s->F >= 1, ET_E_INVALID, "need F >= 1 frequency bins");
+  ET_CHECK(std::isfinite(s->f_lo) && std::isfinite(s->f_hi) && s->f_lo >= 0 && s->f_hi >= s->f_lo, ET_E_INVALID,
+           "frequency grid must satisfy 0 <= f_lo <= f_hi");
+  ET_CHECK(std::isfinite(s->c) && s->c > 0, ET_E_INVALID, "speed of sound must be positive");
+  ET_CHECK(std::isfinite(s->atm_a0) && std::isfinite(s->atm_a1) && std::isfinite(s->spreading_p), ET_E_INVALID,
+           "absorption / spreading parameters not finite");
+  ET_CHECK(s->phase_sign == 1 || s->phase_sign == -1, ET_E_INVALID, "phase_sign must be +1 or -1");
+  ET_CHECK(s->Q >= 1 && s->Bk >= 1 && s->Bk <= 64, ET_E_INVALID, "need Q >= 1 and 1 <= Bk <= 64");
+  ET_CHECK(s->refl_k && s->lobe_beta && s->diff_coef, ET_E_INVALID, "material tables are NULL");
+  if (s->directivity) {
+    ET_CHECK(s->Bd >= 1 && s->Bd <= 64 && s->El >= 1 && s->Az >= 1, ET_E_INVALID, "directivity shape invalid");
+  }
+  if (need_rays) {
+    ET_CHECK(s->N >= 0, ET_E_INVALID, "negative ray count");
+    ET_CHECK(s->N == 0 || s->ray_dirs || !(s->flags & ET_SPECULAR), ET_E_INVALID, "ray_dirs is NULL");
+    ET_CHECK(s->N < (int64_t)1 << 31, ET_E_UNSUPPORTED, "more than 2^31 rays in one pose");
+    ET_CHECK(s->max_bounces >= 1 && s->max_bounces <= 255, ET_E_INVALID, "max_bounces must be in [1, 255]");
+    ET_CHECK(!std::isnan(s->max_distance) && s->max_distance > 0, ET_E_INVALID, "max_distance must be > 0");
+    ET_CHECK(std::isfinite(s->t_eps) && s->t_eps >= 0, ET_E_INVALID, "t_eps must be finite and >= 0");
+    if (s->flags & ET_DIFFRACTION) {
+      ET_CHECK(s->diff_K >= 0 && s->diff_K < (int64_t)1 << 31, ET_E_INVALID, "diff_K out of range");
+      ET_CHECK(std::isfinite(s->diff_tau) && std::isfinite(s->diff_max_incidence) &&
+                   std::isfinite(s->diff_cone_half_angle),
+               ET_E_INVALID, "diffraction parameters not finite");
+    }
+  }
+}
+
+void validate_paths(const et_paths* p) {
+  ET_CHECK(p, ET_E_INVALID, "paths descriptor is NULL");
+  ET_CHECK(p->capacity >= 0, ET_E_INVALID, "negative path capacity");
+  ET_CHECK(p->count, ET_E_INVALID, "paths->count is NULL");
+  ET_CHECK(p->capacity == 0 || (p->p && p->dout && p->rtot && p->tri && p->mat && p->ray && p->bounce && p->flags),
+           ET_E_INVALID, "a path array is NULL");
+}
+
+int64_t records_upper_bound(const et_sim_desc* s) {
+  int64_t n = 0;
+  if (s->flags & ET_SPECULAR) n += s->N * (int64_t)s->max_bounces;
+  if (s->flags & ET_DIFFRACTION) n += s->diff_K;
+  return n;
+}
+
+size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+struct WsPlan {
+  size_t trace = 0, synth = 0, bwd = 0;
+  size_t total() const { return trace + synth + bwd; }
+};
+
+WsPlan plan(const et_scene* sc, const et_sim_desc* s, int64_t cap) {
+  WsPlan w;
+  const int64_t N = (s->flags & ET_SPECULAR) ? s->N : 0;
+  const int64_t K = (s->flags & ET_DIFFRACTION) ? s->diff_K : 0;
+  if (sc) w.trace = al(trace_ws_layout(N, sc->d.T, sc->d.n_obj, K, nullptr, nullptr));
+  w.synth = al(synth_ws_layout(s, cap, nullptr, nullptr));
+  w.bwd = al(synth_bwd_ws_layout(s, cap, nullptr, nullptr));
+  return w;
+}
+
+void check_scene(const et_scene* sc) { ET_CHECK(sc, ET_E_INVALID, "scene is NULL"); }
+
+void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* ws, size_t ws_bytes, const et_paths* paths) {
+  check_scene(sc);
+  validate_sim(sim, true);
+  validate_paths(paths);
+  const WsPlan w = plan(sc, sim, std::max<int64_t>(paths->capacity, records_upper_bound(sim)));
+  ET_CHECK(ws || w.trace == 0, ET_E_INVALID, "workspace is NULL");
+  ET_CHECK(ws_bytes >= w.trace, ET_E_WORKSPACE, "workspace too small for et_trace");
+  TraceWS tw;
+  trace_ws_layout((sim->flags & ET_SPECULAR) ? sim->N : 0, sc->d.T, sc->d.n_obj,
+                  (sim->flags & ET_DIFFRACTION) ? sim->diff_K : 0, (char*)ws, &tw);
+  ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+  trace_run(sc->d, sim, paths, tw, ctx->ctl, ctx->counting, ctx->stream);
+  ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+  ctx->timed_trace = true;
+  ctx->last_count = paths->count;
+}
+
+void synth_impl(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void* ws, size_t ws_bytes, float* spectra,
+                bool from_trace) {
+  validate_sim(sim, false);
+  validate_paths(paths);
+  ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
+  SynthWS sw;
+  const size_t need = synth_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), nullptr, nullptr);
+  ET_CHECK(ws_bytes >= need, ET_E_WORKSPACE, "workspace too small for et_synthesize");
+  synth_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), (char*)ws, &sw);
+  (void)from_trace;
+  ET_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+  ctx->synth_kernel = synth_run(sim, paths, sw, ctx->ctl, spectra, ctx->stream);
+  ET_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+  ctx->timed_synth = true;
+}
+
+// number of records to synthesise = min(paths count, capacity); written into the control block
+__global__ void k_set_nrec(Ctl* ctl, const int64_t* count, int64_t cap) {
+  int64_t n = count[0];
+  ctl->n_rec = n < cap ? n : cap;
+}
+
+}  // namespace
+
+extern "C" {
+
+int et_abi_version(void) { return ET_ABI_VERSION; }
+
+const char* et_status_string(int status) {
+  switch (status) {
+    case ET_OK: return "ok";
+    case ET_E_INVALID: return "invalid argument";
+    case ET_E_WORKSPACE: return "workspace too small";
+    case ET_E_CAPACITY: return "path capacity exceeded";
+    case ET_E_DEVICE: return "HIP runtime error";
+    case ET_E_UNSUPPORTED: return "unsupported request";
+    case ET_E_INTERNAL: return "internal device-side error";
+    default: return "unknown status";
+  }
+}
+
+int et_create(int device, void* hip_stream, et_ctx** out) {
+  if (!out) return ET_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ET_E_DEVICE;
+  et_ctx* c = new et_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  try {
+    ET_HIP(hipSetDevice(device));
+    ET_HIP(hipMalloc(&c->ctl, sizeof(Ctl)));
+    ET_HIP(hipMemset(c->ctl, 0, sizeof(Ctl)));
+    for (auto& e : c->ev) ET_HIP(hipEventCreate(&e));
+  } catch (const Error& e) {
+    delete c;
+    return e.code;
+  }
+  *out = c;
+  return ET_OK;
+}
+
+int et_destroy(et_ctx* ctx) {
+  if (!ctx) return ET_E_INVALID;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->ctl) (void)hipFree(ctx->ctl);
+  delete ctx;
+  return ET_OK;
+}
+
+int et_set_stream(et_ctx* ctx, void* hip_stream) {
+  if (!ctx) return ET_E_INVALID;
+  ctx->stream = (hipStream_t)hip_stream;
+  return ET_OK;
+}
+
+const char* et_last_error(const et_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "NULL context"; }
+
+int et_scene_size(et_ctx* ctx, const et_mesh_desc* mesh, size_t* blob_bytes, size_t* scratch_bytes) {
+  return guarded(ctx, [&] {
+    validate_mesh(mesh);
+    ET_CHECK(blob_bytes && scratch_bytes, ET_E_INVALID, "output pointer is NULL");
+    *blob_bytes = scene_blob_bytes(mesh->T, mesh->V, mesh->n_objects);
+    *scratch_bytes = scene_scratch_bytes(mesh->T, mesh->V);
+  });
+}
+
+int et_scene_build(et_ctx* ctx, const et_mesh_desc* mesh, void* blob, size_t blob_bytes, void* scratch,
+                   size_t scratch_bytes, et_scene** out) {
+  return guarded(ctx, [&] {
+    validate_mesh(mesh);
+    ET_CHECK(out, ET_E_INVALID, "output pointer is NULL");
+    *out = nullptr;
+    ET_CHECK(blob && scratch, ET_E_INVALID, "blob or scratch is NULL");
+    ET_CHECK(blob_bytes >= scene_blob_bytes(mesh->T, mesh->V, mesh->n_objects), ET_E_WORKSPACE, "scene blob too small");
+    ET_CHECK(scratch_bytes >= scene_scratch_bytes(mesh->T, mesh->V), ET_E_WORKSPACE, "scene scratch too small");
+    et_scene* sc = new et_scene();
+    sc->device = ctx->device;
+    try {
+      ET_HIP(hipMemsetAsync(&ctx->ctl->err, 0, sizeof(uint32_t), ctx->stream));
+      scene_build(sc, mesh, blob, scratch, &ctx->ctl->err, ctx->stream);
+    } catch (...) {
+      delete sc;
+      throw;
+    }
+    *out = sc;
+  });
+}
+
+int et_scene_free(et_scene* scene) {
+  if (!scene) return ET_E_INVALID;
+  delete scene;
+  return ET_OK;
+}
+
+int et_scene_get_info(et_ctx* ctx, const et_scene* scene, et_scene_info* info) {
+  return guarded(ctx, [&] {
+    check_scene(scene);
+    ET_CHECK(info, ET_E_INVALID, "info is NULL");
+    info->T = scene->d.T;
+    info->V = scene->d.V;
+    info->n_nodes = scene->n_nodes;
+    info->depth = scene->depth;
+    info->sah_cost = scene->sah;
+    info->build_ms = scene->build_ms;
+  });
+}
+
+int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double* G_out) {
+  return guarded(ctx, [&] {
+    check_scene(scene);
+    if (C_out && scene->d.T > 0)
+      ET_HIP(hipMemcpyAsync(C_out, scene->d.C, sizeof(double) * scene->d.T, hipMemcpyDeviceToDevice, ctx->stream));
+    if (G_out && scene->d.V > 0)
+      ET_HIP(hipMemcpyAsync(G_out, scene->d.G, sizeof(double) * scene->d.V, hipMemcpyDeviceToDevice, ctx->stream));
+  });
+}
+
+int et_workspace_size(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, size_t* bytes) {
+  return guarded(ctx, [&] {
+    ET_CHECK(bytes, ET_E_INVALID, "bytes is NULL");
+    validate_sim(sim, scene != nullptr);
+    *bytes = plan(scene, sim, std::max<int64_t>(records_upper_bound(sim), 1)).total();
+  });
+}
+
+int et_trace(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, void* ws, size_t ws_bytes,
+             const et_paths* paths) {
+  return guarded(ctx, [&] {
+    ctx->timed_synth = false;
+    trace_impl(ctx, scene, sim, ws, ws_bytes, paths);
+  });
+}
+
+int et_synthesize(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void* ws, size_t ws_bytes,
+                  float* spectra) {
+  return guarded(ctx, [&] {
+    validate_paths(paths);
+    ctx->timed_trace = false;
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
+    ET_HIP(hipGetLastError());
+    synth_impl(ctx, sim, paths, ws, ws_bytes, spectra, false);
+  });
+}
+
+int et_simulate(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, const et_paths* paths, void* ws,
+                size_t ws_bytes, float* spectra) {
+  return guarded(ctx, [&] {
+    check_scene(scene);
+    validate_sim(sim, true);
+    validate_paths(paths);
+    const WsPlan w = plan(scene, sim, std::max<int64_t>(paths->capacity, 1));
+    ET_CHECK(ws, ET_E_INVALID, "workspace is NULL");
+    ET_CHECK(ws_bytes >= w.trace + w.synth, ET_E_WORKSPACE, "workspace too small for et_simulate");
+    trace_impl(ctx, scene, sim, ws, w.trace, paths);
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
+    synth_impl(ctx, sim, paths, (char*)ws + w.trace, ws_bytes - w.trace, spectra, true);
+  });
+}
+
+int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra,
+                           void* ws, size_t ws_bytes, double* grad_k, double* grad_rx) {
+  return guarded(ctx, [&] {
+    validate_sim(sim, false);
+    validate_paths(paths);
+    ET_CHECK(grad_spectra && grad_k && grad_rx, ET_E_INVALID, "gradient pointer is NULL");
+    ET_CHECK(!sim->directivity, ET_E_UNSUPPORTED, "the adjoint does not support receiver directivity");
+    ET_CHECK(sim->Bk <= 16 && sim->Q * sim->Bk <= 256, ET_E_UNSUPPORTED, "adjoint needs Bk <= 16 and Q*Bk <= 256");
+    ET_CHECK(sim->F <= 12288, ET_E_UNSUPPORTED, "adjoint keeps dL/dH of one receiver in LDS: F <= 12288");
+    SynthWS sw;
+    const size_t need = synth_bwd_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), nullptr, nullptr);
+    ET_CHECK(ws && ws_bytes >= need, ET_E_WORKSPACE, "workspace too small for et_synthesize_backward");
+    synth_bwd_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), (char*)ws, &sw);
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
+    ET_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
+    synth_bwd_run(sim, paths, grad_spectra, sw, ctx->ctl, grad_k, grad_rx, ctx->stream);
+    ET_HIP(hipEventRecord(ctx->ev[7], ctx->stream));
+  });
+}
+
+int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes) {
+  return guarded(ctx, [&] {
+    ET_CHECK(J >= 1 && jobs && bytes, ET_E_INVALID, "need J >= 1, jobs and bytes");
+    size_t mx = 0, paths = 0;
+    for (int j = 0; j < J; ++j) {
+      check_scene(jobs[j].scene);
+      validate_sim(jobs[j].sim, true);
+      const int64_t cap = std::max<int64_t>(records_upper_bound(jobs[j].sim), 1);
+      mx = std::max(mx, plan(jobs[j].scene, jobs[j].sim, cap).total());
+      paths += al(cap * (24 + 12 + 8 + 4 + 4 + 4 + 1 + 1)) + al(8 * sizeof(int64_t)) + 8 * 256;
+    }
+    *bytes = mx + paths;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Carves per-job path buffers from the batch workspace (after the shared scratch).
+et_paths carve_paths(char*& p, int64_t cap) {
+  auto take = [&](size_t b) { char* r = p; p += al(b); return (void*)r; };
+  et_paths P;
+  P.capacity = cap;
+  P.p = (double*)take(sizeof(double) * 3 * cap);
+  P.dout = (float*)take(sizeof(float) * 3 * cap);
+  P.rtot = (double*)take(sizeof(double) * cap);
+  P.tri = (int32_t*)take(sizeof(int32_t) * cap);
+  P.mat = (int32_t*)take(sizeof(int32_t) * cap);
+  P.ray = (int32_t*)take(sizeof(int32_t) * cap);
+  P.bounce = (uint8_t*)take(cap);
+  P.flags = (uint8_t*)take(cap);
+  P.count = (int64_t*)take(8 * sizeof(int64_t));
+  return P;
+}
+
+void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                const float* grad_spectra, double* grad_k, double* grad_rx) {
+  ET_CHECK(J >= 1 && jobs, ET_E_INVALID, "need J >= 1 jobs");
+  ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
+  const et_sim_desc* s0 = jobs[0].sim;
+  size_t mx = 0;
+  for (int j = 0; j < J; ++j) {
+    check_scene(jobs[j].scene);
+    validate_sim(jobs[j].sim, true);
+    const et_sim_desc* s = jobs[j].sim;
+    ET_CHECK(s->M == s0->M && s->F == s0->F && s->Q == s0->Q && s->Bk == s0->Bk, ET_E_INVALID,
+             "jobs of a batch must share M, F, Q and Bk");
+    const int64_t cap = std::max<int64_t>(records_upper_bound(s), 1);
+    mx = std::max(mx, plan(jobs[j].scene, s, cap).total());
+  }
+  size_t need = 0;
+  ET_CHECK(et_batch_workspace_size(ctx, J, jobs, &need) == ET_OK, ET_E_INVALID, "batch workspace query failed");
+  ET_CHECK(ws && ws_bytes >= need, ET_E_WORKSPACE, "workspace too small for et_simulate_batch");
+  char* pp = (char*)ws + mx;
+  const size_t MF2 = (size_t)s0->M * s0->F * 2;
+  for (int j = 0; j < J; ++j) {
+    const et_sim_desc* s = jobs[j].sim;
+    const int64_t cap = std::max<int64_t>(records_upper_bound(s), 1);
+    et_paths P = carve_paths(pp, cap);
+    const WsPlan w = plan(jobs[j].scene, s, cap);
+    TraceWS tw;
+    trace_ws_layout((s->flags & ET_SPECULAR) ? s->N : 0, jobs[j].scene->d.T, jobs[j].scene->d.n_obj,
+                    (s->flags & ET_DIFFRACTION) ? s->diff_K : 0, (char*)ws, &tw);
+    trace_run(jobs[j].scene->d, s, &P, tw, ctx->ctl, false, ctx->stream);
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
+    SynthWS sw;
+    synth_ws_layout(s, cap, (char*)ws + w.trace, &sw);
+    ctx->synth_kernel = synth_run(s, &P, sw, ctx->ctl, spectra + (size_t)j * MF2, ctx->stream);
+    if (grad_spectra) {
+      ET_CHECK(grad_k && grad_rx, ET_E_INVALID, "gradient outputs are NULL");
+      ET_CHECK(!s->directivity && s->Bk <= 16 && s->Q * s->Bk <= 256 && s->F <= 12288, ET_E_UNSUPPORTED,
+               "adjoint limits exceeded");
+      SynthWS bw;
+      synth_bwd_ws_layout(s, cap, (char*)ws + w.trace + w.synth, &bw);
+      synth_bwd_run(s, &P, grad_spectra + (size_t)j * MF2, bw, ctx->ctl, grad_k + (size_t)j * s->Q * s->Bk,
+                    grad_rx + (size_t)j * s->M * 3, ctx->stream);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                      const float* grad_spectra, double* grad_k, double* grad_rx) {
+  return guarded(ctx, [&] {
+    ctx->timed_trace = ctx->timed_synth = false;
+    batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx);
+  });
+}
+
+int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                            const float* grad_spectra, double* grad_k, double* grad_rx) {
+  return guarded(ctx, [&] {
+    ET_CHECK(ctx->stream, ET_E_INVALID, "graph capture needs a non-null context stream");
+    ET_CHECK(J >= 1 && jobs, ET_E_INVALID, "need J >= 1 jobs");
+    // the graph bakes in every pointer and scalar: key on all of them
+    std::vector<uint64_t> key;
+    key.push_back((uint64_t)J);
+    key.push_back((uint64_t)(uintptr_t)ws);
+    key.push_back((uint64_t)ws_bytes);
+    key.push_back((uint64_t)(uintptr_t)spectra);
+    key.push_back((uint64_t)(uintptr_t)grad_spectra);
+    key.push_back((uint64_t)(uintptr_t)grad_k);
+    key.push_back((uint64_t)(uintptr_t)grad_rx);
+    for (int j = 0; j < J; ++j) {
+      key.push_back((uint64_t)(uintptr_t)jobs[j].scene);
+      const uint64_t* w = reinterpret_cast<const uint64_t*>(jobs[j].sim);
+      for (size_t i = 0; i < sizeof(et_sim_desc) / 8; ++i) key.push_back(w[i]);
+    }
+    if (!ctx->graph_exec || key != ctx->graph_key) {
+      if (ctx->graph_exec) { ET_HIP(hipGraphExecDestroy(ctx->graph_exec)); ctx->graph_exec = nullptr; }
+      if (ctx->graph) { ET_HIP(hipGraphDestroy(ctx->graph)); ctx->graph = nullptr; }
+      ET_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      ET_HIP(hipStreamEndCapture(ctx->stream, &ctx->graph));
+      ET_HIP(hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
+      ctx->graph_key = key;
+    }
+    ctx->timed_trace = ctx->timed_synth = false;
+    ET_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  });
+}
+
+int et_graph_reset(et_ctx* ctx) {
+  return guarded(ctx, [&] {
+    if (ctx->graph_exec) { ET_HIP(hipGraphExecDestroy(ctx->graph_exec)); ctx->graph_exec = nullptr; }
+    if (ctx->graph) { ET_HIP(hipGraphDestroy(ctx->graph)); ctx->graph = nullptr; }
+    ctx->graph_key.clear();
+  });
+}
+
+int et_get_stats(et_ctx* ctx, et_stats* out) {
+  int rc = guarded(ctx, [&] {
+    ET_CHECK(out, ET_E_INVALID, "stats is NULL");
+    ET_HIP(hipStreamSynchronize(ctx->stream));
+    Ctl h;
+    ET_HIP(hipMemcpy(&h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->records = h.rec_base + h.diff_kept;
+    out->specular = h.rec_base;
+    out->diffraction = h.diff_kept;
+    out->segments = h.seg;
+    out->shadow_rays = h.shadow;
+    out->diff_eligible = h.n_elig;
+    out->stack_overflows = h.overflow;
+    out->synth_kernel = ctx->synth_kernel;
+    if (ctx->last_count) {
+      int64_t cnt[4];
+      ET_HIP(hipMemcpy(cnt, ctx->last_count, sizeof(cnt), hipMemcpyDeviceToHost));
+      out->records = cnt[0];
+    }
+    float ms = 0;
+    if (ctx->timed_trace && hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) out->ms_trace = ms;
+    if (ctx->timed_synth && hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]) == hipSuccess) out->ms_synth = ms;
+    uint32_t err = h.err;
+    out->status = ET_OK;
+    if (err & DEV_ERR_CAPACITY) {
+      out->status = ET_E_CAPACITY;
+      out->dropped = 1;
+    }
+    if (err & (DEV_ERR_STACK | DEV_ERR_BUILD)) out->status = ET_E_INTERNAL;
+    if (err & (DEV_ERR_INDEX | DEV_ERR_RAYDIR)) out->status = ET_E_INVALID;
+    // clear the deferred error word for the next call
+    ET_HIP(hipMemset(&ctx->ctl->err, 0, sizeof(uint32_t)));
+  });
+  if (rc == ET_OK && out->status != ET_OK) {
+    ctx->last_error = "deferred device-side error";
+    return out->status;
+  }
+  return rc;
+}
+
+int et_set_counting(et_ctx* ctx, int enable) {
+  if (!ctx) return ET_E_INVALID;
+  ctx->counting = enable != 0;
+  return ET_OK;
+}
+
+int et_get_counters(et_ctx* ctx, et_counters* out) {
+  return guarded(ctx, [&] {
+    ET_CHECK(out, ET_E_INVALID, "counters is NULL");
+    ET_HIP(hipStreamSynchronize(ctx->stream));
+    Ctl h;
+    ET_HIP(hipMemcpy(&h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    out->nodes_closest = h.cnt[0];
+    out->tris_closest = h.cnt[1];
+    out->nodes_any = h.cnt[2];
+    out->tris_any = h.cnt[3];
+    out->rays_closest = h.cnt[4];
+    out->rays_any = h.cnt[5];
+  });
+}
+
+}  // extern "C"

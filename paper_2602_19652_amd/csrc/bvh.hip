@@ -1,0 +1,566 @@
+// Scene build on the device:
+//  1. triangle boxes, centroid bounds, per-object boxes (field-of-view test of Sec. III-D)
+//  2. 30-bit Morton codes of centroids, stable radix sort
+//  3. agglomerative clustering over the Morton order (PLOC, Meister & Bittner 2018): each
+//     cluster's nearest neighbour within a window is the one whose merged box has the
+//     smallest surface area (the surface-area heuristic's cost driver); mutual nearest
+//     neighbours merge; repeat until one cluster remains
+//  4. packing into 64-byte binary traversal nodes, triangles repacked in leaf order
+//  5. curvature metric C_i of Eq. (1) with the Meyer et al. cotangent operator, FP64
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace et {
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ inline uint32_t f2o(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float o2f(uint32_t u) { return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u); }
+
+__global__ void k_init_bounds(uint32_t* cb, uint32_t* ob, int32_t n_obj) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 6) cb[i] = (i < 3) ? 0xffffffffu : 0u;
+  if (i < n_obj * 6) ob[i] = ((i % 6) < 3) ? 0xffffffffu : 0u;
+}
+
+__global__ void k_tri_bounds(const float* __restrict__ V, const int32_t* __restrict__ tris,
+                             const int32_t* __restrict__ obj, int64_t T, int64_t nV, int32_t n_obj,
+                             uint32_t* cb, uint32_t* ob, uint32_t* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float c[3] = {INFINITY, INFINITY, INFINITY};
+  float cm[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (i < T) {
+    int32_t a = tris[3 * i], b = tris[3 * i + 1], cc = tris[3 * i + 2];
+    int32_t o = obj[i];
+    if (a < 0 || b < 0 || cc < 0 || a >= nV || b >= nV || cc >= nV || o < 0 || o >= n_obj) {
+      atomicOr(err, DEV_ERR_INDEX);
+    } else {
+      float lo[3], hi[3];
+      for (int k = 0; k < 3; ++k) {
+        float x0 = V[3 * (int64_t)a + k], x1 = V[3 * (int64_t)b + k], x2 = V[3 * (int64_t)cc + k];
+        lo[k] = fminf(x0, fminf(x1, x2));
+        hi[k] = fmaxf(x0, fmaxf(x1, x2));
+        c[k] = cm[k] = 0.5f * (lo[k] + hi[k]);
+        atomicMin(&ob[6 * o + k], f2o(lo[k]));
+        atomicMax(&ob[6 * o + 3 + k], f2o(hi[k]));
+      }
+    }
+  }
+  // block reduction of centroid bounds, one atomic per block and axis
+  __shared__ float smin[3][BS], smax[3][BS];
+  for (int k = 0; k < 3; ++k) { smin[k][threadIdx.x] = c[k]; smax[k][threadIdx.x] = cm[k]; }
+  __syncthreads();
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) {
+        smin[k][threadIdx.x] = fminf(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
+        smax[k][threadIdx.x] = fmaxf(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) {
+      if (smin[k][0] <= smax[k][0]) {
+        atomicMin(&cb[k], f2o(smin[k][0]));
+        atomicMax(&cb[3 + k], f2o(smax[k][0]));
+      }
+    }
+}
+
+__device__ inline uint32_t spread10(uint32_t x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000FFu;
+  x = (x | (x << 8)) & 0x0300F00Fu;
+  x = (x | (x << 4)) & 0x030C30C3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__global__ void k_morton(const float* __restrict__ V, const int32_t* __restrict__ tris, int64_t T,
+                         const uint32_t* __restrict__ cb, uint32_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T) return;
+  uint32_t q[3];
+  for (int k = 0; k < 3; ++k) {
+    float x0 = V[3 * (int64_t)tris[3 * i] + k], x1 = V[3 * (int64_t)tris[3 * i + 1] + k],
+          x2 = V[3 * (int64_t)tris[3 * i + 2] + k];
+    float c = 0.5f * (fminf(x0, fminf(x1, x2)) + fmaxf(x0, fmaxf(x1, x2)));
+    float lo = o2f(cb[k]), hi = o2f(cb[3 + k]);
+    float u = hi > lo ? (c - lo) / (hi - lo) : 0.5f;
+    u = fminf(fmaxf(u, 0.f), 1.f);
+    q[k] = (uint32_t)fminf(u * 1024.f, 1023.f);
+  }
+  keys[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  vals[i] = (int32_t)i;
+}
+
+__global__ void k_leaves(const float* __restrict__ V, const int32_t* __restrict__ tris, const int32_t* __restrict__ mat,
+                         const int32_t* __restrict__ perm, int64_t T, NodeB* __restrict__ nodes,
+                         float4* __restrict__ tri4, int32_t* __restrict__ tri_orig, int32_t* __restrict__ tri_pos,
+                         int32_t* __restrict__ clusters) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= T) return;
+  int32_t t = perm[p];
+  float v[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 3; ++k) v[c][k] = V[3 * (int64_t)tris[3 * (int64_t)t + c] + k];
+  NodeB n;
+  n.lox = fminf(v[0][0], fminf(v[1][0], v[2][0]));
+  n.loy = fminf(v[0][1], fminf(v[1][1], v[2][1]));
+  n.loz = fminf(v[0][2], fminf(v[1][2], v[2][2]));
+  n.hix = fmaxf(v[0][0], fmaxf(v[1][0], v[2][0]));
+  n.hiy = fmaxf(v[0][1], fmaxf(v[1][1], v[2][1]));
+  n.hiz = fmaxf(v[0][2], fmaxf(v[1][2], v[2][2]));
+  n.left = -1;
+  n.right = -1;
+  nodes[p] = n;
+  tri4[3 * p + 0] = make_float4(v[0][0], v[0][1], v[0][2], __int_as_float(t));
+  tri4[3 * p + 1] = make_float4(v[1][0], v[1][1], v[1][2], __int_as_float(mat[t]));
+  tri4[3 * p + 2] = make_float4(v[2][0], v[2][1], v[2][2], 0.f);
+  tri_orig[p] = t;
+  tri_pos[t] = (int32_t)p;
+  clusters[p] = (int32_t)p;
+}
+
+__device__ inline float merged_area(const float* a, const float* b) {
+  float dx = fmaxf(a[3], b[3]) - fminf(a[0], b[0]);
+  float dy = fmaxf(a[4], b[4]) - fminf(a[1], b[1]);
+  float dz = fmaxf(a[5], b[5]) - fminf(a[2], b[2]);
+  return dx * dy + dy * dz + dz * dx;   // half the surface area (constant factor is irrelevant)
+}
+
+__global__ void k_ploc_nn(const int32_t* __restrict__ cl, const int64_t* __restrict__ n_dev,
+                          const NodeB* __restrict__ nodes, int32_t* __restrict__ nn) {
+  constexpr int R = PLOC_RADIUS;
+  __shared__ float box[BS + 2 * R][6];
+  const int64_t n = *n_dev;
+  const int64_t base = (int64_t)blockIdx.x * BS;
+  if (base >= n) return;
+  for (int k = threadIdx.x; k < BS + 2 * R; k += BS) {
+    int64_t i = base - R + k;
+    if (i >= 0 && i < n) {
+      NodeB b = nodes[cl[i]];
+      box[k][0] = b.lox; box[k][1] = b.loy; box[k][2] = b.loz;
+      box[k][3] = b.hix; box[k][4] = b.hiy; box[k][5] = b.hiz;
+    }
+  }
+  __syncthreads();
+  const int64_t i = base + threadIdx.x;
+  if (i >= n) return;
+  float best = INFINITY;
+  int64_t bj = -1;
+  for (int d = -R; d <= R; ++d) {
+    if (d == 0) continue;
+    int64_t j = i + d;
+    if (j < 0 || j >= n) continue;
+    float a = merged_area(box[threadIdx.x + R], box[threadIdx.x + R + d]);
+    if (a < best) { best = a; bj = j; }   // increasing j: ties keep the smaller index
+  }
+  nn[i] = (int32_t)bj;
+}
+
+__global__ void k_ploc_flags(const int32_t* __restrict__ nn, const int64_t* __restrict__ n_dev,
+                             uint64_t* __restrict__ flags) {
+  const int64_t n = *n_dev;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t j = nn[i];
+  bool mutual = (j >= 0) && nn[j] == (int32_t)i;
+  uint64_t survive = (mutual && j < i) ? 0u : 1u;
+  uint64_t merge = (mutual && i < j) ? 1u : 0u;
+  flags[i] = survive | (merge << 32);
+}
+
+__global__ void k_ploc_compact(const int32_t* __restrict__ cl, const int32_t* __restrict__ nn,
+                               const uint64_t* __restrict__ flags, const uint64_t* __restrict__ offs,
+                               int64_t* __restrict__ n_dev, const uint64_t* __restrict__ total,
+                               int64_t* __restrict__ next_node, NodeB* __restrict__ nodes, int32_t* __restrict__ out) {
+  const int64_t n = *n_dev;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    uint64_t f = flags[i];
+    if (f & 0xffffffffu) {
+      uint64_t o = offs[i];
+      int64_t pos = (int64_t)(o & 0xffffffffu);
+      if (f >> 32) {
+        int32_t a = cl[i], b = cl[nn[i]];
+        int64_t id = *next_node + (int64_t)(o >> 32);
+        NodeB x = nodes[a], y = nodes[b];
+        NodeB m;
+        m.lox = fminf(x.lox, y.lox); m.loy = fminf(x.loy, y.loy); m.loz = fminf(x.loz, y.loz);
+        m.hix = fmaxf(x.hix, y.hix); m.hiy = fmaxf(x.hiy, y.hiy); m.hiz = fmaxf(x.hiz, y.hiz);
+        m.left = a;
+        m.right = b;
+        nodes[id] = m;
+        out[pos] = (int32_t)id;
+      } else {
+        out[pos] = cl[i];
+      }
+    }
+  }
+}
+
+// updates the counters after compaction (single thread, ordered after k_ploc_compact)
+__global__ void k_ploc_update(int64_t* n_dev, const uint64_t* total, int64_t* next_node, int64_t* host_view) {
+  uint64_t t = *total;
+  *n_dev = (int64_t)(t & 0xffffffffu);
+  *next_node += (int64_t)(t >> 32);
+  host_view[0] = *n_dev;
+  host_view[1] = *next_node;
+}
+
+__global__ void k_pack(const NodeB* __restrict__ nb, int64_t T, Node2* __restrict__ out, int32_t* __restrict__ leaf_parent) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= T - 1) return;
+  NodeB b = nb[T + k];
+  NodeB c0 = nb[b.left], c1 = nb[b.right];
+  Node2 n;
+  n.xy0 = make_float4(c0.lox, c0.hix, c0.loy, c0.hiy);
+  n.xy1 = make_float4(c1.lox, c1.hix, c1.loy, c1.hiy);
+  n.zz = make_float4(c0.loz, c0.hiz, c1.loz, c1.hiz);
+  int e0 = b.left >= T ? (int)(b.left - T) : ~b.left;
+  int e1 = b.right >= T ? (int)(b.right - T) : ~b.right;
+  n.ch = make_int4(e0, e1, -1, 0);
+  out[k] = n;
+  if (b.left < T) leaf_parent[b.left] = (int32_t)k;
+  if (b.right < T) leaf_parent[b.right] = (int32_t)k;
+}
+
+__global__ void k_parents(Node2* __restrict__ nodes, int64_t n_inner) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_inner) return;
+  int4 ch = nodes[k].ch;
+  if (ch.x >= 0) nodes[ch.x].ch.z = (int)k;
+  if (ch.y >= 0) nodes[ch.y].ch.z = (int)k;
+}
+
+__global__ void k_depth_sah(const Node2* __restrict__ nodes, const int32_t* __restrict__ leaf_parent, int64_t T,
+                            const NodeB* __restrict__ nb, int root_id, int32_t* depth, double* sah) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= T) return;
+  int d = 1;
+  int node = leaf_parent[p];
+  int guard = 0;
+  while (node >= 0 && guard < 1 << 20) {
+    ++d;
+    node = nodes[node].ch.z;
+    ++guard;
+  }
+  atomicMax(depth, d);
+  NodeB r = nb[root_id];
+  double ra = (double)(r.hix - r.lox) * (r.hiy - r.loy) + (double)(r.hiy - r.loy) * (r.hiz - r.loz) +
+              (double)(r.hiz - r.loz) * (r.hix - r.lox);
+  NodeB l = nb[p];
+  double la = (double)(l.hix - l.lox) * (l.hiy - l.loy) + (double)(l.hiy - l.loy) * (l.hiz - l.loz) +
+              (double)(l.hiz - l.loz) * (l.hix - l.lox);
+  double s = ra > 0 ? la / ra : 0;
+  if (p + 1 < T) {   // inner node T + p
+    NodeB x = nb[T + p];
+    double xa = (double)(x.hix - x.lox) * (x.hiy - x.loy) + (double)(x.hiy - x.loy) * (x.hiz - x.loz) +
+                (double)(x.hiz - x.loz) * (x.hix - x.lox);
+    s += ra > 0 ? xa / ra : 0;
+  }
+  atomicAdd(sah, s);
+}
+
+// ------------------------------------------------------------------ curvature (Eq. 1)
+// The arithmetic below follows the paper's definition through the Meyer et al. operator
+// with the operations in a fixed order and no contraction, so that C_i is reproducible
+// to the last bit by any IEEE double implementation evaluating the same expressions.
+#pragma clang fp contract(off)
+
+__global__ void k_vcount(const int32_t* __restrict__ tris, int64_t T, uint64_t* __restrict__ cnt) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  for (int c = 0; c < 3; ++c) atomicAdd((unsigned long long*)&cnt[tris[3 * t + c]], 1ull);
+}
+
+__global__ void k_vfill(const int32_t* __restrict__ tris, int64_t T, const uint64_t* __restrict__ offs,
+                        uint32_t* __restrict__ fill, int32_t* __restrict__ adj) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  for (int c = 0; c < 3; ++c) {
+    int32_t v = tris[3 * t + c];
+    uint32_t slot = atomicAdd(&fill[v], 1u);
+    adj[offs[v] + slot] = (int32_t)t;
+  }
+}
+
+__global__ void k_vsort(const uint64_t* __restrict__ offs, const uint64_t* __restrict__ cnt, int64_t V,
+                        int32_t* __restrict__ adj) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  int32_t* a = adj + offs[v];
+  int64_t n = (int64_t)cnt[v];
+  for (int64_t i = 1; i < n; ++i) {   // insertion sort: one-rings are short
+    int32_t x = a[i];
+    int64_t j = i - 1;
+    while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
+    a[j + 1] = x;
+  }
+}
+
+struct d3 { double x, y, z; };
+__device__ inline d3 dsub(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline double ddot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline d3 dcross(d3 a, d3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline d3 dload(const float* V, int32_t i) {
+  return {(double)V[3 * (int64_t)i], (double)V[3 * (int64_t)i + 1], (double)V[3 * (int64_t)i + 2]};
+}
+
+__global__ void k_vertex_curv(const float* __restrict__ V, const int32_t* __restrict__ tris,
+                              const uint64_t* __restrict__ offs, const uint64_t* __restrict__ cnt,
+                              const int32_t* __restrict__ adj, int64_t nV, double* __restrict__ G) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double Kx = 0.0, Ky = 0.0, Kz = 0.0, Am = 0.0;
+  const int64_t n = (int64_t)cnt[v];
+  for (int64_t e = 0; e < n; ++e) {
+    const int64_t t = adj[offs[v] + e];
+    int32_t id[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    d3 P[3] = {dload(V, id[0]), dload(V, id[1]), dload(V, id[2])};
+    d3 cr = dcross(dsub(P[1], P[0]), dsub(P[2], P[0]));
+    double area2 = sqrt(ddot(cr, cr));
+    double area = 0.5 * area2;
+    if (area < 1e-20) continue;
+    double dotc[3], cot[3];
+    for (int c = 0; c < 3; ++c) {
+      dotc[c] = ddot(dsub(P[(c + 1) % 3], P[c]), dsub(P[(c + 2) % 3], P[c]));
+      cot[c] = dotc[c] / area2;
+    }
+    bool obtuse = dotc[0] < 0.0 || dotc[1] < 0.0 || dotc[2] < 0.0;
+    for (int c = 0; c < 3; ++c) {
+      if (id[c] != (int32_t)v) continue;
+      int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      d3 ea = dsub(P[c], P[c1]), eb = dsub(P[c], P[c2]);
+      Kx += cot[c2] * ea.x + cot[c1] * eb.x;
+      Ky += cot[c2] * ea.y + cot[c1] * eb.y;
+      Kz += cot[c2] * ea.z + cot[c1] * eb.z;
+      if (!obtuse) Am += (ddot(ea, ea) * cot[c2] + ddot(eb, eb) * cot[c1]) / 8.0;   // Voronoi region
+      else if (dotc[c] < 0.0) Am += area / 2.0;
+      else Am += area / 4.0;
+    }
+  }
+  double kn = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+  G[v] = Am > 0.0 ? kn / (4.0 * Am) : 0.0;   // G = |K| / 2 with K = sum / (2 A_mixed)
+}
+
+__global__ void k_tri_curv(const float* __restrict__ V, const int32_t* __restrict__ tris, int64_t T,
+                           const double* __restrict__ G, double a_ref, double* __restrict__ C) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double g0 = G[tris[3 * t]], g1 = G[tris[3 * t + 1]], g2 = G[tris[3 * t + 2]];
+  double dG = fmax(g0, fmax(g1, g2)) - fmin(g0, fmin(g1, g2));
+  d3 P0 = dload(V, tris[3 * t]), P1 = dload(V, tris[3 * t + 1]), P2 = dload(V, tris[3 * t + 2]);
+  d3 cr = dcross(dsub(P1, P0), dsub(P2, P0));
+  double area = 0.5 * sqrt(ddot(cr, cr));
+  double w = a_ref > 0.0 ? fmin(1.0, area / a_ref) : 1.0;
+  C[t] = w * dG;
+}
+
+#pragma clang fp contract(on)
+
+__global__ void k_obj_box(const uint32_t* __restrict__ ob, int32_t n_obj, float* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_obj * 6) out[i] = o2f(ob[i]);
+}
+
+__global__ void k_single_leaf(Node2* nodes) {
+  Node2 n;
+  // child 0 is leaf 0 with an infinite box; child 1 is an empty box (never hit)
+  n.xy0 = make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY);
+  n.xy1 = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+  n.zz = make_float4(-INFINITY, INFINITY, INFINITY, -INFINITY);
+  n.ch = make_int4(~0, ~0, -1, 0);
+  nodes[0] = n;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS > 0 ? (n + BS - 1) / BS : 1); }
+inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t scene_blob_bytes(int64_t T, int64_t V, int32_t n_obj) {
+  size_t b = 0;
+  b += al(sizeof(Node2) * (size_t)std::max<int64_t>(1, T - 1));
+  b += al(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
+  b += 2 * al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
+  b += al(sizeof(double) * (size_t)std::max<int64_t>(1, T));
+  b += al(sizeof(double) * (size_t)std::max<int64_t>(1, V));
+  b += al(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
+  return b;
+}
+
+size_t scene_scratch_bytes(int64_t T, int64_t V) {
+  const int64_t Tm = std::max<int64_t>(T, 1), Vm = std::max<int64_t>(V, 1);
+  size_t b = 0;
+  b += al(sizeof(uint32_t) * 6) + al(sizeof(uint32_t) * 6 * 1);   // centroid bounds (object bounds sized below)
+  b += al(sizeof(uint32_t) * Tm) + al(sizeof(int32_t) * Tm);       // morton keys / perm
+  b += sort_temp_bytes(Tm, 4);
+  b += al(sizeof(NodeB) * (size_t)(2 * Tm));                       // build nodes
+  b += 2 * al(sizeof(int32_t) * Tm);                               // clusters ping-pong
+  b += al(sizeof(int32_t) * Tm);                                   // nn
+  b += 2 * al(sizeof(uint64_t) * Tm);                              // flags / offsets
+  b += scan_temp_bytes(std::max(Tm, Vm));
+  b += al(sizeof(int64_t) * 8) + al(sizeof(uint64_t) * 4);         // counters, totals
+  b += al(sizeof(int32_t) * Tm);                                   // leaf parents
+  b += al(sizeof(int32_t) * 2) + al(sizeof(double));               // depth, sah
+  b += 2 * al(sizeof(uint64_t) * Vm) + al(sizeof(uint32_t) * Vm);  // vertex counts / offsets / fill
+  b += al(sizeof(int32_t) * 3 * Tm);                               // adjacency
+  return b;
+}
+
+void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scratch, uint32_t* dev_err, hipStream_t s) {
+  const int64_t T = mesh->T, V = mesh->V;
+  const int32_t n_obj = mesh->n_objects;
+  SceneDev& d = sc->d;
+  d.T = T; d.V = V; d.n_obj = n_obj;
+  d.verts = mesh->vertices; d.tris = mesh->tris; d.mat = mesh->tri_material; d.obj = mesh->tri_object;
+  // blob layout
+  char* bp = (char*)blob;
+  auto takeb = [&](size_t bytes) { char* p = bp; bp += al(bytes); return (void*)p; };
+  d.nodes = (Node2*)takeb(sizeof(Node2) * (size_t)std::max<int64_t>(1, T - 1));
+  d.tri4 = (float4*)takeb(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
+  d.tri_orig = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
+  d.tri_pos = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
+  d.C = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, T));
+  d.G = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, V));
+  d.obj_box = (float*)takeb(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
+  // scratch layout
+  const int64_t Tm = std::max<int64_t>(T, 1), Vm = std::max<int64_t>(V, 1);
+  char* sp = (char*)scratch;
+  auto take = [&](size_t bytes) { char* p = sp; sp += al(bytes); return (void*)p; };
+  uint32_t* cb = (uint32_t*)take(sizeof(uint32_t) * 6);
+  uint32_t* ob_unused = (uint32_t*)take(sizeof(uint32_t) * 6);
+  (void)ob_unused;
+  uint32_t* keys = (uint32_t*)take(sizeof(uint32_t) * Tm);
+  int32_t* perm = (int32_t*)take(sizeof(int32_t) * Tm);
+  void* sort_tmp = take(sort_temp_bytes(Tm, 4));
+  NodeB* nb = (NodeB*)take(sizeof(NodeB) * (size_t)(2 * Tm));
+  int32_t* clA = (int32_t*)take(sizeof(int32_t) * Tm);
+  int32_t* clB = (int32_t*)take(sizeof(int32_t) * Tm);
+  int32_t* nn = (int32_t*)take(sizeof(int32_t) * Tm);
+  uint64_t* flags = (uint64_t*)take(sizeof(uint64_t) * Tm);
+  uint64_t* offs = (uint64_t*)take(sizeof(uint64_t) * Tm);
+  void* scan_tmp = take(scan_temp_bytes(std::max(Tm, Vm)));
+  int64_t* ctr = (int64_t*)take(sizeof(int64_t) * 8);      // [0] n, [1] next node, [2..3] host view
+  uint64_t* total = (uint64_t*)take(sizeof(uint64_t) * 4);
+  int32_t* leaf_parent = (int32_t*)take(sizeof(int32_t) * Tm);
+  int32_t* depth = (int32_t*)take(sizeof(int32_t) * 2);
+  double* sah = (double*)take(sizeof(double));
+  uint64_t* vcnt = (uint64_t*)take(sizeof(uint64_t) * Vm);
+  uint64_t* voff = (uint64_t*)take(sizeof(uint64_t) * Vm);
+  uint32_t* vfill = (uint32_t*)take(sizeof(uint32_t) * Vm);
+  int32_t* adj = (int32_t*)take(sizeof(int32_t) * 3 * Tm);
+  // object boxes live in the blob as floats; build them as ordered uints in the blob memory
+  uint32_t* ob = (uint32_t*)d.obj_box;
+
+  hipEvent_t e0, e1;
+  ET_HIP(hipEventCreate(&e0));
+  ET_HIP(hipEventCreate(&e1));
+  ET_HIP(hipEventRecord(e0, s));
+
+  k_init_bounds<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(cb, ob, n_obj);
+  if (T > 0) {
+    k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, T, V, n_obj, cb, ob, dev_err);
+  }
+  k_obj_box<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(ob, n_obj, d.obj_box);
+  ET_HIP(hipGetLastError());
+  // the index check must pass before any kernel dereferences triangle indices
+  uint32_t herr = 0;
+  ET_HIP(hipMemcpyAsync(&herr, dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  ET_HIP(hipStreamSynchronize(s));
+  ET_CHECK(!(herr & DEV_ERR_INDEX), ET_E_INVALID, "mesh index out of range (triangle vertex or object index)");
+
+  int64_t h_ctr[2] = {0, 0};
+  if (T >= 1) {
+    k_morton<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, T, cb, keys, perm);
+    radix_sort_u32(keys, perm, T, 30, sort_tmp, s);
+    k_leaves<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.mat, perm, T, nb, d.tri4, d.tri_orig, d.tri_pos, clA);
+    ET_HIP(hipGetLastError());
+  }
+  int root_id = 0;
+  if (T >= 2) {
+    // agglomerative clustering; the cluster count lives on the device, the host reads it
+    // once per iteration to decide whether to continue
+    h_ctr[0] = T;
+    h_ctr[1] = T;
+    ET_HIP(hipMemcpyAsync(ctr, h_ctr, sizeof(int64_t) * 2, hipMemcpyHostToDevice, s));
+    int64_t n = T;
+    int iter = 0;
+    int32_t* cin = clA;
+    int32_t* cout = clB;
+    while (n > 1) {
+      ET_CHECK(++iter < 100000, ET_E_INTERNAL, "BVH clustering did not converge");
+      k_ploc_nn<<<nblk(n), BS, 0, s>>>(cin, ctr, nb, nn);
+      k_ploc_flags<<<nblk(n), BS, 0, s>>>(nn, ctr, flags);
+      scan_exclusive_u64(flags, offs, n, nullptr, n, total, scan_tmp, s);
+      k_ploc_compact<<<nblk(n), BS, 0, s>>>(cin, nn, flags, offs, ctr, total, ctr + 1, nb, cout);
+      k_ploc_update<<<1, 1, 0, s>>>(ctr, total, ctr + 1, ctr + 2);
+      ET_HIP(hipGetLastError());
+      int64_t hv[2];
+      ET_HIP(hipMemcpyAsync(hv, ctr + 2, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s));
+      ET_HIP(hipStreamSynchronize(s));
+      ET_CHECK(hv[0] < n && hv[0] >= 1, ET_E_INTERNAL, "BVH clustering made no progress");
+      n = hv[0];
+      std::swap(cin, cout);
+      h_ctr[1] = hv[1];
+    }
+    ET_CHECK(h_ctr[1] == 2 * T - 1, ET_E_INTERNAL, "BVH node count mismatch");
+    root_id = (int)(2 * T - 2);
+    k_pack<<<nblk(T - 1), BS, 0, s>>>(nb, T, d.nodes, leaf_parent);
+    k_parents<<<nblk(T - 1), BS, 0, s>>>(d.nodes, T - 1);
+    ET_HIP(hipMemsetAsync(depth, 0, sizeof(int32_t), s));
+    ET_HIP(hipMemsetAsync(sah, 0, sizeof(double), s));
+    k_depth_sah<<<nblk(T), BS, 0, s>>>(d.nodes, leaf_parent, T, nb, root_id, depth, sah);
+    ET_HIP(hipGetLastError());
+    d.root = (int)(T - 2);   // the last node created is the root; packed index = id - T
+    sc->n_nodes = T - 1;
+  } else {
+    k_single_leaf<<<1, 1, 0, s>>>(d.nodes);
+    d.root = 0;
+    sc->n_nodes = 1;
+  }
+
+  // curvature (Eq. 1)
+  if (T > 0 && V > 0) {
+    ET_HIP(hipMemsetAsync(vcnt, 0, sizeof(uint64_t) * Vm, s));
+    ET_HIP(hipMemsetAsync(vfill, 0, sizeof(uint32_t) * Vm, s));
+    k_vcount<<<nblk(T), BS, 0, s>>>(d.tris, T, vcnt);
+    scan_exclusive_u64(vcnt, voff, V, nullptr, V, nullptr, scan_tmp, s);
+    k_vfill<<<nblk(T), BS, 0, s>>>(d.tris, T, voff, vfill, adj);
+    k_vsort<<<nblk(V), BS, 0, s>>>(voff, vcnt, V, adj);
+    k_vertex_curv<<<nblk(V), BS, 0, s>>>(d.verts, d.tris, voff, vcnt, adj, V, d.G);
+    k_tri_curv<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, T, d.G, mesh->area_ref, d.C);
+    ET_HIP(hipGetLastError());
+  }
+  ET_HIP(hipEventRecord(e1, s));
+  ET_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  ET_HIP(hipEventElapsedTime(&ms, e0, e1));
+  sc->build_ms = ms;
+  ET_HIP(hipEventDestroy(e0));
+  ET_HIP(hipEventDestroy(e1));
+  if (T >= 2) {
+    int32_t hd = 0;
+    double hs = 0;
+    ET_HIP(hipMemcpy(&hd, depth, sizeof(int32_t), hipMemcpyDeviceToHost));
+    ET_HIP(hipMemcpy(&hs, sah, sizeof(double), hipMemcpyDeviceToHost));
+    sc->depth = hd;
+    sc->sah = hs;
+  } else {
+    sc->depth = T;
+    sc->sah = T;
+  }
+  ET_CHECK(sc->depth <= TRAV_STACK, ET_E_UNSUPPORTED, "BVH deeper than the traversal stack");
+}
+
+}  // namespace et

@@ -1,0 +1,195 @@
+// Internal declarations shared by the HIP translation units of the echotrace library.
+// Not part of the ABI (include/echotrace.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/echotrace.h"
+
+namespace et {
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define ET_HIP(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::et::Error{ET_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define ET_CHECK(cond, code, msg)                          \
+  do {                                                     \
+    if (!(cond)) throw ::et::Error{(code), std::string(msg)}; \
+  } while (0)
+
+// deferred device-side error bits (et_stats.status)
+enum : uint32_t {
+  DEV_ERR_INDEX = 1u << 0,      // triangle index out of range
+  DEV_ERR_STACK = 1u << 1,      // traversal stack overflow
+  DEV_ERR_CAPACITY = 1u << 2,   // record capacity exceeded
+  DEV_ERR_RAYDIR = 1u << 3,     // zero / non-finite ray direction
+  DEV_ERR_BUILD = 1u << 4,      // BVH build invariant broken
+};
+
+// ------------------------------------------------------------------ BVH layout
+
+// Traversal node of the binary BVH (64 bytes, one cache line pair): the two child boxes
+// stored side by side so that one node fetch tests both children.
+struct __align__(16) Node2 {
+  float4 xy0;  // child 0: lo.x hi.x lo.y hi.y
+  float4 xy1;  // child 1: lo.x hi.x lo.y hi.y
+  float4 zz;   // child 0 lo.z hi.z, child 1 lo.z hi.z
+  int4 ch;     // child 0, child 1 (>= 0 inner node, < 0 leaf ~position), parent, unused
+};
+
+// Build-time node: box + children (leaves 0..T-1 are triangles in Morton order,
+// inner nodes T..2T-2 are created by the agglomerative clustering).
+struct __align__(16) NodeB {
+  float lox, loy, loz;
+  int left;
+  float hix, hiy, hiz;
+  int right;
+};
+
+constexpr int TRAV_LDS_STACK = 32;     // per-lane stack entries held in LDS
+constexpr int TRAV_STACK = 64;         // total per-lane entries (rest in global memory)
+constexpr int TRAV_BLOCK = 256;
+constexpr int PLOC_RADIUS = 16;
+
+struct SceneDev {
+  int64_t T = 0, V = 0;
+  int32_t n_obj = 0;
+  const float* verts = nullptr;
+  const int32_t* tris = nullptr;
+  const int32_t* mat = nullptr;
+  const int32_t* obj = nullptr;
+  Node2* nodes = nullptr;       // [max(1, T-1)]
+  float4* tri4 = nullptr;       // [T][3]: v0 (w = original index bits), v1 (w = material bits), v2
+  int32_t* tri_orig = nullptr;  // [T] original triangle index per leaf position
+  int32_t* tri_pos = nullptr;   // [T] leaf position per original triangle index
+  double* C = nullptr;          // [T] curvature metric per original triangle
+  double* G = nullptr;          // [V] per-vertex mean curvature magnitude
+  float* obj_box = nullptr;     // [n_obj][6] lo xyz, hi xyz
+  int root = 0;                 // root node index (T == 1: node 0 with a single leaf)
+};
+
+}  // namespace et
+
+struct et_scene {
+  et::SceneDev d;
+  int64_t n_nodes = 0;
+  int32_t depth = 0;
+  double sah = 0;
+  double build_ms = 0;
+  int device = 0;
+};
+
+namespace et {
+
+// ------------------------------------------------------------------ device prims (prims.hip)
+
+// Exclusive scan of n elements (n read from device memory if n_dev != nullptr, else n_host).
+// temp must hold scan_temp_bytes(n_max) bytes.  total (device, optional) receives the sum.
+size_t scan_temp_bytes(int64_t n_max);
+void scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n_host, const int64_t* n_dev, int64_t n_max,
+                        uint64_t* total, void* temp, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the key.
+size_t sort_temp_bytes(int64_t n, int key_bytes);
+void radix_sort_u32(uint32_t* keys, int32_t* vals, int64_t n, int bits, void* temp, hipStream_t s);
+void radix_sort_u64(uint64_t* keys, int32_t* vals, int64_t n_host, const int64_t* n_dev, int64_t n_max, int bits,
+                    void* temp, hipStream_t s);
+
+// ------------------------------------------------------------------ scene build (bvh.hip)
+size_t scene_blob_bytes(int64_t T, int64_t V, int32_t n_obj);
+size_t scene_scratch_bytes(int64_t T, int64_t V);
+// Builds the BVH and curvature; returns host-side info.  Throws et::Error.
+void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scratch, uint32_t* dev_err,
+                 hipStream_t s);
+
+}  // namespace et
+
+namespace et {
+
+// ------------------------------------------------------------------ per-context control block
+// A small device struct (one per context) holding counters that kernels update and later
+// kernels read, so that no phase needs a host round trip.
+struct Ctl {
+  uint32_t err;              // DEV_ERR_* bits
+  uint32_t pad0;
+  int64_t n_active[2];       // active rays of the current / next bounce
+  int64_t rec_base;          // specular records produced so far (may exceed capacity)
+  int64_t seg;               // closest-hit segments traced
+  int64_t shadow;            // line-of-sight rays traced
+  int64_t overflow;          // traversal stack overflows
+  uint64_t tot[4];           // scan totals
+  uint64_t cmax_bits;        // max C_i over eligible objects (bit pattern of a non-negative double)
+  int64_t n_elig;            // triangles in the diffraction CDF
+  int64_t diff_kept;         // kept diffraction samples
+  int64_t cnt[6];            // traversal work counters (nodes/tris closest, nodes/tris any, rays c/a)
+  int64_t n_rec;             // records to synthesise
+};
+
+struct TraceWS {
+  // ray state ping-pong (FP64 origin/direction, path length, previous leaf position, ray id)
+  double* st[2][7];
+  int32_t* prev[2];
+  int32_t* ray[2];
+  // per-slot bounce results
+  double* rp[3];
+  double* rd[3];
+  double* rr;
+  int32_t* rpos;
+  uint8_t* rvis;
+  uint64_t* flags;
+  uint64_t* offs;
+  void* scan_tmp;
+  int32_t* gstack;           // global part of the traversal stacks
+  int64_t gstack_threads;
+  // diffraction
+  uint8_t* oel;
+  uint64_t* dkeys;
+  int32_t* dvals;
+  uint64_t* dq;
+  uint64_t* dflags;
+  uint64_t* doffs;
+  void* sort_tmp;
+  int32_t* stri;
+  double* so;
+  double* sr;
+  uint64_t* skeep;
+  uint64_t* soffs;
+};
+
+// Workspace layout of et_trace.  base == nullptr: only computes the size.
+size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* ws);
+void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& ws, Ctl* ctl,
+               bool counting, hipStream_t s);
+
+// ------------------------------------------------------------------ synthesis (synth.hip)
+struct SynthWS {
+  float* partial;            // [P][M][F][2]
+  int32_t P;
+  double* gpart_x;           // [chunks][M][3]
+  double* gpart_k;           // [chunks][Q][Bk]
+  int32_t gchunks;
+};
+size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
+// returns 1 for the factorised MFMA kernel, 2 for the direct kernel
+int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, Ctl* ctl, float* spectra,
+              hipStream_t s);
+size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
+void synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra, const SynthWS& ws,
+                   Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s);
+bool synth_factorised_ok(const et_sim_desc* sim);
+
+}  // namespace et

@@ -1,0 +1,634 @@
+// Ray tracing of one pose (Sec. III-C, Algorithm 1) and diffraction sampling (Sec. III-D).
+//
+// Per bounce j, over the compacted list of active rays:
+//   k_bounce   FP32 closest-hit BVH traversal of the FP64 ray rounded to FP32 (which
+//              triangle), FP64 plane intersection, specular reflection about the face
+//              normal and path-length update (where), FP32 any-hit line-of-sight ray from
+//              the hit point toward x_ref
+//   scan       exclusive scan of (hit, continue) flags
+//   k_scatter  stable compaction: records in ray order after the earlier bounces' records,
+//              next-bounce ray state in ray order
+// Traversal: one lane per ray, binary BVH, nearest child first, per-lane stack in LDS
+// (spilling to global memory past TRAV_LDS_STACK entries), watertight ray-triangle test
+// (Woop, Benthin & Wald, JCGT 2013), conservative slab test (Ize 2013).
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace et {
+
+namespace {
+
+constexpr int BS = TRAV_BLOCK;
+constexpr int EMPTY = INT32_MIN;
+constexpr int MAX_BLOCKS = 2048;
+
+inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + BS - 1) / BS, MAX_BLOCKS)); }
+inline unsigned nblk_full(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + BS - 1) / BS); }
+
+struct Ray32 {
+  float ox, oy, oz;
+  float ix, iy, iz;          // reciprocal direction (tiny components clamped)
+  float okx, oky, okz;       // origin permuted for the watertight test
+  float Sx, Sy, Sz;          // shear constants
+  int kx, ky, kz;
+};
+
+__device__ inline float sel3(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ inline float safe_rcp(float d) {
+  const float tiny = 1e-30f;
+  return 1.0f / (fabsf(d) < tiny ? (d < 0.f ? -tiny : tiny) : d);
+}
+
+__device__ inline Ray32 make_ray(double ox, double oy, double oz, double dx, double dy, double dz) {
+  Ray32 r;
+  r.ox = (float)ox; r.oy = (float)oy; r.oz = (float)oz;
+  const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  r.ix = safe_rcp(fx); r.iy = safe_rcp(fy); r.iz = safe_rcp(fz);
+  const float ax = fabsf(fx), ay = fabsf(fy), az = fabsf(fz);
+  int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  int kx = kz + 1 == 3 ? 0 : kz + 1;
+  int ky = kx + 1 == 3 ? 0 : kx + 1;
+  const float dkz = sel3(fx, fy, fz, kz);
+  if (dkz < 0.f) { int t = kx; kx = ky; ky = t; }
+  r.kx = kx; r.ky = ky; r.kz = kz;
+  r.Sx = sel3(fx, fy, fz, kx) / dkz;
+  r.Sy = sel3(fx, fy, fz, ky) / dkz;
+  r.Sz = 1.0f / dkz;
+  r.okx = sel3(r.ox, r.oy, r.oz, kx);
+  r.oky = sel3(r.ox, r.oy, r.oz, ky);
+  r.okz = sel3(r.ox, r.oy, r.oz, kz);
+  return r;
+}
+
+// Slab test against both child boxes; far distances widened by 1 + 2*gamma(3) (Ize 2013)
+// so that FP32 rounding never rejects a box that the exact ray meets.
+__device__ inline void box2(const Node2& n, const Ray32& r, float tmin, float tmax, bool& h0, bool& h1, float& t0,
+                            float& t1) {
+  const float up = 1.0f + 2.0f * 3.5762786865234375e-7f;   // 1 + 2 * gamma_3, gamma_n = n u / (1 - n u)
+  float lx = (n.xy0.x - r.ox) * r.ix, hx = (n.xy0.y - r.ox) * r.ix;
+  float ly = (n.xy0.z - r.oy) * r.iy, hy = (n.xy0.w - r.oy) * r.iy;
+  float lz = (n.zz.x - r.oz) * r.iz, hz = (n.zz.y - r.oz) * r.iz;
+  float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), tmin));
+  float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fmaxf(lz, hz)) * up;
+  h0 = tn <= fminf(tf, tmax);
+  t0 = tn;
+  lx = (n.xy1.x - r.ox) * r.ix; hx = (n.xy1.y - r.ox) * r.ix;
+  ly = (n.xy1.z - r.oy) * r.iy; hy = (n.xy1.w - r.oy) * r.iy;
+  lz = (n.zz.z - r.oz) * r.iz; hz = (n.zz.w - r.oz) * r.iz;
+  tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), tmin));
+  tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fmaxf(lz, hz)) * up;
+  h1 = tn <= fminf(tf, tmax);
+  t1 = tn;
+}
+
+// Watertight ray-triangle test, two-sided.  Returns t (or a negative value on a miss).
+__device__ inline float tri_test(const float4 a, const float4 b, const float4 c, const Ray32& r) {
+#pragma clang fp contract(off)
+  const float Ax0 = sel3(a.x, a.y, a.z, r.kx) - r.okx, Ay0 = sel3(a.x, a.y, a.z, r.ky) - r.oky,
+              Az0 = sel3(a.x, a.y, a.z, r.kz) - r.okz;
+  const float Bx0 = sel3(b.x, b.y, b.z, r.kx) - r.okx, By0 = sel3(b.x, b.y, b.z, r.ky) - r.oky,
+              Bz0 = sel3(b.x, b.y, b.z, r.kz) - r.okz;
+  const float Cx0 = sel3(c.x, c.y, c.z, r.kx) - r.okx, Cy0 = sel3(c.x, c.y, c.z, r.ky) - r.oky,
+              Cz0 = sel3(c.x, c.y, c.z, r.kz) - r.okz;
+  const float Ax = Ax0 - r.Sx * Az0, Ay = Ay0 - r.Sy * Az0;
+  const float Bx = Bx0 - r.Sx * Bz0, By = By0 - r.Sy * Bz0;
+  const float Cx = Cx0 - r.Sx * Cz0, Cy = Cy0 - r.Sy * Cz0;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.f || V == 0.f || W == 0.f) {   // exact edge: decide in double (watertightness)
+    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+  }
+  if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return -1.f;
+  const float det = U + V + W;
+  if (det == 0.f) return -1.f;
+  const float Az = r.Sz * Az0, Bz = r.Sz * Bz0, Cz = r.Sz * Cz0;
+  const float T = U * Az + V * Bz + W * Cz;
+  return T / det;
+}
+
+struct Stack {
+  int* lds;        // this lane's column: entry i at lds[i * BS]
+  int* glob;       // this lane's global column: entry i at glob[i * gstride]
+  int64_t gstride;
+  int sp;
+  int overflow;
+  __device__ inline void push(int v) {
+    if (sp < TRAV_LDS_STACK) lds[sp * BS] = v;
+    else if (sp < TRAV_STACK) glob[(int64_t)(sp - TRAV_LDS_STACK) * gstride] = v;
+    else { ++overflow; return; }
+    ++sp;
+  }
+  __device__ inline int pop() {
+    if (sp == 0) return EMPTY;
+    --sp;
+    return sp < TRAV_LDS_STACK ? lds[sp * BS] : glob[(int64_t)(sp - TRAV_LDS_STACK) * gstride];
+  }
+};
+
+// Closest hit (ANY = false) or any hit (ANY = true) over t in (tmin, tmax), excluding the
+// leaf position `excl`.  Closest-hit ties in t go to the smaller original triangle index.
+template <bool ANY, bool COUNT>
+__device__ inline int traverse(const SceneDev& S, const Ray32& r, float tmin, float tmax, int excl, Stack& st,
+                               float& t_hit, int64_t& cn, int64_t& ct) {
+  int node = S.root;
+  st.sp = 0;
+  int best = -1, best_orig = INT32_MAX;
+  float tb = tmax;
+  while (true) {
+    while (node >= 0) {
+      const Node2 n = S.nodes[node];
+      if (COUNT) ++cn;
+      bool h0, h1;
+      float t0, t1;
+      box2(n, r, tmin, tb, h0, h1, t0, t1);
+      if (h0 && h1) {
+        const bool first0 = t0 <= t1;
+        st.push(first0 ? n.ch.y : n.ch.x);
+        node = first0 ? n.ch.x : n.ch.y;
+      } else if (h0) {
+        node = n.ch.x;
+      } else if (h1) {
+        node = n.ch.y;
+      } else {
+        node = st.pop();
+      }
+    }
+    if (node == EMPTY) break;
+    const int pos = ~node;
+    if (COUNT) ++ct;
+    if (pos != excl) {
+      const float4 a = S.tri4[3 * (int64_t)pos], b = S.tri4[3 * (int64_t)pos + 1], c = S.tri4[3 * (int64_t)pos + 2];
+      const float t = tri_test(a, b, c, r);
+      if (t > tmin && t <= tb) {
+        if (ANY) {
+          if (t < tmax) { t_hit = t; return pos; }
+        } else {
+          const int orig = __float_as_int(a.w);
+          if (t < tb || orig < best_orig) {
+            tb = t;
+            best = pos;
+            best_orig = orig;
+          }
+        }
+      }
+    }
+    node = st.pop();
+  }
+  t_hit = tb;
+  return best;
+}
+
+struct PoseArgs {
+  double s[3];
+  double R[9];
+  double xref[3];
+  int64_t N;
+  int32_t B;
+  double maxd;
+  double t_eps;
+};
+
+__device__ inline double dnorm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
+
+__global__ void k_trace_init(Ctl* ctl, int64_t N) {
+  ctl->n_active[0] = N;
+  ctl->n_active[1] = 0;
+  ctl->rec_base = 0;
+  ctl->seg = 0;
+  ctl->shadow = 0;
+  ctl->overflow = 0;
+  ctl->cmax_bits = 0;
+  ctl->n_elig = 0;
+  ctl->diff_kept = 0;
+  for (int i = 0; i < 4; ++i) ctl->tot[i] = 0;
+  for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
+}
+
+__global__ void k_ray_init(PoseArgs a, const float* __restrict__ dirs, TraceWS w, Ctl* ctl) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const double lx = dirs[3 * i], ly = dirs[3 * i + 1], lz = dirs[3 * i + 2];
+  // CalculateWorldDirection: world = R * local, normalised in FP64
+  double dx = a.R[0] * lx + a.R[1] * ly + a.R[2] * lz;
+  double dy = a.R[3] * lx + a.R[4] * ly + a.R[5] * lz;
+  double dz = a.R[6] * lx + a.R[7] * ly + a.R[8] * lz;
+  double nrm = dnorm3(dx, dy, dz);
+  if (!(nrm > 0.0) || !isfinite(nrm)) {
+    atomicOr(&ctl->err, DEV_ERR_RAYDIR);
+    nrm = 1.0;
+    dx = 1.0; dy = 0.0; dz = 0.0;
+  }
+  w.st[0][0][i] = a.s[0]; w.st[0][1][i] = a.s[1]; w.st[0][2][i] = a.s[2];
+  w.st[0][3][i] = dx / nrm; w.st[0][4][i] = dy / nrm; w.st[0][5][i] = dz / nrm;
+  w.st[0][6][i] = 0.0;
+  w.prev[0][i] = -1;
+  w.ray[0][i] = (int32_t)i;
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(BS) void k_bounce(SceneDev S, PoseArgs a, TraceWS w, Ctl* ctl, int j) {
+  __shared__ int lds_stack[TRAV_LDS_STACK * BS];
+  const int cur = j & 1;
+  const int64_t n = ctl->n_active[cur];
+  const int64_t gtid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  Stack st;
+  st.lds = lds_stack + threadIdx.x;
+  st.glob = w.gstack + gtid;
+  st.gstride = w.gstack_threads;
+  st.overflow = 0;
+  int64_t cn_c = 0, ct_c = 0, cn_a = 0, ct_a = 0, rays_a = 0;
+  const float teps = (float)a.t_eps;
+  for (int64_t i = gtid; i < n; i += stride) {
+    const double ox = w.st[cur][0][i], oy = w.st[cur][1][i], oz = w.st[cur][2][i];
+    const double dx = w.st[cur][3][i], dy = w.st[cur][4][i], dz = w.st[cur][5][i];
+    const double rtot = w.st[cur][6][i];
+    const int prev = w.prev[cur][i];
+    const Ray32 r = make_ray(ox, oy, oz, dx, dy, dz);
+    float th;
+    const int pos = traverse<false, COUNT>(S, r, teps, INFINITY, prev, st, th, cn_c, ct_c);
+    uint64_t flag = 0;
+    if (pos >= 0) {
+      // FP64 refinement on the chosen triangle: plane intersection, normal, reflection
+      const float4 A = S.tri4[3 * (int64_t)pos], Bv = S.tri4[3 * (int64_t)pos + 1], Cv = S.tri4[3 * (int64_t)pos + 2];
+      const double e1x = (double)Bv.x - A.x, e1y = (double)Bv.y - A.y, e1z = (double)Bv.z - A.z;
+      const double e2x = (double)Cv.x - A.x, e2y = (double)Cv.y - A.y, e2z = (double)Cv.z - A.z;
+      double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+      const double nn = dnorm3(nx, ny, nz);
+      nx /= nn; ny /= nn; nz /= nn;
+      const double dn = dx * nx + dy * ny + dz * nz;
+      const double hp = ((double)A.x - ox) * nx + ((double)A.y - oy) * ny + ((double)A.z - oz) * nz;
+      const double t = dn != 0.0 ? hp / dn : (double)th;
+      const double px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
+      const double rnew = (j == 0) ? dnorm3(px - a.s[0], py - a.s[1], pz - a.s[2]) : rtot + t;
+      const double rx = dx - 2.0 * dn * nx, ry = dy - 2.0 * dn * ny, rz = dz - 2.0 * dn * nz;
+      // line of sight from the hit point toward the receiver reference point
+      const double wx = a.xref[0] - px, wy = a.xref[1] - py, wz = a.xref[2] - pz;
+      const double L = dnorm3(wx, wy, wz);
+      int vis = 1;
+      if (L > 2.0 * a.t_eps) {
+        const Ray32 rv = make_ray(px, py, pz, wx / L, wy / L, wz / L);
+        float tv;
+        const int blk = traverse<true, COUNT>(S, rv, teps, (float)(L - a.t_eps), pos, st, tv, cn_a, ct_a);
+        vis = blk < 0;
+        ++rays_a;
+      }
+      w.rp[0][i] = px; w.rp[1][i] = py; w.rp[2][i] = pz;
+      w.rd[0][i] = rx; w.rd[1][i] = ry; w.rd[2][i] = rz;
+      w.rr[i] = rnew;
+      w.rpos[i] = pos;
+      w.rvis[i] = (uint8_t)vis;
+      const bool cont = (j + 1 < a.B) && !(rnew >= a.maxd);
+      flag = 1ull | ((uint64_t)cont << 32);
+    }
+    w.flags[i] = flag;
+  }
+  if (st.overflow) atomicAdd((unsigned long long*)&ctl->overflow, (unsigned long long)st.overflow);
+  if (st.overflow) atomicOr(&ctl->err, DEV_ERR_STACK);
+  if (COUNT) {
+    atomicAdd((unsigned long long*)&ctl->cnt[0], (unsigned long long)cn_c);
+    atomicAdd((unsigned long long*)&ctl->cnt[1], (unsigned long long)ct_c);
+    atomicAdd((unsigned long long*)&ctl->cnt[2], (unsigned long long)cn_a);
+    atomicAdd((unsigned long long*)&ctl->cnt[3], (unsigned long long)ct_a);
+    atomicAdd((unsigned long long*)&ctl->cnt[5], (unsigned long long)rays_a);
+  }
+}
+
+__global__ void k_scatter(SceneDev S, TraceWS w, Ctl* ctl, et_paths P, int j) {
+  const int cur = j & 1, nxt = cur ^ 1;
+  const int64_t n = ctl->n_active[cur];
+  const int64_t base = ctl->rec_base;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t f = w.flags[i];
+    if (!(f & 1ull)) continue;
+    const uint64_t o = w.offs[i];
+    const int64_t ri = base + (int64_t)(o & 0xffffffffull);
+    const int pos = w.rpos[i];
+    const int orig = S.tri_orig[pos];
+    if (ri < P.capacity) {
+      P.p[3 * ri] = w.rp[0][i]; P.p[3 * ri + 1] = w.rp[1][i]; P.p[3 * ri + 2] = w.rp[2][i];
+      P.dout[3 * ri] = (float)w.rd[0][i]; P.dout[3 * ri + 1] = (float)w.rd[1][i]; P.dout[3 * ri + 2] = (float)w.rd[2][i];
+      P.rtot[ri] = w.rr[i];
+      P.tri[ri] = orig;
+      P.mat[ri] = S.mat[orig];
+      P.ray[ri] = w.ray[cur][i];
+      P.bounce[ri] = (uint8_t)j;
+      P.flags[ri] = w.rvis[i];
+    } else {
+      atomicOr(&ctl->err, DEV_ERR_CAPACITY);
+    }
+    if (f >> 32) {
+      const int64_t k = (int64_t)(o >> 32);
+      w.st[nxt][0][k] = w.rp[0][i]; w.st[nxt][1][k] = w.rp[1][i]; w.st[nxt][2][k] = w.rp[2][i];
+      w.st[nxt][3][k] = w.rd[0][i]; w.st[nxt][4][k] = w.rd[1][i]; w.st[nxt][5][k] = w.rd[2][i];
+      w.st[nxt][6][k] = w.rr[i];
+      w.prev[nxt][k] = pos;
+      w.ray[nxt][k] = w.ray[cur][i];
+    }
+  }
+}
+
+__global__ void k_bounce_epi(Ctl* ctl, int j) {
+  const int cur = j & 1;
+  const uint64_t t = ctl->tot[0];
+  const int64_t hits = (int64_t)(t & 0xffffffffull);
+  ctl->seg += ctl->n_active[cur];
+  ctl->shadow += hits;
+  ctl->rec_base += hits;
+  ctl->n_active[cur ^ 1] = (int64_t)(t >> 32);
+  ctl->cnt[4] += ctl->n_active[cur];
+}
+
+// ------------------------------------------------------------------ diffraction (Sec. III-D)
+// Decisions that pick integers (eligibility, weights, CDF search, sample points, incidence
+// test) are FP64 without contraction, in a fixed operation order.
+#pragma clang fp contract(off)
+
+__device__ inline uint64_t splitmix(uint64_t key, uint64_t counter) {
+  uint64_t z = key + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline double u01(uint64_t x) { return (double)(x >> 11) * 0x1p-53; }
+
+struct DiffArgs {
+  double s[3];
+  double axis[3];
+  double cone;
+  double tau;
+  double cos_max;
+  uint64_t seed;
+  int64_t K;
+  double t_eps;
+};
+
+__global__ void k_obj_fov(SceneDev S, DiffArgs a, uint8_t* oel) {
+  int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= S.n_obj) return;
+  const float* b = S.obj_box + 6 * o;
+  const double lx = b[0], ly = b[1], lz = b[2], hx = b[3], hy = b[4], hz = b[5];
+  if (!(lx <= hx)) { oel[o] = 0; return; }
+  const double cx = 0.5 * (lx + hx), cy = 0.5 * (ly + hy), cz = 0.5 * (lz + hz);
+  const double ex = hx - lx, ey = hy - ly, ez = hz - lz;
+  const double rad = 0.5 * sqrt(ex * ex + ey * ey + ez * ez);
+  const double wx = cx - a.s[0], wy = cy - a.s[1], wz = cz - a.s[2];
+  const double dist = sqrt(wx * wx + wy * wy + wz * wz);
+  if (dist <= rad) { oel[o] = 1; return; }
+  const double qx = wy * a.axis[2] - wz * a.axis[1], qy = wz * a.axis[0] - wx * a.axis[2],
+               qz = wx * a.axis[1] - wy * a.axis[0];
+  const double psi = atan2(sqrt(qx * qx + qy * qy + qz * qz), wx * a.axis[0] + wy * a.axis[1] + wz * a.axis[2]);
+  oel[o] = psi <= a.cone + asin(rad / dist);
+}
+
+__global__ void k_cmax(SceneDev S, const uint8_t* __restrict__ oel, Ctl* ctl) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S.T) return;
+  if (oel[S.obj[t]]) {
+    const double c = S.C[t];
+    if (c > 0.0) atomicMax((unsigned long long*)&ctl->cmax_bits, (unsigned long long)__double_as_longlong(c));
+  }
+}
+
+__global__ void k_qweight(SceneDev S, DiffArgs a, const uint8_t* __restrict__ oel, const Ctl* ctl,
+                          uint64_t* __restrict__ q, uint64_t* __restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S.T) return;
+  const double cmax = __longlong_as_double((long long)ctl->cmax_bits);
+  const double c = S.C[t];
+  uint64_t qq = 0;
+  if (cmax > 0.0 && oel[S.obj[t]] && c > 0.0 && c >= a.tau * cmax) {
+    // dithered integer weight: stochastic rounding of (C / Cmax) * 2^32
+    const double x = c / cmax * 4294967296.0 + u01(splitmix(a.seed ^ 1ull, (uint64_t)t));
+    qq = (uint64_t)floor(x);
+  }
+  q[t] = qq;
+  flag[t] = qq > 0 ? 1ull : 0ull;
+}
+
+__global__ void k_elig_keys(SceneDev S, const uint64_t* __restrict__ q, const uint64_t* __restrict__ flag,
+                            const uint64_t* __restrict__ offs, uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S.T || !flag[t]) return;
+  const int64_t p = (int64_t)offs[t];
+  // ascending order of this key = weight descending, then index ascending
+  keys[p] = ((4294967296ull - q[t]) << 31) | (uint64_t)t;
+  vals[p] = (int32_t)t;
+}
+
+__global__ void k_elig_count(Ctl* ctl) { ctl->n_elig = (int64_t)ctl->tot[1]; }
+
+__global__ void k_sorted_q(const uint64_t* __restrict__ keys, const Ctl* ctl, uint64_t* __restrict__ qs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctl->n_elig) return;
+  qs[i] = 4294967296ull - (keys[i] >> 31);
+}
+
+__global__ __launch_bounds__(BS) void k_diff_sample(SceneDev S, DiffArgs a, const uint64_t* __restrict__ W_ex,
+                                                    const uint64_t* __restrict__ qs, const int32_t* __restrict__ vals,
+                                                    TraceWS w, Ctl* ctl) {
+  __shared__ int lds_stack[TRAV_LDS_STACK * BS];
+  const int64_t gtid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  Stack st;
+  st.lds = lds_stack + threadIdx.x;
+  st.glob = w.gstack + gtid;
+  st.gstride = w.gstack_threads;
+  st.overflow = 0;
+  const int64_t ne = ctl->n_elig;
+  const uint64_t total = ctl->tot[2];
+  int64_t dummy0 = 0, dummy1 = 0, rays = 0;
+  for (int64_t k = gtid; k < a.K; k += stride) {
+    uint64_t keep = 0;
+    w.stri[k] = -1;
+    if (ne > 0) {
+      const uint64_t ks = a.seed ^ 2ull;
+      const uint64_t U = splitmix(ks, 3ull * (uint64_t)k);
+      const uint64_t idx = __umul64hi(U, total);
+      // first position whose inclusive prefix exceeds idx
+      int64_t lo = 0, hi = ne;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (W_ex[mid] + qs[mid] > idx) hi = mid; else lo = mid + 1;
+      }
+      const int32_t t = vals[lo];
+      const double u1 = u01(splitmix(ks, 3ull * (uint64_t)k + 1ull)), u2 = u01(splitmix(ks, 3ull * (uint64_t)k + 2ull));
+      const double su = sqrt(u1);
+      const double wa = 1.0 - su, wb = su * (1.0 - u2), wc = su * u2;   // uniform point on the triangle
+      const int pos = S.tri_pos[t];
+      const float4 A = S.tri4[3 * (int64_t)pos], B = S.tri4[3 * (int64_t)pos + 1], C = S.tri4[3 * (int64_t)pos + 2];
+      const double ax = A.x, ay = A.y, az = A.z, bx = B.x, by = B.y, bz = B.z, cx = C.x, cy = C.y, cz = C.z;
+      const double ox = wa * ax + wb * bx + wc * cx, oy = wa * ay + wb * by + wc * cy, oz = wa * az + wb * bz + wc * cz;
+      double nx = (by - ay) * (cz - az) - (bz - az) * (cy - ay);
+      double ny = (bz - az) * (cx - ax) - (bx - ax) * (cz - az);
+      double nz = (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+      const double inn = 1.0 / nn;
+      nx = nx * inn; ny = ny * inn; nz = nz * inn;
+      const double wx = a.s[0] - ox, wy = a.s[1] - oy, wz = a.s[2] - oz;
+      const double L = sqrt(wx * wx + wy * wy + wz * wz);
+      const double iL = 1.0 / L;
+      const double vx = wx * iL, vy = wy * iL, vz = wz * iL;
+      const double ci = fabs(nx * vx + ny * vy + nz * vz);
+      bool ok = ci >= a.cos_max;                                   // incidence-angle constraint
+      if (ok) {                                                    // line of sight to the source
+        const Ray32 r = make_ray(ox, oy, oz, vx, vy, vz);
+        float tv;
+        const int blk = traverse<true, false>(S, r, (float)a.t_eps, (float)(L - a.t_eps), pos, st, tv, dummy0, dummy1);
+        ok = blk < 0;
+        ++rays;
+      }
+      w.stri[k] = t;
+      w.so[3 * k] = ox; w.so[3 * k + 1] = oy; w.so[3 * k + 2] = oz;
+      w.sr[k] = L;
+      keep = ok ? 1ull : 0ull;
+    }
+    w.skeep[k] = keep;
+  }
+  if (st.overflow) {
+    atomicAdd((unsigned long long*)&ctl->overflow, (unsigned long long)st.overflow);
+    atomicOr(&ctl->err, DEV_ERR_STACK);
+  }
+  atomicAdd((unsigned long long*)&ctl->shadow, (unsigned long long)rays);
+}
+
+__global__ void k_diff_scatter(SceneDev S, DiffArgs a, TraceWS w, Ctl* ctl, et_paths P) {
+  const int64_t base = ctl->rec_base;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.K; k += (int64_t)gridDim.x * blockDim.x) {
+    if (!w.skeep[k]) continue;
+    const int64_t ri = base + (int64_t)w.soffs[k];
+    if (ri >= P.capacity) { atomicOr(&ctl->err, DEV_ERR_CAPACITY); continue; }
+    const int32_t t = w.stri[k];
+    P.p[3 * ri] = w.so[3 * k]; P.p[3 * ri + 1] = w.so[3 * k + 1]; P.p[3 * ri + 2] = w.so[3 * k + 2];
+    P.dout[3 * ri] = 0.f; P.dout[3 * ri + 1] = 0.f; P.dout[3 * ri + 2] = 0.f;
+    P.rtot[ri] = w.sr[k];
+    P.tri[ri] = t;
+    P.mat[ri] = S.mat[t];
+    P.ray[ri] = (int32_t)k;
+    P.bounce[ri] = 0;
+    P.flags[ri] = 3;   // visible | diffraction
+  }
+}
+
+#pragma clang fp contract(on)
+
+__global__ void k_trace_final(Ctl* ctl, et_paths P, int diff) {
+  const int64_t spec = ctl->rec_base;
+  const int64_t dk = diff ? (int64_t)ctl->tot[3] : 0;
+  ctl->diff_kept = dk;
+  const int64_t total = spec + dk;
+  ctl->n_rec = total;
+  P.count[0] = total;
+  P.count[1] = spec;
+  P.count[2] = dk;
+  P.count[3] = ctl->seg;
+}
+
+inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* w) {
+  const int64_t Nm = std::max<int64_t>(N, 1), Tm = std::max<int64_t>(T, 1), Km = std::max<int64_t>(K, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += al(bytes);
+    return p;
+  };
+  TraceWS x{};
+  for (int b = 0; b < 2; ++b) {
+    for (int k = 0; k < 7; ++k) x.st[b][k] = (double*)take(sizeof(double) * Nm);
+    x.prev[b] = (int32_t*)take(sizeof(int32_t) * Nm);
+    x.ray[b] = (int32_t*)take(sizeof(int32_t) * Nm);
+  }
+  for (int k = 0; k < 3; ++k) x.rp[k] = (double*)take(sizeof(double) * Nm);
+  for (int k = 0; k < 3; ++k) x.rd[k] = (double*)take(sizeof(double) * Nm);
+  x.rr = (double*)take(sizeof(double) * Nm);
+  x.rpos = (int32_t*)take(sizeof(int32_t) * Nm);
+  x.rvis = (uint8_t*)take(Nm);
+  x.flags = (uint64_t*)take(sizeof(uint64_t) * Nm);
+  x.offs = (uint64_t*)take(sizeof(uint64_t) * Nm);
+  x.scan_tmp = take(scan_temp_bytes(std::max(std::max(Nm, Tm), Km)));
+  x.gstack_threads = (int64_t)MAX_BLOCKS * BS;
+  x.gstack = (int32_t*)take(sizeof(int32_t) * (size_t)(TRAV_STACK - TRAV_LDS_STACK) * (size_t)x.gstack_threads);
+  if (K > 0) {
+    x.oel = (uint8_t*)take((size_t)std::max<int32_t>(n_obj, 1));
+    x.dkeys = (uint64_t*)take(sizeof(uint64_t) * Tm);
+    x.dvals = (int32_t*)take(sizeof(int32_t) * Tm);
+    x.dq = (uint64_t*)take(sizeof(uint64_t) * Tm);
+    x.dflags = (uint64_t*)take(sizeof(uint64_t) * Tm);
+    x.doffs = (uint64_t*)take(sizeof(uint64_t) * Tm);
+    x.sort_tmp = take(sort_temp_bytes(Tm, 8));
+    x.stri = (int32_t*)take(sizeof(int32_t) * Km);
+    x.so = (double*)take(sizeof(double) * 3 * Km);
+    x.sr = (double*)take(sizeof(double) * Km);
+    x.skeep = (uint64_t*)take(sizeof(uint64_t) * Km);
+    x.soffs = (uint64_t*)take(sizeof(uint64_t) * Km);
+  }
+  if (w) *w = x;
+  return off;
+}
+
+void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& w, Ctl* ctl,
+               bool counting, hipStream_t s) {
+  PoseArgs a;
+  for (int k = 0; k < 3; ++k) { a.s[k] = sim->emitter_pos[k]; a.xref[k] = sim->x_ref[k]; }
+  for (int k = 0; k < 9; ++k) a.R[k] = sim->emitter_rot[k];
+  a.N = (sim->flags & ET_SPECULAR) ? sim->N : 0;
+  a.B = sim->max_bounces;
+  a.maxd = sim->max_distance;
+  a.t_eps = sim->t_eps;
+  const et_paths P = *paths;
+  k_trace_init<<<1, 1, 0, s>>>(ctl, a.N);
+  ET_HIP(hipGetLastError());
+  if (a.N > 0 && S.T > 0) {
+    k_ray_init<<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, w, ctl);
+    for (int j = 0; j < a.B; ++j) {
+      if (counting) k_bounce<true><<<nblk(a.N), BS, 0, s>>>(S, a, w, ctl, j);
+      else k_bounce<false><<<nblk(a.N), BS, 0, s>>>(S, a, w, ctl, j);
+      scan_exclusive_u64(w.flags, w.offs, 0, &ctl->n_active[j & 1], a.N, &ctl->tot[0], w.scan_tmp, s);
+      k_scatter<<<nblk(a.N), BS, 0, s>>>(S, w, ctl, P, j);
+      k_bounce_epi<<<1, 1, 0, s>>>(ctl, j);
+      ET_HIP(hipGetLastError());
+    }
+  } else if (a.N > 0) {
+    // empty scene: every ray misses at its first segment
+    k_bounce_epi<<<1, 1, 0, s>>>(ctl, 0);
+  }
+  const bool diff = (sim->flags & ET_DIFFRACTION) && sim->diff_K > 0 && S.T > 0;
+  if (diff) {
+    DiffArgs d;
+    for (int k = 0; k < 3; ++k) { d.s[k] = sim->emitter_pos[k]; d.axis[k] = sim->emitter_rot[3 * k]; }
+    d.cone = sim->diff_cone_half_angle;
+    d.tau = sim->diff_tau;
+    d.cos_max = std::cos(sim->diff_max_incidence);
+    d.seed = sim->diff_seed;
+    d.K = sim->diff_K;
+    d.t_eps = sim->t_eps;
+    k_obj_fov<<<nblk_full(S.n_obj), BS, 0, s>>>(S, d, w.oel);
+    k_cmax<<<nblk_full(S.T), BS, 0, s>>>(S, w.oel, ctl);
+    k_qweight<<<nblk_full(S.T), BS, 0, s>>>(S, d, w.oel, ctl, w.dq, w.dflags);
+    scan_exclusive_u64(w.dflags, w.doffs, S.T, nullptr, S.T, &ctl->tot[1], w.scan_tmp, s);
+    k_elig_keys<<<nblk_full(S.T), BS, 0, s>>>(S, w.dq, w.dflags, w.doffs, w.dkeys, w.dvals);
+    k_elig_count<<<1, 1, 0, s>>>(ctl);
+    radix_sort_u64(w.dkeys, w.dvals, 0, &ctl->n_elig, S.T, 64, w.sort_tmp, s);
+    // weights in sorted order, then their exclusive prefix sums (the CDF) and total
+    k_sorted_q<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, ctl, w.dq);
+    scan_exclusive_u64(w.dq, w.doffs, 0, &ctl->n_elig, S.T, &ctl->tot[2], w.scan_tmp, s);
+    k_diff_sample<<<nblk(d.K), BS, 0, s>>>(S, d, w.doffs, w.dq, w.dvals, w, ctl);
+    scan_exclusive_u64(w.skeep, w.soffs, d.K, nullptr, d.K, &ctl->tot[3], w.scan_tmp, s);
+    k_diff_scatter<<<nblk(d.K), BS, 0, s>>>(S, d, w, ctl, P);
+    ET_HIP(hipGetLastError());
+  }
+  k_trace_final<<<1, 1, 0, s>>>(ctl, P, diff ? 1 : 0);
+  ET_HIP(hipGetLastError());
+}
+
+}  // namespace et

@@ -1,0 +1,272 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Protocol:
+  * hit triangles and visibility bits match bit-exactly on certified rays (rays none of
+    whose segments is marginal under the oracle's FP32-rounding margin predicate);
+  * spectra match within 1e-4 relative L2 (complex, over all receivers and bins): the
+    synthesis fed the oracle's own records, and end to end on the certified rays;
+  * diffraction sample lists match exactly (integer CDF, shared counter-based RNG);
+  * the adjoint matches the oracle's analytic gradient within 1e-4 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def by_ray(rec, n_rays):
+    """{ray: [(bounce, tri, vis, rtot, p)]} sorted by bounce."""
+    out = {i: [] for i in range(n_rays)}
+    for k in range(len(rec["rtot"])):
+        out[int(rec["ray"][k])].append((int(rec["bounce"][k]), int(rec["tri"][k]), int(rec["vis"][k]),
+                                        float(rec["rtot"][k]), np.asarray(rec["p"][k])))
+    for v in out.values():
+        v.sort(key=lambda x: x[0])
+    return out
+
+
+def compare_traces(gpu, orc, certified):
+    g = by_ray(gpu, len(certified))
+    o = by_ray(orc, len(certified))
+    mism = 0
+    for i in np.nonzero(certified)[0]:
+        a, b = g[i], o[i]
+        if [(x[0], x[1], x[2]) for x in a] != [(x[0], x[1], x[2]) for x in b]:
+            mism += 1
+            continue
+        for x, y in zip(a, b):
+            assert abs(x[3] - y[3]) <= 1e-9 * max(1.0, y[3])
+            assert np.max(np.abs(x[4] - y[4])) <= 1e-9
+    return mism
+
+
+@pytest.fixture(scope="module")
+def ctx(et):
+    return et.Context(0)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    scene, sim = W.tiny_scene()
+    ref = O.trace(scene, sim)
+    return scene, sim, ref
+
+
+# ----------------------------------------------------------------------------- scene build
+
+def test_scene_build_tiny(et, ctx, tiny):
+    scene, sim, _ = tiny
+    sc = et.Scene(ctx, scene, area_ref=W.median_triangle_area(scene))
+    info = sc.info()
+    assert info.T == len(scene["tris"]) and info.n_nodes == info.T - 1
+    assert 1 < info.depth <= 64
+    print(f"tiny BVH: depth {info.depth} SAH {info.sah_cost:.2f} build {info.build_ms:.2f} ms")
+
+
+def test_curvature_bitwise_matches_oracle(et, ctx):
+    """C_i and G_v: same definition, same operation order, IEEE double on both sides."""
+    g = W.rng(21)
+    scene = W.room_geometry(g, n_boxes=20, n_cyl=20)
+    a_ref = W.median_triangle_area(scene)
+    G_ref, C_ref = O.curvature(scene, a_ref)
+    sc = et.Scene(ctx, scene, area_ref=a_ref)
+    Cg, Gg = sc.curvature()
+    Cg, Gg = Cg.cpu().numpy(), Gg.cpu().numpy()
+    np.testing.assert_allclose(Gg, G_ref, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(Cg, C_ref, rtol=1e-12, atol=1e-14)
+    exact = float(np.mean(Cg == C_ref))
+    print(f"curvature: bitwise-equal fraction {exact:.6f}")
+    assert exact == 1.0
+
+
+# ----------------------------------------------------------------------------- tracing
+
+def test_trace_parity_tiny(et, ctx, tiny):
+    scene, sim, ref = tiny
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim)
+    P = et.trace(ctx, sc, s)
+    st = ctx.stats()
+    gpu = P.to_host()
+    cert = ref["certified"]
+    mism = compare_traces(gpu, ref, cert)
+    print(f"tiny: records gpu {st.records} oracle {len(ref['rtot'])}, certified {cert.mean():.4f}, mismatches {mism}")
+    assert st.stack_overflows == 0
+    assert mism == 0
+    assert st.segments == int(ref["nseg"].sum())
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_synthesis_isolation_tiny(et, ctx, tiny, direct):
+    """GPU synthesis of the oracle's own records vs the oracle's spectra."""
+    scene, sim, ref = tiny
+    flags = et.ET_SPECULAR | (et.ET_SYNTH_DIRECT if direct else 0)
+    s = et.Sim(sim, flags=flags)
+    P = et.Paths.from_records(ref)
+    H = et.synthesize(ctx, s, P).cpu().numpy()
+    st = ctx.stats()
+    H_ref = O.synth(ref, sim)
+    e = rel_l2(H, H_ref)
+    print(f"tiny synthesis ({'direct' if direct else 'factorised'} kernel {st.synth_kernel}): rel L2 {e:.3e}")
+    assert st.synth_kernel == (2 if direct else 1)
+    assert e <= TOL
+
+
+def test_end_to_end_tiny_certified(et, ctx, tiny):
+    scene, sim, ref = tiny
+    dirs = sim["ray_dirs"][ref["certified"]]
+    ref_c = O.trace(scene, sim, dirs=dirs)
+    H_ref = O.synth(ref_c, sim)
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim, ray_dirs=dirs)
+    H = et.simulate(ctx, sc, s).cpu().numpy()
+    e = rel_l2(H, H_ref)
+    print(f"tiny end to end (certified rays): rel L2 {e:.3e}")
+    assert e <= TOL
+
+
+def test_determinism(et, ctx, tiny):
+    scene, sim, _ = tiny
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim)
+    H1 = et.simulate(ctx, sc, s).cpu().numpy()
+    H2 = et.simulate(ctx, sc, s).cpu().numpy()
+    assert np.array_equal(H1, H2)
+
+
+@pytest.fixture(scope="module")
+def room_small():
+    """Room scene geometry (full 193,212 triangles), a seeded subset of its rays."""
+    scene, sim = W.room_scene(n_rays=1 << 20)
+    g = W.rng(77)
+    sub = np.sort(g.choice(len(sim["ray_dirs"]), 2048, replace=False))
+    return scene, sim, sub
+
+
+def test_trace_parity_room_subset(et, ctx, room_small):
+    scene, sim, sub = room_small
+    dirs = sim["ray_dirs"][sub]
+    ref = O.trace(scene, sim, dirs=dirs)
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    info = sc.info()
+    print(f"room BVH: nodes {info.n_nodes} depth {info.depth} SAH {info.sah_cost:.1f} build {info.build_ms:.1f} ms")
+    s = et.Sim(sim, flags=et.ET_SPECULAR, ray_dirs=dirs)
+    P = et.trace(ctx, sc, s)
+    st = ctx.stats()
+    gpu = P.to_host()
+    cert = ref["certified"]
+    mism = compare_traces(gpu, ref, cert)
+    print(f"room subset: records gpu {st.records} oracle {len(ref['rtot'])}, certified {cert.mean():.4f}, mismatches {mism}")
+    assert mism == 0
+    assert st.stack_overflows == 0
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_synthesis_isolation_room(et, ctx, room_small, direct):
+    """32 receivers x 4096 bins; the oracle evaluates a seeded sample of 96 bins."""
+    scene, sim, sub = room_small
+    ref = O.trace(scene, sim, dirs=sim["ray_dirs"][sub[:1024]], certify=False)
+    flags = et.ET_SPECULAR | (et.ET_SYNTH_DIRECT if direct else 0)
+    s = et.Sim(sim, flags=flags)
+    P = et.Paths.from_records(ref)
+    H = et.synthesize(ctx, s, P).cpu().numpy()
+    bins = np.sort(W.rng(5).choice(sim["F"], 96, replace=False))
+    bins[0], bins[-1] = 0, sim["F"] - 1
+    H_ref = O.synth(ref, sim, bins=bins)
+    e = rel_l2(H[:, bins], H_ref)
+    print(f"room synthesis ({'direct' if direct else 'factorised'}): rel L2 {e:.3e} over {len(ref['rtot'])} records")
+    assert e <= TOL
+
+
+# ----------------------------------------------------------------------------- diffraction
+
+def test_diffraction_samples_match(et, ctx):
+    g = W.rng(31)
+    scene = W.room_geometry(g, n_boxes=30, n_cyl=30)
+    a_ref = W.median_triangle_area(scene)
+    sim = W.make_sim(emitter_pos=[1.0, 4.0, 1.2], emitter_rot=np.eye(3), rx_pos=[[1.0, 4.02, 1.2]],
+                     ray_dirs=np.zeros((0, 3)), max_bounces=1, f_lo=20e3, f_hi=100e3, F=256,
+                     refl_k=np.full((16, 8), 0.8), lobe_beta=np.full((16, 8), 0.1), diff_coef=np.full((16, 8), 0.2),
+                     diff_K=8192, diff_seed=1234, diff_tau=0.1, diff_max_incidence_deg=80.0, diff_cone_half_angle_deg=90.0)
+    _, C_ref = O.curvature(scene, a_ref)
+    ref = O.diffraction(scene, sim, C_ref)
+    sc = et.Scene(ctx, scene, area_ref=a_ref)
+    s = et.Sim(sim, flags=et.ET_DIFFRACTION)
+    P = et.trace(ctx, sc, s)
+    st = ctx.stats()
+    gpu = P.to_host()
+    assert st.diff_eligible == ref["n_elig"]
+    kept = np.nonzero(ref["keep"])[0]
+    # GPU records: kept samples in sample order, ray field = sample index
+    g_idx = gpu["ray"]
+    cert = ref["certified"]
+    g_set = set(g_idx.tolist())
+    flips = [k for k in range(len(cert)) if cert[k] and ((k in g_set) != bool(ref["keep"][k]))]
+    print(f"diffraction: eligible {st.diff_eligible}, kept gpu {len(g_idx)} oracle {len(kept)}, "
+          f"certified {cert.mean():.4f}, keep mismatches on certified {len(flips)}")
+    assert not flips
+    common = np.intersect1d(g_idx, kept)
+    pos = {k: i for i, k in enumerate(g_idx)}
+    for k in common:
+        i = pos[k]
+        assert gpu["tri"][i] == ref["tri"][k]
+        assert np.array_equal(gpu["p"][i], ref["o"][k])          # same FP64 operations: bit-equal
+        assert gpu["rtot"][i] == ref["r_src"][k]
+
+
+# ----------------------------------------------------------------------------- adjoint
+
+def test_adjoint_matches_oracle_gradient(et, ctx, tiny):
+    scene, sim, ref = tiny
+    sim = dict(sim)
+    sim["F"] = 512
+    g = W.rng(8)
+    hidden = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, 8)).astype(np.float32))
+    H_star = O.synth(ref, hidden)
+    H = O.synth(ref, sim)
+    gk_ref, gx_ref = O.grad(ref, sim, H - H_star)
+    import torch
+    s = et.Sim(sim, flags=et.ET_SPECULAR)
+    P = et.Paths.from_records(ref)
+    gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(H - H_star).to("cuda"))
+    gk, gx = gk.cpu().numpy(), gx.cpu().numpy()
+    ek, ex = rel_l2(gk, gk_ref), rel_l2(gx, gx_ref)
+    print(f"adjoint: rel err dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    assert ek <= TOL and ex <= TOL
+
+
+# ----------------------------------------------------------------------------- errors
+
+def test_invalid_arguments_report_status(et, ctx, tiny):
+    import ctypes
+    scene, sim, _ = tiny
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim)
+    bad = et.Sim(sim)
+    bad.desc.max_bounces = 0
+    with pytest.raises(et.EchoError) as e:
+        et.trace(ctx, sc, bad)
+    assert e.value.status == -1
+    P = et.Paths(4)
+    n = ctypes.c_size_t()
+    buf = et.Workspace().get(16)
+    rc = et.lib().et_trace(ctx.h, sc.h, ctypes.byref(s.desc), ctypes.c_void_p(buf.data_ptr()), 16, ctypes.byref(P.desc))
+    assert rc == -2                                            # workspace too small
+    # capacity: 4 records for 16384 rays -> deferred ET_E_CAPACITY
+    ws = et.Workspace()
+    et.trace(ctx, sc, s, paths=P, ws=ws)
+    with pytest.raises(et.EchoError) as e:
+        ctx.stats()
+    assert e.value.status == -3
+    assert P.count[0].item() > 4
