@@ -118,25 +118,34 @@ static int any_hit(v3 o, v3 d, const tri_t* tr, int64_t T, int64_t excl, double 
  */
 typedef struct { int cls; double t, et, cosn; } probe_t;  /* cls: 0 miss, 1 certain hit, 2 uncertain */
 
+/* Error model of the FP32 decision.  The sign of the edge function E_ab = d.((a-o)x(b-o))
+ * says on which side of the edge line the ray passes; E_ab / |d x (b - a)| is the signed
+ * distance between the ray and the edge line measured across the ray.  In FP32 that
+ * distance is perturbed by: rounding the FP64 origin (|do| <= u |o|_inf per component),
+ * rounding the direction (|dd| <= u, i.e. u |a - o| at the vertex), and the arithmetic of
+ * the test (differences a - o are exactly rounded, so relative to |a - o|; shear and
+ * products add a few more u |a - o|).  The vertices are FP32 inputs on both sides.  A
+ * decision is certain when the distance exceeds kappa * u * (max(|a-o|, |b-o|) + |o|_inf). */
 static probe_t probe(v3 o, v3 d, const tri_t* T, double kappa) {
   probe_t r;
   double eps = kappa * 0x1p-24;
-  double cm = fmax(1.0, fmax(ninf(o), T->cm));
+  double co = fmax(1.0, ninf(o));
   double dn = dot(T->n, d);
   double h = dot(T->n, sub(T->a, o));
   r.cosn = dn;
   if (dn != 0.0) {
     r.t = h / dn;
-    r.et = eps * (cm + fabs(r.t)) / fmax(fabs(dn), 1e-12);
+    r.et = eps * (co + fabs(r.t)) / fmax(fabs(dn), 1e-12);
   } else {
     r.t = INFINITY;
     r.et = INFINITY;
   }
   v3 A = sub(T->a, o), B = sub(T->b, o), C = sub(T->c, o);
   double la = norm(A), lb = norm(B), lc = norm(C);
+  double pab = norm(cross(d, sub(T->b, T->a))), pbc = norm(cross(d, sub(T->c, T->b))),
+         pca = norm(cross(d, sub(T->a, T->c)));
   double E[3] = {dot(d, cross(A, B)), dot(d, cross(B, C)), dot(d, cross(C, A))};
-  double bnd[3] = {eps * (la * lb + 2 * cm * (la + lb)), eps * (lb * lc + 2 * cm * (lb + lc)),
-                   eps * (lc * la + 2 * cm * (lc + la))};
+  double bnd[3] = {eps * (fmax(la, lb) + co) * pab, eps * (fmax(lb, lc) + co) * pbc, eps * (fmax(lc, la) + co) * pca};
   int pos = 0, neg = 0;
   for (int k = 0; k < 3; ++k) {
     if (E[k] > bnd[k]) ++pos;
@@ -158,7 +167,7 @@ static int closest_marginal(v3 o, v3 d, const tri_t* tr, int64_t T, int64_t excl
     probe_t ph = probe(o, d, &tr[h], kappa);
     if (ph.cls != 1) return 1;                     /* hit near an edge of its triangle */
     if (fabs(ph.cosn) < mu_g) return 1;            /* grazing incidence */
-    double et = eps * (fmax(1.0, fmax(ninf(o), tr[h].cm)) + t_star) / fmax(fabs(ph.cosn), 1e-12);
+    double et = eps * (fmax(1.0, ninf(o)) + t_star) / fmax(fabs(ph.cosn), 1e-12);
     if (t_star - et <= t_eps) return 1;            /* near the self-intersection threshold */
     hi_star = t_star + et;
   }
@@ -169,7 +178,7 @@ static int closest_marginal(v3 o, v3 d, const tri_t* tr, int64_t T, int64_t excl
       if (p.cls != 0 && fabs(p.cosn) < 1e-12) {
         /* line parallel to a plane it might touch: marginal if it runs within the bound */
         double hgt = fabs(dot(tr[j].n, sub(tr[j].a, o)));
-        if (hgt < eps * fmax(1.0, fmax(ninf(o), tr[j].cm))) return 1;
+        if (hgt < eps * fmax(1.0, ninf(o))) return 1;
       }
       continue;
     }
@@ -191,7 +200,7 @@ static int anyhit_marginal(v3 o, v3 d, const tri_t* tr, int64_t T, int64_t excl,
     if (p.cls == 0) continue;
     if (!isfinite(p.t)) {
       double hgt = fabs(dot(tr[j].n, sub(tr[j].a, o)));
-      if (hgt < eps * fmax(1.0, fmax(ninf(o), tr[j].cm))) return 1;
+      if (hgt < eps * fmax(1.0, ninf(o))) return 1;
       continue;
     }
     double lo = p.t - p.et, hi = p.t + p.et;
