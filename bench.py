@@ -1,0 +1,209 @@
+"""Benchmark of the echo-simulation hot path on one MI355X.
+
+Workload (room scene): a 10x8x3 m room with 100 boxes and 100 cylinders (193,212
+triangles, 16 materials x 8 bands), 2^20 rays over the frontal hemisphere, <= 4 reflection
+points per ray, 32 receivers in a 12 cm planar aperture, 4096 bins over 20-100 kHz, 65,536
+curvature-importance diffraction samples.  Seeded synthetic inputs (no dataset).
+
+One step = one et_simulate call: ray init, 4 bounces of closest-hit + line-of-sight
+traversal, diffraction sampling and filtering, synthesis of every record into the 32 x
+4096 complex spectra.  The scene (BVH, curvature) is built once before timing, like the
+paper's offline pre-processing.
+
+Printed: one JSON line.  value = closest-hit segments (ray-bounces, hits plus the final
+misses) per second of the whole step, in millions.  Extra keys give the tracing-stage and
+synthesis-stage throughputs (the metric's second half, G(record.receiver.bin)/s), the
+roofline of the dominant kernel and the FP64 oracle on the host cores as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays·bounces/s + G(hit·mic·bin)/s synthesis; batched fwd+adjoint vs plain"
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_F32_TFLOPS = 157.3
+SYNTH_FLOP_PER_TERM = 8          # one complex multiply-accumulate as real MFMA products
+NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 128
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rays", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=1024, help="rays of the oracle's bounded sample")
+    ap.add_argument("--profile-only", action="store_true", help="a few steps, no baselines (for rocprofv3)")
+    return ap.parse_args()
+
+
+def source_hash(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on the current source."""
+    f = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    e = d.get(kernel)
+    if not e:
+        return None
+    src = os.path.join(ROOT, "paper_2602_19652_amd", "csrc", e["source"])
+    if source_hash(src) != e["source_sha"]:
+        return None
+    return e["bytes_per_launch"]
+
+
+def cpu_baseline(scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_total: int):
+    """The oracle (FP64 brute force) on a bounded sample of the same workload, scaled to the
+    whole job: time per segment (trace, with the per-hit line-of-sight rays) and per term
+    (synthesis) measured on the sample, then the job's segment and term counts."""
+    import oracle as O
+    g = np.random.Generator(np.random.PCG64(4242))
+    sub = np.sort(g.choice(len(sim["ray_dirs"]), n_rays, replace=False))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    rec = O.trace(scene, sim, dirs=sim["ray_dirs"][sub], certify=False)
+    t1 = time.perf_counter()
+    bins = np.arange(0, F, 16, dtype=np.int32)        # 1/16 of the bins, all receivers
+    O.synth(rec, sim, bins=bins)
+    t2 = time.perf_counter()
+    seg = int(rec["nseg"].sum())
+    terms = len(rec["rtot"]) * M * len(bins)
+    t_seg = (t1 - t0) / max(seg, 1)
+    t_term = (t2 - t1) / max(terms, 1)
+    job_s = seg_total * t_seg + terms_total * t_term
+    return {"value": seg_total / job_s / 1e6, "unit": "Mrays·bounces/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_rays} seeded rays traced by brute force ({seg} segments, {t1 - t0:.1f} s) and their "
+                      f"{len(rec['rtot'])} records synthesised on every 16th bin ({terms:.3g} terms, {t2 - t1:.1f} s); "
+                      f"whole-job time extrapolated linearly in segments and terms",
+            "sec_per_segment": t_seg, "sec_per_term": t_term}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path does not shard across GPUs "
+              f"in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2602_19652_amd as et
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench needs the GPU"
+    torch.cuda.set_device(0)
+    scene, sim = W.room_scene(n_rays=args.rays)
+    ctx = et.Context(0)
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    info = sc.info()
+    s = et.Sim(sim)
+    P = et.Paths(s.capacity())
+    ws = et.Workspace()
+    out = torch.empty(s.M, s.F, 2, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        et.simulate(ctx, sc, s, paths=P, ws=ws, out=out)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        et.simulate(ctx, sc, s, paths=P, ws=ws, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    st = ctx.stats()
+    seg = st.segments
+    n_rec = st.records
+    terms = n_rec * s.M * s.F
+    if args.profile_only:
+        # calibration for hardware byte counters: one plain device copy of a known size
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": True, "ms_per_step": ms_step, "segments": seg, "records": n_rec,
+                          "calibration_copy_bytes": a.numel()}))
+        return
+
+    # stage timings on the same stream: tracing (with diffraction) and synthesis alone
+    reps = max(3, args.steps)
+    e0.record(stream)
+    for _ in range(reps):
+        et.trace(ctx, sc, s, paths=P, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_trace = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        et.synthesize(ctx, s, P, ws=ws, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_synth = e0.elapsed_time(e1) / reps
+    kern = ctx.stats().synth_kernel
+
+    # traversal work counters (separate counting pass, outside the timed region)
+    ctx.set_counting(True)
+    et.trace(ctx, sc, s, paths=P, ws=ws)
+    cnt = ctx.counters()
+    ctx.set_counting(False)
+    trav_bytes = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
+                  + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
+
+    synth_flops = terms * SYNTH_FLOP_PER_TERM
+    synth_tflops = synth_flops / (ms_synth * 1e-3) / 1e12
+    trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
+    if ms_synth >= ms_trace:
+        roof = {"kernel": "k_synth_mfma" if kern == 1 else "k_synth_direct", "bound": "mfma",
+                "achieved": synth_tflops, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
+                "frac": synth_tflops / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for("k_synth_mfma")}
+    else:
+        roof = {"kernel": "k_bounce", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false>")}
+    line = {
+        "metric": METRIC,
+        "value": seg / (ms_step * 1e-3) / 1e6,
+        "unit": "Mrays·bounces/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "room scene: 10x8x3 m room + 100 boxes + 100 cylinders (193,212 tris), 2^20 rays, "
+                               "<=4 reflection points, 32 mics, 4096 bins 20-100 kHz, 65,536 diffraction samples",
+                   "rays": s.desc.N, "triangles": info.T, "receivers": s.M, "bins": s.F, "max_bounces": s.desc.max_bounces,
+                   "diff_samples": s.desc.diff_K},
+        "segments": seg, "records": n_rec, "shadow_rays": st.shadow_rays,
+        "trace_ms": ms_trace, "trace_mrays_bounces_per_s": seg / (ms_trace * 1e-3) / 1e6,
+        "synth_ms": ms_synth, "synth_g_terms_per_s": terms / (ms_synth * 1e-3) / 1e9, "synth_kernel": kern,
+        "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
+        "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
+                      "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
+                      "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
+                      "algorithmic_bytes": trav_bytes, "effective_GBs": trace_gbs,
+                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, sim, args.cpu_rays, s.M, s.F, seg, terms)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
