@@ -131,7 +131,8 @@ def main():
     st = ctx.stats()
     seg = st.segments
     n_rec = st.records
-    terms = n_rec * s.M * s.F
+    n_vis = int((P.flags[:n_rec] & 1).sum().item())      # blocked records contribute nothing
+    terms = n_vis * s.M * s.F
     if args.profile_only:
         # calibration for hardware byte counters: one plain device copy of a known size
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
@@ -188,7 +189,7 @@ def main():
                                "<=4 reflection points, 32 mics, 4096 bins 20-100 kHz, 65,536 diffraction samples",
                    "rays": s.desc.N, "triangles": info.T, "receivers": s.M, "bins": s.F, "max_bounces": s.desc.max_bounces,
                    "diff_samples": s.desc.diff_K},
-        "segments": seg, "records": n_rec, "shadow_rays": st.shadow_rays,
+        "segments": seg, "records": n_rec, "visible_records": n_vis, "shadow_rays": st.shadow_rays,
         "trace_ms": ms_trace, "trace_mrays_bounces_per_s": seg / (ms_trace * 1e-3) / 1e6,
         "synth_ms": ms_synth, "synth_g_terms_per_s": terms / (ms_synth * 1e-3) / 1e9, "synth_kernel": kern,
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},

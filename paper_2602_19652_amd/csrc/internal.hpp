@@ -137,6 +137,7 @@ struct Ctl {
   int64_t diff_kept;         // kept diffraction samples
   int64_t cnt[6];            // traversal work counters (nodes/tris closest, nodes/tris any, rays c/a)
   int64_t n_rec;             // records to synthesise
+  int64_t n_vis;             // of which visible (compacted index list)
 };
 
 struct TraceWS {
@@ -182,6 +183,14 @@ struct SynthWS {
   double* gpart_x;           // [chunks][M][3]
   double* gpart_k;           // [chunks][Q][Bk]
   int32_t gchunks;
+  int64_t cap;               // record capacity
+  uint64_t* vflags;          // visible-record compaction: flags, offsets, index list, scan scratch
+  uint64_t* voffs;
+  int32_t* vidx;
+  void* vscan;
+  float* lk;                 // per (material, band): log2 k, log2(e)/(2 beta^2), log2 I_d
+  float* lc;
+  float* ld;
 };
 size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
 // returns 1 for the factorised MFMA kernel, 2 for the direct kernel

@@ -5,7 +5,9 @@
 //   H_m[k] += A_nmk exp(j 2 pi sigma f_k r / c)
 //   A_nmk = r^-p 10^(-(a0 + a1 f_k) r / 20) * I[b(k)] * D_m[bd(k)]
 //   I[b] = k_qb exp(-gamma^2 / (2 beta_qb^2)) (specular),  I_d,qb (diffraction)
-// where gamma is the angle between d' and the direction from p to x_m.
+// where gamma is the angle between d' and the direction from p to x_m.  Records whose
+// line-of-sight ray was blocked contribute nothing; a first pass compacts the indices of
+// the visible records so that no kernel spends work on the others.
 //
 // Precision: the receiver leg, total path and the delay in cycles at f_lo and per bin are
 // FP64 (the phase needs the path to ~1e-8 m at 100-200 kHz); sin/cos/exp2 and the
@@ -17,10 +19,12 @@
 //      A e^{j phi} = X[n,k1] * Y[n,k2],
 //      X = exp2(base + 64 k1 slope + band(k1)) e^{j 2 pi (c0 + 64 k1 cb)},
 //      Y = exp2(k2 slope) e^{j 2 pi k2 cb},
-//    whenever the material/directivity bands are constant over each run of 64 bins, so
+//    whenever the material/directivity bands are constant over runs of 512 bins, so
 //    H_m[k1, k2] = sum_n X[n,k1] Y[n,k2] is a complex matrix product contracting over the
-//    records.  It runs on the FP32 matrix cores (v_mfma_f32_16x16x4f32); only 128
-//    transcendental triples per (record, receiver) remain instead of one per bin.
+//    records.  It runs on the FP32 matrix cores (v_mfma_f32_16x16x4f32) as Gauss's three
+//    real products; X and Y themselves come from 32 exp2/sin/cos factors per (record,
+//    receiver) (a second 8 x 8 split), so only 32 transcendental triples remain of the 4096
+//    per (record, receiver) of a 4096-bin grid.
 //  * direct: one sin/cos/exp2 per (record, receiver, bin), any band layout.
 // Both write per-chunk partial spectra that a final kernel sums in a fixed order
 // (bit-reproducible results).
@@ -47,6 +51,11 @@ struct SynthArgs {
   const float* dcoef;
   const float* dir;
   int32_t P;               // record chunks
+  double kc0, kcb;         // sigma f_lo / c and sigma df / c: cycles per metre of path
+  double kbase, kslope;    // log2 absorption per metre at f_lo and per bin
+  const float* lk;         // [Q][Bk] log2 k
+  const float* lc;         // [Q][Bk] log2(e) / (2 beta^2)
+  const float* ld;         // [Q][Bk] log2 I_d
 };
 
 SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
@@ -62,6 +71,10 @@ SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
   a.refl_k = sim->refl_k; a.beta = sim->lobe_beta; a.dcoef = sim->diff_coef;
   a.dir = sim->directivity;
   a.P = P;
+  a.kc0 = (double)a.sigma * a.f_lo / a.c;
+  a.kcb = (double)a.sigma * a.df / a.c;
+  a.kbase = -(a.A0 + a.A1 * a.f_lo) / 20.0 * LOG2_10;
+  a.kslope = -a.A1 * a.df / 20.0 * LOG2_10;
   return a;
 }
 
@@ -125,13 +138,22 @@ __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t
   return true;
 }
 
-__device__ inline float band_log2(const SynthArgs& a, const Pair& q, int b) {
-  if (q.kind == 0) {
-    const float bt = a.beta[q.mat * a.Bk + b];
-    return log2f(a.refl_k[q.mat * a.Bk + b]) - q.gamma * q.gamma / (2.0f * bt * bt) * LOG2E_F;
-  }
-  return log2f(a.dcoef[q.mat * a.Bk + b]);
+// log2 of the band factor: k exp(-gamma^2 / (2 beta^2)) (specular) or I_d (diffraction)
+__device__ inline float band_log2_v(const SynthArgs& a, int kind, int mat, float gamma, int b) {
+  const int i = mat * a.Bk + b;
+  return kind == 0 ? a.lk[i] - gamma * gamma * a.lc[i] : a.ld[i];
 }
+
+__global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.Q * a.Bk) return;
+  const float bt = a.beta[i];
+  lk[i] = log2f(a.refl_k[i]);
+  lc[i] = LOG2E_F / (2.0f * bt * bt);
+  ld[i] = log2f(a.dcoef[i]);
+}
+
+__device__ inline float band_log2(const SynthArgs& a, const Pair& q, int b) { return band_log2_v(a, q.kind, q.mat, q.gamma, b); }
 
 // direction of arrival in the receiver frame: v = R_m^T (p - x_m) / l = -R_m^T u
 __device__ inline void arrival(const SynthArgs& a, const Pair& q, int m, float& vx, float& vy, float& vz) {
@@ -148,152 +170,232 @@ __device__ inline void arrival(const SynthArgs& a, const Pair& q, int m, float& 
 
 __device__ inline double frac(double x) { return x - floor(x); }
 
-__device__ inline void chunk_range(int64_t n_rec, int32_t P, int p, int64_t& lo, int64_t& hi) {
-  const int64_t per = (n_rec + P - 1) / P;
-  lo = std::min<int64_t>((int64_t)p * per, n_rec);
-  hi = std::min<int64_t>(lo + per, n_rec);
+__device__ inline void chunk_range(int64_t n, int32_t P, int p, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + P - 1) / P;
+  lo = std::min<int64_t>((int64_t)p * per, n);
+  hi = std::min<int64_t>(lo + per, n);
 }
+
+// ------------------------------------------------------------------ visible-record list
+
+__global__ void k_vis_flags(et_paths P, const Ctl* ctl, uint64_t* __restrict__ flags) {
+  const int64_t n = ctl->n_rec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = (P.flags[i] & 1) ? 1ull : 0ull;
+}
+
+__global__ void k_vis_scatter(const uint64_t* __restrict__ flags, const uint64_t* __restrict__ offs, const Ctl* ctl,
+                              int32_t* __restrict__ idx) {
+  const int64_t n = ctl->n_rec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (flags[i]) idx[offs[i]] = (int32_t)i;
+}
+
+__global__ void k_vis_count(Ctl* ctl) { ctl->n_vis = (int64_t)ctl->tot[3]; }
 
 // ------------------------------------------------------------------ factorised MFMA kernel
 
-constexpr int K2 = 64;        // bins per inner run
+constexpr int K2 = 64;        // bins per inner run (k = 64 k1 + k2)
 constexpr int KT1 = 64;       // outer indices per workgroup
-constexpr int RB = 32;        // records per batch (contraction depth per batch)
+constexpr int RB = 32;        // records per stage (contraction depth per stage)
+constexpr int RPW = RB / 4;   // records per wave and stage
 constexpr int XS = 80;        // LDS row stride (floats): 16-lane groups land on distinct banks
-constexpr int BMAX = 16;      // band tables per record held in LDS
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-struct MfmaLds {
-  float X[2][RB][XS];         // X real / imag, [record][k1]
-  float Y[2][RB][XS];         // Y real / imag, [record][k2]
-  double c0[RB], cb[RB];
-  float base[RB], slope[RB];
-  float band[RB][BMAX];
-  float dirl[RB][BMAX];
-  int bk[KT1], bd[KT1];
+__device__ inline uint32_t q32(double cyc) {   // fraction of a cycle in Q0.32 (mod 2^32)
+  return (uint32_t)((cyc - floor(cyc)) * 4294967296.0);   // in [0, 2^32]; the conversion saturates
+}
+
+// Lean per-(record, receiver) setup: FP64 only for the receiver leg, the path and the delay
+// reductions.  Phases of the generated values are integer phase accumulators in Q0.32
+// (a32 + k1 bx32 for X, k2 by32 for Y), exact mod 1 up to the quantisation of the steps
+// (<= 128 * 2^-33 cycles).
+struct PairLean {
+  uint32_t a32, bx32, by32;
+  float base, slope, gamma;
+  float vx, vy, vz;
+  int mat, kind;
 };
 
-__global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, const Ctl* ctl, float* __restrict__ part) {
-  __shared__ __align__(16) char smem[sizeof(MfmaLds) > 2 * 64 * 64 * 4 ? sizeof(MfmaLds) : 2 * 64 * 64 * 4];
-  MfmaLds& L = *reinterpret_cast<MfmaLds*>(smem);
+__device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const int32_t* __restrict__ idx, int64_t e,
+                                 int64_t hi, int m, PairLean& q) {
+  q.a32 = q.bx32 = q.by32 = 0;
+  q.base = -INFINITY;
+  q.slope = q.gamma = q.vx = q.vy = q.vz = 0.f;
+  q.mat = q.kind = 0;
+  if (e >= hi) return;
+  const int64_t n = idx[e];
+  const uint8_t fl = P.flags[n];
+  if (!(fl & 1)) return;
+  q.kind = (fl >> 1) & 1;
+  const double wx = a.rx_pos[3 * m] - P.p[3 * n], wy = a.rx_pos[3 * m + 1] - P.p[3 * n + 1],
+               wz = a.rx_pos[3 * m + 2] - P.p[3 * n + 2];
+  const double l = sqrt(wx * wx + wy * wy + wz * wz);
+  const double r = P.rtot[n] + l;                          // emitter -> point -> receiver
+  const double cb = r * a.kcb;
+  q.a32 = q32(r * a.kc0);
+  q.bx32 = q32((double)K2 * cb);
+  q.by32 = q32(cb);
+  q.base = -(float)a.ps * log2f((float)r) + (float)(r * a.kbase);
+  q.slope = (float)(r * a.kslope);
+  q.mat = P.mat[n];
+  const double il = 1.0 / l;
+  const float ux = (float)(wx * il), uy = (float)(wy * il), uz = (float)(wz * il);
+  if (q.kind == 0) {
+    const float dx = P.dout[3 * n], dy = P.dout[3 * n + 1], dz = P.dout[3 * n + 2];
+    const float cx = dy * uz - dz * uy, cy = dz * ux - dx * uz, cz = dx * uy - dy * ux;
+    q.gamma = atan2f(sqrtf(cx * cx + cy * cy + cz * cz), dx * ux + dy * uy + dz * uz);
+  }
+  if (a.Bd) {   // direction of arrival in the receiver frame: -R_m^T u
+    if (a.rx_rot) {
+      const double* R = a.rx_rot + 9 * m;
+      q.vx = -(float)(R[0] * ux + R[3] * uy + R[6] * uz);
+      q.vy = -(float)(R[1] * ux + R[4] * uy + R[7] * uz);
+      q.vz = -(float)(R[2] * ux + R[5] * uy + R[8] * uz);
+    } else {
+      q.vx = -ux; q.vy = -uy; q.vz = -uz;
+    }
+  }
+}
+
+// The contraction runs as Gauss's three real products: with X = Xr + j Xi, Y = Yr + j Yi,
+//   A0 = Xr + Xi, A1 = Xr, A2 = Xi;  B0 = Yr, B1 = Yi - Yr, B2 = Yr + Yi,
+//   Re H = A0.B0 - A2.B2,  Im H = A0.B0 + A1.B1.
+// The LDS holds Xr, Xi, Yr, Yi; the sums are formed when the operands are loaded.
+struct GaussBuf {
+  float X[2][RB][XS];         // [re/im][record][k1]
+  float Y[2][RB][XS];         // [re/im][record][k2]
+};
+
+// Two-level generation: X[8a+b] = Xa[a] Xb[b] and Y[8a+b] = Ya[a] Yb[b], with the material
+// and directivity bands folded into Xa (the bands are constant over each group of 8 outer
+// indices = 512 bins).  32 exp2/sin/cos factors per record instead of 128 values.
+struct WaveScratch {
+  float2 xa[RPW][8], xb[RPW][8], ya[RPW][8], yb[RPW][8];
+};
+
+__device__ inline float2 cexp2(float lg, float rev) {
+  const float amp = exp2f(lg);
+  return make_float2(amp * __builtin_amdgcn_cosf(rev), amp * __builtin_amdgcn_sinf(rev));
+}
+__device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
+__device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
+                                int row0, GaussBuf& B, WaveScratch& W) {
+  const int r = lane >> 3, j = lane & 7;
+  const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
+  const float g_r = __shfl(q.gamma, src);
+  const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
+  const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
+  const uint32_t a_r = (uint32_t)__shfl((int)q.a32, src), bx_r = (uint32_t)__shfl((int)q.bx32, src),
+                 by_r = (uint32_t)__shfl((int)q.by32, src);
+  const bool ok = base_r != -INFINITY;
+  const uint32_t k1a = (uint32_t)(k1_0 + 8 * j);   // first outer index of group j
+  const int kga = (int)(k1a * K2);
+  float lg = base_r + (float)kga * slope_r;
+  if (ok) {
+    lg += band_log2_v(a, k_r, m_r, g_r, (int)(((int64_t)kga * a.Bk) / a.F));
+    if (a.Bd) {
+      const float x = __shfl(q.vx, src), y = __shfl(q.vy, src), z = __shfl(q.vz, src);
+      const int bd = (int)(((int64_t)kga * a.Bd) / a.F);
+      const float* tab = a.dir + ((size_t)m * a.Bd + bd) * a.El * a.Az;
+      lg += log2f(dir_gain(tab, a.El, a.Az, x, y, z));
+    }
+  }
+  const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
+  const float2 z0 = make_float2(0.f, 0.f);
+  W.xa[r][j] = ok && 8 * j < nk1 ? cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S) : z0;
+  W.xb[r][j] = ok ? cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S) : z0;
+  W.ya[r][j] = ok ? cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S) : z0;
+  W.yb[r][j] = ok ? cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S) : z0;
+  // the factors are read back by other lanes of this wave only
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int ka = lane >> 3, kb = lane & 7;
+  const bool xon = lane < nk1;
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) {
+    float2 x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
+    const float2 y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
+    if (!xon) x = z0;
+    B.X[0][row0 + rr][lane] = x.x;
+    B.X[1][row0 + rr][lane] = x.y;
+    B.Y[0][row0 + rr][lane] = y.x;
+    B.Y[1][row0 + rr][lane] = y.y;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Workgroup = (record chunk p, receiver m, 64 outer indices).  Every 8 stages each wave sets
+// up 64 records (one per lane); every stage each wave generates 8 of them, then each wave
+// contracts all 32 records of the stage into its 32 x 32 block of (k1, k2) on the matrix
+// cores.  Three workgroups share a CU, so one's generation hides another's latency.
+__global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
+                                                    const Ctl* ctl, float* __restrict__ part) {
+  __shared__ __align__(16) GaussBuf buf;
+  __shared__ WaveScratch wscr[4];
   const int p = blockIdx.x, m = blockIdx.y, k1t = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = a.F / K2;
   const int k1_0 = k1t * KT1;
   const int nk1 = min(KT1, K1 - k1_0);
   int64_t lo, hi;
-  chunk_range(ctl->n_rec, a.P, p, lo, hi);
-  if (tid < KT1) {
-    const int64_t k = (int64_t)(k1_0 + tid) * K2;
-    L.bk[tid] = (int)((k * a.Bk) / a.F);
-    L.bd[tid] = a.Bd ? (int)((k * a.Bd) / a.F) : 0;
-  }
-  floatx4 acc[4][4];
+  chunk_range(ctl->n_vis, a.P, p, lo, hi);
+  const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
+  const int h1 = wv >> 1, h2 = wv & 1;                        // this wave's 32 x 32 block of (k1, k2)
+  floatx4 acc[3][2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // quadrant of this wave: A from X real (waves 0,1) or imag (2,3); B from Y real (0,2) or imag (1,3)
-  const int xa = wv >> 1, yb = wv & 1;
-
-  for (int64_t n0 = lo; n0 < hi; n0 += RB) {
-    __syncthreads();   // previous batch fully consumed
-    if (tid < RB) {
-      const int64_t n = n0 + tid;
-      Pair q;
-      bool ok = n < hi && pair_setup(a, P, n, m, q);
-      if (ok) {
-        L.c0[tid] = q.c0;
-        L.cb[tid] = q.cb;
-        L.base[tid] = q.base;
-        L.slope[tid] = q.slope;
-        for (int b = 0; b < a.Bk; ++b) L.band[tid][b] = band_log2(a, q, b);
-        if (a.Bd) {
-          float vx, vy, vz;
-          arrival(a, q, m, vx, vy, vz);
-          const float* tab = a.dir + (size_t)m * a.Bd * a.El * a.Az;
-          for (int b = 0; b < a.Bd; ++b) L.dirl[tid][b] = log2f(dir_gain(tab + (size_t)b * a.El * a.Az, a.El, a.Az, vx, vy, vz));
-        }
-      } else {
-        L.c0[tid] = 0.0;
-        L.cb[tid] = 0.0;
-        L.base[tid] = -INFINITY;
-        L.slope[tid] = 0.f;
-        for (int b = 0; b < a.Bk; ++b) L.band[tid][b] = 0.f;
-        for (int b = 0; b < a.Bd; ++b) L.dirl[tid][b] = 0.f;
-      }
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[t][i][jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+  PairLean q;
+  for (int64_t s = 0; s < nst; ++s) {
+    const int t = (int)(s & 7);
+    // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
+    if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, buf, wscr[wv]);
     __syncthreads();
-    // generate X[n][k1] and Y[n][k2] for the batch: 2 * RB * 64 values, 16 per thread
-#pragma unroll 4
-    for (int e = tid; e < 2 * RB * 64; e += 256) {
-      const int isY = e >= RB * 64;
-      const int ee = isY ? e - RB * 64 : e;
-      const int r = ee >> 6, k = ee & 63;
-      float amp, rev;
-      if (!isY) {
-        const int kg = (k1_0 + k) * K2;
-        const double cyc = L.c0[r] + (double)kg * L.cb[r];
-        rev = (float)frac(cyc);
-        float lg = L.base[r] + (float)kg * L.slope[r] + L.band[r][L.bk[k]];
-        if (a.Bd) lg += L.dirl[r][L.bd[k]];
-        amp = (k < nk1) ? exp2f(lg) : 0.f;
-      } else {
-        rev = (float)frac((double)k * L.cb[r]);
-        amp = exp2f((float)k * L.slope[r]);
-        if (L.base[r] == -INFINITY) amp = 0.f;
-      }
-      const float cr = __builtin_amdgcn_cosf(rev) * amp, ci = __builtin_amdgcn_sinf(rev) * amp;
-      if (!isY) { L.X[0][r][k] = cr; L.X[1][r][k] = ci; }
-      else { L.Y[0][r][k] = cr; L.Y[1][r][k] = ci; }
-    }
-    __syncthreads();
-    // contraction over the batch's records on the matrix cores
 #pragma unroll
     for (int kk = 0; kk < RB; kk += 4) {
       const int rr = kk + (lane >> 4), cc = lane & 15;
-      float av[4], bv[4];
+      float av[3][2], bv[3][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = L.X[xa][rr][i * 16 + cc];
+      for (int i = 0; i < 2; ++i) {
+        const float xr = buf.X[0][rr][h1 * 32 + i * 16 + cc], xi = buf.X[1][rr][h1 * 32 + i * 16 + cc];
+        const float yr = buf.Y[0][rr][h2 * 32 + i * 16 + cc], yi = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
+        av[0][i] = xr + xi; av[1][i] = xr; av[2][i] = xi;
+        bv[0][i] = yr; bv[1][i] = yi - yr; bv[2][i] = yr + yi;
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = L.Y[yb][rr][j * 16 + cc];
+      for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int jj = 0; jj < 2; ++jj)
+            acc[tt][i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt][i], bv[tt][jj], acc[tt][i][jj], 0, 0, 0);
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // combine quadrants: Hr = XrYr - XiYi (waves 0, 3), Hi = XrYi + XiYr (waves 1, 2)
-  float* sh = reinterpret_cast<float*>(smem);   // [2][64][64]: waves 3 and 2 deposit theirs
-  if (wv >= 2) {
-    float* dst = sh + (wv == 3 ? 0 : 64 * 64);
+  // accumulator (i, jj, v) of lane l holds row k1 = 16 i + 4 (l / 16) + v, column k2 = 16 jj + l % 16
+  float* out = part + (((size_t)p * a.M + m) * a.F) * 2;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(i * 16 + (lane >> 4) * 4 + v) * 64 + j * 16 + (lane & 15)] = acc[i][j][v];
-  }
-  __syncthreads();
-  if (wv < 2) {
-    const float* src = sh + (wv == 0 ? 0 : 64 * 64);
-    const float sgn = wv == 0 ? -1.f : 1.f;
-    float* out = part + (((size_t)p * a.M + m) * a.F) * 2;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int k1 = i * 16 + (lane >> 4) * 4 + v, k2 = j * 16 + (lane & 15);
-          if (k1 < nk1) {
-            const float val = acc[i][j][v] + sgn * src[k1 * 64 + k2];
-            out[(size_t)((k1_0 + k1) * K2 + k2) * 2 + wv] = val;
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int k1 = h1 * 32 + i * 16 + (lane >> 4) * 4 + v, k2 = h2 * 32 + jj * 16 + (lane & 15);
+        if (k1 < nk1) {
+          const size_t o = (size_t)((k1_0 + k1) * K2 + k2) * 2;
+          out[o] = acc[0][i][jj][v] - acc[2][i][jj][v];
+          out[o + 1] = acc[0][i][jj][v] + acc[1][i][jj][v];
         }
-  }
+      }
 }
 
 // ------------------------------------------------------------------ direct kernel
@@ -311,13 +413,14 @@ struct DirectLds {
   float dirl[DRB][DBMAX];
 };
 
-__global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a, et_paths P, const Ctl* ctl, float* __restrict__ part) {
+__global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
+                                                     const Ctl* ctl, float* __restrict__ part) {
   __shared__ DirectLds L;
   const int p = blockIdx.x, m = blockIdx.y;
   const int tid = threadIdx.x;
   const int kbase = blockIdx.z * DTILE + tid * DPT;
   int64_t lo, hi;
-  chunk_range(ctl->n_rec, a.P, p, lo, hi);
+  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   int bk[DPT], bd[DPT];
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
@@ -331,9 +434,9 @@ __global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a, et_paths P, co
   for (int64_t n0 = lo; n0 < hi; n0 += DRB) {
     __syncthreads();
     if (tid < DRB) {
-      const int64_t n = n0 + tid;
+      const int64_t e = n0 + tid;
       Pair q;
-      if (n < hi && pair_setup(a, P, n, m, q)) {
+      if (e < hi && pair_setup(a, P, idx[e], m, q)) {
         // integer phase accumulator (Q0.32 cycles): phase_k = a32 + k b32 mod 2^32
         L.a32[tid] = (uint32_t)(uint64_t)llrint(frac(q.c0) * 4294967296.0);
         L.b32[tid] = (uint32_t)(uint64_t)llrint(frac(q.cb) * 4294967296.0);
@@ -392,9 +495,10 @@ __global__ void k_reduce_partials(const float* __restrict__ part, int32_t P, int
 constexpr int GB = 256;
 constexpr int GANCHOR = 32;   // bins between exact re-anchoring of the rotation recurrence
 
-__global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const Ctl* ctl, const float* __restrict__ g,
+__global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
+                                                 const Ctl* ctl, const float* __restrict__ g,
                                                  double* __restrict__ gpx, double* __restrict__ gpk) {
-  extern __shared__ float2 gl[];   // conj-free copy of dL/dH* for this receiver, [F]
+  extern __shared__ float2 gl[];   // dL/dconj(H) of this receiver, [F]
   __shared__ double red[GB];
   __shared__ double kval[16][GB];
   __shared__ int kmat[GB];
@@ -403,18 +507,20 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const
   for (int k = tid; k < a.F; k += GB) gl[k] = make_float2(g[((size_t)m * a.F + k) * 2], g[((size_t)m * a.F + k) * 2 + 1]);
   for (int i = tid; i < a.Q * a.Bk; i += GB) kacc[i] = 0.0;
   int64_t lo, hi;
-  chunk_range(ctl->n_rec, a.P, p, lo, hi);
+  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   double gx0 = 0, gx1 = 0, gx2 = 0;
   const double ln10 = 2.30258509299404568402;
   __syncthreads();
   for (int64_t n0 = lo; n0 < hi; n0 += GB) {
-    const int64_t n = n0 + tid;
+    const int64_t e = n0 + tid;
     double sb[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) sb[b] = 0.0;
     int mat = -1;
     Pair q;
-    if (n < hi && pair_setup(a, P, n, m, q)) {
+    int64_t n = -1;
+    if (e < hi) n = idx[e];
+    if (n >= 0 && pair_setup(a, P, n, m, q)) {
       mat = q.kind == 0 ? q.mat : -1;
       // step of the rotation recurrence: exp2(slope) e^{j 2 pi cb}
       const float wrev = (float)frac(q.cb);
@@ -539,24 +645,64 @@ __global__ void k_bwd_reduce(const double* __restrict__ gpx, const double* __res
 inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 int choose_P(const et_sim_desc* sim, int64_t cap, bool mfma) {
-  // enough workgroups to fill 256 CUs several times over, records per chunk >= a few batches
+  // about four workgroups per CU over the launch (three run at a time), chunk count a
+  // multiple of 8 so that every receiver's workgroups of one chunk share an XCD's L2
   const int64_t tiles = mfma ? (int64_t)sim->M * std::max<int64_t>(1, (sim->F / K2 + KT1 - 1) / KT1)
                              : (int64_t)sim->M * ((sim->F + DTILE - 1) / DTILE);
-  int64_t P = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-  P = std::min<int64_t>(P, std::max<int64_t>(1, cap / 256));
+  const int64_t target = mfma ? 1024 : 2048;
+  int64_t P = std::max<int64_t>(1, (target + tiles - 1) / tiles);
+  if (P >= 8) P = (P + 7) / 8 * 8;
+  P = std::min<int64_t>(P, std::max<int64_t>(1, cap / 64));
   return (int)std::min<int64_t>(P, 256);
+}
+
+size_t vis_ws(int64_t cap, char* base, size_t off, uint64_t** fl, uint64_t** of, int32_t** idx, void** tmp) {
+  auto take = [&](size_t b) -> void* { void* p = base ? (void*)(base + off) : nullptr; off += al(b); return p; };
+  *fl = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap);
+  *of = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap);
+  *idx = (int32_t*)take(sizeof(int32_t) * (size_t)cap);
+  *tmp = take(scan_temp_bytes(cap));
+  return off;
+}
+
+void build_tables(SynthArgs& a, const SynthWS& ws, hipStream_t s) {
+  a.lk = ws.lk;
+  a.lc = ws.lc;
+  a.ld = ws.ld;
+  const int n = a.Q * a.Bk;
+  k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld);
+}
+
+size_t table_ws(const et_sim_desc* sim, char* base, size_t off, SynthWS& w) {
+  const size_t n = (size_t)sim->Q * sim->Bk;
+  w.lk = (float*)(base ? base + off : nullptr);
+  off += al(sizeof(float) * n);
+  w.lc = (float*)(base ? base + off : nullptr);
+  off += al(sizeof(float) * n);
+  w.ld = (float*)(base ? base + off : nullptr);
+  off += al(sizeof(float) * n);
+  return off;
+}
+
+void build_vis(const et_paths& P, const SynthWS& ws, int64_t cap, Ctl* ctl, hipStream_t s) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 255) / 256, 4096));
+  k_vis_flags<<<nb, 256, 0, s>>>(P, ctl, ws.vflags);
+  scan_exclusive_u64(ws.vflags, ws.voffs, 0, &ctl->n_rec, cap, &ctl->tot[3], ws.vscan, s);
+  k_vis_scatter<<<nb, 256, 0, s>>>(ws.vflags, ws.voffs, ctl, ws.vidx);
+  k_vis_count<<<1, 1, 0, s>>>(ctl);
+  ET_HIP(hipGetLastError());
 }
 
 }  // namespace
 
 bool synth_factorised_ok(const et_sim_desc* sim) {
+  // needs k = 64 k1 + k2 and material / directivity bands constant over each group of 8
+  // outer indices (512 bins), where the two-level generation folds them into one factor
   if (sim->flags & ET_SYNTH_DIRECT) return false;
   if (sim->F < K2 || sim->F % K2) return false;
-  if (sim->Bk > BMAX) return false;
-  if (sim->directivity && sim->Bd > BMAX) return false;
-  const int K1 = sim->F / K2;
-  for (int k1 = 0; k1 < K1; ++k1) {
-    const int64_t ka = (int64_t)k1 * K2, kb = ka + K2 - 1;
+  const int64_t G = 8 * K2;
+  for (int64_t ka = 0; ka < sim->F; ka += G) {
+    const int64_t kb = std::min<int64_t>(ka + G, sim->F) - 1;
     if ((ka * sim->Bk) / sim->F != (kb * sim->Bk) / sim->F) return false;
     if (sim->directivity && (ka * sim->Bd) / sim->F != (kb * sim->Bd) / sim->F) return false;
   }
@@ -564,13 +710,17 @@ bool synth_factorised_ok(const et_sim_desc* sim) {
 }
 
 size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
+  cap = std::max<int64_t>(cap, 1);
   const bool mf = synth_factorised_ok(sim);
   const int P = choose_P(sim, cap, mf);
   size_t off = 0;
   SynthWS w{};
   w.P = P;
+  w.cap = cap;
   w.partial = (float*)(base ? base + off : nullptr);
   off += al(sizeof(float) * 2 * (size_t)P * sim->M * sim->F);
+  off = vis_ws(cap, base, off, &w.vflags, &w.voffs, &w.vidx, &w.vscan);
+  off = table_ws(sim, base, off, w);
   if (ws) *ws = w;
   return off;
 }
@@ -579,13 +729,15 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   const bool mf = synth_factorised_ok(sim);
   SynthArgs a = make_args(sim, ws.P);
   const et_paths P = *paths;
+  build_vis(P, ws, ws.cap, ctl, s);
+  build_tables(a, ws, s);
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(ws.P, sim->M, (K1 + KT1 - 1) / KT1);
-    k_synth_mfma<<<grid, 256, 0, s>>>(a, P, ctl, ws.partial);
+    k_synth_mfma<<<grid, 256, 0, s>>>(a, P, ws.vidx, ctl, ws.partial);
   } else {
     dim3 grid(ws.P, sim->M, (sim->F + DTILE - 1) / DTILE);
-    k_synth_direct<<<grid, DB, 0, s>>>(a, P, ctl, ws.partial);
+    k_synth_direct<<<grid, DB, 0, s>>>(a, P, ws.vidx, ctl, ws.partial);
   }
   const int64_t MF2 = (int64_t)sim->M * sim->F * 2;
   k_reduce_partials<<<(unsigned)std::min<int64_t>((MF2 + 255) / 256, 4096), 256, 0, s>>>(ws.partial, ws.P, MF2, spectra);
@@ -594,6 +746,7 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
 }
 
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
+  cap = std::max<int64_t>(cap, 1);
   const int64_t tiles = sim->M;
   int64_t P = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
   P = std::min<int64_t>(P, std::max<int64_t>(1, (cap + GB - 1) / GB));
@@ -601,10 +754,13 @@ size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, Synt
   size_t off = 0;
   SynthWS w{};
   w.gchunks = (int)P;
+  w.cap = cap;
   w.gpart_x = (double*)(base ? base + off : nullptr);
   off += al(sizeof(double) * 3 * (size_t)P * sim->M);
   w.gpart_k = (double*)(base ? base + off : nullptr);
   off += al(sizeof(double) * (size_t)P * sim->M * sim->Q * sim->Bk);
+  off = vis_ws(cap, base, off, &w.vflags, &w.voffs, &w.vidx, &w.vscan);
+  off = table_ws(sim, base, off, w);
   if (ws) *ws = w;
   return off;
 }
@@ -613,9 +769,11 @@ void synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* g
                    Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s) {
   SynthArgs a = make_args(sim, ws.gchunks);
   const et_paths P = *paths;
+  build_vis(P, ws, ws.cap, ctl, s);
+  build_tables(a, ws, s);
   dim3 grid(ws.gchunks, sim->M);
   const size_t shm = sizeof(float2) * (size_t)sim->F;
-  k_synth_bwd<<<grid, GB, shm, s>>>(a, P, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+  k_synth_bwd<<<grid, GB, shm, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
   const int QB = sim->Q * sim->Bk;
   const int n = std::max(QB, sim->M * 3);
   k_bwd_reduce<<<(n + 255) / 256, 256, 0, s>>>(ws.gpart_x, ws.gpart_k, ws.gchunks, sim->M, QB, grad_k, grad_rx);

@@ -111,6 +111,12 @@ def test_trace_parity_tiny(et, ctx, tiny):
 def test_synthesis_isolation_tiny(et, ctx, tiny, direct):
     """GPU synthesis of the oracle's own records vs the oracle's spectra."""
     scene, sim, ref = tiny
+    if not direct:
+        # the factorised kernel needs bands constant over 512-bin runs: 2 bands over 1024 bins
+        g = W.rng(12)
+        sim = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, 2)).astype(np.float32),
+                   lobe_beta=g.uniform(0.05, 0.3, (1, 2)).astype(np.float32),
+                   diff_coef=np.full((1, 2), 0.1, np.float32))
     flags = et.ET_SPECULAR | (et.ET_SYNTH_DIRECT if direct else 0)
     s = et.Sim(sim, flags=flags)
     P = et.Paths.from_records(ref)
