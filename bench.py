@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=1024, help="rays of the oracle's bounded sample")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baselines (for rocprofv3)")
+    ap.add_argument("--batch-poses", type=int, default=256, help="poses of the batch leg (0 with 0 scenes skips it)")
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--batch-rays", type=int, default=1 << 18)
     return ap.parse_args()
 
 
@@ -203,7 +206,73 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, sim, args.cpu_rays, s.M, s.F, seg, terms)
+    if args.batch_poses + args.batch_scenes > 0:
+        del P, ws
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(ctx, args)
     print(json.dumps(line))
+
+
+def batched_leg(ctx, args):
+    """Batch workload: poses along a spline through the room plus uneven independent scenes
+    (2^18 rays, <= 4 reflection points, 8 receivers, 2048 bins each).  Jobs per second of
+    (a) separate single-pose forward calls, (b) one batched forward call, (c) one batched
+    forward + adjoint call (seeded synthetic dL/dconj(H) per job), (d) (c) replayed from a
+    captured HIP graph.  The ratio asked for is (c) / (a)."""
+    import torch
+    import paper_2602_19652_amd as et
+    import workloads as W
+    t0 = time.perf_counter()
+    b = W.batched_workload(n_poses=args.batch_poses, n_scenes=args.batch_scenes, n_rays=args.batch_rays)
+    gen_s = time.perf_counter() - t0
+    scenes = [et.Scene(ctx, sc) for sc in b.scenes]
+    sims = [et.Sim(j.sim, flags=et.ET_SPECULAR) for j in b.jobs]
+    J = len(b.jobs)
+    ws = et.Workspace()
+    paths = et.Paths(max(s.capacity() for s in sims))
+    out = torch.empty(sims[0].M, sims[0].F, 2, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def plain():
+        for i, j in enumerate(b.jobs):
+            et.simulate(ctx, scenes[j.scene_index], sims[i], paths=paths, ws=ws, out=out)
+    ms_plain = timed(plain, 2)
+    batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+    g = torch.Generator(device="cuda").manual_seed(1004)
+    grad = torch.randn(J, sims[0].M, sims[0].F, dtype=torch.complex64, device="cuda", generator=g) * 1e-3
+    ms_fwd = timed(lambda: batch.run(), 2)
+    ms_fwd_adj = timed(lambda: batch.run(grad_spectra=grad), 2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        batch.run(grad_spectra=grad, graph=True)          # capture
+        torch.cuda.synchronize()
+        e0.record(side)
+        for _ in range(2):
+            batch.run(grad_spectra=grad, graph=True)
+        e1.record(side)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / 2
+    st = ctx.stats()
+    jobs_s = lambda ms: J / (ms * 1e-3)
+    return {"jobs": J, "poses": args.batch_poses, "scenes": args.batch_scenes, "rays_per_job": args.batch_rays,
+            "receivers": sims[0].M, "bins": sims[0].F, "scene_triangles": [int(len(sc["tris"])) for sc in b.scenes],
+            "plain_fwd_ms": ms_plain, "batched_fwd_ms": ms_fwd, "batched_fwd_adj_ms": ms_fwd_adj,
+            "batched_fwd_adj_graph_ms": ms_graph,
+            "plain_fwd_jobs_per_s": jobs_s(ms_plain), "batched_fwd_jobs_per_s": jobs_s(ms_fwd),
+            "batched_fwd_adj_jobs_per_s": jobs_s(ms_fwd_adj), "batched_fwd_adj_graph_jobs_per_s": jobs_s(ms_graph),
+            "ratio_batched_fwd_adj_vs_plain_fwd": ms_plain / ms_fwd_adj,
+            "ratio_graph_fwd_adj_vs_plain_fwd": ms_plain / ms_graph, "input_generation_s": gen_s}
 
 
 if __name__ == "__main__":

@@ -13,8 +13,9 @@
  *    et_last_error() gives a message for the last failing call on a context.
  *  - Pointers documented as "device" are HIP device pointers (e.g. torch CUDA tensors on
  *    ROCm); "host" pointers are read during the call only.  The caller owns every buffer:
- *    scene blob, scratch, workspace, inputs and outputs.  The library allocates no
- *    device memory.
+ *    scene blob, scratch, workspace, inputs and outputs.  Apart from one small control
+ *    block per context (counters and error word, allocated by et_create, freed by
+ *    et_destroy) the library allocates no device memory.
  *  - Calls enqueue work on the context's stream and return; outputs are valid once the
  *    stream has completed the work (the Python binding uses torch's current stream).
  *    et_get_stats() synchronises the stream.
@@ -127,9 +128,11 @@ typedef struct {
   double spreading_p;           /* spreading L_geo = r^-p (p = 2 in the paper) */
   int32_t phase_sign;           /* +1: exp(+j 2 pi f r / c) as printed in Eq. (4); -1 conjugates */
   int32_t Q, Bk;                /* materials x frequency bands; band of bin k is floor(k Bk / F) */
-  const float* refl_k;          /* device [Q][Bk] reflection magnitude k (Eq. 2) */
-  const float* lobe_beta;       /* device [Q][Bk] lobe opening angle beta, radians (Eq. 2) */
-  const float* diff_coef;       /* device [Q][Bk] diffraction coefficient I_d (Eq. 7) */
+  const float* refl_k;          /* device [Q][Bk] reflection magnitude k (Eq. 2), >= 0; the kernels
+                                   take log2 k, so a negative entry gives NaN spectra (device data
+                                   are not inspected on the host) */
+  const float* lobe_beta;       /* device [Q][Bk] lobe opening angle beta, radians (Eq. 2), > 0 */
+  const float* diff_coef;       /* device [Q][Bk] diffraction coefficient I_d (Eq. 7), >= 0 */
   int32_t Bd, El, Az;           /* directivity bands, elevation and azimuth cells */
   const float* directivity;     /* device [M][Bd][El][Az] real gain or NULL */
   int64_t diff_K;               /* diffraction samples */

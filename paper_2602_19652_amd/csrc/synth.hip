@@ -19,12 +19,12 @@
 //      A e^{j phi} = X[n,k1] * Y[n,k2],
 //      X = exp2(base + 64 k1 slope + band(k1)) e^{j 2 pi (c0 + 64 k1 cb)},
 //      Y = exp2(k2 slope) e^{j 2 pi k2 cb},
-//    whenever the material/directivity bands are constant over runs of 512 bins, so
+//    whenever the material/directivity bands are constant over each run of 64 bins, so
 //    H_m[k1, k2] = sum_n X[n,k1] Y[n,k2] is a complex matrix product contracting over the
 //    records.  It runs on the FP32 matrix cores (v_mfma_f32_16x16x4f32) as Gauss's three
 //    real products; X and Y themselves come from 32 exp2/sin/cos factors per (record,
-//    receiver) (a second 8 x 8 split), so only 32 transcendental triples remain of the 4096
-//    per (record, receiver) of a 4096-bin grid.
+//    receiver) (a second 8 x 8 split) plus one exp2 per band segment, so only about 40
+//    transcendental triples remain of the 4096 per (record, receiver) of a 4096-bin grid.
 //  * direct: one sin/cos/exp2 per (record, receiver, bin), any band layout.
 // Both write per-chunk partial spectra that a final kernel sums in a fixed order
 // (bit-reproducible results).
@@ -200,6 +200,7 @@ constexpr int KT1 = 64;       // outer indices per workgroup
 constexpr int RB = 32;        // records per stage (contraction depth per stage)
 constexpr int RPW = RB / 4;   // records per wave and stage
 constexpr int XS = 80;        // LDS row stride (floats): 16-lane groups land on distinct banks
+constexpr int SMAX = 16;      // band segments (runs of equal material and directivity band) per 64-row tile
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
@@ -268,11 +269,18 @@ struct GaussBuf {
   float Y[2][RB][XS];         // [re/im][record][k2]
 };
 
-// Two-level generation: X[8a+b] = Xa[a] Xb[b] and Y[8a+b] = Ya[a] Yb[b], with the material
-// and directivity bands folded into Xa (the bands are constant over each group of 8 outer
-// indices = 512 bins).  32 exp2/sin/cos factors per record instead of 128 values.
+// Two-level generation: X[8a+b] = Xa[a] Xb[b] bf[seg(8a+b)] and Y[8a+b] = Ya[a] Yb[b]:
+// 32 exp2/sin/cos factors per record instead of 128 values, plus one real band factor
+// bf = 2^(band + directivity log2) per segment of outer indices with equal bands.
 struct WaveScratch {
   float2 xa[RPW][8], xb[RPW][8], ya[RPW][8], yb[RPW][8];
+  float bf[RPW][SMAX];
+};
+
+// Band segments of a tile of outer indices: segment s covers the rows whose material band
+// is sb[s] and directivity band sd[s].
+struct SegTable {
+  int32_t sb[SMAX], sd[SMAX];
 };
 
 __device__ inline float2 cexp2(float lg, float rev) {
@@ -282,34 +290,42 @@ __device__ inline float2 cexp2(float lg, float rev) {
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
 // One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
+// nseg band segments cover the tile; this lane's row lies in segment myseg.
 __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                int row0, GaussBuf& B, WaveScratch& W) {
+                                int row0, int nseg, int myseg, const SegTable& st, GaussBuf& B, WaveScratch& W) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
-  const float g_r = __shfl(q.gamma, src);
-  const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
   const uint32_t a_r = (uint32_t)__shfl((int)q.a32, src), bx_r = (uint32_t)__shfl((int)q.bx32, src),
                  by_r = (uint32_t)__shfl((int)q.by32, src);
   const bool ok = base_r != -INFINITY;
   const uint32_t k1a = (uint32_t)(k1_0 + 8 * j);   // first outer index of group j
-  const int kga = (int)(k1a * K2);
-  float lg = base_r + (float)kga * slope_r;
-  if (ok) {
-    lg += band_log2_v(a, k_r, m_r, g_r, (int)(((int64_t)kga * a.Bk) / a.F));
-    if (a.Bd) {
-      const float x = __shfl(q.vx, src), y = __shfl(q.vy, src), z = __shfl(q.vz, src);
-      const int bd = (int)(((int64_t)kga * a.Bd) / a.F);
-      const float* tab = a.dir + ((size_t)m * a.Bd + bd) * a.El * a.Az;
-      lg += log2f(dir_gain(tab, a.El, a.Az, x, y, z));
-    }
-  }
+  const float lg = base_r + (float)(k1a * K2) * slope_r;
   const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
   const float2 z0 = make_float2(0.f, 0.f);
   W.xa[r][j] = ok && 8 * j < nk1 ? cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S) : z0;
   W.xb[r][j] = ok ? cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S) : z0;
   W.ya[r][j] = ok ? cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S) : z0;
   W.yb[r][j] = ok ? cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S) : z0;
+  // band factors of (record, segment); the trip count is uniform, so every lane takes part
+  // in the shuffles
+  for (int i0 = 0; i0 < RPW * nseg; i0 += 64) {
+    const int i = i0 + lane;
+    const int rr = min(i / nseg, RPW - 1), sg = i - (i / nseg) * nseg;
+    const int sr = t * RPW + rr;
+    const float g_r = __shfl(q.gamma, sr), b_r = __shfl(q.base, sr);
+    const int m_r = __shfl(q.mat, sr), k_r = __shfl(q.kind, sr);
+    const float vx = __shfl(q.vx, sr), vy = __shfl(q.vy, sr), vz = __shfl(q.vz, sr);
+    if (i < RPW * nseg) {
+      float f = 0.f;
+      if (b_r != -INFINITY) {
+        float lb = band_log2_v(a, k_r, m_r, g_r, st.sb[sg]);
+        if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
+        f = exp2f(lb);
+      }
+      W.bf[rr][sg] = f;
+    }
+  }
   // the factors are read back by other lanes of this wave only
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -317,8 +333,11 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
   const bool xon = lane < nk1;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
+    const float f = W.bf[rr][myseg];
     float2 x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
     const float2 y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
+    x.x *= f;
+    x.y *= f;
     if (!xon) x = z0;
     B.X[0][row0 + rr][lane] = x.x;
     B.X[1][row0 + rr][lane] = x.y;
@@ -337,11 +356,22 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
                                                     const Ctl* ctl, float* __restrict__ part) {
   __shared__ __align__(16) GaussBuf buf;
   __shared__ WaveScratch wscr[4];
+  __shared__ SegTable st;
   const int p = blockIdx.x, m = blockIdx.y, k1t = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = a.F / K2;
   const int k1_0 = k1t * KT1;
   const int nk1 = min(KT1, K1 - k1_0);
+  // band segments of this tile (the host guarantees bands constant per row and <= SMAX segments)
+  const int kr = (k1_0 + min(lane, nk1 - 1)) * K2;
+  const int bb = (int)(((int64_t)kr * a.Bk) / a.F), bd = a.Bd ? (int)(((int64_t)kr * a.Bd) / a.F) : 0;
+  const int bb_prev = __shfl(bb, lane - 1), bd_prev = __shfl(bd, lane - 1);
+  const bool starts = lane < nk1 && (lane == 0 || bb != bb_prev || bd != bd_prev);
+  const uint64_t sm = __ballot(starts);
+  const int nseg = __popcll(sm);
+  const int myseg = __popcll(sm & (~0ull >> (63 - lane))) - 1;
+  if (wv == 0 && starts && myseg < SMAX) { st.sb[myseg] = bb; st.sd[myseg] = bd; }
+  __syncthreads();
   int64_t lo, hi;
   chunk_range(ctl->n_vis, a.P, p, lo, hi);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
@@ -358,7 +388,7 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
     const int t = (int)(s & 7);
     // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
     if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, buf, wscr[wv]);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, buf, wscr[wv]);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < RB; kk += 4) {
@@ -526,39 +556,43 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const
       const float wrev = (float)frac(q.cb);
       const float wamp = exp2f(q.slope);
       const float wr = wamp * __builtin_amdgcn_cosf(wrev), wi = wamp * __builtin_amdgcn_sinf(wrev);
-      float s1r = 0.f, s1i = 0.f;
-      const float fdf = (float)a.df;
+      // S_b = sum_{k in band b} conj(g_k) T_k and S1 = sum_k f_k conj(g_k) T_k.  Within a
+      // block of GANCHOR bins the FP32 sums carry the small weights (k - ka); blocks combine
+      // in FP64 as S1 += f_ka sum z + df sum (k - ka) z.
+      double s1r = 0.0, s1i = 0.0;
       for (int b = 0; b < a.Bk; ++b) {
         const int k0 = (int)(((int64_t)b * a.F + a.Bk - 1) / a.Bk);
         const int k1 = (int)(((int64_t)(b + 1) * a.F + a.Bk - 1) / a.Bk);
         const float blog = band_log2(a, q, b);
-        float sbr = 0.f;
+        double sbr = 0.0;
         for (int ka = k0; ka < k1; ka += GANCHOR) {
           const int ke = min(ka + GANCHOR, k1);
           const float rev = (float)frac(q.c0 + (double)ka * q.cb);
           const float amp = exp2f(q.base + (float)ka * q.slope + blog);
           float tr = amp * __builtin_amdgcn_cosf(rev), ti = amp * __builtin_amdgcn_sinf(rev);
-          float f = (float)(a.f_lo + (double)ka * a.df);
-          float c1r = 0.f, c1i = 0.f, c0r = 0.f;
+          float w = 0.f;
+          float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
           for (int k = ka; k < ke; ++k) {
             const float2 gg = gl[k];
             const float zr = gg.x * tr + gg.y * ti;   // Re(conj(g) T)
             const float zi = gg.x * ti - gg.y * tr;   // Im(conj(g) T)
             c0r += zr;
-            c1r += f * zr;
-            c1i += f * zi;
+            c0i += zi;
+            c1r += w * zr;
+            c1i += w * zi;
             const float nr = tr * wr - ti * wi;
             ti = tr * wi + ti * wr;
             tr = nr;
-            f += fdf;
+            w += 1.f;
           }
-          sbr += c0r;
-          s1r += c1r;
-          s1i += c1i;
+          const double fa = a.f_lo + (double)ka * a.df;
+          sbr += (double)c0r;
+          s1r += fa * (double)c0r + a.df * (double)c1r;
+          s1i += fa * (double)c0i + a.df * (double)c1i;
         }
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb)
-          if (bb == b) sb[bb] = (double)sbr;
+          if (bb == b) sb[bb] = sbr;
       }
       double s0 = 0;
 #pragma unroll
@@ -696,15 +730,24 @@ void build_vis(const et_paths& P, const SynthWS& ws, int64_t cap, Ctl* ctl, hipS
 }  // namespace
 
 bool synth_factorised_ok(const et_sim_desc* sim) {
-  // needs k = 64 k1 + k2 and material / directivity bands constant over each group of 8
-  // outer indices (512 bins), where the two-level generation folds them into one factor
+  // needs k = 64 k1 + k2, material / directivity bands constant over each run of 64 bins
+  // (the band factor is per outer index), and at most SMAX band segments per tile of KT1
+  // outer indices
   if (sim->flags & ET_SYNTH_DIRECT) return false;
   if (sim->F < K2 || sim->F % K2) return false;
-  const int64_t G = 8 * K2;
-  for (int64_t ka = 0; ka < sim->F; ka += G) {
-    const int64_t kb = std::min<int64_t>(ka + G, sim->F) - 1;
-    if ((ka * sim->Bk) / sim->F != (kb * sim->Bk) / sim->F) return false;
-    if (sim->directivity && (ka * sim->Bd) / sim->F != (kb * sim->Bd) / sim->F) return false;
+  const int64_t F = sim->F, Bk = sim->Bk, Bd = sim->directivity ? sim->Bd : 0;
+  int nseg = 0;
+  int64_t pb = -1, pd = -1;
+  for (int64_t k1 = 0; k1 < F / K2; ++k1) {
+    const int64_t ka = k1 * K2, kb = ka + K2 - 1;
+    const int64_t b = ka * Bk / F, d = Bd ? ka * Bd / F : 0;
+    if (b != kb * Bk / F) return false;
+    if (Bd && d != kb * Bd / F) return false;
+    if (k1 % KT1 == 0) nseg = 0;
+    if (k1 % KT1 == 0 || b != pb || d != pd) ++nseg;
+    if (nseg > SMAX) return false;
+    pb = b;
+    pd = d;
   }
   return true;
 }

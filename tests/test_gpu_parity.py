@@ -107,16 +107,30 @@ def test_trace_parity_tiny(et, ctx, tiny):
     assert st.segments == int(ref["nseg"].sum())
 
 
-@pytest.mark.parametrize("direct", [False, True])
-def test_synthesis_isolation_tiny(et, ctx, tiny, direct):
-    """GPU synthesis of the oracle's own records vs the oracle's spectra."""
+SYNTH_LAYOUTS = {
+    # name: (material bands, directivity bands or 0, forced direct, kernel expected)
+    "bands8": (8, 0, False, 1),          # 128-bin bands: one band per two 64-bin rows
+    "bands16": (16, 0, False, 1),        # 64-bin bands: a segment per row
+    "bands2": (2, 0, False, 1),
+    "bands12": (12, 0, False, 2),        # band edges inside 64-bin rows: only the direct kernel applies
+    "bands16_dir4": (16, 4, False, 1),   # receiver directivity with its own band split
+    "bands8_dir4_direct": (8, 4, True, 2),
+    "bands8_direct": (8, 0, True, 2),
+}
+
+
+@pytest.mark.parametrize("layout", list(SYNTH_LAYOUTS))
+def test_synthesis_isolation_tiny(et, ctx, tiny, layout):
+    """GPU synthesis of the oracle's own records vs the oracle's spectra, over band layouts
+    that select the factorised or the direct kernel."""
     scene, sim, ref = tiny
-    if not direct:
-        # the factorised kernel needs bands constant over 512-bin runs: 2 bands over 1024 bins
-        g = W.rng(12)
-        sim = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, 2)).astype(np.float32),
-                   lobe_beta=g.uniform(0.05, 0.3, (1, 2)).astype(np.float32),
-                   diff_coef=np.full((1, 2), 0.1, np.float32))
+    Bk, Bd, direct, kernel = SYNTH_LAYOUTS[layout]
+    g = W.rng(12)
+    sim = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, Bk)).astype(np.float32),
+               lobe_beta=g.uniform(0.05, 0.3, (1, Bk)).astype(np.float32),
+               diff_coef=np.full((1, Bk), 0.1, np.float32))
+    if Bd:
+        sim["directivity"] = g.uniform(0.2, 1.0, (len(sim["rx_pos"]), Bd, 8, 16)).astype(np.float32)
     flags = et.ET_SPECULAR | (et.ET_SYNTH_DIRECT if direct else 0)
     s = et.Sim(sim, flags=flags)
     P = et.Paths.from_records(ref)
@@ -124,8 +138,8 @@ def test_synthesis_isolation_tiny(et, ctx, tiny, direct):
     st = ctx.stats()
     H_ref = O.synth(ref, sim)
     e = rel_l2(H, H_ref)
-    print(f"tiny synthesis ({'direct' if direct else 'factorised'} kernel {st.synth_kernel}): rel L2 {e:.3e}")
-    assert st.synth_kernel == (2 if direct else 1)
+    print(f"tiny synthesis {layout} (kernel {st.synth_kernel}): rel L2 {e:.3e}")
+    assert st.synth_kernel == kernel
     assert e <= TOL
 
 

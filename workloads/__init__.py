@@ -443,10 +443,12 @@ def batched_workload(seed: int = 1004, n_poses: int = 256, n_scenes: int = 64, n
         target = int(round(math.exp(g.uniform(math.log(tmin), math.log(tmax)))))
         dims = (g.uniform(3, 10), g.uniform(3, 8), g.uniform(2.5, 4))
         sensor = np.array([dims[0] * 0.3, dims[1] * 0.5, 1.2])
-        # objects: 972-tri boxes / 960-tri cylinders at lower tessellation to reach the target size
-        n_obj = max(0, (target - 12) // 400)
+        # objects: 300-tri boxes (5x5 faces) and 400-tri cylinders, about half the triangles each,
+        # so that the scene lands within 200 triangles of the target size
+        nb = max(1, int(round((target - 12) * 0.5 / 300)))
+        nc = max(0, int(round((target - 12 - 300 * nb) / 400)))
         sub = rng(seed * 1000 + s_i)
-        scene = room_geometry(sub, n_boxes=n_obj // 2, n_cyl=n_obj - n_obj // 2, sensor=sensor, box_subdiv=5,
+        scene = room_geometry(sub, n_boxes=nb, n_cyl=nc, sensor=sensor, box_subdiv=5,
                               cyl_segments=40, cyl_rings=4, room=dims, keepout=0.6)
         batch.scenes.append(scene)
         tables = band_tables(g, 16, 8)
