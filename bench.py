@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Mrays·bounces/s + G(hit·mic·bin)/s synthesis; batched fwd+adjoint vs plain"
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_F32_TFLOPS = 157.3
-SYNTH_FLOP_PER_TERM = 8          # one complex multiply-accumulate as real MFMA products
+SYNTH_FLOP_PER_TERM = 8          # one complex multiply-accumulate (4 mul + 4 add)
+ADJ_FLOP_PER_TERM = 16           # two: the band sum conj(g) T and the frequency-weighted sum
 NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 128
 
 
@@ -162,6 +163,29 @@ def main():
     torch.cuda.synchronize()
     ms_synth = e0.elapsed_time(e1) / reps
     kern = ctx.stats().synth_kernel
+    # the synthesis kernel alone: HIP events the library records around its launch, on the same stream
+    ms_synth_kernel = 0.0
+    for _ in range(reps):
+        et.synthesize(ctx, s, P, ws=ws, out=out)
+        ms_synth_kernel += ctx.stats().ms_synth_kernel / reps
+
+    # adjoint over the fixed paths of the step (32 receivers x 4096 bins): seeded dL/dconj(H)
+    gen = torch.Generator(device="cuda").manual_seed(2024)
+    gH = torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda", generator=gen)
+    et.synthesize_backward(ctx, s, P, gH, ws=ws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        et.synthesize_backward(ctx, s, P, gH, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / reps
+    ms_adj_kernel = 0.0
+    for _ in range(reps):
+        et.synthesize_backward(ctx, s, P, gH, ws=ws)
+        sta = ctx.stats()
+        ms_adj_kernel += sta.ms_adjoint_kernel / reps
+    adj_kern = sta.adjoint_kernel
 
     # traversal work counters (separate counting pass, outside the timed region)
     ctx.set_counting(True)
@@ -172,12 +196,16 @@ def main():
                   + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
 
     synth_flops = terms * SYNTH_FLOP_PER_TERM
-    synth_tflops = synth_flops / (ms_synth * 1e-3) / 1e12
+    synth_tflops = synth_flops / (ms_synth_kernel * 1e-3) / 1e12
+    adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
     trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
     if ms_synth >= ms_trace:
-        roof = {"kernel": "k_synth_mfma" if kern == 1 else "k_synth_direct", "bound": "mfma",
+        kname = "k_synth_mfma" if kern == 1 else "k_synth_direct"
+        roof = {"kernel": kname, "bound": "mfma",
                 "achieved": synth_tflops, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
-                "frac": synth_tflops / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for("k_synth_mfma")}
+                "frac": synth_tflops / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for(kname),
+                "kernel_ms": ms_synth_kernel, "algorithmic_flop_per_launch": synth_flops,
+                "per_unit": f"{SYNTH_FLOP_PER_TERM} flop per (visible record, receiver, bin)"}
     else:
         roof = {"kernel": "k_bounce", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false>")}
@@ -194,7 +222,12 @@ def main():
                    "diff_samples": s.desc.diff_K},
         "segments": seg, "records": n_rec, "visible_records": n_vis, "shadow_rays": st.shadow_rays,
         "trace_ms": ms_trace, "trace_mrays_bounces_per_s": seg / (ms_trace * 1e-3) / 1e6,
-        "synth_ms": ms_synth, "synth_g_terms_per_s": terms / (ms_synth * 1e-3) / 1e9, "synth_kernel": kern,
+        "synth_ms": ms_synth, "synth_kernel_ms": ms_synth_kernel,
+        "synth_g_terms_per_s": terms / (ms_synth * 1e-3) / 1e9, "synth_kernel": kern,
+        "adjoint": {"workload": "fixed paths of the step, 32 receivers x 4096 bins, seeded dL/dconj(H)",
+                    "ms": ms_adj, "kernel_ms": ms_adj_kernel, "kernel": adj_kern,
+                    "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,
+                    "kernel_tflops_algorithmic": adj_tflops, "frac_of_mfma_peak": adj_tflops / PEAK_MFMA_F32_TFLOPS},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define ET_ABI_VERSION 1
+#define ET_ABI_VERSION 2
 
 typedef enum {
   ET_OK = 0,
@@ -106,7 +106,7 @@ int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double
 enum {
   ET_SPECULAR = 1u << 0,      /* trace rays (Algorithm 1) and synthesise their records */
   ET_DIFFRACTION = 1u << 1,   /* draw diff_K curvature-importance samples (Sec. III-D) */
-  ET_SYNTH_DIRECT = 1u << 2   /* force the per-term synthesis kernel (no factorised MFMA path) */
+  ET_SYNTH_DIRECT = 1u << 2   /* force the per-term synthesis and adjoint kernels (no factorised MFMA path) */
 };
 
 typedef struct {
@@ -217,6 +217,10 @@ typedef struct {
   int32_t synth_kernel;                              /* 1 factorised MFMA, 2 direct per-term */
   int32_t status;                                    /* deferred device-side status */
   double ms_trace, ms_diffraction, ms_synth;         /* event-timed phases of the last calls */
+  double ms_adjoint;                                 /* event-timed et_synthesize_backward */
+  double ms_synth_kernel, ms_adjoint_kernel;         /* the main synthesis / adjoint kernel alone */
+  int32_t adjoint_kernel;                            /* 1 factorised MFMA, 2 direct per-term */
+  int32_t reserved0;
 } et_stats;
 int et_get_stats(et_ctx* ctx, et_stats* out);   /* synchronises the context stream */
 

@@ -67,7 +67,9 @@ class Stats(C.Structure):
     _fields_ = [("records", C.c_int64), ("specular", C.c_int64), ("diffraction", C.c_int64), ("segments", C.c_int64),
                 ("shadow_rays", C.c_int64), ("diff_eligible", C.c_int64), ("stack_overflows", C.c_int64),
                 ("dropped", C.c_int64), ("synth_kernel", C.c_int32), ("status", C.c_int32), ("ms_trace", C.c_double),
-                ("ms_diffraction", C.c_double), ("ms_synth", C.c_double)]
+                ("ms_diffraction", C.c_double), ("ms_synth", C.c_double), ("ms_adjoint", C.c_double),
+                ("ms_synth_kernel", C.c_double), ("ms_adjoint_kernel", C.c_double),
+                ("adjoint_kernel", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class Counters(C.Structure):

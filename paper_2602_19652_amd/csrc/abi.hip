@@ -15,9 +15,11 @@ struct et_ctx {
   std::string last_error;
   Ctl* ctl = nullptr;                 // device control block (the only library allocation)
   bool counting = false;
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[12] = {};
   bool timed_trace = false, timed_diff = false, timed_synth = false;
   int synth_kernel = 0;
+  int adjoint_kernel = 0;
+  bool timed_adjoint = false;
   const int64_t* last_count = nullptr;   // device count array of the last traced paths
   // graph replay of a batch
   hipGraph_t graph = nullptr;
@@ -154,7 +156,7 @@ void synth_impl(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void
   synth_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), (char*)ws, &sw);
   (void)from_trace;
   ET_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
-  ctx->synth_kernel = synth_run(sim, paths, sw, ctx->ctl, spectra, ctx->stream);
+  ctx->synth_kernel = synth_run(sim, paths, sw, ctx->ctl, spectra, ctx->stream, ctx->ev[8], ctx->ev[9]);
   ET_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
   ctx->timed_synth = true;
 }
@@ -342,8 +344,10 @@ int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* 
     synth_bwd_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), (char*)ws, &sw);
     k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
     ET_HIP(hipEventRecord(ctx->ev[6], ctx->stream));
-    synth_bwd_run(sim, paths, grad_spectra, sw, ctx->ctl, grad_k, grad_rx, ctx->stream);
+    ctx->adjoint_kernel = synth_bwd_run(sim, paths, grad_spectra, sw, ctx->ctl, grad_k, grad_rx, ctx->stream,
+                                        ctx->ev[10], ctx->ev[11]);
     ET_HIP(hipEventRecord(ctx->ev[7], ctx->stream));
+    ctx->timed_adjoint = true;
   });
 }
 
@@ -422,7 +426,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
                "adjoint limits exceeded");
       SynthWS bw;
       synth_bwd_ws_layout(s, cap, (char*)ws + w.trace + w.synth, &bw);
-      synth_bwd_run(s, &P, grad_spectra + (size_t)j * MF2, bw, ctx->ctl, grad_k + (size_t)j * s->Q * s->Bk,
+      ctx->adjoint_kernel = synth_bwd_run(s, &P, grad_spectra + (size_t)j * MF2, bw, ctx->ctl, grad_k + (size_t)j * s->Q * s->Bk,
                     grad_rx + (size_t)j * s->M * 3, ctx->stream);
     }
   }
@@ -435,7 +439,7 @@ extern "C" {
 int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
                       const float* grad_spectra, double* grad_k, double* grad_rx) {
   return guarded(ctx, [&] {
-    ctx->timed_trace = ctx->timed_synth = false;
+    ctx->timed_trace = ctx->timed_synth = ctx->timed_adjoint = false;
     batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx);
   });
 }
@@ -511,6 +515,11 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
     float ms = 0;
     if (ctx->timed_trace && hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) out->ms_trace = ms;
     if (ctx->timed_synth && hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]) == hipSuccess) out->ms_synth = ms;
+    if (ctx->timed_synth && hipEventElapsedTime(&ms, ctx->ev[8], ctx->ev[9]) == hipSuccess) out->ms_synth_kernel = ms;
+    if (ctx->timed_adjoint && hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) == hipSuccess) out->ms_adjoint = ms;
+    if (ctx->timed_adjoint && hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]) == hipSuccess)
+      out->ms_adjoint_kernel = ms;
+    out->adjoint_kernel = ctx->adjoint_kernel;
     uint32_t err = h.err;
     out->status = ET_OK;
     if (err & DEV_ERR_CAPACITY) {

@@ -180,9 +180,10 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
 struct SynthWS {
   float* partial;            // [P][M][F][2]
   int32_t P;
-  double* gpart_x;           // [chunks][M][3]
-  double* gpart_k;           // [chunks][Q][Bk]
-  int32_t gchunks;
+  double* gpart_x;           // [chunks][tiles][M][3]
+  double* gpart_k;           // [chunks][tiles][M][Q][Bk]
+  int32_t gchunks;           // adjoint record chunks
+  int32_t gtiles;            // adjoint tiles of outer indices (factorised kernel)
   int64_t cap;               // record capacity
   uint64_t* vflags;          // visible-record compaction: flags, offsets, index list, scan scratch
   uint64_t* voffs;
@@ -194,11 +195,14 @@ struct SynthWS {
 };
 size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
 // returns 1 for the factorised MFMA kernel, 2 for the direct kernel
+// kb/ke (optional) are recorded around the main synthesis kernel alone
 int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, Ctl* ctl, float* spectra,
-              hipStream_t s);
+              hipStream_t s, hipEvent_t kb = nullptr, hipEvent_t ke = nullptr);
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
-void synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra, const SynthWS& ws,
-                   Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s);
+// returns 1 (factorised MFMA adjoint) or 2 (direct adjoint)
+int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra, const SynthWS& ws,
+                  Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s, hipEvent_t kb = nullptr,
+                  hipEvent_t ke = nullptr);
 bool synth_factorised_ok(const et_sim_desc* sim);
 
 }  // namespace et

@@ -280,8 +280,34 @@ struct WaveScratch {
 // Band segments of a tile of outer indices: segment s covers the rows whose material band
 // is sb[s] and directivity band sd[s].
 struct SegTable {
-  int32_t sb[SMAX], sd[SMAX];
+  int32_t sb[SMAX], sd[SMAX];   // material and directivity band of segment s
+  int32_t s0[SMAX], s1[SMAX];   // its rows [s0, s1) within the tile
+  int32_t bseg[16];             // segment of material band b, -1 if none (used without directivity)
 };
+
+// Band segments of the tile [k1_0, k1_0 + nk1) (the host guarantees bands constant per row
+// and at most SMAX segments).  Every thread learns nseg and the segment of its lane's row.
+__device__ inline void seg_init(const SynthArgs& a, int k1_0, int nk1, int tid, SegTable& st, int& nseg, int& myseg) {
+  const int lane = tid & 63, wv = tid >> 6;
+  const int kr = (k1_0 + min(lane, nk1 - 1)) * K2;
+  const int bb = (int)(((int64_t)kr * a.Bk) / a.F), bd = a.Bd ? (int)(((int64_t)kr * a.Bd) / a.F) : 0;
+  const int bb_prev = __shfl(bb, lane - 1), bd_prev = __shfl(bd, lane - 1);
+  const bool starts = lane < nk1 && (lane == 0 || bb != bb_prev || bd != bd_prev);
+  const uint64_t sm = __ballot(starts);
+  nseg = __popcll(sm);
+  myseg = __popcll(sm & (~0ull >> (63 - lane))) - 1;
+  if (tid < 16) st.bseg[tid] = -1;
+  __syncthreads();
+  if (wv == 0 && starts && myseg < SMAX) {
+    st.sb[myseg] = bb;
+    st.sd[myseg] = bd;
+    st.s0[myseg] = lane;
+    if (bb < 16) st.bseg[bb] = myseg;
+  }
+  __syncthreads();
+  if (tid < nseg && tid < SMAX) st.s1[tid] = tid + 1 < nseg ? st.s0[tid + 1] : nk1;
+  __syncthreads();
+}
 
 __device__ inline float2 cexp2(float lg, float rev) {
   const float amp = exp2f(lg);
@@ -291,8 +317,10 @@ __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x
 
 // One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
 // nseg band segments cover the tile; this lane's row lies in segment myseg.
+// X lands at xr/xi[record * XS + k1], Y at yr/yi[record * ys_rec + k2 * ys_k].
 __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                int row0, int nseg, int myseg, const SegTable& st, GaussBuf& B, WaveScratch& W) {
+                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi,
+                                float* yr, float* yi, int ys_rec, int ys_k, WaveScratch& W) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
@@ -339,10 +367,10 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
     x.x *= f;
     x.y *= f;
     if (!xon) x = z0;
-    B.X[0][row0 + rr][lane] = x.x;
-    B.X[1][row0 + rr][lane] = x.y;
-    B.Y[0][row0 + rr][lane] = y.x;
-    B.Y[1][row0 + rr][lane] = y.y;
+    xr[(row0 + rr) * XS + lane] = x.x;
+    xi[(row0 + rr) * XS + lane] = x.y;
+    yr[(row0 + rr) * ys_rec + lane * ys_k] = y.x;
+    yi[(row0 + rr) * ys_rec + lane * ys_k] = y.y;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -362,16 +390,8 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
   const int K1 = a.F / K2;
   const int k1_0 = k1t * KT1;
   const int nk1 = min(KT1, K1 - k1_0);
-  // band segments of this tile (the host guarantees bands constant per row and <= SMAX segments)
-  const int kr = (k1_0 + min(lane, nk1 - 1)) * K2;
-  const int bb = (int)(((int64_t)kr * a.Bk) / a.F), bd = a.Bd ? (int)(((int64_t)kr * a.Bd) / a.F) : 0;
-  const int bb_prev = __shfl(bb, lane - 1), bd_prev = __shfl(bd, lane - 1);
-  const bool starts = lane < nk1 && (lane == 0 || bb != bb_prev || bd != bd_prev);
-  const uint64_t sm = __ballot(starts);
-  const int nseg = __popcll(sm);
-  const int myseg = __popcll(sm & (~0ull >> (63 - lane))) - 1;
-  if (wv == 0 && starts && myseg < SMAX) { st.sb[myseg] = bb; st.sd[myseg] = bd; }
-  __syncthreads();
+  int nseg, myseg;
+  seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
   int64_t lo, hi;
   chunk_range(ctl->n_vis, a.P, p, lo, hi);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
@@ -388,7 +408,8 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
     const int t = (int)(s & 7);
     // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
     if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, buf, wscr[wv]);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &buf.X[0][0][0], &buf.X[1][0][0],
+             &buf.Y[0][0][0], &buf.Y[1][0][0], XS, 1, wscr[wv]);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < RB; kk += 4) {
@@ -660,6 +681,207 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const
   for (int i = tid; i < a.Q * a.Bk; i += GB) gpk[((size_t)p * a.M + m) * a.Q * a.Bk + i] = kacc[i];
 }
 
+// Factorised adjoint.  For record n and receiver m the adjoint needs, per material band b,
+//   S_b = sum_{k in b} conj(g_k) T_k   and   S1 = sum_k f_k conj(g_k) T_k,
+// with T_k = X[k1] Y[k2] as in the forward kernel and G = conj(g) as a [k1][k2] matrix:
+//   S_b = sum_{k1 in b} X[k1] Z[k1],          Z[k1]  = sum_k2 G[k1, k2] Y[k2],
+//   S1  = sum_k1 X[k1] (f_k1 Z[k1] + df Z'[k1]),  Z'[k1] = sum_k2 G[k1, k2] k2 Y[k2],
+// f_k1 the frequency of bin 64 k1.  Z and Z' are complex matrix products contracting over
+// k2 (Gauss's three real products on the matrix cores, G in registers).  The per-row
+// products go to LDS; per record, band sums and the weighted sum run in FP64 in a fixed
+// order, and the FP64 chain rule of the direct adjoint turns them into dL/dk and dL/dx_m.
+constexpr int YT = 33;   // LDS stride of transposed Y (records fast); odd, so writes spread over banks
+
+struct BwdBuf {
+  float X[2][RB][XS];        // [re/im][record][k1]
+  float Yt[2][K2][YT];       // [re/im][k2][record]
+  float R0[RB][KT1 + 1];     // Re(X Z) per (record, row)
+  float2 R1[RB][17];         // sum over 4 rows of X (f Z + df Z') per (record, row group)
+  double kv[RB][16];         // dL/dk contribution per (record, band)
+  int32_t kmat[RB];          // material of a specular record, -1 otherwise
+};
+
+__global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
+                                                        const Ctl* ctl, const float* __restrict__ g,
+                                                        double* __restrict__ gpx, double* __restrict__ gpk) {
+  __shared__ __align__(16) BwdBuf bb;
+  __shared__ WaveScratch wscr[4];
+  __shared__ SegTable st;
+  __shared__ double red[256];
+  const int p = blockIdx.x, m = blockIdx.y, k1t = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int K1 = a.F / K2;
+  const int k1_0 = k1t * KT1;
+  const int nk1 = min(KT1, K1 - k1_0);
+  int nseg, myseg;
+  seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
+  // A operands: rows k1 = 16 wv + lane % 16 of G, columns k2 = 4 ks + lane / 16, as Gauss forms
+  float ga[3][16];
+  const int r1g = wv * 16 + (lane & 15);
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    float gr = 0.f, gi = 0.f;
+    if (r1g < nk1) {
+      const int k = (k1_0 + r1g) * K2 + 4 * ks + (lane >> 4);
+      gr = g[((size_t)m * a.F + k) * 2];
+      gi = -g[((size_t)m * a.F + k) * 2 + 1];
+    }
+    ga[0][ks] = gr + gi; ga[1][ks] = gr; ga[2][ks] = gi;
+  }
+  const float frow0 = (float)(a.f_lo + (double)(k1_0 * K2) * a.df), df64 = (float)(K2 * a.df), dff = (float)a.df;
+  int64_t lo, hi;
+  chunk_range(ctl->n_vis, a.P, p, lo, hi);
+  const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;
+  const double ln10 = 2.30258509299404568402;
+  const int QB = a.Q * a.Bk;
+  double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
+  double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
+  PairLean q;
+  for (int64_t s = 0; s < nst; ++s) {
+    const int t = (int)(s & 7);
+    if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0],
+             &bb.Yt[0][0][0], &bb.Yt[1][0][0], 1, YT, wscr[wv]);
+    __syncthreads();
+    floatx4 acc[6][2];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[i][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int kk = 4 * ks + (lane >> 4);
+      const float w2 = (float)kk;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int nn = nb * 16 + (lane & 15);
+        const float yr = bb.Yt[0][kk][nn], yi = bb.Yt[1][kk][nn];
+        const float b0 = yr, b1 = yi - yr, b2 = yr + yi;
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], b0, acc[0][nb], 0, 0, 0);
+        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], b1, acc[1][nb], 0, 0, 0);
+        acc[2][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], b2, acc[2][nb], 0, 0, 0);
+        acc[3][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], w2 * b0, acc[3][nb], 0, 0, 0);
+        acc[4][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], w2 * b1, acc[4][nb], 0, 0, 0);
+        acc[5][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], w2 * b2, acc[5][nb], 0, 0, 0);
+      }
+    }
+    // accumulator (nb, v) of lane l: row 16 wv + 4 (l / 16) + v, record 16 nb + l % 16
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int n = nb * 16 + (lane & 15);
+      float s1r = 0.f, s1i = 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r1 = wv * 16 + (lane >> 4) * 4 + v;
+        const float zr = acc[0][nb][v] - acc[2][nb][v], zi = acc[0][nb][v] + acc[1][nb][v];
+        const float wr = acc[3][nb][v] - acc[5][nb][v], wi = acc[3][nb][v] + acc[4][nb][v];
+        const float xr = bb.X[0][n][r1], xi = bb.X[1][n][r1];
+        const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
+        const float fr = frow0 + (float)r1 * df64;
+        bb.R0[n][r1] = cr;
+        s1r += fr * cr + dff * (xr * wr - xi * wi);
+        s1i += fr * ci + dff * (xr * wi + xi * wr);
+      }
+      bb.R1[n][wv * 4 + (lane >> 4)] = make_float2(s1r, s1i);
+    }
+    __syncthreads();
+    {
+      // eight threads per record: row sums in FP64, bands j and j + 8
+      const int n = tid >> 3, j = tid & 7;
+      const int64_t e = lo + (s >> 3) * (8 * RB) + (n >> 3) * 64 + t * RPW + (n & 7);
+      const bool valid = e < hi;
+      int64_t rn = 0;
+      int mat = 0, kind = 1;
+      if (valid) {
+        rn = idx[e];
+        kind = (P.flags[rn] >> 1) & 1;
+        mat = P.mat[rn];
+      }
+      double s1r = 0.0, s1i = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float2 c = bb.R1[n][j + 8 * h];
+        s1r += (double)c.x;
+        s1i += (double)c.y;
+      }
+      double s0 = 0.0, wl = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int b = j + 8 * h;
+        double sb = 0.0;
+        if (b < a.Bk) {
+          const int sg = st.bseg[b];
+          if (sg >= 0)
+            for (int r1 = st.s0[sg]; r1 < st.s1[sg]; ++r1) sb += (double)bb.R0[n][r1];
+        }
+        s0 += sb;
+        double kvv = 0.0;
+        if (valid && kind == 0 && b < a.Bk) {
+          const double bt = (double)a.beta[mat * a.Bk + b];
+          wl += sb / (2.0 * bt * bt);
+          const double kk = (double)a.refl_k[mat * a.Bk + b];
+          kvv = kk != 0.0 ? 2.0 * sb / kk : 0.0;
+        }
+        bb.kv[n][b] = kvv;
+      }
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        s1r += __shfl_xor(s1r, o);
+        s1i += __shfl_xor(s1i, o);
+        s0 += __shfl_xor(s0, o);
+        wl += __shfl_xor(wl, o);
+      }
+      if (j == 0) bb.kmat[n] = valid && kind == 0 ? mat : -1;
+      if (j == 0 && valid) {
+        // receiver leg and path in FP64, as in the forward set-up
+        const double wx = a.rx_pos[3 * m] - P.p[3 * rn], wy = a.rx_pos[3 * m + 1] - P.p[3 * rn + 1],
+                     wz = a.rx_pos[3 * m + 2] - P.p[3 * rn + 2];
+        const double l = sqrt(wx * wx + wy * wy + wz * wz), il = 1.0 / l;
+        const double r = P.rtot[rn] + l;
+        const double u0 = wx * il, u1 = wy * il, u2 = wz * il;
+        // d(ln A + j phi)/dx_m = [(-p/r - ln10 (a0 + a1 f)/20) + j sigma 2 pi f / c] u - d(gamma^2)/dx / (2 beta^2)
+        const double cu = (-a.ps / r - ln10 * a.A0 / 20.0) * s0 - ln10 * a.A1 / 20.0 * s1r -
+                          (double)a.sigma * 2.0 * M_PI / a.c * s1i;
+        double g0 = 2.0 * cu * u0, g1 = 2.0 * cu * u1, g2 = 2.0 * cu * u2;
+        if (kind == 0) {
+          const double dx = P.dout[3 * rn], dy = P.dout[3 * rn + 1], dz = P.dout[3 * rn + 2];
+          const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+          const double hx = dx * idn, hy = dy * idn, hz = dz * idn;
+          const double cg = hx * u0 + hy * u1 + hz * u2;
+          const double qx = hy * u2 - hz * u1, qy = hz * u0 - hx * u2, qz = hx * u1 - hy * u0;
+          const double sg = sqrt(qx * qx + qy * qy + qz * qz);
+          // gamma / sin(gamma) needs no more than FP32 atan2: the ratio is a smooth factor
+          const double gam = (double)atan2f((float)sg, (float)cg);
+          const double ratio = gam < 1e-4 ? 2.0 : 2.0 * gam / sg;
+          // d(gamma^2)/dx = -(2 gamma / sin gamma) (d' - cos(gamma) u) / l
+          const double cl = -ratio * il * 2.0 * wl;
+          g0 -= cl * (hx - cg * u0); g1 -= cl * (hy - cg * u1); g2 -= cl * (hz - cg * u2);
+        }
+        gx0 += g0; gx1 += g1; gx2 += g2;
+      }
+    }
+    __syncthreads();
+    if (tid < QB) {
+      const int qq = tid / a.Bk, b = tid - qq * a.Bk;
+      for (int n = 0; n < RB; ++n)
+        if (bb.kmat[n] == qq) kacc += bb.kv[n][b];
+    }
+  }
+  const size_t slot = ((size_t)p * gridDim.z + k1t) * a.M + m;
+  const double gv[3] = {gx0, gx1, gx2};
+  for (int c = 0; c < 3; ++c) {
+    red[tid] = gv[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) gpx[slot * 3 + c] = red[0];
+    __syncthreads();
+  }
+  if (tid < QB) gpk[slot * QB + tid] = kacc;
+}
+
 __global__ void k_bwd_reduce(const double* __restrict__ gpx, const double* __restrict__ gpk, int32_t P, int32_t M,
                              int32_t QB, double* __restrict__ grad_k, double* __restrict__ grad_x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -768,12 +990,14 @@ size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS*
   return off;
 }
 
-int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, Ctl* ctl, float* spectra, hipStream_t s) {
+int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, Ctl* ctl, float* spectra, hipStream_t s,
+              hipEvent_t kb, hipEvent_t ke) {
   const bool mf = synth_factorised_ok(sim);
   SynthArgs a = make_args(sim, ws.P);
   const et_paths P = *paths;
   build_vis(P, ws, ws.cap, ctl, s);
   build_tables(a, ws, s);
+  if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(ws.P, sim->M, (K1 + KT1 - 1) / KT1);
@@ -782,45 +1006,65 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
     dim3 grid(ws.P, sim->M, (sim->F + DTILE - 1) / DTILE);
     k_synth_direct<<<grid, DB, 0, s>>>(a, P, ws.vidx, ctl, ws.partial);
   }
+  if (ke) ET_HIP(hipEventRecord(ke, s));
   const int64_t MF2 = (int64_t)sim->M * sim->F * 2;
   k_reduce_partials<<<(unsigned)std::min<int64_t>((MF2 + 255) / 256, 4096), 256, 0, s>>>(ws.partial, ws.P, MF2, spectra);
   ET_HIP(hipGetLastError());
   return mf ? 1 : 2;
 }
 
+bool synth_bwd_factorised_ok(const et_sim_desc* sim) { return !sim->directivity && synth_factorised_ok(sim); }
+
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
   cap = std::max<int64_t>(cap, 1);
-  const int64_t tiles = sim->M;
-  int64_t P = std::max<int64_t>(1, (1024 + tiles - 1) / tiles);
-  P = std::min<int64_t>(P, std::max<int64_t>(1, (cap + GB - 1) / GB));
-  P = std::min<int64_t>(P, 256);
+  const bool mf = synth_bwd_factorised_ok(sim);
+  const int64_t T1 = mf ? (sim->F / K2 + KT1 - 1) / KT1 : 1;
+  int64_t P;
+  if (mf) {
+    P = choose_P(sim, cap, true);
+  } else {
+    P = std::max<int64_t>(1, (1024 + sim->M - 1) / sim->M);
+    P = std::min<int64_t>(P, std::max<int64_t>(1, (cap + GB - 1) / GB));
+    P = std::min<int64_t>(P, 256);
+  }
   size_t off = 0;
   SynthWS w{};
   w.gchunks = (int)P;
+  w.gtiles = (int)T1;
   w.cap = cap;
   w.gpart_x = (double*)(base ? base + off : nullptr);
-  off += al(sizeof(double) * 3 * (size_t)P * sim->M);
+  off += al(sizeof(double) * 3 * (size_t)P * T1 * sim->M);
   w.gpart_k = (double*)(base ? base + off : nullptr);
-  off += al(sizeof(double) * (size_t)P * sim->M * sim->Q * sim->Bk);
+  off += al(sizeof(double) * (size_t)P * T1 * sim->M * sim->Q * sim->Bk);
   off = vis_ws(cap, base, off, &w.vflags, &w.voffs, &w.vidx, &w.vscan);
   off = table_ws(sim, base, off, w);
   if (ws) *ws = w;
   return off;
 }
 
-void synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra, const SynthWS& ws,
-                   Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s) {
+int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra, const SynthWS& ws,
+                  Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s, hipEvent_t kb, hipEvent_t ke) {
+  const bool mf = synth_bwd_factorised_ok(sim);
   SynthArgs a = make_args(sim, ws.gchunks);
   const et_paths P = *paths;
   build_vis(P, ws, ws.cap, ctl, s);
   build_tables(a, ws, s);
-  dim3 grid(ws.gchunks, sim->M);
-  const size_t shm = sizeof(float2) * (size_t)sim->F;
-  k_synth_bwd<<<grid, GB, shm, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+  if (kb) ET_HIP(hipEventRecord(kb, s));
+  if (mf) {
+    dim3 grid(ws.gchunks, sim->M, ws.gtiles);
+    k_synth_bwd_mfma<<<grid, 256, 0, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+  } else {
+    dim3 grid(ws.gchunks, sim->M);
+    const size_t shm = sizeof(float2) * (size_t)sim->F;
+    k_synth_bwd<<<grid, GB, shm, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+  }
+  if (ke) ET_HIP(hipEventRecord(ke, s));
   const int QB = sim->Q * sim->Bk;
   const int n = std::max(QB, sim->M * 3);
-  k_bwd_reduce<<<(n + 255) / 256, 256, 0, s>>>(ws.gpart_x, ws.gpart_k, ws.gchunks, sim->M, QB, grad_k, grad_rx);
+  k_bwd_reduce<<<(n + 255) / 256, 256, 0, s>>>(ws.gpart_x, ws.gpart_k, ws.gchunks * ws.gtiles, sim->M, QB, grad_k,
+                                                grad_rx);
   ET_HIP(hipGetLastError());
+  return mf ? 1 : 2;
 }
 
 }  // namespace et

@@ -247,22 +247,46 @@ def test_diffraction_samples_match(et, ctx):
 
 # ----------------------------------------------------------------------------- adjoint
 
-def test_adjoint_matches_oracle_gradient(et, ctx, tiny):
+ADJOINT_CASES = {
+    # name: (bins, material bands, forced direct, diffraction records added, kernel expected)
+    "factorised_F512": (512, 8, False, False, 1),
+    "factorised_F8192_two_tiles": (8192, 16, False, False, 1),
+    "factorised_F512_diffraction": (512, 8, False, True, 1),
+    "direct_F512": (512, 8, True, False, 2),
+    "direct_F500": (500, 4, False, False, 2),      # bins not a multiple of 64
+}
+
+
+@pytest.mark.parametrize("case", list(ADJOINT_CASES))
+def test_adjoint_matches_oracle_gradient(et, ctx, tiny, case):
+    """dL/dk and dL/dx_m of L = sum |H - H*|^2 from the GPU adjoint vs the FP64 oracle gradient."""
     scene, sim, ref = tiny
-    sim = dict(sim)
-    sim["F"] = 512
+    F, Bk, direct, diffraction, kernel = ADJOINT_CASES[case]
     g = W.rng(8)
-    hidden = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, 8)).astype(np.float32))
+    sim = dict(sim, F=F, refl_k=g.uniform(0.3, 0.99, (1, Bk)).astype(np.float32),
+               lobe_beta=g.uniform(0.05, 0.3, (1, Bk)).astype(np.float32),
+               diff_coef=g.uniform(0.05, 0.3, (1, Bk)).astype(np.float32))
+    if F > 4096:   # keep the FP64 oracle to seconds: a ray subset
+        ref = O.trace(scene, sim, dirs=sim["ray_dirs"][:2048], certify=False)
+    if diffraction:
+        _, C_ref = O.curvature(scene, W.median_triangle_area(scene))
+        smp = O.diffraction(scene, dict(sim, diff_K=4096, diff_seed=77), C_ref)
+        ref = O.concat_records(ref, O.diffraction_records(scene, smp))
+    hidden = dict(sim, refl_k=g.uniform(0.3, 0.99, (1, Bk)).astype(np.float32),
+                  diff_coef=g.uniform(0.05, 0.3, (1, Bk)).astype(np.float32))
     H_star = O.synth(ref, hidden)
     H = O.synth(ref, sim)
     gk_ref, gx_ref = O.grad(ref, sim, H - H_star)
     import torch
-    s = et.Sim(sim, flags=et.ET_SPECULAR)
+    s = et.Sim(sim, flags=et.ET_SPECULAR | (et.ET_SYNTH_DIRECT if direct else 0))
     P = et.Paths.from_records(ref)
     gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(H - H_star).to("cuda"))
+    st = ctx.stats()
     gk, gx = gk.cpu().numpy(), gx.cpu().numpy()
     ek, ex = rel_l2(gk, gk_ref), rel_l2(gx, gx_ref)
-    print(f"adjoint: rel err dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    print(f"adjoint {case} (kernel {st.adjoint_kernel}, {len(ref['rtot'])} records): rel err dL/dk {ek:.3e}, "
+          f"dL/dx {ex:.3e}")
+    assert st.adjoint_kernel == kernel
     assert ek <= TOL and ex <= TOL
 
 
