@@ -249,9 +249,10 @@ def main():
 def batched_leg(ctx, args):
     """Batch workload: poses along a spline through the room plus uneven independent scenes
     (2^18 rays, <= 4 reflection points, 8 receivers, 2048 bins each).  Jobs per second of
-    (a) separate single-pose forward calls, (b) one batched forward call, (c) one batched
-    forward + adjoint call (seeded synthetic dL/dconj(H) per job), (d) (c) replayed from a
-    captured HIP graph.  The ratio asked for is (c) / (a)."""
+    (a) separate single-pose forward calls, (b) one fused batched forward call, (c) one
+    fused batched forward + adjoint call (seeded synthetic dL/dconj(H) per job), (d) (c)
+    replayed from a captured HIP graph, and (b), (c) again with the autotuner's launch
+    shapes.  The ratio reported is the throughput of (c) over that of (a)."""
     import torch
     import paper_2602_19652_amd as et
     import workloads as W
@@ -296,8 +297,17 @@ def batched_leg(ctx, args):
         e1.record(side)
         torch.cuda.synchronize()
         ms_graph = e0.elapsed_time(e1) / 2
+    # launch shapes from the autotuner, then the same legs again
+    tune = batch.autotune(grad_spectra=grad)
+    ms_fwd_t = timed(lambda: batch.run(), 2)
+    ms_fwd_adj_t = timed(lambda: batch.run(grad_spectra=grad), 2)
+    batch.run(grad_spectra=grad)
     st = ctx.stats()
     jobs_s = lambda ms: J / (ms * 1e-3)
+    tuned = {"synth_wgs": tune.synth_wgs, "adjoint_wgs": tune.adjoint_wgs, "trace_blocks": tune.trace_blocks,
+             "batched_fwd_ms": ms_fwd_t, "batched_fwd_adj_ms": ms_fwd_adj_t,
+             "phase_ms": {"trace": st.ms_trace, "synth_kernel": st.ms_synth_kernel, "adjoint_kernel": st.ms_adjoint_kernel},
+             "ratio_batched_fwd_adj_vs_plain_fwd": ms_plain / ms_fwd_adj_t}
     return {"jobs": J, "poses": args.batch_poses, "scenes": args.batch_scenes, "rays_per_job": args.batch_rays,
             "receivers": sims[0].M, "bins": sims[0].F, "scene_triangles": [int(len(sc["tris"])) for sc in b.scenes],
             "plain_fwd_ms": ms_plain, "batched_fwd_ms": ms_fwd, "batched_fwd_adj_ms": ms_fwd_adj,
@@ -305,7 +315,8 @@ def batched_leg(ctx, args):
             "plain_fwd_jobs_per_s": jobs_s(ms_plain), "batched_fwd_jobs_per_s": jobs_s(ms_fwd),
             "batched_fwd_adj_jobs_per_s": jobs_s(ms_fwd_adj), "batched_fwd_adj_graph_jobs_per_s": jobs_s(ms_graph),
             "ratio_batched_fwd_adj_vs_plain_fwd": ms_plain / ms_fwd_adj,
-            "ratio_graph_fwd_adj_vs_plain_fwd": ms_plain / ms_graph, "input_generation_s": gen_s}
+            "ratio_graph_fwd_adj_vs_plain_fwd": ms_plain / ms_graph, "autotuned": tuned,
+            "input_generation_s": gen_s}
 
 
 if __name__ == "__main__":

@@ -191,13 +191,19 @@ typedef struct {
   const et_sim_desc* sim;       /* per-job descriptor (M, F, B, Q, Bk equal across jobs) */
 } et_job;
 
-/* Workspace for a batch (all jobs' rays and records) and per-job record capacity. */
+/* Workspace for a batch (all jobs' rays and records and the synthesis scratch). */
 int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes);
 
-/* Traces and synthesises J jobs with one launch sequence per phase: all jobs' rays share
- * the bounce kernels, all records share the synthesis kernels.  spectra is device
- * float [J][M][F][2].  grad_spectra (optional, same shape) adds the adjoint of every
- * job into grad_k [J][Q][Bk] and grad_rx [J][M][3] (device double). */
+/* Traces and synthesises J jobs (poses and scenes may all differ; M, F, Q and Bk are shared).
+ * When every job is specular-only the batch runs fused: one ray-state array holds all jobs'
+ * rays and each bounce is one launch over all of them (every ray reads its scene and pose
+ * from a device job table); the visible records of all jobs are sorted by job (stably) and
+ * cut into chunks that never mix jobs, so one synthesis launch (and one adjoint launch)
+ * covers the batch, followed by a per-job reduction in a fixed order.  Launch shapes come
+ * from the context's tuning (et_autotune_batch).  Batches with diffraction jobs run job after
+ * job.  spectra is device float [J][M][F][2].  grad_spectra (optional, same shape, dL/dconj(H)
+ * per job) makes the call also write every job's adjoint into grad_k [J][Q][Bk] and
+ * grad_rx [J][M][3] (device double).  Results are bit-reproducible for a given tuning. */
 int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
                       const float* grad_spectra, double* grad_k, double* grad_rx);
 
@@ -206,6 +212,30 @@ int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
 int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes,
                             float* spectra, const float* grad_spectra, double* grad_k, double* grad_rx);
 int et_graph_reset(et_ctx* ctx);
+
+/* ------------------------------------------------------------------ tuning of fused batches
+ * Launch shapes kept per context: the workgroups that the record chunks of the synthesis and
+ * adjoint kernels aim at, and the grid of the bounce kernels (grid-stride over the active
+ * rays).  Workspaces from et_batch_workspace_size serve every allowed value. */
+typedef struct {
+  int32_t synth_wgs;      /* 64 .. 4096 */
+  int32_t adjoint_wgs;    /* 64 .. 4096 */
+  int32_t trace_blocks;   /* 64 .. 4096 */
+  int32_t reserved0;
+  double ms_trace, ms_synth, ms_adjoint;   /* event times of the chosen shape (et_autotune_batch) */
+} et_tuning;
+int et_get_tuning(et_ctx* ctx, et_tuning* out);
+int et_set_tuning(et_ctx* ctx, const et_tuning* t);   /* ET_E_INVALID outside the ranges */
+
+/* Autotuner: runs the fused batch (as et_simulate_batch, with the adjoint when grad_spectra
+ * is given) once per candidate shape (synthesis and adjoint workgroups 512, 1024, 2048,
+ * 4096; bounce grids 1024, 1280, 2048, 4096 blocks), times the trace phase, the synthesis
+ * kernel and the adjoint kernel with events, keeps for each knob its fastest candidate in
+ * the context (the phases do not interact) and returns the choice with its times.  The
+ * outputs hold the results of the last run.  ET_E_UNSUPPORTED for batches that do not run
+ * fused (jobs with diffraction). */
+int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                      const float* grad_spectra, double* grad_k, double* grad_rx, et_tuning* out);
 
 /* ------------------------------------------------------------------ statistics */
 typedef struct {

@@ -81,6 +81,12 @@ class Job(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("sim", C.POINTER(SimDesc))]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("synth_wgs", C.c_int32), ("adjoint_wgs", C.c_int32), ("trace_blocks", C.c_int32),
+                ("reserved0", C.c_int32), ("ms_trace", C.c_double), ("ms_synth", C.c_double),
+                ("ms_adjoint", C.c_double)]
+
+
 _lib = None
 
 
@@ -122,6 +128,9 @@ def lib():
             "et_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
             "et_set_counting": ([vp, C.c_int], C.c_int),
             "et_get_counters": ([vp, C.POINTER(Counters)], C.c_int),
+            "et_get_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "et_set_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
+            "et_autotune_batch": ([vp, i32, C.POINTER(Job), vp, sz, vp, vp, vp, vp, C.POINTER(Tuning)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -183,6 +192,15 @@ class Context:
 
     def set_counting(self, on: bool):
         self.call("et_set_counting", 1 if on else 0)
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        self.call("et_get_tuning", C.byref(t))
+        return t
+
+    def set_tuning(self, synth_wgs: int, adjoint_wgs: int, trace_blocks: int):
+        t = Tuning(synth_wgs=synth_wgs, adjoint_wgs=adjoint_wgs, trace_blocks=trace_blocks)
+        self.call("et_set_tuning", C.byref(t))
 
     def close(self):
         if getattr(self, "h", None):
@@ -473,3 +491,13 @@ class Batch:
         self.ctx.call(name, len(self.jobs), self.arr, _ptr(self.ws), self.ws.numel(), _ptr(self.spectra), _ptr(g),
                       _ptr(self.grad_k) if g is not None else None, _ptr(self.grad_rx) if g is not None else None)
         return torch.view_as_complex(self.spectra)
+
+    def autotune(self, grad_spectra: torch.Tensor | None = None) -> Tuning:
+        """Times the batch over the library's candidate launch shapes and keeps the fastest
+        (per knob) in the context; returns the choice and its phase times."""
+        g = None if grad_spectra is None else torch.view_as_real(grad_spectra.to(torch.complex64).contiguous())
+        t = Tuning()
+        self.ctx.call("et_autotune_batch", len(self.jobs), self.arr, _ptr(self.ws), self.ws.numel(),
+                      _ptr(self.spectra), _ptr(g), _ptr(self.grad_k) if g is not None else None,
+                      _ptr(self.grad_rx) if g is not None else None, C.byref(t))
+        return t

@@ -9,6 +9,9 @@
 
 using namespace et;
 
+// which of the context's event pairs hold times of the last calls
+enum : uint32_t { TM_TRACE = 1, TM_SYNTH = 2, TM_ADJ = 4, TM_SYNTH_K = 8, TM_ADJ_K = 16 };
+
 struct et_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -16,10 +19,10 @@ struct et_ctx {
   Ctl* ctl = nullptr;                 // device control block (the only library allocation)
   bool counting = false;
   hipEvent_t ev[12] = {};
-  bool timed_trace = false, timed_diff = false, timed_synth = false;
+  uint32_t timed = 0;   // event pairs holding the last calls' times (TM_* bits)
   int synth_kernel = 0;
+  et::BatchTune tune;
   int adjoint_kernel = 0;
-  bool timed_adjoint = false;
   const int64_t* last_count = nullptr;   // device count array of the last traced paths
   // graph replay of a batch
   hipGraph_t graph = nullptr;
@@ -111,6 +114,18 @@ int64_t records_upper_bound(const et_sim_desc* s) {
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
+size_t paths_bytes(int64_t cap) {
+  return al(cap * (24 + 12 + 8 + 4 + 4 + 4 + 1 + 1)) + al(8 * sizeof(int64_t)) + 8 * 256;
+}
+
+// A batch runs fused (all rays in shared bounce kernels, all records in shared synthesis
+// kernels) when every job is specular-only; otherwise jobs run one after another.
+bool batch_fused(int32_t J, const et_job* jobs) {
+  for (int32_t j = 0; j < J; ++j)
+    if (jobs[j].sim->flags & ET_DIFFRACTION) return false;
+  return true;
+}
+
 struct WsPlan {
   size_t trace = 0, synth = 0, bwd = 0;
   size_t total() const { return trace + synth + bwd; }
@@ -124,6 +139,37 @@ WsPlan plan(const et_scene* sc, const et_sim_desc* s, int64_t cap) {
   w.synth = al(synth_ws_layout(s, cap, nullptr, nullptr));
   w.bwd = al(synth_bwd_ws_layout(s, cap, nullptr, nullptr));
   return w;
+}
+
+// Workspace of a fused batch: trace job table, ray state of all jobs, records of all jobs,
+// synthesis scratch (visible list sorted by job, chunk tables, partial spectra, gradients).
+struct FusedPlan {
+  int64_t N = 0, cap = 0;
+  size_t tj = 0, tw = 0, pp = 0, sy = 0, total = 0;
+};
+
+FusedPlan fused_plan(et_ctx* ctx, int32_t J, const et_job* jobs) {
+  FusedPlan f;
+  f.N = trace_batch_rays(J, jobs);
+  for (int32_t j = 0; j < J; ++j) f.cap += records_upper_bound(jobs[j].sim);
+  f.cap = std::max<int64_t>(f.cap, 1);
+  f.tj = al(trace_batch_jobs_bytes(J));
+  f.tw = al(trace_ws_layout(f.N, 0, 0, 0, nullptr, nullptr, TUNE_MAX_TRACE_BLOCKS));
+  f.pp = al(paths_bytes(f.cap));
+  f.sy = al(synth_batch_ws_layout(J, jobs, f.cap, ctx->tune, true, nullptr, nullptr));
+  f.total = f.tj + f.tw + f.pp + f.sy;
+  return f;
+}
+
+// Workspace of a batch run job after job: the largest job's scratch plus every job's records.
+size_t sequential_bytes(int32_t J, const et_job* jobs) {
+  size_t mx = 0, paths = 0;
+  for (int j = 0; j < J; ++j) {
+    const int64_t cap = std::max<int64_t>(records_upper_bound(jobs[j].sim), 1);
+    mx = std::max(mx, plan(jobs[j].scene, jobs[j].sim, cap).total());
+    paths += paths_bytes(cap);
+  }
+  return mx + paths;
 }
 
 void check_scene(const et_scene* sc) { ET_CHECK(sc, ET_E_INVALID, "scene is NULL"); }
@@ -141,7 +187,7 @@ void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* w
   ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
   trace_run(sc->d, sim, paths, tw, ctx->ctl, ctx->counting, ctx->stream);
   ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  ctx->timed_trace = true;
+  ctx->timed |= TM_TRACE;
   ctx->last_count = paths->count;
 }
 
@@ -158,7 +204,7 @@ void synth_impl(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void
   ET_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
   ctx->synth_kernel = synth_run(sim, paths, sw, ctx->ctl, spectra, ctx->stream, ctx->ev[8], ctx->ev[9]);
   ET_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
-  ctx->timed_synth = true;
+  ctx->timed |= TM_SYNTH | TM_SYNTH_K;
 }
 
 // number of records to synthesise = min(paths count, capacity); written into the control block
@@ -298,7 +344,7 @@ int et_workspace_size(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim
 int et_trace(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, void* ws, size_t ws_bytes,
              const et_paths* paths) {
   return guarded(ctx, [&] {
-    ctx->timed_synth = false;
+    ctx->timed = 0;
     trace_impl(ctx, scene, sim, ws, ws_bytes, paths);
   });
 }
@@ -307,7 +353,7 @@ int et_synthesize(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, vo
                   float* spectra) {
   return guarded(ctx, [&] {
     validate_paths(paths);
-    ctx->timed_trace = false;
+    ctx->timed = 0;
     k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
     ET_HIP(hipGetLastError());
     synth_impl(ctx, sim, paths, ws, ws_bytes, spectra, false);
@@ -320,6 +366,7 @@ int et_simulate(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, cons
     check_scene(scene);
     validate_sim(sim, true);
     validate_paths(paths);
+    ctx->timed = 0;
     const WsPlan w = plan(scene, sim, std::max<int64_t>(paths->capacity, 1));
     ET_CHECK(ws, ET_E_INVALID, "workspace is NULL");
     ET_CHECK(ws_bytes >= w.trace + w.synth, ET_E_WORKSPACE, "workspace too small for et_simulate");
@@ -347,22 +394,18 @@ int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* 
     ctx->adjoint_kernel = synth_bwd_run(sim, paths, grad_spectra, sw, ctx->ctl, grad_k, grad_rx, ctx->stream,
                                         ctx->ev[10], ctx->ev[11]);
     ET_HIP(hipEventRecord(ctx->ev[7], ctx->stream));
-    ctx->timed_adjoint = true;
+    ctx->timed = TM_ADJ | TM_ADJ_K;
   });
 }
 
 int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes) {
   return guarded(ctx, [&] {
     ET_CHECK(J >= 1 && jobs && bytes, ET_E_INVALID, "need J >= 1, jobs and bytes");
-    size_t mx = 0, paths = 0;
     for (int j = 0; j < J; ++j) {
       check_scene(jobs[j].scene);
       validate_sim(jobs[j].sim, true);
-      const int64_t cap = std::max<int64_t>(records_upper_bound(jobs[j].sim), 1);
-      mx = std::max(mx, plan(jobs[j].scene, jobs[j].sim, cap).total());
-      paths += al(cap * (24 + 12 + 8 + 4 + 4 + 4 + 1 + 1)) + al(8 * sizeof(int64_t)) + 8 * 256;
     }
-    *bytes = mx + paths;
+    *bytes = batch_fused(J, jobs) ? fused_plan(ctx, J, jobs).total : sequential_bytes(J, jobs);
   });
 }
 
@@ -387,24 +430,57 @@ et_paths carve_paths(char*& p, int64_t cap) {
   return P;
 }
 
+// timed: record the phase events (trace, synthesis kernel, adjoint kernel) of a fused batch
 void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
-                const float* grad_spectra, double* grad_k, double* grad_rx) {
+                const float* grad_spectra, double* grad_k, double* grad_rx, bool timed = false) {
   ET_CHECK(J >= 1 && jobs, ET_E_INVALID, "need J >= 1 jobs");
   ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
   const et_sim_desc* s0 = jobs[0].sim;
-  size_t mx = 0;
   for (int j = 0; j < J; ++j) {
     check_scene(jobs[j].scene);
     validate_sim(jobs[j].sim, true);
     const et_sim_desc* s = jobs[j].sim;
     ET_CHECK(s->M == s0->M && s->F == s0->F && s->Q == s0->Q && s->Bk == s0->Bk, ET_E_INVALID,
              "jobs of a batch must share M, F, Q and Bk");
-    const int64_t cap = std::max<int64_t>(records_upper_bound(s), 1);
-    mx = std::max(mx, plan(jobs[j].scene, s, cap).total());
+    if (grad_spectra)
+      ET_CHECK(!s->directivity && s->Bk <= 16 && s->Q * s->Bk <= 256 && s->F <= 12288, ET_E_UNSUPPORTED,
+               "adjoint limits exceeded");
   }
+  if (grad_spectra) ET_CHECK(grad_k && grad_rx, ET_E_INVALID, "gradient outputs are NULL");
   size_t need = 0;
   ET_CHECK(et_batch_workspace_size(ctx, J, jobs, &need) == ET_OK, ET_E_INVALID, "batch workspace query failed");
   ET_CHECK(ws && ws_bytes >= need, ET_E_WORKSPACE, "workspace too small for et_simulate_batch");
+  ctx->last_count = nullptr;
+  if (batch_fused(J, jobs)) {
+    const FusedPlan f = fused_plan(ctx, J, jobs);
+    char* base = (char*)ws;
+    void* dj = base;
+    base += f.tj;
+    TraceWS tw;
+    trace_ws_layout(f.N, 0, 0, 0, base, &tw, TUNE_MAX_TRACE_BLOCKS);
+    base += f.tw;
+    char* pp = base;
+    et_paths P = carve_paths(pp, f.cap);
+    base += f.pp;
+    SynthBatchWS sw;
+    synth_batch_ws_layout(J, jobs, f.cap, ctx->tune, true, base, &sw);
+    if (timed) ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+    trace_batch_run(J, jobs, dj, &P, tw, ctx->ctl, ctx->counting, ctx->tune.trace_blocks, ctx->stream);
+    if (timed) ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
+    int ak = 0;
+    const hipEvent_t kev[4] = {ctx->ev[8], ctx->ev[9], ctx->ev[10], ctx->ev[11]};
+    ctx->synth_kernel = synth_batch_run(J, jobs, &P, sw, ctx->ctl, spectra, grad_spectra, grad_k, grad_rx, &ak,
+                                        timed ? kev : nullptr, ctx->stream);
+    if (grad_spectra) ctx->adjoint_kernel = ak;
+    ctx->timed = timed ? (TM_TRACE | TM_SYNTH_K | (grad_spectra ? TM_ADJ_K : 0u)) : 0u;
+    return;
+  }
+  size_t mx = 0;
+  for (int j = 0; j < J; ++j) {
+    const int64_t cap = std::max<int64_t>(records_upper_bound(jobs[j].sim), 1);
+    mx = std::max(mx, plan(jobs[j].scene, jobs[j].sim, cap).total());
+  }
   char* pp = (char*)ws + mx;
   const size_t MF2 = (size_t)s0->M * s0->F * 2;
   for (int j = 0; j < J; ++j) {
@@ -421,13 +497,11 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     synth_ws_layout(s, cap, (char*)ws + w.trace, &sw);
     ctx->synth_kernel = synth_run(s, &P, sw, ctx->ctl, spectra + (size_t)j * MF2, ctx->stream);
     if (grad_spectra) {
-      ET_CHECK(grad_k && grad_rx, ET_E_INVALID, "gradient outputs are NULL");
-      ET_CHECK(!s->directivity && s->Bk <= 16 && s->Q * s->Bk <= 256 && s->F <= 12288, ET_E_UNSUPPORTED,
-               "adjoint limits exceeded");
       SynthWS bw;
       synth_bwd_ws_layout(s, cap, (char*)ws + w.trace + w.synth, &bw);
-      ctx->adjoint_kernel = synth_bwd_run(s, &P, grad_spectra + (size_t)j * MF2, bw, ctx->ctl, grad_k + (size_t)j * s->Q * s->Bk,
-                    grad_rx + (size_t)j * s->M * 3, ctx->stream);
+      ctx->adjoint_kernel = synth_bwd_run(s, &P, grad_spectra + (size_t)j * MF2, bw, ctx->ctl,
+                                          grad_k + (size_t)j * s->Q * s->Bk, grad_rx + (size_t)j * s->M * 3,
+                                          ctx->stream);
     }
   }
 }
@@ -439,8 +513,8 @@ extern "C" {
 int et_simulate_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
                       const float* grad_spectra, double* grad_k, double* grad_rx) {
   return guarded(ctx, [&] {
-    ctx->timed_trace = ctx->timed_synth = ctx->timed_adjoint = false;
-    batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx);
+    ctx->timed = 0;
+    batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx, true);
   });
 }
 
@@ -458,6 +532,8 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
     key.push_back((uint64_t)(uintptr_t)grad_spectra);
     key.push_back((uint64_t)(uintptr_t)grad_k);
     key.push_back((uint64_t)(uintptr_t)grad_rx);
+    key.push_back(((uint64_t)(uint32_t)ctx->tune.synth_wgs << 32) | (uint32_t)ctx->tune.adjoint_wgs);
+    key.push_back((uint64_t)(uint32_t)ctx->tune.trace_blocks);
     for (int j = 0; j < J; ++j) {
       key.push_back((uint64_t)(uintptr_t)jobs[j].scene);
       const uint64_t* w = reinterpret_cast<const uint64_t*>(jobs[j].sim);
@@ -479,7 +555,7 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
       ET_HIP(hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
       ctx->graph_key = key;
     }
-    ctx->timed_trace = ctx->timed_synth = false;
+    ctx->timed = 0;
     ET_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
   });
 }
@@ -513,11 +589,14 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
       out->records = cnt[0];
     }
     float ms = 0;
-    if (ctx->timed_trace && hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) out->ms_trace = ms;
-    if (ctx->timed_synth && hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]) == hipSuccess) out->ms_synth = ms;
-    if (ctx->timed_synth && hipEventElapsedTime(&ms, ctx->ev[8], ctx->ev[9]) == hipSuccess) out->ms_synth_kernel = ms;
-    if (ctx->timed_adjoint && hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) == hipSuccess) out->ms_adjoint = ms;
-    if (ctx->timed_adjoint && hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]) == hipSuccess)
+    auto pair = [&](uint32_t bit, int a, int b, double& dst) {
+      if ((ctx->timed & bit) && hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) == hipSuccess) dst = ms;
+    };
+    pair(TM_TRACE, 0, 1, out->ms_trace);
+    pair(TM_SYNTH, 4, 5, out->ms_synth);
+    pair(TM_SYNTH_K, 8, 9, out->ms_synth_kernel);
+    pair(TM_ADJ, 6, 7, out->ms_adjoint);
+    if ((ctx->timed & TM_ADJ_K) && hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]) == hipSuccess)
       out->ms_adjoint_kernel = ms;
     out->adjoint_kernel = ctx->adjoint_kernel;
     uint32_t err = h.err;
@@ -536,6 +615,78 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
     return out->status;
   }
   return rc;
+}
+
+int et_get_tuning(et_ctx* ctx, et_tuning* out) {
+  return guarded(ctx, [&] {
+    ET_CHECK(out, ET_E_INVALID, "tuning is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->synth_wgs = ctx->tune.synth_wgs;
+    out->adjoint_wgs = ctx->tune.adjoint_wgs;
+    out->trace_blocks = ctx->tune.trace_blocks;
+  });
+}
+
+int et_set_tuning(et_ctx* ctx, const et_tuning* t) {
+  return guarded(ctx, [&] {
+    ET_CHECK(t, ET_E_INVALID, "tuning is NULL");
+    auto in = [](int32_t v, int32_t hi) { return v >= 64 && v <= hi; };
+    ET_CHECK(in(t->synth_wgs, TUNE_MAX_WGS) && in(t->adjoint_wgs, TUNE_MAX_WGS) &&
+                 in(t->trace_blocks, TUNE_MAX_TRACE_BLOCKS),
+             ET_E_INVALID, "tuning values must lie in 64 .. 4096");
+    ctx->tune.synth_wgs = t->synth_wgs;
+    ctx->tune.adjoint_wgs = t->adjoint_wgs;
+    ctx->tune.trace_blocks = t->trace_blocks;
+  });
+}
+
+int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
+                      const float* grad_spectra, double* grad_k, double* grad_rx, et_tuning* out) {
+  return guarded(ctx, [&] {
+    ET_CHECK(out, ET_E_INVALID, "tuning is NULL");
+    ET_CHECK(J >= 1 && jobs, ET_E_INVALID, "need J >= 1 jobs");
+    for (int j = 0; j < J; ++j) {
+      check_scene(jobs[j].scene);
+      validate_sim(jobs[j].sim, true);
+    }
+    ET_CHECK(batch_fused(J, jobs), ET_E_UNSUPPORTED, "autotuning applies to fused (specular-only) batches");
+    const int32_t cw[4] = {512, 1024, 2048, 4096};
+    const int32_t cb[4] = {1024, 1280, 2048, 4096};
+    auto run = [&](double* t) {
+      batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx, true);
+      ET_HIP(hipStreamSynchronize(ctx->stream));
+      float ms = 0.f;
+      ET_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+      t[0] = ms;
+      ET_HIP(hipEventElapsedTime(&ms, ctx->ev[8], ctx->ev[9]));
+      t[1] = ms;
+      t[2] = 0.0;
+      if (grad_spectra) {
+        ET_HIP(hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]));
+        t[2] = ms;
+      }
+    };
+    double t[3], best[3] = {INFINITY, INFINITY, INFINITY};
+    BatchTune pick = ctx->tune;
+    run(t);   // warm-up
+    for (int i = 0; i < 4; ++i) {
+      ctx->tune.synth_wgs = ctx->tune.adjoint_wgs = cw[i];
+      ctx->tune.trace_blocks = cb[i];
+      run(t);
+      if (t[0] < best[0]) { best[0] = t[0]; pick.trace_blocks = cb[i]; }
+      if (t[1] < best[1]) { best[1] = t[1]; pick.synth_wgs = cw[i]; }
+      if (grad_spectra && t[2] < best[2]) { best[2] = t[2]; pick.adjoint_wgs = cw[i]; }
+    }
+    ctx->tune = pick;
+    run(t);
+    std::memset(out, 0, sizeof(*out));
+    out->synth_wgs = pick.synth_wgs;
+    out->adjoint_wgs = pick.adjoint_wgs;
+    out->trace_blocks = pick.trace_blocks;
+    out->ms_trace = t[0];
+    out->ms_synth = t[1];
+    out->ms_adjoint = t[2];
+  });
 }
 
 int et_set_counting(et_ctx* ctx, int enable) {

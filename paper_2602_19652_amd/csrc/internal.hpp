@@ -172,7 +172,15 @@ struct TraceWS {
 };
 
 // Workspace layout of et_trace.  base == nullptr: only computes the size.
-size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* ws);
+// max_blocks: largest bounce-kernel grid the workspace serves (0: the single-pose default)
+size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* ws,
+                       int32_t max_blocks = 0);
+// Fused batch (specular jobs): all jobs' rays share the bounce kernels; records carry the
+// job index in their ray field.  dev_jobs holds trace_batch_jobs_bytes(J) bytes.
+size_t trace_batch_jobs_bytes(int32_t J);
+int64_t trace_batch_rays(int32_t J, const et_job* jobs);
+void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_paths* paths, const TraceWS& w,
+                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s);
 void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& ws, Ctl* ctl,
                bool counting, hipStream_t s);
 
@@ -204,5 +212,48 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
                   Ctl* ctl, double* grad_k, double* grad_rx, hipStream_t s, hipEvent_t kb = nullptr,
                   hipEvent_t ke = nullptr);
 bool synth_factorised_ok(const et_sim_desc* sim);
+bool synth_bwd_factorised_ok(const et_sim_desc* sim);
+
+// Launch shapes of the fused batch (the autotuner's knobs): workgroups of the main synthesis
+// and adjoint kernels the record chunks aim at.
+struct BatchTune {
+  int32_t synth_wgs = 2048;
+  int32_t adjoint_wgs = 1024;
+  int32_t trace_blocks = 2048;    // grid of the bounce kernels (grid-stride over the active rays)
+};
+// Largest values the autotuner tries; workspaces are sized for them.
+constexpr int32_t TUNE_MAX_WGS = 4096;
+constexpr int32_t TUNE_MAX_TRACE_BLOCKS = 4096;
+
+// Fused batch synthesis: the visible records of all jobs, sorted by job, in chunks that never
+// mix jobs; one launch of the synthesis (and adjoint) kernel for the whole batch.
+struct SynthBatchWS {
+  int32_t J;
+  int64_t cap;
+  bool mf, mf_bwd;
+  int32_t target, target_bwd;   // chunk count the batch aims at
+  int32_t chunks, chunks_bwd;   // grid size: target + J bounds the chunk count
+  int32_t T1;                   // adjoint tiles of outer indices
+  float* partial;               // [chunks][M][F][2]
+  double* gpart_x;              // [chunks][T1][M][3]
+  double* gpart_k;              // [chunks][T1][M][Q][Bk]
+  uint64_t* vflags;
+  uint64_t* voffs;
+  int32_t* vidx;
+  void* vscan;
+  uint64_t* keys;               // job of each visible record (sort keys)
+  void* sort_tmp;
+  int64_t* tab;                 // chunk tables (forward, adjoint)
+  void* jobs;                   // device job table
+  float* tables;                // [J][3][Q][Bk] band tables
+};
+bool synth_batch_factorised(int32_t J, const et_job* jobs, bool adjoint);
+size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const BatchTune& tune, bool adjoint,
+                             char* base, SynthBatchWS* ws);
+// returns the forward kernel (1 MFMA, 2 direct); *adjoint_kernel likewise when grad != nullptr
+// ev (optional): 4 events recorded around the synthesis kernel and the adjoint kernel
+int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const SynthBatchWS& w, Ctl* ctl,
+                    float* spectra, const float* grad, double* grad_k, double* grad_rx, int* adjoint_kernel,
+                    const hipEvent_t* ev, hipStream_t s);
 
 }  // namespace et

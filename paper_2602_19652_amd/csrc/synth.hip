@@ -176,6 +176,44 @@ __device__ inline void chunk_range(int64_t n, int32_t P, int p, int64_t& lo, int
   hi = std::min<int64_t>(lo + per, n);
 }
 
+// Chunks of a fused batch: the visible records are sorted by job, job j owns positions
+// [lo[j], hi[j]) and chunks [off[j], off[j + 1]) of at most `per` records each, so no chunk
+// mixes jobs.  off[J] is the batch's chunk count.
+struct ChunkTab {
+  const int64_t* off;   // [J + 1]
+  const int64_t* lo;    // [J]
+  const int64_t* hi;    // [J]
+  const int64_t* per;   // [1]
+  int32_t J;
+};
+
+// Resolves chunk c to its job and record range; false if c is past the batch's chunks.
+__device__ inline bool batch_chunk(const ChunkTab& ct, int64_t c, int& j, int64_t& lo, int64_t& hi) {
+  if (c >= ct.off[ct.J]) return false;
+  int a = 0, b = ct.J - 1;   // last job with off <= c (jobs without chunks share off with the next)
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (ct.off[mid] <= c) a = mid;
+    else b = mid - 1;
+  }
+  j = a;
+  lo = ct.lo[a] + (c - ct.off[a]) * ct.per[0];
+  hi = std::min<int64_t>(lo + ct.per[0], ct.hi[a]);
+  return true;
+}
+
+// Common prologue: the workgroup's arguments and record range, plain or batched.
+#define SYNTH_RESOLVE()                                                      \
+  SynthArgs a = a0;                                                          \
+  int64_t lo, hi;                                                            \
+  int jb = 0;                                                                \
+  if (BATCH) {                                                               \
+    if (!batch_chunk(ct, blockIdx.x, jb, lo, hi)) return;                    \
+    a = jobs[jb];                                                            \
+  } else {                                                                   \
+    chunk_range(ctl->n_vis, a.P, blockIdx.x, lo, hi);                        \
+  }
+
 // ------------------------------------------------------------------ visible-record list
 
 __global__ void k_vis_flags(et_paths P, const Ctl* ctl, uint64_t* __restrict__ flags) {
@@ -376,12 +414,42 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
   __builtin_amdgcn_wave_barrier();
 }
 
+// NK contraction steps of 4 records from record kk0: the (k1, k2) block of rows xrow0 + [0, 32)
+// and columns 32 h2 + [0, 32), Gauss forms built as the operands are loaded.
+template <int NK>
+__device__ inline void contract(const GaussBuf& buf, int kk0, int xrow0, int h2, int lane, floatx4 (&acc)[3][2][2]) {
+#pragma unroll
+  for (int kq = 0; kq < NK; ++kq) {
+    const int rr = kk0 + 4 * kq + (lane >> 4), cc = lane & 15;
+    float av[3][2], bv[3][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float xr = buf.X[0][rr][xrow0 + i * 16 + cc], xi = buf.X[1][rr][xrow0 + i * 16 + cc];
+      const float yr = buf.Y[0][rr][h2 * 32 + i * 16 + cc], yi = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
+      av[0][i] = xr + xi; av[1][i] = xr; av[2][i] = xi;
+      bv[0][i] = yr; bv[1][i] = yi - yr; bv[2][i] = yr + yi;
+    }
+#pragma unroll
+    for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          acc[tt][i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt][i], bv[tt][jj], acc[tt][i][jj], 0, 0, 0);
+  }
+}
+
 // Workgroup = (record chunk p, receiver m, 64 outer indices).  Every 8 stages each wave sets
 // up 64 records (one per lane); every stage each wave generates 8 of them, then each wave
 // contracts all 32 records of the stage into its 32 x 32 block of (k1, k2) on the matrix
-// cores.  Three workgroups share a CU, so one's generation hides another's latency.
-__global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
-                                                    const Ctl* ctl, float* __restrict__ part) {
+// cores.  SPLIT (a single tile of at most 32 outer indices, e.g. 2048 bins, so one row
+// block): the wave pairs split each stage's records instead and add their accumulators at
+// the end.
+template <bool BATCH, bool SPLIT>
+__global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
+                                                    et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
+                                                    float* __restrict__ part) {
+  SYNTH_RESOLVE();
   __shared__ __align__(16) GaussBuf buf;
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
@@ -392,10 +460,9 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
-  int64_t lo, hi;
-  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
   const int h1 = wv >> 1, h2 = wv & 1;                        // this wave's 32 x 32 block of (k1, k2)
+  const int xrow0 = SPLIT ? 0 : h1 * 32;                      // SPLIT: one row block, records split
   floatx4 acc[3][2][2];
 #pragma unroll
   for (int t = 0; t < 3; ++t)
@@ -411,28 +478,36 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
     generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &buf.X[0][0][0], &buf.X[1][0][0],
              &buf.Y[0][0][0], &buf.Y[1][0][0], XS, 1, wscr[wv]);
     __syncthreads();
+    if (SPLIT) contract<RB / 8>(buf, h1 * (RB / 2), 0, h2, lane, acc);
+    else contract<RB / 4>(buf, 0, xrow0, h2, lane, acc);
+    __syncthreads();
+  }
+  if (SPLIT) {
+    // the second wave of each pair hands its accumulators over through the (now idle) buffer
+    static_assert(sizeof(GaussBuf) >= sizeof(float) * 2 * 48 * 64, "hand-over space");
+    float* xs = reinterpret_cast<float*>(&buf);
+    if (h1 == 1) {
 #pragma unroll
-    for (int kk = 0; kk < RB; kk += 4) {
-      const int rr = kk + (lane >> 4), cc = lane & 15;
-      float av[3][2], bv[3][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float xr = buf.X[0][rr][h1 * 32 + i * 16 + cc], xi = buf.X[1][rr][h1 * 32 + i * 16 + cc];
-        const float yr = buf.Y[0][rr][h2 * 32 + i * 16 + cc], yi = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
-        av[0][i] = xr + xi; av[1][i] = xr; av[2][i] = xi;
-        bv[0][i] = yr; bv[1][i] = yi - yr; bv[2][i] = yr + yi;
-      }
-#pragma unroll
-      for (int tt = 0; tt < 3; ++tt)
+      for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj)
-            acc[tt][i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt][i], bv[tt][jj], acc[tt][i][jj], 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xs[((((h2 * 3 + t) * 2 + i) * 2 + jj) * 4 + v) * 64 + lane] = acc[t][i][jj][v];
     }
     __syncthreads();
+    if (h1 == 1) return;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[t][i][jj][v] += xs[((((h2 * 3 + t) * 2 + i) * 2 + jj) * 4 + v) * 64 + lane];
   }
-  // accumulator (i, jj, v) of lane l holds row k1 = 16 i + 4 (l / 16) + v, column k2 = 16 jj + l % 16
+  // accumulator (i, jj, v) of lane l holds row k1 = xrow0 + 16 i + 4 (l / 16) + v, column k2 = 16 jj + l % 16
   float* out = part + (((size_t)p * a.M + m) * a.F) * 2;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -440,7 +515,7 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a, et_paths P, con
     for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int k1 = h1 * 32 + i * 16 + (lane >> 4) * 4 + v, k2 = h2 * 32 + jj * 16 + (lane & 15);
+        const int k1 = xrow0 + i * 16 + (lane >> 4) * 4 + v, k2 = h2 * 32 + jj * 16 + (lane & 15);
         if (k1 < nk1) {
           const size_t o = (size_t)((k1_0 + k1) * K2 + k2) * 2;
           out[o] = acc[0][i][jj][v] - acc[2][i][jj][v];
@@ -464,14 +539,15 @@ struct DirectLds {
   float dirl[DRB][DBMAX];
 };
 
-__global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
-                                                     const Ctl* ctl, float* __restrict__ part) {
+template <bool BATCH>
+__global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
+                                                     et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
+                                                     float* __restrict__ part) {
+  SYNTH_RESOLVE();
   __shared__ DirectLds L;
   const int p = blockIdx.x, m = blockIdx.y;
   const int tid = threadIdx.x;
   const int kbase = blockIdx.z * DTILE + tid * DPT;
-  int64_t lo, hi;
-  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   int bk[DPT], bd[DPT];
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
@@ -546,9 +622,13 @@ __global__ void k_reduce_partials(const float* __restrict__ part, int32_t P, int
 constexpr int GB = 256;
 constexpr int GANCHOR = 32;   // bins between exact re-anchoring of the rotation recurrence
 
-__global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
-                                                 const Ctl* ctl, const float* __restrict__ g,
-                                                 double* __restrict__ gpx, double* __restrict__ gpk) {
+template <bool BATCH>
+__global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
+                                                 et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
+                                                 const float* __restrict__ g, double* __restrict__ gpx,
+                                                 double* __restrict__ gpk) {
+  SYNTH_RESOLVE();
+  if (BATCH) g += (size_t)jb * a.M * a.F * 2;
   extern __shared__ float2 gl[];   // dL/dconj(H) of this receiver, [F]
   __shared__ double red[GB];
   __shared__ double kval[16][GB];
@@ -557,8 +637,6 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a, et_paths P, const
   const int p = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
   for (int k = tid; k < a.F; k += GB) gl[k] = make_float2(g[((size_t)m * a.F + k) * 2], g[((size_t)m * a.F + k) * 2 + 1]);
   for (int i = tid; i < a.Q * a.Bk; i += GB) kacc[i] = 0.0;
-  int64_t lo, hi;
-  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   double gx0 = 0, gx1 = 0, gx2 = 0;
   const double ln10 = 2.30258509299404568402;
   __syncthreads();
@@ -698,12 +776,16 @@ struct BwdBuf {
   float R0[RB][KT1 + 1];     // Re(X Z) per (record, row)
   float2 R1[RB][17];         // sum over 4 rows of X (f Z + df Z') per (record, row group)
   double kv[RB][16];         // dL/dk contribution per (record, band)
-  int32_t kmat[RB];          // material of a specular record, -1 otherwise
+  uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
 };
 
-__global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths P, const int32_t* __restrict__ idx,
+template <bool BATCH>
+__global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
+                                                        ChunkTab ct, et_paths P, const int32_t* __restrict__ idx,
                                                         const Ctl* ctl, const float* __restrict__ g,
                                                         double* __restrict__ gpx, double* __restrict__ gpk) {
+  SYNTH_RESOLVE();
+  if (BATCH) g += (size_t)jb * a.M * a.F * 2;
   __shared__ __align__(16) BwdBuf bb;
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
@@ -715,9 +797,14 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
-  // A operands: rows k1 = 16 wv + lane % 16 of G, columns k2 = 4 ks + lane / 16, as Gauss forms
+  // wave -> block of 16 rows; a tile of at most 32 rows (two blocks) gives each wave pair one
+  // block and each wave of a pair one of the stage's two record blocks
+  const bool split = nk1 <= 32;
+  const int rbw = split ? (wv & 1) : wv;
+  const int nbw = split ? (wv >> 1) : -1;
+  // A operands: rows k1 = 16 rbw + lane % 16 of G, columns k2 = 4 ks + lane / 16, as Gauss forms
   float ga[3][16];
-  const int r1g = wv * 16 + (lane & 15);
+  const int r1g = rbw * 16 + (lane & 15);
 #pragma unroll
   for (int ks = 0; ks < 16; ++ks) {
     float gr = 0.f, gi = 0.f;
@@ -729,13 +816,12 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
     ga[0][ks] = gr + gi; ga[1][ks] = gr; ga[2][ks] = gi;
   }
   const float frow0 = (float)(a.f_lo + (double)(k1_0 * K2) * a.df), df64 = (float)(K2 * a.df), dff = (float)a.df;
-  int64_t lo, hi;
-  chunk_range(ctl->n_vis, a.P, p, lo, hi);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;
   const double ln10 = 2.30258509299404568402;
   const int QB = a.Q * a.Bk;
   double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
+  for (int i = tid; i < a.Q; i += 256) bb.kmask[0][i] = bb.kmask[1][i] = 0u;   // first used after two barriers
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
@@ -754,6 +840,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
       const float w2 = (float)kk;
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
+        if (nbw >= 0 && nb != nbw) continue;
         const int nn = nb * 16 + (lane & 15);
         const float yr = bb.Yt[0][kk][nn], yi = bb.Yt[1][kk][nn];
         const float b0 = yr, b1 = yi - yr, b2 = yr + yi;
@@ -765,14 +852,15 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
         acc[5][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], w2 * b2, acc[5][nb], 0, 0, 0);
       }
     }
-    // accumulator (nb, v) of lane l: row 16 wv + 4 (l / 16) + v, record 16 nb + l % 16
+    // accumulator (nb, v) of lane l: row 16 rbw + 4 (l / 16) + v, record 16 nb + l % 16
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
+      if (nbw >= 0 && nb != nbw) continue;
       const int n = nb * 16 + (lane & 15);
       float s1r = 0.f, s1i = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r1 = wv * 16 + (lane >> 4) * 4 + v;
+        const int r1 = rbw * 16 + (lane >> 4) * 4 + v;
         const float zr = acc[0][nb][v] - acc[2][nb][v], zi = acc[0][nb][v] + acc[1][nb][v];
         const float wr = acc[3][nb][v] - acc[5][nb][v], wi = acc[3][nb][v] + acc[4][nb][v];
         const float xr = bb.X[0][n][r1], xi = bb.X[1][n][r1];
@@ -782,7 +870,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
         s1r += fr * cr + dff * (xr * wr - xi * wi);
         s1i += fr * ci + dff * (xr * wi + xi * wr);
       }
-      bb.R1[n][wv * 4 + (lane >> 4)] = make_float2(s1r, s1i);
+      bb.R1[n][rbw * 4 + (lane >> 4)] = make_float2(s1r, s1i);
     }
     __syncthreads();
     {
@@ -798,8 +886,10 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
         mat = P.mat[rn];
       }
       double s1r = 0.0, s1i = 0.0;
+      const int ngroups = split ? 8 : 16;   // row groups of 4 written this stage
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
+        if (j + 8 * h >= ngroups) continue;
         const float2 c = bb.R1[n][j + 8 * h];
         s1r += (double)c.x;
         s1i += (double)c.y;
@@ -831,7 +921,10 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
         s0 += __shfl_xor(s0, o);
         wl += __shfl_xor(wl, o);
       }
-      if (j == 0) bb.kmat[n] = valid && kind == 0 ? mat : -1;
+      // record n joins its material's mask of this stage (an OR: the result is order-free);
+      // the other parity's masks (read by the previous stage) are cleared for the next one
+      if (j == 0 && valid && kind == 0) atomicOr(&bb.kmask[s & 1][mat], 1u << n);
+      for (int i = tid; i < a.Q; i += 256) bb.kmask[(s + 1) & 1][i] = 0u;
       if (j == 0 && valid) {
         // receiver leg and path in FP64, as in the forward set-up
         const double wx = a.rx_pos[3 * m] - P.p[3 * rn], wy = a.rx_pos[3 * m + 1] - P.p[3 * rn + 1],
@@ -862,9 +955,14 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a, et_paths
     }
     __syncthreads();
     if (tid < QB) {
+      // this material's records of the stage, in increasing order
       const int qq = tid / a.Bk, b = tid - qq * a.Bk;
-      for (int n = 0; n < RB; ++n)
-        if (bb.kmat[n] == qq) kacc += bb.kv[n][b];
+      uint32_t mk = bb.kmask[s & 1][qq];
+      while (mk) {
+        const int n = __ffs(mk) - 1;
+        kacc += bb.kv[n][b];
+        mk &= mk - 1u;
+      }
     }
   }
   const size_t slot = ((size_t)p * gridDim.z + k1t) * a.M + m;
@@ -949,6 +1047,105 @@ void build_vis(const et_paths& P, const SynthWS& ws, int64_t cap, Ctl* ctl, hipS
   ET_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ fused batches
+
+constexpr int SJOB_PACK = 16;
+struct SynthJobPack {
+  SynthArgs j[SJOB_PACK];
+  int32_t first, n;
+};
+static_assert(sizeof(SynthJobPack) <= 4000, "job pack must fit the kernel argument space");
+
+__global__ void k_put_synth_jobs(SynthJobPack pk, SynthArgs* __restrict__ dst) {
+  if ((int)threadIdx.x < pk.n) dst[pk.first + threadIdx.x] = pk.j[threadIdx.x];
+}
+
+// workgroup j fills job j's band tables (its lk / lc / ld point into the batch's table block)
+__global__ void k_band_tables_batch(const SynthArgs* __restrict__ jobs) {
+  const SynthArgs a = jobs[blockIdx.x];
+  for (int i = threadIdx.x; i < a.Q * a.Bk; i += blockDim.x) {
+    const float bt = a.beta[i];
+    const_cast<float*>(a.lk)[i] = log2f(a.refl_k[i]);
+    const_cast<float*>(a.lc)[i] = LOG2E_F / (2.0f * bt * bt);
+    const_cast<float*>(a.ld)[i] = log2f(a.dcoef[i]);
+  }
+}
+
+// sort key of each visible record: its job (the ray field of a batch record)
+__global__ void k_vis_jobkeys(et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl, uint64_t* __restrict__ keys) {
+  const int64_t n = ctl->n_vis;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = (uint64_t)(uint32_t)P.ray[idx[i]];
+}
+
+// Per-job ranges of the job-sorted visible list and chunk offsets: chunks of
+// per = ceil(n_vis / target) records, never crossing a job.  One workgroup.
+__global__ void k_job_chunks(const uint64_t* __restrict__ keys, const Ctl* ctl, int32_t J, int64_t target,
+                             int64_t* __restrict__ off, int64_t* __restrict__ lo, int64_t* __restrict__ hi,
+                             int64_t* __restrict__ per) {
+  const int64_t n = ctl->n_vis;
+  const int64_t pc = std::max<int64_t>(1, (n + target - 1) / target);
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    int64_t a = 0, b = n;   // first position with key >= j
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (keys[mid] < (uint64_t)j) a = mid + 1;
+      else b = mid;
+    }
+    const int64_t l = a;
+    b = n;                  // first position with key >= j + 1
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (keys[mid] < (uint64_t)j + 1) a = mid + 1;
+      else b = mid;
+    }
+    lo[j] = l;
+    hi[j] = a;
+    off[j + 1] = (a - l + pc - 1) / pc;   // chunk count, turned into offsets below
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    for (int j = 0; j < J; ++j) off[j + 1] += off[j];
+    per[0] = pc;
+  }
+}
+
+__global__ void k_reduce_batch(const float* __restrict__ part, ChunkTab ct, int64_t MF2, float* __restrict__ out) {
+  const int64_t total = (int64_t)ct.J * MF2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / MF2, r = e - j * MF2;
+    float s = 0.f;
+    for (int64_t c = ct.off[j]; c < ct.off[j + 1]; ++c) s += part[c * MF2 + r];
+    out[e] = s;
+  }
+}
+
+// per job: dL/dk[Q Bk] and dL/dx[M][3] summed over its chunks, tiles and receivers in a fixed order
+__global__ void k_bwd_reduce_batch(const double* __restrict__ gpx, const double* __restrict__ gpk, ChunkTab ct,
+                                   int32_t T1, int32_t M, int32_t QB, double* __restrict__ grad_k,
+                                   double* __restrict__ grad_x) {
+  const int per_job = max(QB, 3 * M);
+  const int64_t total = (int64_t)ct.J * per_job;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / per_job;
+    const int i = (int)(e - j * per_job);
+    if (i < QB) {
+      double s = 0.0;
+      for (int64_t c = ct.off[j]; c < ct.off[j + 1]; ++c)
+        for (int t = 0; t < T1; ++t)
+          for (int m = 0; m < M; ++m) s += gpk[(((size_t)c * T1 + t) * M + m) * QB + i];
+      grad_k[j * QB + i] = s;
+    }
+    if (i < 3 * M) {
+      double s = 0.0;
+      for (int64_t c = ct.off[j]; c < ct.off[j + 1]; ++c)
+        for (int t = 0; t < T1; ++t) s += gpx[((size_t)c * T1 + t) * M * 3 + i];
+      grad_x[j * 3 * M + i] = s;
+    }
+  }
+}
+
 }  // namespace
 
 bool synth_factorised_ok(const et_sim_desc* sim) {
@@ -1001,10 +1198,11 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(ws.P, sim->M, (K1 + KT1 - 1) / KT1);
-    k_synth_mfma<<<grid, 256, 0, s>>>(a, P, ws.vidx, ctl, ws.partial);
+    if (K1 <= 32) k_synth_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
+    else k_synth_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
   } else {
     dim3 grid(ws.P, sim->M, (sim->F + DTILE - 1) / DTILE);
-    k_synth_direct<<<grid, DB, 0, s>>>(a, P, ws.vidx, ctl, ws.partial);
+    k_synth_direct<false><<<grid, DB, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
   }
   if (ke) ET_HIP(hipEventRecord(ke, s));
   const int64_t MF2 = (int64_t)sim->M * sim->F * 2;
@@ -1052,11 +1250,13 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);
-    k_synth_bwd_mfma<<<grid, 256, 0, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+    k_synth_bwd_mfma<false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra, ws.gpart_x,
+                                                 ws.gpart_k);
   } else {
     dim3 grid(ws.gchunks, sim->M);
     const size_t shm = sizeof(float2) * (size_t)sim->F;
-    k_synth_bwd<<<grid, GB, shm, s>>>(a, P, ws.vidx, ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+    k_synth_bwd<false><<<grid, GB, shm, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra, ws.gpart_x,
+                                             ws.gpart_k);
   }
   if (ke) ET_HIP(hipEventRecord(ke, s));
   const int QB = sim->Q * sim->Bk;
@@ -1065,6 +1265,142 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
                                                 grad_rx);
   ET_HIP(hipGetLastError());
   return mf ? 1 : 2;
+}
+
+
+// ------------------------------------------------------------------ fused batches (host)
+
+namespace {
+int chunk_target(const et_sim_desc* s0, bool mf, int32_t wgs) {
+  // record chunks over the whole batch for about `wgs` workgroups of the main kernel
+  const int64_t per_chunk = mf ? (int64_t)s0->M * std::max<int64_t>(1, (s0->F / K2 + KT1 - 1) / KT1)
+                               : (int64_t)s0->M * ((s0->F + DTILE - 1) / DTILE);
+  return (int)std::max<int64_t>(1, (wgs + per_chunk - 1) / per_chunk);
+}
+}  // namespace
+
+bool synth_batch_factorised(int32_t J, const et_job* jobs, bool adjoint) {
+  for (int32_t i = 0; i < J; ++i)
+    if (!(adjoint ? synth_bwd_factorised_ok(jobs[i].sim) : synth_factorised_ok(jobs[i].sim))) return false;
+  return true;
+}
+
+size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const BatchTune& tune, bool adjoint,
+                             char* base, SynthBatchWS* ws) {
+  const et_sim_desc* s0 = jobs[0].sim;
+  cap = std::max<int64_t>(cap, 1);
+  SynthBatchWS w{};
+  w.J = J;
+  w.cap = cap;
+  w.mf = synth_batch_factorised(J, jobs, false);
+  w.mf_bwd = adjoint && synth_batch_factorised(J, jobs, true);
+  w.target = chunk_target(s0, w.mf, tune.synth_wgs);
+  w.target_bwd = chunk_target(s0, w.mf_bwd, tune.adjoint_wgs);
+  // grid size: the chunk count is at most target + J (sum_j ceil(n_j / per)); buffers are
+  // sized for the largest target the tuner tries, so that tuning keeps the workspace valid
+  w.chunks = w.target + J;
+  w.chunks_bwd = w.target_bwd + J;
+  const int64_t cmax = chunk_target(s0, w.mf, TUNE_MAX_WGS) + J;
+  const int64_t cmax_bwd = chunk_target(s0, w.mf_bwd, TUNE_MAX_WGS) + J;
+  w.T1 = w.mf_bwd ? (int)((s0->F / K2 + KT1 - 1) / KT1) : 1;
+  size_t off = 0;
+  auto take = [&](size_t b) -> void* { void* p = base ? (void*)(base + off) : nullptr; off += al(b); return p; };
+  const size_t MF2 = (size_t)s0->M * s0->F * 2;
+  w.partial = (float*)take(sizeof(float) * MF2 * (size_t)std::max<int64_t>(cmax, w.chunks));
+  if (adjoint) {
+    const size_t cb = (size_t)std::max<int64_t>(cmax_bwd, w.chunks_bwd);
+    w.gpart_x = (double*)take(sizeof(double) * 3 * cb * w.T1 * s0->M);
+    w.gpart_k = (double*)take(sizeof(double) * cb * w.T1 * s0->M * s0->Q * s0->Bk);
+  }
+  off = vis_ws(cap, base, off, &w.vflags, &w.voffs, &w.vidx, &w.vscan);
+  w.keys = (uint64_t*)take(sizeof(uint64_t) * (size_t)cap);
+  w.sort_tmp = take(sort_temp_bytes(cap, 8));
+  w.tab = (int64_t*)take(sizeof(int64_t) * (size_t)(3 * J + 2) * 2);
+  w.jobs = take(sizeof(SynthArgs) * (size_t)J);
+  w.tables = (float*)take(sizeof(float) * 3 * (size_t)J * s0->Q * s0->Bk);
+  if (ws) *ws = w;
+  return off;
+}
+
+namespace {
+ChunkTab chunk_tab(const SynthBatchWS& w, int which) {
+  int64_t* t = w.tab + (size_t)which * (3 * w.J + 2);
+  return ChunkTab{t, t + w.J + 1, t + 2 * w.J + 1, t + 3 * w.J + 1, w.J};
+}
+}  // namespace
+
+int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const SynthBatchWS& w, Ctl* ctl,
+                    float* spectra, const float* grad, double* grad_k, double* grad_rx, int* adjoint_kernel,
+                    const hipEvent_t* ev, hipStream_t s) {
+  const et_sim_desc* s0 = jobs[0].sim;
+  const et_paths P = *paths;
+  const int QB = s0->Q * s0->Bk;
+  // job table with per-job band tables
+  SynthArgs* dj = (SynthArgs*)w.jobs;
+  SynthJobPack pk{};
+  for (int32_t i = 0; i < J; ++i) {
+    SynthArgs a = make_args(jobs[i].sim, 0);
+    a.lk = w.tables + (size_t)i * 3 * QB;
+    a.lc = a.lk + QB;
+    a.ld = a.lc + QB;
+    pk.j[pk.n++] = a;
+    if (pk.n == SJOB_PACK || i + 1 == J) {
+      k_put_synth_jobs<<<1, SJOB_PACK, 0, s>>>(pk, dj);
+      pk.first += pk.n;
+      pk.n = 0;
+    }
+  }
+  k_band_tables_batch<<<J, 256, 0, s>>>(dj);
+  // visible records, sorted by job (stable: each job keeps its record order)
+  SynthWS vw{};
+  vw.vflags = w.vflags; vw.voffs = w.voffs; vw.vidx = w.vidx; vw.vscan = w.vscan;
+  build_vis(P, vw, w.cap, ctl, s);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.cap + 255) / 256, 4096));
+  k_vis_jobkeys<<<nb, 256, 0, s>>>(P, w.vidx, ctl, w.keys);
+  int bits = 0;
+  while ((1ll << bits) < (int64_t)J) ++bits;
+  if (bits > 0) radix_sort_u64(w.keys, w.vidx, 0, &ctl->n_vis, w.cap, bits, w.sort_tmp, s);
+  const int64_t MF2 = (int64_t)s0->M * s0->F * 2;
+  // forward
+  {
+    const ChunkTab ct = chunk_tab(w, 0);
+    k_job_chunks<<<1, 256, 0, s>>>(w.keys, ctl, J, w.target, const_cast<int64_t*>(ct.off), const_cast<int64_t*>(ct.lo),
+                                   const_cast<int64_t*>(ct.hi), const_cast<int64_t*>(ct.per));
+    const SynthArgs a0 = make_args(s0, 0);
+    if (ev) ET_HIP(hipEventRecord(ev[0], s));
+    if (w.mf) {
+      dim3 grid(w.chunks, s0->M, (s0->F / K2 + KT1 - 1) / KT1);
+      if (s0->F / K2 <= 32) k_synth_mfma<true, true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
+      else k_synth_mfma<true, false><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
+    } else {
+      dim3 grid(w.chunks, s0->M, (s0->F + DTILE - 1) / DTILE);
+      k_synth_direct<true><<<grid, DB, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
+    }
+    if (ev) ET_HIP(hipEventRecord(ev[1], s));
+    k_reduce_batch<<<(unsigned)std::min<int64_t>((J * MF2 + 255) / 256, 8192), 256, 0, s>>>(w.partial, ct, MF2, spectra);
+  }
+  if (grad) {
+    const ChunkTab ct = chunk_tab(w, 1);
+    k_job_chunks<<<1, 256, 0, s>>>(w.keys, ctl, J, w.target_bwd, const_cast<int64_t*>(ct.off),
+                                   const_cast<int64_t*>(ct.lo), const_cast<int64_t*>(ct.hi), const_cast<int64_t*>(ct.per));
+    const SynthArgs a0 = make_args(s0, 0);
+    if (ev) ET_HIP(hipEventRecord(ev[2], s));
+    if (w.mf_bwd) {
+      dim3 grid(w.chunks_bwd, s0->M, w.T1);
+      k_synth_bwd_mfma<true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
+    } else {
+      dim3 grid(w.chunks_bwd, s0->M);
+      k_synth_bwd<true><<<grid, GB, sizeof(float2) * (size_t)s0->F, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,
+                                                                         w.gpart_k);
+    }
+    if (ev) ET_HIP(hipEventRecord(ev[3], s));
+    const int64_t n = (int64_t)J * std::max(QB, 3 * s0->M);
+    k_bwd_reduce_batch<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(
+        w.gpart_x, w.gpart_k, ct, w.T1, s0->M, QB, grad_k, grad_rx);
+    if (adjoint_kernel) *adjoint_kernel = w.mf_bwd ? 1 : 2;
+  }
+  ET_HIP(hipGetLastError());
+  return w.mf ? 1 : 2;
 }
 
 }  // namespace et

@@ -194,6 +194,28 @@ struct PoseArgs {
   double t_eps;
 };
 
+// One job of a fused batch: its scene, pose and ray directions.  Rays [ray0, ray0 + a.N) of
+// the batch belong to it; in the ray state and the records the ray field holds the job.
+struct TraceJob {
+  SceneDev S;
+  PoseArgs a;
+  const float* dirs;
+  int64_t ray0;
+};
+
+// Job tables reach the device through kernel arguments, a few jobs per launch, so that no
+// host buffer has to outlive the call (and graph capture records the values).
+constexpr int JOB_PACK = 8;
+struct TraceJobPack {
+  TraceJob j[JOB_PACK];
+  int32_t first, n;
+};
+static_assert(sizeof(TraceJobPack) <= 4000, "job pack must fit the kernel argument space");
+
+__global__ void k_put_trace_jobs(TraceJobPack pk, TraceJob* __restrict__ dst) {
+  if ((int)threadIdx.x < pk.n) dst[pk.first + threadIdx.x] = pk.j[threadIdx.x];
+}
+
 __device__ inline double dnorm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
 
 __global__ void k_trace_init(Ctl* ctl, int64_t N) {
@@ -210,10 +232,29 @@ __global__ void k_trace_init(Ctl* ctl, int64_t N) {
   for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
 }
 
-__global__ void k_ray_init(PoseArgs a, const float* __restrict__ dirs, TraceWS w, Ctl* ctl) {
+// BATCH: a0.N is the batch's total ray count and each ray finds its job in the table.
+template <bool BATCH>
+__global__ void k_ray_init(PoseArgs a0, const float* __restrict__ dirs0, const TraceJob* __restrict__ jobs, int32_t J,
+                           TraceWS w, Ctl* ctl) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
-  const double lx = dirs[3 * i], ly = dirs[3 * i + 1], lz = dirs[3 * i + 2];
+  if (i >= a0.N) return;
+  PoseArgs a = a0;
+  const float* dirs = dirs0;
+  int64_t li = i;
+  int32_t tag = (int32_t)i;
+  if (BATCH) {
+    int lo = 0, hi = J - 1;   // last job with ray0 <= i (jobs without rays share ray0 with the next)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].ray0 <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    a = jobs[lo].a;
+    dirs = jobs[lo].dirs;
+    li = i - jobs[lo].ray0;
+    tag = lo;
+  }
+  const double lx = dirs[3 * li], ly = dirs[3 * li + 1], lz = dirs[3 * li + 2];
   // CalculateWorldDirection: world = R * local, normalised in FP64
   double dx = a.R[0] * lx + a.R[1] * ly + a.R[2] * lz;
   double dy = a.R[3] * lx + a.R[4] * ly + a.R[5] * lz;
@@ -228,11 +269,13 @@ __global__ void k_ray_init(PoseArgs a, const float* __restrict__ dirs, TraceWS w
   w.st[0][3][i] = dx / nrm; w.st[0][4][i] = dy / nrm; w.st[0][5][i] = dz / nrm;
   w.st[0][6][i] = 0.0;
   w.prev[0][i] = -1;
-  w.ray[0][i] = (int32_t)i;
+  w.ray[0][i] = tag;
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(BS) void k_bounce(SceneDev S, PoseArgs a, TraceWS w, Ctl* ctl, int j) {
+// BATCH: each ray reads its scene and pose from the job table (the ray field is the job).
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w,
+                                               Ctl* ctl, int j) {
   __shared__ int lds_stack[TRAV_LDS_STACK * BS];
   const int cur = j & 1;
   const int64_t n = ctl->n_active[cur];
@@ -244,15 +287,22 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S, PoseArgs a, TraceWS w
   st.gstride = w.gstack_threads;
   st.overflow = 0;
   int64_t cn_c = 0, ct_c = 0, cn_a = 0, ct_a = 0, rays_a = 0;
-  const float teps = (float)a.t_eps;
   for (int64_t i = gtid; i < n; i += stride) {
+    SceneDev S = S0;
+    PoseArgs a = a0;
+    if (BATCH) {
+      const TraceJob* tj = jobs + w.ray[cur][i];
+      S = tj->S;
+      a = tj->a;
+    }
+    const float teps = (float)a.t_eps;
     const double ox = w.st[cur][0][i], oy = w.st[cur][1][i], oz = w.st[cur][2][i];
     const double dx = w.st[cur][3][i], dy = w.st[cur][4][i], dz = w.st[cur][5][i];
     const double rtot = w.st[cur][6][i];
     const int prev = w.prev[cur][i];
     const Ray32 r = make_ray(ox, oy, oz, dx, dy, dz);
-    float th;
-    const int pos = traverse<false, COUNT>(S, r, teps, INFINITY, prev, st, th, cn_c, ct_c);
+    float th = INFINITY;
+    const int pos = (!BATCH || S.T > 0) ? traverse<false, COUNT>(S, r, teps, INFINITY, prev, st, th, cn_c, ct_c) : -1;
     uint64_t flag = 0;
     if (pos >= 0) {
       // FP64 refinement on the chosen triangle: plane intersection, normal, reflection
@@ -300,7 +350,8 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S, PoseArgs a, TraceWS w
   }
 }
 
-__global__ void k_scatter(SceneDev S, TraceWS w, Ctl* ctl, et_paths P, int j) {
+template <bool BATCH>
+__global__ void k_scatter(SceneDev S, const TraceJob* __restrict__ jobs, TraceWS w, Ctl* ctl, et_paths P, int j) {
   const int cur = j & 1, nxt = cur ^ 1;
   const int64_t n = ctl->n_active[cur];
   const int64_t base = ctl->rec_base;
@@ -310,13 +361,20 @@ __global__ void k_scatter(SceneDev S, TraceWS w, Ctl* ctl, et_paths P, int j) {
     const uint64_t o = w.offs[i];
     const int64_t ri = base + (int64_t)(o & 0xffffffffull);
     const int pos = w.rpos[i];
-    const int orig = S.tri_orig[pos];
+    const int32_t* tri_orig = S.tri_orig;
+    const int32_t* matp = S.mat;
+    if (BATCH) {
+      const TraceJob* tj = jobs + w.ray[cur][i];
+      tri_orig = tj->S.tri_orig;
+      matp = tj->S.mat;
+    }
+    const int orig = tri_orig[pos];
     if (ri < P.capacity) {
       P.p[3 * ri] = w.rp[0][i]; P.p[3 * ri + 1] = w.rp[1][i]; P.p[3 * ri + 2] = w.rp[2][i];
       P.dout[3 * ri] = (float)w.rd[0][i]; P.dout[3 * ri + 1] = (float)w.rd[1][i]; P.dout[3 * ri + 2] = (float)w.rd[2][i];
       P.rtot[ri] = w.rr[i];
       P.tri[ri] = orig;
-      P.mat[ri] = S.mat[orig];
+      P.mat[ri] = matp[orig];
       P.ray[ri] = w.ray[cur][i];
       P.bounce[ri] = (uint8_t)j;
       P.flags[ri] = w.rvis[i];
@@ -534,7 +592,7 @@ inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
-size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* w) {
+size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* base, TraceWS* w, int32_t max_blocks) {
   const int64_t Nm = std::max<int64_t>(N, 1), Tm = std::max<int64_t>(T, 1), Km = std::max<int64_t>(K, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
@@ -556,7 +614,7 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
   x.flags = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.offs = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.scan_tmp = take(scan_temp_bytes(std::max(std::max(Nm, Tm), Km)));
-  x.gstack_threads = (int64_t)MAX_BLOCKS * BS;
+  x.gstack_threads = (int64_t)(max_blocks > 0 ? max_blocks : MAX_BLOCKS) * BS;
   x.gstack = (int32_t*)take(sizeof(int32_t) * (size_t)(TRAV_STACK - TRAV_LDS_STACK) * (size_t)x.gstack_threads);
   if (K > 0) {
     x.oel = (uint8_t*)take((size_t)std::max<int32_t>(n_obj, 1));
@@ -576,8 +634,8 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
   return off;
 }
 
-void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& w, Ctl* ctl,
-               bool counting, hipStream_t s) {
+namespace {
+PoseArgs pose_args(const et_sim_desc* sim) {
   PoseArgs a;
   for (int k = 0; k < 3; ++k) { a.s[k] = sim->emitter_pos[k]; a.xref[k] = sim->x_ref[k]; }
   for (int k = 0; k < 9; ++k) a.R[k] = sim->emitter_rot[k];
@@ -585,16 +643,74 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
   a.B = sim->max_bounces;
   a.maxd = sim->max_distance;
   a.t_eps = sim->t_eps;
+  return a;
+}
+}  // namespace
+
+size_t trace_batch_jobs_bytes(int32_t J) { return sizeof(TraceJob) * (size_t)std::max(J, 1); }
+
+int64_t trace_batch_rays(int32_t J, const et_job* jobs) {
+  int64_t n = 0;
+  for (int32_t i = 0; i < J; ++i) n += (jobs[i].sim->flags & ET_SPECULAR) ? jobs[i].sim->N : 0;
+  return n;
+}
+
+void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_paths* paths, const TraceWS& w,
+                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s) {
+  TraceJob* dj = (TraceJob*)dev_jobs;
+  TraceJobPack pk{};
+  int64_t N = 0;
+  int B = 0;
+  for (int32_t i = 0; i < J; ++i) {
+    TraceJob& t = pk.j[pk.n++];
+    t.S = jobs[i].scene->d;
+    t.a = pose_args(jobs[i].sim);
+    t.dirs = jobs[i].sim->ray_dirs;
+    t.ray0 = N;
+    N += t.a.N;
+    B = std::max(B, (int)t.a.B);
+    if (pk.n == JOB_PACK || i + 1 == J) {
+      k_put_trace_jobs<<<1, JOB_PACK, 0, s>>>(pk, dj);
+      pk.first += pk.n;
+      pk.n = 0;
+    }
+  }
+  PoseArgs all{};
+  all.N = N;
+  const et_paths P = *paths;
+  k_trace_init<<<1, 1, 0, s>>>(ctl, N);
+  ET_HIP(hipGetLastError());
+  // bounce grid: the tuned block count, within what the workspace's global stacks serve
+  const int64_t cap_blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, w.gstack_threads / BS));
+  const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + BS - 1) / BS, cap_blocks));
+  if (N > 0) {
+    k_ray_init<true><<<nblk_full(N), BS, 0, s>>>(all, nullptr, dj, J, w, ctl);
+    for (int j = 0; j < B; ++j) {
+      if (counting) k_bounce<true, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
+      else k_bounce<false, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
+      scan_exclusive_u64(w.flags, w.offs, 0, &ctl->n_active[j & 1], N, &ctl->tot[0], w.scan_tmp, s);
+      k_scatter<true><<<nblk(N), BS, 0, s>>>(SceneDev{}, dj, w, ctl, P, j);
+      k_bounce_epi<<<1, 1, 0, s>>>(ctl, j);
+      ET_HIP(hipGetLastError());
+    }
+  }
+  k_trace_final<<<1, 1, 0, s>>>(ctl, P, 0);
+  ET_HIP(hipGetLastError());
+}
+
+void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& w, Ctl* ctl,
+               bool counting, hipStream_t s) {
+  const PoseArgs a = pose_args(sim);
   const et_paths P = *paths;
   k_trace_init<<<1, 1, 0, s>>>(ctl, a.N);
   ET_HIP(hipGetLastError());
   if (a.N > 0 && S.T > 0) {
-    k_ray_init<<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, w, ctl);
+    k_ray_init<false><<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, nullptr, 0, w, ctl);
     for (int j = 0; j < a.B; ++j) {
-      if (counting) k_bounce<true><<<nblk(a.N), BS, 0, s>>>(S, a, w, ctl, j);
-      else k_bounce<false><<<nblk(a.N), BS, 0, s>>>(S, a, w, ctl, j);
+      if (counting) k_bounce<true, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
+      else k_bounce<false, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
       scan_exclusive_u64(w.flags, w.offs, 0, &ctl->n_active[j & 1], a.N, &ctl->tot[0], w.scan_tmp, s);
-      k_scatter<<<nblk(a.N), BS, 0, s>>>(S, w, ctl, P, j);
+      k_scatter<false><<<nblk(a.N), BS, 0, s>>>(S, nullptr, w, ctl, P, j);
       k_bounce_epi<<<1, 1, 0, s>>>(ctl, j);
       ET_HIP(hipGetLastError());
     }

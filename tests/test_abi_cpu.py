@@ -60,7 +60,7 @@ def test_binding_structs_match_header_field_order():
     import paper_2602_19652_amd as et
     txt = open(HEADER).read()
     for cls, cname in [(et.MeshDesc, "et_mesh_desc"), (et.SimDesc, "et_sim_desc"), (et.PathsDesc, "et_paths"),
-                       (et.Stats, "et_stats"), (et.SceneInfo, "et_scene_info")]:
+                       (et.Stats, "et_stats"), (et.SceneInfo, "et_scene_info"), (et.Tuning, "et_tuning")]:
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + cname + ";", txt).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[\d+\])?\s*[,;]", body)

@@ -77,16 +77,35 @@ def batch_small():
     return W.batched_workload(n_poses=6, n_scenes=4, n_rays=1 << 11, M=8, F=2048, tmax=2e4)
 
 
-def test_batch_matches_plain_and_graph(et, ctx, batch_small):
+def _batch_sims(et, b, extra_flags=0):
+    """Uneven jobs: job i keeps its first 2^11 - 97 i rays."""
+    sims = []
+    for i, j in enumerate(b.jobs):
+        n = max(64, (1 << 11) - 97 * i)
+        sims.append(et.Sim(j.sim, flags=et.ET_SPECULAR | extra_flags, ray_dirs=j.sim["ray_dirs"][:n]))
+    return sims
+
+
+def test_batch_fused_matches_plain_and_graph(et, ctx, batch_small):
+    """Fused batch (all rays in shared bounce kernels, records sorted by job into shared
+    synthesis launches) vs one plain simulation per job: same segments, spectra equal up to
+    the FP32 summation order; repeated runs and graph replays bit-identical."""
     import torch
     b = batch_small
     scenes = [et.Scene(ctx, s) for s in b.scenes]
-    sims = [et.Sim(j.sim, flags=et.ET_SPECULAR) for j in b.jobs]
-    plain = [et.simulate(ctx, scenes[j.scene_index], sims[i]).cpu().numpy() for i, j in enumerate(b.jobs)]
+    sims = _batch_sims(et, b)
+    plain, seg = [], 0
+    for i, j in enumerate(b.jobs):
+        plain.append(et.simulate(ctx, scenes[j.scene_index], sims[i]).cpu().numpy())
+        seg += ctx.stats().segments
     batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
     Hb = batch.run().cpu().numpy()
-    for i in range(len(b.jobs)):
-        assert np.array_equal(Hb[i], plain[i]), f"job {i} differs from its plain simulation"
+    st = ctx.stats()
+    assert st.segments == seg
+    errs = [rel_l2(Hb[i], plain[i]) for i in range(len(b.jobs))]
+    print(f"fused batch of {len(b.jobs)} jobs: segments {st.segments}, max rel L2 vs plain {max(errs):.3e}")
+    assert max(errs) <= 1e-5
+    assert np.array_equal(batch.run().cpu().numpy(), Hb), "fused batch not deterministic"
     # graph capture on a side stream, replayed several times with eager work in between
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -107,6 +126,71 @@ def test_batch_matches_plain_and_graph(et, ctx, batch_small):
     e = rel_l2(Hc[:, bins], H_ref)
     print(f"batch job 0 vs oracle on certified rays ({ref['certified'].mean():.4f}): rel L2 {e:.3e}")
     assert e <= TOL
+
+
+def test_batch_fused_adjoint_matches_per_job(et, ctx, batch_small):
+    """Batched forward + adjoint: every job's dL/dk and dL/dx vs its own adjoint call."""
+    import torch
+    b = batch_small
+    scenes = [et.Scene(ctx, s) for s in b.scenes]
+    sims = _batch_sims(et, b)
+    batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+    g = torch.Generator(device="cuda").manual_seed(5)
+    J, M, F = len(b.jobs), sims[0].M, sims[0].F
+    grad = torch.randn(J, M, F, dtype=torch.complex64, device="cuda", generator=g)
+    batch.run(grad_spectra=grad)
+    gk_b, gx_b = batch.grad_k.cpu().numpy(), batch.grad_rx.cpu().numpy()
+    assert ctx.stats().adjoint_kernel == 1
+    ek, ex = [], []
+    for i, j in enumerate(b.jobs):
+        P = et.trace(ctx, scenes[j.scene_index], sims[i])
+        gk, gx = et.synthesize_backward(ctx, sims[i], P, grad[i])
+        ek.append(rel_l2(gk_b[i], gk.cpu().numpy()))
+        ex.append(rel_l2(gx_b[i], gx.cpu().numpy()))
+    print(f"batched adjoint vs per job: max rel dL/dk {max(ek):.3e}, dL/dx {max(ex):.3e}")
+    assert max(ek) <= 1e-5 and max(ex) <= 1e-5
+
+
+def test_batch_autotune(et, ctx, batch_small):
+    """The autotuner picks candidate launch shapes with measured phase times; results under
+    the new shapes agree with the default ones (same records, other summation chunks)."""
+    import torch
+    b = batch_small
+    scenes = [et.Scene(ctx, s) for s in b.scenes]
+    sims = _batch_sims(et, b)
+    batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+    H0 = batch.run().cpu().numpy()
+    g = torch.Generator(device="cuda").manual_seed(6)
+    grad = torch.randn(len(b.jobs), sims[0].M, sims[0].F, dtype=torch.complex64, device="cuda", generator=g)
+    try:
+        t = batch.autotune(grad_spectra=grad)
+        print(f"autotune: synth {t.synth_wgs} wgs ({t.ms_synth:.3f} ms), adjoint {t.adjoint_wgs} wgs "
+              f"({t.ms_adjoint:.3f} ms), bounce grid {t.trace_blocks} ({t.ms_trace:.3f} ms)")
+        assert t.synth_wgs in (512, 1024, 2048, 4096) and t.adjoint_wgs in (512, 1024, 2048, 4096)
+        assert t.trace_blocks in (1024, 1280, 2048, 4096)
+        assert t.ms_trace > 0 and t.ms_synth > 0 and t.ms_adjoint > 0
+        cur = ctx.tuning()
+        assert (cur.synth_wgs, cur.adjoint_wgs, cur.trace_blocks) == (t.synth_wgs, t.adjoint_wgs, t.trace_blocks)
+        H1 = batch.run().cpu().numpy()
+        assert rel_l2(H1, H0) <= 1e-5
+        with pytest.raises(et.EchoError):
+            ctx.set_tuning(32, 1024, 2048)
+    finally:
+        ctx.set_tuning(2048, 1024, 2048)
+
+
+def test_batch_with_diffraction_runs_job_by_job(et, ctx, batch_small):
+    """Jobs with diffraction sampling take the sequential path: bit-identical to plain calls."""
+    b = batch_small
+    jobs = b.jobs[:3]
+    scenes = [et.Scene(ctx, s, area_ref=W.median_triangle_area(s)) for s in b.scenes]
+    sims = [et.Sim(dict(j.sim, diff_K=1024, diff_seed=9 + i), flags=et.ET_SPECULAR | et.ET_DIFFRACTION)
+            for i, j in enumerate(jobs)]
+    plain = [et.simulate(ctx, scenes[j.scene_index], sims[i]).cpu().numpy() for i, j in enumerate(jobs)]
+    batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(jobs)])
+    Hb = batch.run().cpu().numpy()
+    for i in range(len(jobs)):
+        assert np.array_equal(Hb[i], plain[i]), f"job {i} differs from its plain simulation"
 
 
 # ----------------------------------------------------------------------------- differentiation
