@@ -138,6 +138,11 @@ def main():
     n_vis = int((P.flags[:n_rec] & 1).sum().item())      # blocked records contribute nothing
     terms = n_vis * s.M * s.F
     if args.profile_only:
+        # one adjoint call over the step's paths, for the counter runs
+        gen = torch.Generator(device="cuda").manual_seed(2024)
+        et.synthesize_backward(ctx, s, P, torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda", generator=gen),
+                               ws=ws)
+        torch.cuda.synchronize()
         # calibration for hardware byte counters: one plain device copy of a known size
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
@@ -200,15 +205,17 @@ def main():
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
     trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
     if ms_synth >= ms_trace:
-        kname = "k_synth_mfma" if kern == 1 else "k_synth_direct"
+        # kernel instantiation names as the profiler reports them
+        kname = (f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}>" if kern == 1
+                 else "k_synth_direct<false>")
         roof = {"kernel": kname, "bound": "mfma",
                 "achieved": synth_tflops, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
                 "frac": synth_tflops / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for(kname),
                 "kernel_ms": ms_synth_kernel, "algorithmic_flop_per_launch": synth_flops,
                 "per_unit": f"{SYNTH_FLOP_PER_TERM} flop per (visible record, receiver, bin)"}
     else:
-        roof = {"kernel": "k_bounce", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false>")}
+        roof = {"kernel": "k_bounce<false, false>", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false>")}
     line = {
         "metric": METRIC,
         "value": seg / (ms_step * 1e-3) / 1e6,
@@ -227,13 +234,15 @@ def main():
         "adjoint": {"workload": "fixed paths of the step, 32 receivers x 4096 bins, seeded dL/dconj(H)",
                     "ms": ms_adj, "kernel_ms": ms_adj_kernel, "kernel": adj_kern,
                     "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,
-                    "kernel_tflops_algorithmic": adj_tflops, "frac_of_mfma_peak": adj_tflops / PEAK_MFMA_F32_TFLOPS},
+                    "kernel_tflops_algorithmic": adj_tflops, "frac_of_mfma_peak": adj_tflops / PEAK_MFMA_F32_TFLOPS,
+                    "per_unit": f"{ADJ_FLOP_PER_TERM} flop per (visible record, receiver, bin)",
+                    "traffic": traffic_for("k_synth_bwd_mfma<false>" if adj_kern == 1 else "k_synth_bwd<false>")},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
                       "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
                       "algorithmic_bytes": trav_bytes, "effective_GBs": trace_gbs,
-                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS},
+                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false>")},
         "roofline": roof,
         "cpu_baseline": None,
     }
