@@ -255,14 +255,20 @@ struct PairLean {
   float base, slope, gamma;
   float vx, vy, vz;
   int mat, kind;
+  // GRAD: receiver-gradient coefficients, d/dx_m of (ln A + j phi) = (c1 + c2 f + j c3 f) u - lobe
+  float gux, guy, guz;   // u = (x_m - p) / l
+  float gc1;             // -p / r - ln10 a0 / 20
+  float glx, gly, glz;   // 2 (gamma / sin gamma) (d' - cos(gamma) u) / l (specular; 0 otherwise)
 };
 
+template <bool GRAD = false>
 __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const int32_t* __restrict__ idx, int64_t e,
                                  int64_t hi, int m, PairLean& q) {
   q.a32 = q.bx32 = q.by32 = 0;
   q.base = -INFINITY;
   q.slope = q.gamma = q.vx = q.vy = q.vz = 0.f;
   q.mat = q.kind = 0;
+  if (GRAD) q.gux = q.guy = q.guz = q.gc1 = q.glx = q.gly = q.glz = 0.f;
   if (e >= hi) return;
   const int64_t n = idx[e];
   const uint8_t fl = P.flags[n];
@@ -284,7 +290,22 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   if (q.kind == 0) {
     const float dx = P.dout[3 * n], dy = P.dout[3 * n + 1], dz = P.dout[3 * n + 2];
     const float cx = dy * uz - dz * uy, cy = dz * ux - dx * uz, cz = dx * uy - dy * ux;
-    q.gamma = atan2f(sqrtf(cx * cx + cy * cy + cz * cz), dx * ux + dy * uy + dz * uz);
+    const float sc = sqrtf(cx * cx + cy * cy + cz * cz), cc = dx * ux + dy * uy + dz * uz;
+    q.gamma = atan2f(sc, cc);
+    if (GRAD) {
+      // d(gamma^2)/dx_m = -(2 gamma / sin gamma) (h - cos(gamma) u) / l with h = d' / |d'|
+      const float idn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+      const float sg = sc * idn, cg = cc * idn;
+      const float ratio = q.gamma < 1e-4f ? 2.0f : 2.0f * q.gamma / sg;
+      const float c = ratio * (float)(2.0 * il);
+      q.glx = c * (dx * idn - cg * ux);
+      q.gly = c * (dy * idn - cg * uy);
+      q.glz = c * (dz * idn - cg * uz);
+    }
+  }
+  if (GRAD) {
+    q.gux = ux; q.guy = uy; q.guz = uz;
+    q.gc1 = (float)(-a.ps / r - 2.30258509299404568402 * a.A0 / 20.0);
   }
   if (a.Bd) {   // direction of arrival in the receiver frame: -R_m^T u
     if (a.rx_rot) {
@@ -818,6 +839,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const float frow0 = (float)(a.f_lo + (double)(k1_0 * K2) * a.df), df64 = (float)(K2 * a.df), dff = (float)a.df;
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;
   const double ln10 = 2.30258509299404568402;
+  const double c2 = -ln10 * a.A1 / 20.0, c3 = -(double)a.sigma * 2.0 * M_PI / a.c;
   const int QB = a.Q * a.Bk;
   double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
@@ -825,7 +847,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
-    if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
+    if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
     generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0],
              &bb.Yt[0][0][0], &bb.Yt[1][0][0], 1, YT, wscr[wv]);
     __syncthreads();
@@ -874,17 +896,15 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     }
     __syncthreads();
     {
-      // eight threads per record: row sums in FP64, bands j and j + 8
+      // eight threads per record: row sums in FP64, bands j and j + 8.  Record n of this stage
+      // was set up by lane 8 t + n % 8 of this same wave: its data arrive by shuffle.
       const int n = tid >> 3, j = tid & 7;
-      const int64_t e = lo + (s >> 3) * (8 * RB) + (n >> 3) * 64 + t * RPW + (n & 7);
-      const bool valid = e < hi;
-      int64_t rn = 0;
-      int mat = 0, kind = 1;
-      if (valid) {
-        rn = idx[e];
-        kind = (P.flags[rn] >> 1) & 1;
-        mat = P.mat[rn];
-      }
+      const int src = t * RPW + (n & 7);
+      const bool valid = __shfl(q.base, src) != -INFINITY;
+      const int mat = __shfl(q.mat, src), kind = __shfl(q.kind, src);
+      const float gux = __shfl(q.gux, src), guy = __shfl(q.guy, src), guz = __shfl(q.guz, src);
+      const float gc1 = __shfl(q.gc1, src);
+      const float glx = __shfl(q.glx, src), gly = __shfl(q.gly, src), glz = __shfl(q.glz, src);
       double s1r = 0.0, s1i = 0.0;
       const int ngroups = split ? 8 : 16;   // row groups of 4 written this stage
 #pragma unroll
@@ -926,30 +946,11 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       if (j == 0 && valid && kind == 0) atomicOr(&bb.kmask[s & 1][mat], 1u << n);
       for (int i = tid; i < a.Q; i += 256) bb.kmask[(s + 1) & 1][i] = 0u;
       if (j == 0 && valid) {
-        // receiver leg and path in FP64, as in the forward set-up
-        const double wx = a.rx_pos[3 * m] - P.p[3 * rn], wy = a.rx_pos[3 * m + 1] - P.p[3 * rn + 1],
-                     wz = a.rx_pos[3 * m + 2] - P.p[3 * rn + 2];
-        const double l = sqrt(wx * wx + wy * wy + wz * wz), il = 1.0 / l;
-        const double r = P.rtot[rn] + l;
-        const double u0 = wx * il, u1 = wy * il, u2 = wz * il;
         // d(ln A + j phi)/dx_m = [(-p/r - ln10 (a0 + a1 f)/20) + j sigma 2 pi f / c] u - d(gamma^2)/dx / (2 beta^2)
-        const double cu = (-a.ps / r - ln10 * a.A0 / 20.0) * s0 - ln10 * a.A1 / 20.0 * s1r -
-                          (double)a.sigma * 2.0 * M_PI / a.c * s1i;
-        double g0 = 2.0 * cu * u0, g1 = 2.0 * cu * u1, g2 = 2.0 * cu * u2;
-        if (kind == 0) {
-          const double dx = P.dout[3 * rn], dy = P.dout[3 * rn + 1], dz = P.dout[3 * rn + 2];
-          const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-          const double hx = dx * idn, hy = dy * idn, hz = dz * idn;
-          const double cg = hx * u0 + hy * u1 + hz * u2;
-          const double qx = hy * u2 - hz * u1, qy = hz * u0 - hx * u2, qz = hx * u1 - hy * u0;
-          const double sg = sqrt(qx * qx + qy * qy + qz * qz);
-          // gamma / sin(gamma) needs no more than FP32 atan2: the ratio is a smooth factor
-          const double gam = (double)atan2f((float)sg, (float)cg);
-          const double ratio = gam < 1e-4 ? 2.0 : 2.0 * gam / sg;
-          // d(gamma^2)/dx = -(2 gamma / sin gamma) (d' - cos(gamma) u) / l
-          const double cl = -ratio * il * 2.0 * wl;
-          g0 -= cl * (hx - cg * u0); g1 -= cl * (hy - cg * u1); g2 -= cl * (hz - cg * u2);
-        }
+        const double cu = (double)gc1 * s0 + c2 * s1r + c3 * s1i;
+        const double g0 = 2.0 * cu * (double)gux + wl * (double)glx;
+        const double g1 = 2.0 * cu * (double)guy + wl * (double)gly;
+        const double g2 = 2.0 * cu * (double)guz + wl * (double)glz;
         gx0 += g0; gx1 += g1; gx2 += g2;
       }
     }
