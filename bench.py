@@ -313,6 +313,7 @@ def batched_leg(ctx, args):
     batch.run(grad_spectra=grad)
     st = ctx.stats()
     jobs_s = lambda ms: J / (ms * 1e-3)
+    ws_gb = batch.ws.numel() / 1e9
     tuned = {"synth_wgs": tune.synth_wgs, "adjoint_wgs": tune.adjoint_wgs, "trace_blocks": tune.trace_blocks,
              "batched_fwd_ms": ms_fwd_t, "batched_fwd_adj_ms": ms_fwd_adj_t,
              "phase_ms": {"trace": st.ms_trace, "synth_kernel": st.ms_synth_kernel, "adjoint_kernel": st.ms_adjoint_kernel},
@@ -324,7 +325,7 @@ def batched_leg(ctx, args):
             "plain_fwd_jobs_per_s": jobs_s(ms_plain), "batched_fwd_jobs_per_s": jobs_s(ms_fwd),
             "batched_fwd_adj_jobs_per_s": jobs_s(ms_fwd_adj), "batched_fwd_adj_graph_jobs_per_s": jobs_s(ms_graph),
             "ratio_batched_fwd_adj_vs_plain_fwd": ms_plain / ms_fwd_adj,
-            "ratio_graph_fwd_adj_vs_plain_fwd": ms_plain / ms_graph, "autotuned": tuned,
+            "ratio_graph_fwd_adj_vs_plain_fwd": ms_plain / ms_graph, "autotuned": tuned, "workspace_gb": ws_gb,
             "input_generation_s": gen_s}
 
 
