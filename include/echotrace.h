@@ -145,8 +145,11 @@ typedef struct {
 
 /* Path records (hit buffer B of Algorithm 1 plus diffraction points), caller-owned
  * device SoA arrays of `capacity` entries.  Order: specular records bounce-major (all
- * bounce-0 hits in ray order, then bounce 1, ...), then kept diffraction samples in
- * sample order.  count (device int64[4]) = {records, specular, diffraction, segments}. */
+ * bounce-0 hits, then bounce 1, ...); within a bounce the rays follow the library's
+ * traversal order (ray order, or sorted by direction when there are more rays than threads
+ * in the traversal grid; deterministic either way; `ray` names each record's ray).
+ * Kept diffraction samples follow in sample order.  count (device int64[4]) =
+ * {records, specular, diffraction, segments}. */
 typedef struct {
   int64_t capacity;
   double* p;          /* [cap][3] hit / diffraction point */

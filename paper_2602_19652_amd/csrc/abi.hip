@@ -121,6 +121,7 @@ size_t paths_bytes(int64_t cap) {
 // A batch runs fused (all rays in shared bounce kernels, all records in shared synthesis
 // kernels) when every job is specular-only; otherwise jobs run one after another.
 bool batch_fused(int32_t J, const et_job* jobs) {
+  if (J > 65536) return false;   // the ray sort keys hold the job in 16 bits
   for (int32_t j = 0; j < J; ++j)
     if (jobs[j].sim->flags & ET_DIFFRACTION) return false;
   return true;

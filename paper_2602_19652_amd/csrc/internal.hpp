@@ -154,6 +154,9 @@ struct TraceWS {
   uint64_t* flags;
   uint64_t* offs;
   void* scan_tmp;
+  uint32_t* rkeys;           // ray order: direction keys (job in the high bits in a batch)
+  int32_t* rperm;            // ray index per slot after sorting by key
+  void* rsort_tmp;
   int32_t* gstack;           // global part of the traversal stacks
   int64_t gstack_threads;
   // diffraction

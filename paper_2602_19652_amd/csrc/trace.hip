@@ -8,6 +8,12 @@
 //   scan       exclusive scan of (hit, continue) flags
 //   k_scatter  stable compaction: records in ray order after the earlier bounces' records,
 //              next-bounce ray state in ray order
+// Ray order: when there are more rays than threads in the bounce grid (each thread then
+// traces several rays one after another, and a wave's time per ray is its slowest lane's),
+// the rays are first sorted (stably) by a 16-bit octahedral Morton key of their world
+// direction, so that a wave's lanes walk nearby parts of the BVH; the stable compaction keeps
+// that order through the bounces, and records carry their ray.  A grid that holds every ray
+// at once gains nothing from it (measured), so smaller ray sets keep their given order.
 // Traversal: one lane per ray, binary BVH, nearest child first, per-lane stack in LDS
 // (spilling to global memory past TRAV_LDS_STACK entries), watertight ray-triangle test
 // (Woop, Benthin & Wald, JCGT 2013), conservative slab test (Ize 2013).
@@ -232,27 +238,84 @@ __global__ void k_trace_init(Ctl* ctl, int64_t N) {
   for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
 }
 
+// The job of batch ray g (the last job with ray0 <= g; jobs without rays share ray0 with the next).
+__device__ inline int ray_job(const TraceJob* __restrict__ jobs, int32_t J, int64_t g) {
+  int lo = 0, hi = J - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].ray0 <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int RAY_KEY_BITS = 16;   // direction cells of the ray sort: 2^16 on the octahedral map
+
+__device__ inline uint32_t spread8(uint32_t v) {   // bit i -> bit 2i
+  v = (v | (v << 4)) & 0x0F0Fu;
+  v = (v | (v << 2)) & 0x3333u;
+  v = (v | (v << 1)) & 0x5555u;
+  return v;
+}
+
+// Sort key of ray g: Morton code of its world direction on the octahedral map (the top
+// RAY_KEY_BITS of 8 + 8 bits), the job above it in a batch.  perm[g] = g (the sort's values).
+template <bool BATCH>
+__global__ void k_ray_keys(PoseArgs a0, const float* __restrict__ dirs0, const TraceJob* __restrict__ jobs, int32_t J,
+                           uint32_t* __restrict__ keys, int32_t* __restrict__ perm) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a0.N) return;
+  const float* dirs = dirs0;
+  double R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = a0.R[k];
+  int64_t li = g;
+  uint32_t hi = 0;
+  if (BATCH) {
+    const int j = ray_job(jobs, J, g);
+    dirs = jobs[j].dirs;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = jobs[j].a.R[k];
+    li = g - jobs[j].ray0;
+    hi = (uint32_t)j << RAY_KEY_BITS;
+  }
+  const float lx = dirs[3 * li], ly = dirs[3 * li + 1], lz = dirs[3 * li + 2];
+  float x = (float)(R[0] * lx + R[1] * ly + R[2] * lz);
+  float y = (float)(R[3] * lx + R[4] * ly + R[5] * lz);
+  float z = (float)(R[6] * lx + R[7] * ly + R[8] * lz);
+  const float s = fabsf(x) + fabsf(y) + fabsf(z);
+  uint32_t ux = 0, uy = 0;
+  if (s > 0.f && s < INFINITY) {
+    x /= s; y /= s; z /= s;
+    if (z < 0.f) {
+      const float tx = (1.f - fabsf(y)) * (x >= 0.f ? 1.f : -1.f), ty = (1.f - fabsf(x)) * (y >= 0.f ? 1.f : -1.f);
+      x = tx; y = ty;
+    }
+    ux = (uint32_t)fminf(fmaxf((x * 0.5f + 0.5f) * 256.f, 0.f), 255.f);
+    uy = (uint32_t)fminf(fmaxf((y * 0.5f + 0.5f) * 256.f, 0.f), 255.f);
+  }
+  keys[g] = hi | ((spread8(ux) | (spread8(uy) << 1)) >> (16 - RAY_KEY_BITS));
+  perm[g] = (int32_t)g;
+}
+
 // BATCH: a0.N is the batch's total ray count and each ray finds its job in the table.
+// Slot i starts ray perm[i] (rays in key order).
 template <bool BATCH>
 __global__ void k_ray_init(PoseArgs a0, const float* __restrict__ dirs0, const TraceJob* __restrict__ jobs, int32_t J,
-                           TraceWS w, Ctl* ctl) {
+                           const int32_t* __restrict__ perm, TraceWS w, Ctl* ctl) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a0.N) return;
+  const int64_t g = perm ? perm[i] : i;
   PoseArgs a = a0;
   const float* dirs = dirs0;
-  int64_t li = i;
-  int32_t tag = (int32_t)i;
+  int64_t li = g;
+  int32_t tag = (int32_t)g;
   if (BATCH) {
-    int lo = 0, hi = J - 1;   // last job with ray0 <= i (jobs without rays share ray0 with the next)
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (jobs[mid].ray0 <= i) lo = mid;
-      else hi = mid - 1;
-    }
-    a = jobs[lo].a;
-    dirs = jobs[lo].dirs;
-    li = i - jobs[lo].ray0;
-    tag = lo;
+    const int j = ray_job(jobs, J, g);
+    a = jobs[j].a;
+    dirs = jobs[j].dirs;
+    li = g - jobs[j].ray0;
+    tag = j;
   }
   const double lx = dirs[3 * li], ly = dirs[3 * li + 1], lz = dirs[3 * li + 2];
   // CalculateWorldDirection: world = R * local, normalised in FP64
@@ -614,6 +677,9 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
   x.flags = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.offs = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.scan_tmp = take(scan_temp_bytes(std::max(std::max(Nm, Tm), Km)));
+  x.rkeys = (uint32_t*)take(sizeof(uint32_t) * Nm);
+  x.rperm = (int32_t*)take(sizeof(int32_t) * Nm);
+  x.rsort_tmp = take(sort_temp_bytes(Nm, 4));
   x.gstack_threads = (int64_t)(max_blocks > 0 ? max_blocks : MAX_BLOCKS) * BS;
   x.gstack = (int32_t*)take(sizeof(int32_t) * (size_t)(TRAV_STACK - TRAV_LDS_STACK) * (size_t)x.gstack_threads);
   if (K > 0) {
@@ -684,7 +750,14 @@ void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_pat
   const int64_t cap_blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, w.gstack_threads / BS));
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + BS - 1) / BS, cap_blocks));
   if (N > 0) {
-    k_ray_init<true><<<nblk_full(N), BS, 0, s>>>(all, nullptr, dj, J, w, ctl);
+    const bool sorted = N > (int64_t)gb * BS;
+    if (sorted) {
+      int jb = 0;
+      while ((1ll << jb) < (int64_t)J) ++jb;
+      k_ray_keys<true><<<nblk_full(N), BS, 0, s>>>(all, nullptr, dj, J, w.rkeys, w.rperm);
+      radix_sort_u32(w.rkeys, w.rperm, N, RAY_KEY_BITS + jb, w.rsort_tmp, s);
+    }
+    k_ray_init<true><<<nblk_full(N), BS, 0, s>>>(all, nullptr, dj, J, sorted ? w.rperm : nullptr, w, ctl);
     for (int j = 0; j < B; ++j) {
       if (counting) k_bounce<true, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
       else k_bounce<false, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
@@ -705,7 +778,12 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
   k_trace_init<<<1, 1, 0, s>>>(ctl, a.N);
   ET_HIP(hipGetLastError());
   if (a.N > 0 && S.T > 0) {
-    k_ray_init<false><<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, nullptr, 0, w, ctl);
+    const bool sorted = a.N > (int64_t)nblk(a.N) * BS;
+    if (sorted) {
+      k_ray_keys<false><<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, nullptr, 0, w.rkeys, w.rperm);
+      radix_sort_u32(w.rkeys, w.rperm, a.N, RAY_KEY_BITS, w.rsort_tmp, s);
+    }
+    k_ray_init<false><<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, nullptr, 0, sorted ? w.rperm : nullptr, w, ctl);
     for (int j = 0; j < a.B; ++j) {
       if (counting) k_bounce<true, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
       else k_bounce<false, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
