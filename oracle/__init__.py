@@ -107,7 +107,9 @@ def synth(rec: dict, sim: dict, bins=None, M_subset=None) -> np.ndarray:
     k_list = np.arange(F, dtype=np.int32) if bins is None else _i32(bins)
     rx = _f64(sim["rx_pos"]); rr = _f64(sim["rx_rot"])
     D = sim.get("directivity")
+    rx_id = np.arange(len(rx), dtype=np.int32)
     if M_subset is not None:
+        rx_id = _i32(rx_id[M_subset])
         rx = _f64(rx[M_subset]); rr = _f64(rr[M_subset])
         if D is not None:
             D = D[M_subset]
@@ -125,12 +127,15 @@ def synth(rec: dict, sim: dict, bins=None, M_subset=None) -> np.ndarray:
     vis = np.ascontiguousarray(rec.get("vis", np.ones(n, np.uint8)), np.uint8) if n else np.zeros(1, np.uint8)
     k = _f32(sim["refl_k"]); b = _f32(sim["lobe_beta"]); dc = _f32(sim["diff_coef"])
     Q, Bk = k.shape
+    pc = sim.get("passive_coef")
+    pc = None if pc is None else _f32(pc)
     out = np.zeros((M, len(k_list), 2))
     rc = L.orc_synth(C.c_int64(n), _p(p), _p(dout), _p(rt), _p(mat), _p(kind), _p(vis), C.c_int32(M), _p(rx), _p(rr),
                      C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]), C.c_int32(F), C.c_int32(len(k_list)), _p(k_list),
                      C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
                      C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
-                     _p(k), _p(b), _p(dc), C.c_int32(Bd), C.c_int32(El), C.c_int32(Az), _p(D), _p(out))
+                     _p(k), _p(b), _p(dc), C.c_int32(Bd), C.c_int32(El), C.c_int32(Az), _p(D), _p(pc), _p(rx_id),
+                     _p(out))
     if rc != 0:
         raise ValueError(f"orc_synth failed ({rc})")
     return out[..., 0] + 1j * out[..., 1]
@@ -152,11 +157,13 @@ def grad(rec: dict, sim: dict, g: np.ndarray):
     gk = np.zeros((Q, Bk)); gx = np.zeros((M, 3))
     kind = np.ascontiguousarray(rec.get("kind", np.zeros(n, np.uint8)), np.uint8)
     vis = np.ascontiguousarray(rec.get("vis", np.ones(n, np.uint8)), np.uint8)
+    pc = sim.get("passive_coef")
+    pc = None if pc is None else _f32(pc)
     rc = L.orc_grad(C.c_int64(n), _p(_f64(rec["p"])), _p(_f64(rec["dout"])), _p(_f64(rec["rtot"])), _p(_i32(rec["mat"])),
                     _p(kind), _p(vis), C.c_int32(M), _p(rx), C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]),
                     C.c_int32(F), C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
                     C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
-                    _p(k), _p(b), _p(dc), _p(gg), _p(gk), _p(gx))
+                    _p(k), _p(b), _p(dc), _p(pc), _p(gg), _p(gk), _p(gx))
     if rc != 0:
         raise ValueError(f"orc_grad failed ({rc})")
     return gk, gx
@@ -209,6 +216,31 @@ def diffraction_records(scene: dict, samples: dict) -> dict:
     return {"p": samples["o"][keep].copy(), "dout": np.zeros((n, 3)), "rtot": samples["r_src"][keep].copy(),
             "mat": scene["tri_material"][tri].astype(np.int32), "kind": np.ones(n, np.uint8),
             "vis": np.ones(n, np.uint8), "tri": tri.astype(np.int32)}
+
+
+def passive(scene: dict, sim: dict, certify: bool = True, kappa: float = KAPPA):
+    """Passive component: line of sight from the emitter to every receiver (vis[M]) and the
+    certification of each decision against FP32 traversal."""
+    L = lib()
+    v = _f32(scene["vertices"]); t = _i32(scene["tris"])
+    rx = _f64(sim["rx_pos"])
+    M = len(rx)
+    vis = np.zeros(max(M, 1), np.uint8); cert = np.zeros(max(M, 1), np.uint8)
+    rc = L.orc_passive(C.c_int64(len(v)), C.c_int64(len(t)), _p(v), _p(t), _p(_f64(sim["emitter_pos"])), C.c_int32(M),
+                       _p(rx), C.c_double(sim["t_eps"]), C.c_double(kappa if certify else 0.0), _p(vis), _p(cert))
+    if rc != 0:
+        raise ValueError("orc_passive failed")
+    return vis[:M].astype(bool), cert[:M].astype(bool)
+
+
+def passive_records(sim: dict, vis) -> dict:
+    """One passive record per receiver m: the emitter as the point, path 0 so far, the
+    receiver index in the material field, kind 2."""
+    M = len(sim["rx_pos"])
+    s = np.asarray(sim["emitter_pos"], np.float64).reshape(1, 3)
+    return {"p": np.repeat(s, M, axis=0), "dout": np.zeros((M, 3)), "rtot": np.zeros(M),
+            "mat": np.arange(M, dtype=np.int32), "kind": np.full(M, 2, np.uint8),
+            "vis": np.asarray(vis, np.uint8), "tri": np.full(M, -1, np.int32)}
 
 
 def concat_records(a: dict, b: dict) -> dict:

@@ -299,6 +299,34 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
   return 0;
 }
 
+/* ------------------------------------------------------------------ passive component
+ *
+ * Direct propagation from the emitter to each receiver (the passive component of the
+ * method, with its transfer function P(f) = L_geo L_atm I_p e^{j omega r / c}): one
+ * line-of-sight test per receiver over the open segment (t_eps, r - t_eps), no triangle
+ * excluded.  certified[m] = 0 when that decision is marginal in the FP32 sense. */
+int orc_passive(int64_t V, int64_t T, const float* verts, const int32_t* tris, const double* emitter_pos,
+                int32_t M, const double* rx_pos, double t_eps, double kappa, uint8_t* vis, uint8_t* certified) {
+  if (T < 0 || M < 0 || (T > 0 && (!verts || !tris))) return -1;
+  (void)V;
+  tri_t* tr = T > 0 ? make_tris(T, verts, tris) : NULL;
+  v3 s = ld3d(emitter_pos);
+  for (int32_t m = 0; m < M; ++m) {
+    v3 w = sub(ld3d(rx_pos + 3 * m), s);
+    double r = norm(w);
+    int blocked = 0, marg = 0;
+    if (r > 2.0 * t_eps && T > 0) {
+      v3 d = scl(w, 1.0 / r);
+      blocked = any_hit(s, d, tr, T, -1, t_eps, r - t_eps);
+      marg = kappa > 0.0 && anyhit_marginal(s, d, tr, T, -1, t_eps, r - t_eps, kappa);
+    }
+    vis[m] = (uint8_t)!blocked;
+    if (certified) certified[m] = (uint8_t)!marg;
+  }
+  free(tr);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ synthesis */
 
 /* Receiver directivity: real gain per band, cell-centred az/el grid in the receiver
@@ -342,9 +370,12 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
               double f_lo, double f_hi, int32_t F, int32_t nk, const int32_t* k_list,
               double c, double A0, double A1, double p_s, int32_t sigma,
               int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-              int32_t Bd, int32_t El, int32_t Az, const float* directivity, double* out) {
+              int32_t Bd, int32_t El, int32_t Az, const float* directivity, const float* passive_coef,
+              const int32_t* rx_id, double* out) {
   if (M < 1 || F < 1 || nk < 1 || Q < 1 || Bk < 1) return -1;
   if (directivity && (Bd < 1 || El < 1 || Az < 1)) return -1;
+  for (int64_t n = 0; n < n_rec; ++n)
+    if (kind && kind[n] == 2 && !passive_coef) return -1;   /* passive records need I_p */
   const double df = F > 1 ? (f_hi - f_lo) / (double)(F - 1) : 0.0;
   const int KB = 64;
   const int nkb = (nk + KB - 1) / KB;
@@ -360,6 +391,7 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
       for (int64_t n = 0; n < n_rec; ++n) {
         if (vis && !vis[n]) continue;
         int kd = kind ? kind[n] : 0;
+        if (kd == 2 && mat[n] != (rx_id ? rx_id[m] : m)) continue;   /* passive: its own receiver only */
         v3 pn = ld3d(p + 3 * n);
         pair_t q = pair_setup(pn, kd == 0 ? ld3d(dout + 3 * n) : mk(1, 0, 0), rtot[n], kd, xm);
         if (directivity) {
@@ -380,8 +412,10 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
           if (kd == 0) {
             double bt = (double)beta[mat[n] * Bk + b];
             I = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt)) * (double)refl_k[mat[n] * Bk + b];
-          } else {
+          } else if (kd == 1) {
             I = (double)diff_coef[mat[n] * Bk + b];
+          } else {
+            I = (double)passive_coef[b];
           }
           double A = Lgeo * Latm * I;
           if (directivity) A *= Dg[(k * Bd) / F];
@@ -406,8 +440,10 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const double* g, double* grad_k, double* grad_x) {
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x) {
   if (M < 1 || F < 1 || Q < 1 || Bk < 1 || Bk > 64) return -1;
+  for (int64_t n = 0; n < n_rec; ++n)
+    if (kind && kind[n] == 2 && !passive_coef) return -1;   /* passive records need I_p */
   const double df = F > 1 ? (f_hi - f_lo) / (double)(F - 1) : 0.0;
   const double ln10 = log(10.0);
   double* gk_m = (double*)calloc((size_t)M * Q * Bk, sizeof(double));
@@ -420,6 +456,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
     for (int64_t n = 0; n < n_rec; ++n) {
       if (vis && !vis[n]) continue;
       int kd = kind ? kind[n] : 0;
+      if (kd == 2 && mat[n] != m) continue;   /* passive: its own receiver only */
       v3 pn = ld3d(p + 3 * n);
       v3 dn = kd == 0 ? ld3d(dout + 3 * n) : mk(1, 0, 0);
       pair_t q = pair_setup(pn, dn, rtot[n], kd, xm);
@@ -435,8 +472,10 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
         if (kd == 0) {
           double bt = (double)beta[mat[n] * Bk + b];
           I = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt)) * (double)refl_k[mat[n] * Bk + b];
-        } else {
+        } else if (kd == 1) {
           I = (double)diff_coef[mat[n] * Bk + b];
+        } else {
+          I = (double)passive_coef[b];
         }
         double A = Lgeo * Latm * I;
         double cyc = (double)sigma * f * q.r / c;

@@ -11,6 +11,7 @@
  *   - per-point magnitude and transfer function: Eqs. (2)-(4)
  *   - curvature metric: Section III-B, Eq. (1), Meyer et al. 2003 operator
  *   - Monte Carlo diffraction and its transfer function: Section III-D, Eqs. (7)-(8)
+ *   - passive component (direct emitter-receiver path): its section, Eqs. (11)-(13)
  *
  * All arithmetic is IEEE double, compiled with -ffp-contract=off.  Brute force: no
  * acceleration structure anywhere.  Every function returns 0 on success, a negative
@@ -37,14 +38,17 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
               uint8_t* ray_certified, int32_t* ray_nseg);
 
 /* Eqs. (2)-(4) and (7)-(8): direct spectral sum over records for the listed bins.
- * kind[n] = 0 specular (uses dout, lobe, refl_k), 1 diffraction (uses diff_coef).
- * Records with vis[n]==0 contribute nothing.  out is [M][nk][2] (re, im). */
+ * kind[n] = 0 specular (uses dout, lobe, refl_k), 1 diffraction (uses diff_coef),
+ * 2 passive (the emitter itself as the point, rtot 0, passive_coef [Bk]; it reaches only
+ * the receiver whose id equals mat[n]; rx_id[m] gives the ids of the rx_pos rows, NULL
+ * for 0..M-1).  Records with vis[n]==0 contribute nothing.  out is [M][nk][2] (re, im). */
 int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* rtot, const int32_t* mat,
               const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos, const double* rx_rot,
               double f_lo, double f_hi, int32_t F, int32_t nk, const int32_t* k_list,
               double c, double A0, double A1, double p_s, int32_t sigma,
               int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-              int32_t Bd, int32_t El, int32_t Az, const float* directivity, double* out);
+              int32_t Bd, int32_t El, int32_t Az, const float* directivity, const float* passive_coef,
+              const int32_t* rx_id, double* out);
 
 /* Analytic gradient of L = sum_{m,k} |H_mk - H*_mk|^2 given g = H - H* ([M][F][2]),
  * with respect to refl_k [Q][Bk] and the receiver positions [M][3], over fixed records.
@@ -53,7 +57,12 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const double* g, double* grad_k, double* grad_x);
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x);
+
+/* Passive component: line of sight from the emitter to each receiver (vis[M]) and whether
+ * that decision is certified against FP32 traversal (certified[M], may be NULL). */
+int orc_passive(int64_t V, int64_t T, const float* verts, const int32_t* tris, const double* emitter_pos,
+                int32_t M, const double* rx_pos, double t_eps, double kappa, uint8_t* vis, uint8_t* certified);
 
 /* Section III-B, Eq. (1): per-vertex mean-curvature magnitude G_v (Meyer et al.
  * cotangent operator with mixed Voronoi areas) and per-triangle metric

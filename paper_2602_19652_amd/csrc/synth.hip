@@ -376,10 +376,10 @@ __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x
 
 // One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
 // nseg band segments cover the tile; this lane's row lies in segment myseg.
-// X lands at xr/xi[record * XS + k1], Y at yr/yi[record * ys_rec + k2 * ys_k].
+// X lands at xr/xi[record * xs + k1], Y at yr/yi[record * ys + k2].
 __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi,
-                                float* yr, float* yi, int ys_rec, int ys_k, WaveScratch& W) {
+                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi, int xs,
+                                float* yr, float* yi, int ys, WaveScratch& W) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
@@ -426,10 +426,10 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
     x.x *= f;
     x.y *= f;
     if (!xon) x = z0;
-    xr[(row0 + rr) * XS + lane] = x.x;
-    xi[(row0 + rr) * XS + lane] = x.y;
-    yr[(row0 + rr) * ys_rec + lane * ys_k] = y.x;
-    yi[(row0 + rr) * ys_rec + lane * ys_k] = y.y;
+    xr[(row0 + rr) * xs + lane] = x.x;
+    xi[(row0 + rr) * xs + lane] = x.y;
+    yr[(row0 + rr) * ys + lane] = y.x;
+    yi[(row0 + rr) * ys + lane] = y.y;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -496,8 +496,8 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArg
     const int t = (int)(s & 7);
     // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
     if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &buf.X[0][0][0], &buf.X[1][0][0],
-             &buf.Y[0][0][0], &buf.Y[1][0][0], XS, 1, wscr[wv]);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &buf.X[0][0][0], &buf.X[1][0][0], XS,
+             &buf.Y[0][0][0], &buf.Y[1][0][0], XS, wscr[wv]);
     __syncthreads();
     if (SPLIT) contract<RB / 8>(buf, h1 * (RB / 2), 0, h2, lane, acc);
     else contract<RB / 4>(buf, 0, xrow0, h2, lane, acc);
@@ -789,15 +789,20 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 // k2 (Gauss's three real products on the matrix cores, G in registers).  The per-row
 // products go to LDS; per record, band sums and the weighted sum run in FP64 in a fixed
 // order, and the FP64 chain rule of the direct adjoint turns them into dL/dk and dL/dx_m.
-constexpr int YT = 33;   // LDS stride of transposed Y (records fast); odd, so writes spread over banks
+// LDS record stride of the adjoint's X, Y and R0: with 68 = 4 (mod 64) the MFMA operand reads
+// Y[16 nb + lane % 16][4 ks + lane / 16] hit 64 distinct banks, generation writes stay
+// contiguous, and 16-byte accesses of four consecutive rows are conflict-free per quarter wave.
+constexpr int BS68 = 68;
 
-struct BwdBuf {
-  float X[2][RB][XS];        // [re/im][record][k1]
-  float Yt[2][K2][YT];       // [re/im][k2][record]
-  float R0[RB][KT1 + 1];     // Re(X Z) per (record, row)
+struct __align__(16) BwdBuf {
+  float X[2][RB][BS68];      // [re/im][record][k1]
+  float Y[2][RB][BS68];      // [re/im][record][k2]
+  float R0[RB][BS68];        // Re(X Z) per (record, row)
   float2 R1[RB][17];         // sum over 4 rows of X (f Z + df Z') per (record, row group)
-  double kv[RB][16];         // dL/dk contribution per (record, band)
+  double kv[RB][17];         // dL/dk contribution per (record, band)
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
+  double lobe_w[256];        // per (material, band): 1 / (2 beta^2)
+  double kinv2[256];         // per (material, band): 2 / k (0 where k = 0)
 };
 
 template <bool BATCH>
@@ -844,12 +849,17 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
   for (int i = tid; i < a.Q; i += 256) bb.kmask[0][i] = bb.kmask[1][i] = 0u;   // first used after two barriers
+  for (int i = tid; i < QB; i += 256) {
+    const double bt = (double)a.beta[i], kk = (double)a.refl_k[i];
+    bb.lobe_w[i] = 1.0 / (2.0 * bt * bt);
+    bb.kinv2[i] = kk != 0.0 ? 2.0 / kk : 0.0;
+  }
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0],
-             &bb.Yt[0][0][0], &bb.Yt[1][0][0], 1, YT, wscr[wv]);
+    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0], BS68,
+             &bb.Y[0][0][0], &bb.Y[1][0][0], BS68, wscr[wv]);
     __syncthreads();
     floatx4 acc[6][2];
 #pragma unroll
@@ -864,7 +874,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       for (int nb = 0; nb < 2; ++nb) {
         if (nbw >= 0 && nb != nbw) continue;
         const int nn = nb * 16 + (lane & 15);
-        const float yr = bb.Yt[0][kk][nn], yi = bb.Yt[1][kk][nn];
+        const float yr = bb.Y[0][nn][kk], yi = bb.Y[1][nn][kk];
         const float b0 = yr, b1 = yi - yr, b2 = yr + yi;
         acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], b0, acc[0][nb], 0, 0, 0);
         acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], b1, acc[1][nb], 0, 0, 0);
@@ -879,19 +889,24 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     for (int nb = 0; nb < 2; ++nb) {
       if (nbw >= 0 && nb != nbw) continue;
       const int n = nb * 16 + (lane & 15);
+      const int r10 = rbw * 16 + (lane >> 4) * 4;   // this lane's four rows r10 .. r10 + 3
+      const float4 x4r = *reinterpret_cast<const float4*>(&bb.X[0][n][r10]);
+      const float4 x4i = *reinterpret_cast<const float4*>(&bb.X[1][n][r10]);
+      const float xrv[4] = {x4r.x, x4r.y, x4r.z, x4r.w}, xiv[4] = {x4i.x, x4i.y, x4i.z, x4i.w};
+      float crv[4];
       float s1r = 0.f, s1i = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r1 = rbw * 16 + (lane >> 4) * 4 + v;
         const float zr = acc[0][nb][v] - acc[2][nb][v], zi = acc[0][nb][v] + acc[1][nb][v];
         const float wr = acc[3][nb][v] - acc[5][nb][v], wi = acc[3][nb][v] + acc[4][nb][v];
-        const float xr = bb.X[0][n][r1], xi = bb.X[1][n][r1];
+        const float xr = xrv[v], xi = xiv[v];
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
-        const float fr = frow0 + (float)r1 * df64;
-        bb.R0[n][r1] = cr;
+        const float fr = frow0 + (float)(r10 + v) * df64;
+        crv[v] = cr;
         s1r += fr * cr + dff * (xr * wr - xi * wi);
         s1i += fr * ci + dff * (xr * wi + xi * wr);
       }
+      *reinterpret_cast<float4*>(&bb.R0[n][r10]) = make_float4(crv[0], crv[1], crv[2], crv[3]);
       bb.R1[n][rbw * 4 + (lane >> 4)] = make_float2(s1r, s1i);
     }
     __syncthreads();
@@ -927,10 +942,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         s0 += sb;
         double kvv = 0.0;
         if (valid && kind == 0 && b < a.Bk) {
-          const double bt = (double)a.beta[mat * a.Bk + b];
-          wl += sb / (2.0 * bt * bt);
-          const double kk = (double)a.refl_k[mat * a.Bk + b];
-          kvv = kk != 0.0 ? 2.0 * sb / kk : 0.0;
+          wl += sb * bb.lobe_w[mat * a.Bk + b];
+          kvv = sb * bb.kinv2[mat * a.Bk + b];
         }
         bb.kv[n][b] = kvv;
       }

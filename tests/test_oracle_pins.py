@@ -440,3 +440,65 @@ def test_margin_predicate_flags_edge_hits():
     sim = _sim(ray_dirs=dirs, rx_pos=[[0, 0.01, 0]])
     rec = O.trace(scene, sim)
     assert list(rec["certified"]) == [False, False, True, True]
+
+
+# ---------------------------------------------------------------------------------------- passive component
+
+def test_passive_equals_mirror_image_echo():
+    """A perfect mirror (k = 1, lobe wide enough to be 1 to 1e-12) makes the traced specular
+    echo s -> p -> A equal to the direct (passive) term from s to A's mirror image A':
+    same path |A' - s|, same spreading, absorption and phase.  The two go through different
+    parts of the oracle (tracing + specular synthesis vs the passive record)."""
+    d = 2.0
+    scene = wall_scene(d=d)
+    A = np.array([0.0, 0.3, 0.1])
+    A_img = np.array([2 * d, 0.3, 0.1])
+    p_spec = A_img * 0.5                                  # the specular point on x = d
+    dirs = (p_spec / np.linalg.norm(p_spec)).reshape(1, 3)
+    ones = np.ones((1, 8), np.float32)
+    sim = _sim(rx_pos=[A], ray_dirs=dirs, refl_k=ones, lobe_beta=np.full((1, 8), 1e6, np.float32),
+               passive_coef=np.ones(8, np.float32))
+    rec = O.trace(scene, sim, dirs=dirs.astype(np.float32), certify=False)
+    assert len(rec["rtot"]) == 1 and rec["vis"][0] == 1
+    H_spec = O.synth(rec, sim)
+    sim_img = dict(sim, rx_pos=A_img.reshape(1, 3), x_ref=A_img)
+    H_pass = O.synth(O.passive_records(sim_img, [True]), sim_img)
+    # the ray direction is FP32: compare against the echo of the traced point itself
+    r_traced = rec["rtot"][0] + np.linalg.norm(A - rec["p"][0])
+    assert abs(r_traced - np.linalg.norm(A_img)) < 1e-6
+    sim_img2 = dict(sim_img, rx_pos=(A_img * r_traced / np.linalg.norm(A_img)).reshape(1, 3))
+    H_pass2 = O.synth(O.passive_records(sim_img2, [True]), sim_img2)
+    np.testing.assert_allclose(H_pass2, H_spec, rtol=1e-9, atol=1e-12 * np.abs(H_spec).max())
+    assert np.abs(H_pass).max() > 0
+
+
+def test_passive_line_of_sight():
+    """The wall blocks the emitter's view of the mirror image behind it, not of a receiver in
+    front of it; blocked passive records contribute nothing."""
+    scene = wall_scene(d=2.0)
+    sim = _sim(rx_pos=[[0.0, 0.3, 0.1], [4.0, 0.3, 0.1]], passive_coef=np.ones(8, np.float32))
+    vis, cert = O.passive(scene, sim)
+    assert list(vis) == [True, False] and cert.all()
+    H = O.synth(O.passive_records(sim, vis), sim)
+    assert np.abs(H[0]).min() > 0 and np.abs(H[1]).max() == 0
+
+
+def test_passive_adjoint_matches_finite_differences():
+    """The receiver gradient of the passive term (r = |x_m - s|) by central differences.
+    Receivers half a metre from the emitter: at 2.5 cm the 1/r^2 curvature of the direct
+    term makes the differences, not the gradient, the inaccurate side."""
+    scene, sim = W.tiny_scene(n_rays=24, F=48)
+    sim = dict(sim, rx_pos=np.array([[0.3, 0.4, 0.1], [0.2, -0.5, -0.1]]), x_ref=np.array([0.25, -0.05, 0.0]))
+    sim["passive_coef"] = np.ascontiguousarray(W.rng(4).uniform(0.2, 1.0, 8).astype(np.float32))
+    rec = O.concat_records(O.trace(scene, sim), O.passive_records(sim, [True, True]))
+    g = W.rng(5)
+    Hstar = O.synth(rec, dict(sim, rx_pos=sim["rx_pos"] + g.normal(0, 1e-3, sim["rx_pos"].shape)))
+    H = O.synth(rec, sim)
+    _, gx = O.grad(rec, sim, H - Hstar)
+    h = 1e-6
+    for m in range(2):
+        for a in range(3):
+            sp = dict(sim); sp["rx_pos"] = sim["rx_pos"].copy(); sp["rx_pos"][m, a] += h
+            sm = dict(sim); sm["rx_pos"] = sim["rx_pos"].copy(); sm["rx_pos"][m, a] -= h
+            fd = (_loss(rec, sp, Hstar) - _loss(rec, sm, Hstar)) / (2 * h)
+            np.testing.assert_allclose(gx[m, a], fd, rtol=1e-5, atol=1e-9 * max(1.0, abs(fd)))
