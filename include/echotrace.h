@@ -106,7 +106,10 @@ int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double
 enum {
   ET_SPECULAR = 1u << 0,      /* trace rays (Algorithm 1) and synthesise their records */
   ET_DIFFRACTION = 1u << 1,   /* draw diff_K curvature-importance samples (Sec. III-D) */
-  ET_SYNTH_DIRECT = 1u << 2   /* force the per-term synthesis and adjoint kernels (no factorised MFMA path) */
+  ET_SYNTH_DIRECT = 1u << 2,  /* force the per-term synthesis and adjoint kernels (no factorised MFMA path) */
+  ET_PASSIVE = 1u << 3        /* passive component: direct emitter -> receiver path per receiver,
+                                 P(f) = L_geo L_atm I_p e^{j omega r / c} (Eqs. 11-13), with a
+                                 line-of-sight test from the emitter to each receiver */
 };
 
 typedef struct {
@@ -140,16 +143,19 @@ typedef struct {
   double diff_tau;              /* eligibility: C_i >= tau * max C */
   double diff_max_incidence;    /* incidence limit between normal and source direction */
   double diff_cone_half_angle;  /* emitter field of view for object eligibility */
-  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT */
+  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT | ET_PASSIVE */
+  const float* passive_coef;    /* device [Bk] source magnitude I_p per band (ET_PASSIVE), >= 0 */
 } et_sim_desc;
 
-/* Path records (hit buffer B of Algorithm 1 plus diffraction points), caller-owned
- * device SoA arrays of `capacity` entries.  Order: specular records bounce-major (all
- * bounce-0 hits, then bounce 1, ...); within a bounce the rays follow the library's
- * traversal order (ray order, or sorted by direction when there are more rays than threads
- * in the traversal grid; deterministic either way; `ray` names each record's ray).
- * Kept diffraction samples follow in sample order.  count (device int64[4]) =
- * {records, specular, diffraction, segments}. */
+/* Path records (hit buffer B of Algorithm 1 plus diffraction points and the passive
+ * component), caller-owned device SoA arrays of `capacity` entries.  Order: specular
+ * records bounce-major (all bounce-0 hits, then bounce 1, ...); within a bounce the rays
+ * follow the library's traversal order (ray order, or sorted by direction when there are
+ * more rays than threads in the traversal grid; deterministic either way; `ray` names each
+ * record's ray).  Kept diffraction samples follow in sample order, then with ET_PASSIVE one
+ * record per receiver m (the emitter as the point, rtot 0, mat = ray = m) that reaches
+ * receiver m only.  count (device int64[4]) = {records, specular, diffraction, segments};
+ * passive records = records - specular - diffraction. */
 typedef struct {
   int64_t capacity;
   double* p;          /* [cap][3] hit / diffraction point */
@@ -159,7 +165,8 @@ typedef struct {
   int32_t* mat;       /* [cap] material of the triangle */
   int32_t* ray;       /* [cap] ray index (specular) or sample index (diffraction) */
   uint8_t* bounce;    /* [cap] reflection index within the ray */
-  uint8_t* flags;     /* [cap] bit0 visible (line of sight), bit1 diffraction record */
+  uint8_t* flags;     /* [cap] bit0 visible (line of sight); bits 1-2 kind: 0 specular,
+                         1 diffraction, 2 passive */
   int64_t* count;     /* device int64[4] */
 } et_paths;
 
@@ -254,6 +261,7 @@ typedef struct {
   double ms_synth_kernel, ms_adjoint_kernel;         /* the main synthesis / adjoint kernel alone */
   int32_t adjoint_kernel;                            /* 1 factorised MFMA, 2 direct per-term */
   int32_t reserved0;
+  int64_t passive;                                   /* passive records of the last trace */
 } et_stats;
 int et_get_stats(et_ctx* ctx, et_stats* out);   /* synchronises the context stream */
 

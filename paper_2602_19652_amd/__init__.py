@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libechotrace.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "echotrace.h")
 
-ET_SPECULAR, ET_DIFFRACTION, ET_SYNTH_DIRECT = 1, 2, 4
+ET_SPECULAR, ET_DIFFRACTION, ET_SYNTH_DIRECT, ET_PASSIVE = 1, 2, 4, 8
 STATUS = {0: "ET_OK", -1: "ET_E_INVALID", -2: "ET_E_WORKSPACE", -3: "ET_E_CAPACITY", -4: "ET_E_DEVICE",
           -5: "ET_E_UNSUPPORTED", -6: "ET_E_INTERNAL"}
 
@@ -49,7 +49,7 @@ class SimDesc(C.Structure):
                 ("lobe_beta", C.c_void_p), ("diff_coef", C.c_void_p), ("Bd", C.c_int32), ("El", C.c_int32),
                 ("Az", C.c_int32), ("directivity", C.c_void_p), ("diff_K", C.c_int64), ("diff_seed", C.c_uint64),
                 ("diff_tau", C.c_double), ("diff_max_incidence", C.c_double), ("diff_cone_half_angle", C.c_double),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("passive_coef", C.c_void_p)]
 
 
 class PathsDesc(C.Structure):
@@ -69,7 +69,7 @@ class Stats(C.Structure):
                 ("dropped", C.c_int64), ("synth_kernel", C.c_int32), ("status", C.c_int32), ("ms_trace", C.c_double),
                 ("ms_diffraction", C.c_double), ("ms_synth", C.c_double), ("ms_adjoint", C.c_double),
                 ("ms_synth_kernel", C.c_double), ("ms_adjoint_kernel", C.c_double),
-                ("adjoint_kernel", C.c_int32), ("reserved0", C.c_int32)]
+                ("adjoint_kernel", C.c_int32), ("reserved0", C.c_int32), ("passive", C.c_int64)]
 
 
 class Counters(C.Structure):
@@ -278,8 +278,11 @@ class Sim:
         self.diff_coef = _to_dev(sim["diff_coef"], torch.float32)
         D = sim.get("directivity")
         self.directivity = None if D is None else _to_dev(D, torch.float32)
+        pc = sim.get("passive_coef")
+        self.passive_coef = None if pc is None else _to_dev(pc, torch.float32)
         if flags is None:
-            flags = ET_SPECULAR | (ET_DIFFRACTION if sim.get("diff_K", 0) > 0 else 0)
+            flags = (ET_SPECULAR | (ET_DIFFRACTION if sim.get("diff_K", 0) > 0 else 0)
+                     | (ET_PASSIVE if pc is not None else 0))
         d = SimDesc()
         d.emitter_pos[:] = [float(x) for x in np.asarray(sim["emitter_pos"], float)]
         d.emitter_rot[:] = [float(x) for x in np.asarray(sim["emitter_rot"], float).ravel()]
@@ -310,6 +313,7 @@ class Sim:
         d.rx_pos, d.rx_rot, d.ray_dirs = _ptr(self.rx_pos).value, _ptr(self.rx_rot).value, _ptr(self.ray_dirs).value
         d.refl_k, d.lobe_beta, d.diff_coef = _ptr(self.refl_k).value, _ptr(self.lobe_beta).value, _ptr(self.diff_coef).value
         d.directivity = None if self.directivity is None else _ptr(self.directivity).value
+        d.passive_coef = None if self.passive_coef is None else _ptr(self.passive_coef).value
 
     @property
     def M(self):
@@ -362,7 +366,7 @@ class Paths:
             if "tri" in rec:
                 P.tri[:n] = torch.as_tensor(np.asarray(rec["tri"], np.int32))
             vis = np.asarray(rec.get("vis", np.ones(n)), np.uint8) & 1
-            kind = np.asarray(rec.get("kind", np.zeros(n)), np.uint8) & 1
+            kind = np.asarray(rec.get("kind", np.zeros(n)), np.uint8) & 3
             P.flags[:n] = torch.as_tensor(vis | (kind << 1))
         P.count[0] = n
         P.count[1] = n
@@ -377,7 +381,7 @@ class Paths:
         return {"p": self.p[:n].cpu().numpy(), "dout": self.dout[:n].cpu().numpy().astype(np.float64),
                 "rtot": self.rtot[:n].cpu().numpy(), "tri": self.tri[:n].cpu().numpy(), "mat": self.mat[:n].cpu().numpy(),
                 "ray": self.ray[:n].cpu().numpy(), "bounce": self.bounce[:n].cpu().numpy().astype(np.int32),
-                "vis": (fl & 1).astype(np.uint8), "kind": ((fl >> 1) & 1).astype(np.uint8),
+                "vis": (fl & 1).astype(np.uint8), "kind": ((fl >> 1) & 3).astype(np.uint8),
                 "count": self.count[:4].cpu().numpy()}
 
 

@@ -81,6 +81,7 @@ void validate_sim(const et_sim_desc* s, bool need_rays) {
   if (s->directivity) {
     ET_CHECK(s->Bd >= 1 && s->Bd <= 64 && s->El >= 1 && s->Az >= 1, ET_E_INVALID, "directivity shape invalid");
   }
+  ET_CHECK(!(s->flags & ET_PASSIVE) || s->passive_coef, ET_E_INVALID, "ET_PASSIVE needs passive_coef");
   if (need_rays) {
     ET_CHECK(s->N >= 0, ET_E_INVALID, "negative ray count");
     ET_CHECK(s->N == 0 || s->ray_dirs || !(s->flags & ET_SPECULAR), ET_E_INVALID, "ray_dirs is NULL");
@@ -109,6 +110,7 @@ int64_t records_upper_bound(const et_sim_desc* s) {
   int64_t n = 0;
   if (s->flags & ET_SPECULAR) n += s->N * (int64_t)s->max_bounces;
   if (s->flags & ET_DIFFRACTION) n += s->diff_K;
+  if (s->flags & ET_PASSIVE) n += s->M;
   return n;
 }
 
@@ -123,7 +125,7 @@ size_t paths_bytes(int64_t cap) {
 bool batch_fused(int32_t J, const et_job* jobs) {
   if (J > 65536) return false;   // the ray sort keys hold the job in 16 bits
   for (int32_t j = 0; j < J; ++j)
-    if (jobs[j].sim->flags & ET_DIFFRACTION) return false;
+    if (jobs[j].sim->flags & (ET_DIFFRACTION | ET_PASSIVE)) return false;
   return true;
 }
 
@@ -588,6 +590,7 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
       int64_t cnt[4];
       ET_HIP(hipMemcpy(cnt, ctx->last_count, sizeof(cnt), hipMemcpyDeviceToHost));
       out->records = cnt[0];
+      out->passive = cnt[0] - cnt[1] - cnt[2];
     }
     float ms = 0;
     auto pair = [&](uint32_t bit, int a, int b, double& dst) {

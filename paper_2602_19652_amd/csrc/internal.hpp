@@ -203,6 +203,7 @@ struct SynthWS {
   float* lk;                 // per (material, band): log2 k, log2(e)/(2 beta^2), log2 I_d
   float* lc;
   float* ld;
+  float* lp;                 // [Bk] log2 I_p (passive component)
 };
 size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
 // returns 1 for the factorised MFMA kernel, 2 for the direct kernel
@@ -248,7 +249,7 @@ struct SynthBatchWS {
   void* sort_tmp;
   int64_t* tab;                 // chunk tables (forward, adjoint)
   void* jobs;                   // device job table
-  float* tables;                // [J][3][Q][Bk] band tables
+  float* tables;                // [J][4][Q][Bk] band tables
 };
 bool synth_batch_factorised(int32_t J, const et_job* jobs, bool adjoint);
 size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const BatchTune& tune, bool adjoint,

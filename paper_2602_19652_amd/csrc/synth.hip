@@ -56,6 +56,8 @@ struct SynthArgs {
   const float* lk;         // [Q][Bk] log2 k
   const float* lc;         // [Q][Bk] log2(e) / (2 beta^2)
   const float* ld;         // [Q][Bk] log2 I_d
+  const float* pcoef;      // [Bk] passive source magnitude I_p (NULL without the passive component)
+  const float* lp;         // [Bk] log2 I_p
 };
 
 SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
@@ -75,6 +77,7 @@ SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
   a.kcb = (double)a.sigma * a.df / a.c;
   a.kbase = -(a.A0 + a.A1 * a.f_lo) / 20.0 * LOG2_10;
   a.kslope = -a.A1 * a.df / 20.0 * LOG2_10;
+  a.pcoef = (sim->flags & ET_PASSIVE) ? sim->passive_coef : nullptr;
   return a;
 }
 
@@ -112,11 +115,13 @@ __device__ inline float dir_gain(const float* tab, int El, int Az, float vx, flo
   return (1.f - te) * a0 + te * a1;
 }
 
-// Returns false if the record does not contribute (not visible).
+// Returns false if the record does not contribute to receiver m (not visible, or a passive
+// record of another receiver).
 __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t n, int m, Pair& q) {
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return false;
-  q.kind = (fl >> 1) & 1;
+  q.kind = (fl >> 1) & 3;
+  if (q.kind == 2 && P.mat[n] != m) return false;
   const double px = P.p[3 * n], py = P.p[3 * n + 1], pz = P.p[3 * n + 2];
   const double wx = a.rx_pos[3 * m] - px, wy = a.rx_pos[3 * m + 1] - py, wz = a.rx_pos[3 * m + 2] - pz;
   q.l = sqrt(wx * wx + wy * wy + wz * wz);
@@ -138,19 +143,25 @@ __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t
   return true;
 }
 
-// log2 of the band factor: k exp(-gamma^2 / (2 beta^2)) (specular) or I_d (diffraction)
+// log2 of the band factor: k exp(-gamma^2 / (2 beta^2)) (specular), I_d (diffraction) or
+// I_p (passive)
 __device__ inline float band_log2_v(const SynthArgs& a, int kind, int mat, float gamma, int b) {
   const int i = mat * a.Bk + b;
-  return kind == 0 ? a.lk[i] - gamma * gamma * a.lc[i] : a.ld[i];
+  return kind == 0 ? a.lk[i] - gamma * gamma * a.lc[i] : kind == 1 ? a.ld[i] : a.lp[b];
 }
 
-__global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.Q * a.Bk) return;
+__device__ inline void band_table_entry(const SynthArgs& a, int i, float* lk, float* lc, float* ld, float* lp) {
   const float bt = a.beta[i];
   lk[i] = log2f(a.refl_k[i]);
   lc[i] = LOG2E_F / (2.0f * bt * bt);
   ld[i] = log2f(a.dcoef[i]);
+  if (i < a.Bk) lp[i] = a.pcoef ? log2f(a.pcoef[i]) : -INFINITY;
+}
+
+__global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld, float* lp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.Q * a.Bk) return;
+  band_table_entry(a, i, lk, lc, ld, lp);
 }
 
 __device__ inline float band_log2(const SynthArgs& a, const Pair& q, int b) { return band_log2_v(a, q.kind, q.mat, q.gamma, b); }
@@ -273,7 +284,9 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   const int64_t n = idx[e];
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return;
-  q.kind = (fl >> 1) & 1;
+  const int kind = (fl >> 1) & 3;
+  if (kind == 2 && P.mat[n] != m) return;   // a passive record reaches its own receiver only
+  q.kind = kind;
   const double wx = a.rx_pos[3 * m] - P.p[3 * n], wy = a.rx_pos[3 * m + 1] - P.p[3 * n + 1],
                wz = a.rx_pos[3 * m + 2] - P.p[3 * n + 2];
   const double l = sqrt(wx * wx + wy * wy + wz * wz);
@@ -1037,8 +1050,9 @@ void build_tables(SynthArgs& a, const SynthWS& ws, hipStream_t s) {
   a.lk = ws.lk;
   a.lc = ws.lc;
   a.ld = ws.ld;
+  a.lp = ws.lp;
   const int n = a.Q * a.Bk;
-  k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld);
+  k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld, ws.lp);
 }
 
 size_t table_ws(const et_sim_desc* sim, char* base, size_t off, SynthWS& w) {
@@ -1049,6 +1063,8 @@ size_t table_ws(const et_sim_desc* sim, char* base, size_t off, SynthWS& w) {
   off += al(sizeof(float) * n);
   w.ld = (float*)(base ? base + off : nullptr);
   off += al(sizeof(float) * n);
+  w.lp = (float*)(base ? base + off : nullptr);
+  off += al(sizeof(float) * sim->Bk);
   return off;
 }
 
@@ -1074,15 +1090,12 @@ __global__ void k_put_synth_jobs(SynthJobPack pk, SynthArgs* __restrict__ dst) {
   if ((int)threadIdx.x < pk.n) dst[pk.first + threadIdx.x] = pk.j[threadIdx.x];
 }
 
-// workgroup j fills job j's band tables (its lk / lc / ld point into the batch's table block)
+// workgroup j fills job j's band tables (its lk / lc / ld / lp point into the batch's table block)
 __global__ void k_band_tables_batch(const SynthArgs* __restrict__ jobs) {
   const SynthArgs a = jobs[blockIdx.x];
-  for (int i = threadIdx.x; i < a.Q * a.Bk; i += blockDim.x) {
-    const float bt = a.beta[i];
-    const_cast<float*>(a.lk)[i] = log2f(a.refl_k[i]);
-    const_cast<float*>(a.lc)[i] = LOG2E_F / (2.0f * bt * bt);
-    const_cast<float*>(a.ld)[i] = log2f(a.dcoef[i]);
-  }
+  for (int i = threadIdx.x; i < a.Q * a.Bk; i += blockDim.x)
+    band_table_entry(a, i, const_cast<float*>(a.lk), const_cast<float*>(a.lc), const_cast<float*>(a.ld),
+                     const_cast<float*>(a.lp));
 }
 
 // sort key of each visible record: its job (the ray field of a batch record)
@@ -1331,7 +1344,7 @@ size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const B
   w.sort_tmp = take(sort_temp_bytes(cap, 8));
   w.tab = (int64_t*)take(sizeof(int64_t) * (size_t)(3 * J + 2) * 2);
   w.jobs = take(sizeof(SynthArgs) * (size_t)J);
-  w.tables = (float*)take(sizeof(float) * 3 * (size_t)J * s0->Q * s0->Bk);
+  w.tables = (float*)take(sizeof(float) * 4 * (size_t)J * s0->Q * s0->Bk);
   if (ws) *ws = w;
   return off;
 }
@@ -1354,9 +1367,10 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
   SynthJobPack pk{};
   for (int32_t i = 0; i < J; ++i) {
     SynthArgs a = make_args(jobs[i].sim, 0);
-    a.lk = w.tables + (size_t)i * 3 * QB;
+    a.lk = w.tables + (size_t)i * 4 * QB;
     a.lc = a.lk + QB;
     a.ld = a.lc + QB;
+    a.lp = a.ld + QB;
     pk.j[pk.n++] = a;
     if (pk.n == SJOB_PACK || i + 1 == J) {
       k_put_synth_jobs<<<1, SJOB_PACK, 0, s>>>(pk, dj);

@@ -639,11 +639,57 @@ __global__ void k_diff_scatter(SceneDev S, DiffArgs a, TraceWS w, Ctl* ctl, et_p
 
 #pragma clang fp contract(on)
 
-__global__ void k_trace_final(Ctl* ctl, et_paths P, int diff) {
+// Passive component: one line-of-sight ray from the emitter to each receiver (no triangle
+// excluded) and one record per receiver after the specular and diffraction records: the
+// emitter as the point, path 0, the receiver in `mat` and `ray`, kind 2 in the flags.
+__global__ __launch_bounds__(BS) void k_passive(SceneDev S, PoseArgs a, const double* __restrict__ rx, int32_t M,
+                                                int diff, TraceWS w, Ctl* ctl, et_paths P) {
+  __shared__ int lds_stack[TRAV_LDS_STACK * BS];
+  const int64_t gtid = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * BS;
+  Stack st;
+  st.lds = lds_stack + threadIdx.x;
+  st.glob = w.gstack + gtid;
+  st.gstride = w.gstack_threads;
+  st.overflow = 0;
+  const int64_t base = ctl->rec_base + (diff ? (int64_t)ctl->tot[3] : 0);
+  int64_t dummy0 = 0, dummy1 = 0, rays = 0;
+  for (int64_t m = gtid; m < M; m += stride) {
+    const double wx = rx[3 * m] - a.s[0], wy = rx[3 * m + 1] - a.s[1], wz = rx[3 * m + 2] - a.s[2];
+    const double L = dnorm3(wx, wy, wz);
+    int vis = 1;
+    if (L > 2.0 * a.t_eps && S.T > 0) {
+      const Ray32 r = make_ray(a.s[0], a.s[1], a.s[2], wx / L, wy / L, wz / L);
+      float tv;
+      vis = traverse<true, false>(S, r, (float)a.t_eps, (float)(L - a.t_eps), -1, st, tv, dummy0, dummy1) < 0;
+      ++rays;
+    }
+    const int64_t ri = base + m;
+    if (ri < P.capacity) {
+      P.p[3 * ri] = a.s[0]; P.p[3 * ri + 1] = a.s[1]; P.p[3 * ri + 2] = a.s[2];
+      P.dout[3 * ri] = 0.f; P.dout[3 * ri + 1] = 0.f; P.dout[3 * ri + 2] = 0.f;
+      P.rtot[ri] = 0.0;
+      P.tri[ri] = -1;
+      P.mat[ri] = (int32_t)m;
+      P.ray[ri] = (int32_t)m;
+      P.bounce[ri] = 0;
+      P.flags[ri] = (uint8_t)(vis | 4);   // visible | kind 2
+    } else {
+      atomicOr(&ctl->err, DEV_ERR_CAPACITY);
+    }
+  }
+  if (st.overflow) {
+    atomicAdd((unsigned long long*)&ctl->overflow, (unsigned long long)st.overflow);
+    atomicOr(&ctl->err, DEV_ERR_STACK);
+  }
+  if (rays) atomicAdd((unsigned long long*)&ctl->shadow, (unsigned long long)rays);
+}
+
+__global__ void k_trace_final(Ctl* ctl, et_paths P, int diff, int32_t n_passive) {
   const int64_t spec = ctl->rec_base;
   const int64_t dk = diff ? (int64_t)ctl->tot[3] : 0;
   ctl->diff_kept = dk;
-  const int64_t total = spec + dk;
+  const int64_t total = spec + dk + n_passive;
   ctl->n_rec = total;
   P.count[0] = total;
   P.count[1] = spec;
@@ -767,7 +813,7 @@ void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_pat
       ET_HIP(hipGetLastError());
     }
   }
-  k_trace_final<<<1, 1, 0, s>>>(ctl, P, 0);
+  k_trace_final<<<1, 1, 0, s>>>(ctl, P, 0, 0);
   ET_HIP(hipGetLastError());
 }
 
@@ -821,7 +867,10 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     k_diff_scatter<<<nblk(d.K), BS, 0, s>>>(S, d, w, ctl, P);
     ET_HIP(hipGetLastError());
   }
-  k_trace_final<<<1, 1, 0, s>>>(ctl, P, diff ? 1 : 0);
+  const int32_t n_passive = (sim->flags & ET_PASSIVE) ? sim->M : 0;
+  if (n_passive > 0)
+    k_passive<<<nblk(n_passive), BS, 0, s>>>(S, a, sim->rx_pos, n_passive, diff ? 1 : 0, w, ctl, P);
+  k_trace_final<<<1, 1, 0, s>>>(ctl, P, diff ? 1 : 0, n_passive);
   ET_HIP(hipGetLastError());
 }
 

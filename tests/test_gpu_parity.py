@@ -290,6 +290,66 @@ def test_adjoint_matches_oracle_gradient(et, ctx, tiny, case):
     assert ek <= TOL and ex <= TOL
 
 
+# ----------------------------------------------------------------------------- passive component
+
+def _passive_sim(sim, rx):
+    g = W.rng(21)
+    return dict(sim, rx_pos=np.asarray(rx, float), rx_rot=np.repeat(np.eye(3)[None], len(rx), axis=0),
+                x_ref=np.asarray(rx, float).mean(axis=0),
+                passive_coef=g.uniform(0.2, 1.0, sim["refl_k"].shape[1]).astype(np.float32))
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_passive_component_matches_oracle(et, ctx, tiny, direct):
+    """Receivers in front of and behind the wall (x = 4): the GPU's line-of-sight decisions
+    match the oracle's, the passive records follow the others, and the spectra (specular on
+    certified rays + passive) match the oracle's."""
+    scene, sim, _ = tiny
+    sim = _passive_sim(sim, [[0.0, 0.3, 0.1], [0.2, -0.4, 0.0], [5.0, 0.3, 0.1], [4.5, -1.0, 0.5]])
+    vis_ref, cert = O.passive(scene, sim)
+    assert cert.all() and list(vis_ref) == [True, True, False, False]
+    ref = O.trace(scene, sim)
+    dirs = sim["ray_dirs"][ref["certified"]]
+    ref_c = O.trace(scene, sim, dirs=dirs)
+    rec_ref = O.concat_records(ref_c, O.passive_records(sim, vis_ref))
+    sc = et.Scene(ctx, scene)
+    flags = et.ET_SPECULAR | et.ET_PASSIVE | (et.ET_SYNTH_DIRECT if direct else 0)
+    s = et.Sim(sim, flags=flags, ray_dirs=dirs)
+    P = et.trace(ctx, sc, s)
+    st = ctx.stats()
+    gpu = P.to_host()
+    assert st.passive == 4 and st.records == len(rec_ref["rtot"])
+    tail = slice(len(gpu["rtot"]) - 4, None)
+    assert list(gpu["kind"][tail]) == [2, 2, 2, 2] and list(gpu["mat"][tail]) == [0, 1, 2, 3]
+    assert list(gpu["vis"][tail].astype(bool)) == list(vis_ref)
+    H = et.synthesize(ctx, s, P).cpu().numpy()
+    assert ctx.stats().synth_kernel == (2 if direct else 1)
+    H_ref = O.synth(rec_ref, sim)
+    e = rel_l2(H, H_ref)
+    print(f"passive ({'direct' if direct else 'factorised'}): rel L2 {e:.3e}; receivers behind the wall "
+          f"keep only echoes")
+    assert e <= TOL
+
+
+def test_passive_adjoint_matches_oracle(et, ctx, tiny):
+    """Adjoint over specular + passive records: the direct path's receiver gradient included."""
+    import torch
+    scene, sim, ref = tiny
+    sim = _passive_sim(dict(sim, F=512), [[0.3, 0.4, 0.1], [0.2, -0.5, -0.1]])
+    ref = O.trace(scene, sim, certify=False)
+    rec = O.concat_records(ref, O.passive_records(sim, [True, True]))
+    g = W.rng(22)
+    H_star = O.synth(rec, dict(sim, rx_pos=sim["rx_pos"] + g.normal(0, 1e-3, (2, 3))))
+    H = O.synth(rec, sim)
+    gk_ref, gx_ref = O.grad(rec, sim, H - H_star)
+    s = et.Sim(sim, flags=et.ET_SPECULAR | et.ET_PASSIVE)
+    P = et.Paths.from_records(rec)
+    gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(H - H_star).to("cuda"))
+    ek, ex = rel_l2(gk.cpu().numpy(), gk_ref), rel_l2(gx.cpu().numpy(), gx_ref)
+    print(f"passive adjoint (kernel {ctx.stats().adjoint_kernel}): rel err dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    assert ek <= TOL and ex <= TOL
+
+
 # ----------------------------------------------------------------------------- errors
 
 def test_invalid_arguments_report_status(et, ctx, tiny):
