@@ -246,3 +246,37 @@ def passive_records(sim: dict, vis) -> dict:
 def concat_records(a: dict, b: dict) -> dict:
     keys = ["p", "dout", "rtot", "mat", "kind", "vis"]
     return {k: np.concatenate([np.asarray(a[k]), np.asarray(b[k])]) for k in keys}
+
+
+# ------------------------------------------------------------------ time domain
+
+def impulse_response(H: np.ndarray, sim: dict, n_t: int):
+    """Impulse response per receiver from its spectrum on the grid f_k = f_lo + k df (Eqs. 5-6,
+    9-10, 13: h = F^-1[H]).  Under the e^{-i omega t} convention of the phase (sigma = +1), a
+    delay e^{+j sigma omega tau} becomes a peak at t = tau:
+        h(t) = 2 df Re sum_k H_k exp(-j sigma 2 pi f_k t),   t_n = n / (n_t df), n < n_t,
+    the real signal of the one-sided band spectrum.  The sum over k is a length-n_t DFT of the
+    zero-padded spectrum (numpy's FFT as the step), times the carrier exp(-j sigma 2 pi f_lo t).
+    Returns (h [M, n_t] float64, dt)."""
+    H = np.asarray(H, np.complex128)
+    M, F = H.shape
+    if n_t < F:
+        raise ValueError("n_t must be >= F")
+    sigma = int(sim["phase_sign"])
+    df = (sim["f_hi"] - sim["f_lo"]) / (F - 1) if F > 1 else 0.0
+    dt = 1.0 / (n_t * df)
+    pad = np.zeros((M, n_t), np.complex128)
+    pad[:, :F] = H
+    S = np.fft.fft(pad, axis=1) if sigma > 0 else np.fft.ifft(pad, axis=1) * n_t
+    n = np.arange(n_t)
+    cyc = sim["f_lo"] * n * dt                     # carrier phase in cycles, reduced before the exponential
+    carrier = np.exp(-1j * sigma * 2.0 * np.pi * (cyc - np.floor(cyc)))
+    return 2.0 * df * np.real(carrier[None, :] * S), dt
+
+
+def receiver_signal(h: np.ndarray, s_e: np.ndarray, dt: float) -> np.ndarray:
+    """Eq. 14: s(t) = (h * s_e)(t), sampled: s[n] = dt sum_k h[k] s_e[n - k], length
+    n_t + L - 1 (direct summation)."""
+    h = np.asarray(h, np.float64)
+    s_e = np.asarray(s_e, np.float64)
+    return dt * np.stack([np.convolve(row, s_e) for row in np.atleast_2d(h)])

@@ -502,3 +502,45 @@ def test_passive_adjoint_matches_finite_differences():
             sm = dict(sim); sm["rx_pos"] = sim["rx_pos"].copy(); sm["rx_pos"][m, a] -= h
             fd = (_loss(rec, sp, Hstar) - _loss(rec, sm, Hstar)) / (2 * h)
             np.testing.assert_allclose(gx[m, a], fd, rtol=1e-5, atol=1e-9 * max(1.0, abs(fd)))
+
+
+# ---------------------------------------------------------------------------------------- time domain
+
+@pytest.mark.parametrize("sigma", [1, -1])
+def test_impulse_response_of_a_pure_delay(sigma):
+    """A unit-amplitude path of delay tau has H_k = exp(j sigma 2 pi f_k tau); its impulse
+    response is the closed-form geometric series 2 df Re[e^{j s 2pi f_lo x} (1 - e^{j s 2pi F df x})
+    / (1 - e^{j s 2pi df x})] with x = tau - t, which peaks at t = tau."""
+    sim = _sim(F=256, phase_sign=sigma)
+    F, df = 256, (sim["f_hi"] - sim["f_lo"]) / 255
+    n_t = 1024
+    dt = 1.0 / (n_t * df)
+    tau = 137 * dt                                    # on the sample grid
+    f = sim["f_lo"] + df * np.arange(F)
+    H = np.exp(1j * sigma * 2 * np.pi * f * tau)[None, :]
+    h, dt_o = O.impulse_response(H, sim, n_t)
+    assert dt_o == pytest.approx(dt, rel=1e-15)
+    x = tau - dt * np.arange(n_t)
+    num = 1 - np.exp(1j * sigma * 2 * np.pi * F * df * x)
+    den = 1 - np.exp(1j * sigma * 2 * np.pi * df * x)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        geo = np.where(np.abs(den) > 1e-12, num / den, F)
+    closed = 2 * df * np.real(np.exp(1j * sigma * 2 * np.pi * sim["f_lo"] * x) * geo)
+    np.testing.assert_allclose(h[0], closed, atol=1e-9 * 2 * df * F)
+    assert int(np.argmax(h[0])) == 137
+    assert h[0, 137] == pytest.approx(2 * df * F, rel=1e-12)
+
+
+def test_receiver_signal_is_a_convolution():
+    """Convolving with a sampled delta returns the impulse response; with a delayed delta,
+    the response shifted; and the result is linear in the emitted call."""
+    g = W.rng(31)
+    h = g.normal(size=(3, 64))
+    dt = 1e-6
+    d0 = np.zeros(5); d0[0] = 1 / dt
+    np.testing.assert_allclose(O.receiver_signal(h, d0, dt)[:, :64], h, rtol=1e-14)
+    d2 = np.zeros(5); d2[2] = 1 / dt
+    np.testing.assert_allclose(O.receiver_signal(h, d2, dt)[:, 2:66], h, rtol=1e-14)
+    a, b = g.normal(size=9), g.normal(size=9)
+    np.testing.assert_allclose(O.receiver_signal(h, 2 * a - b, dt),
+                               2 * O.receiver_signal(h, a, dt) - O.receiver_signal(h, b, dt), atol=1e-18)
