@@ -174,6 +174,33 @@ def main():
         et.synthesize(ctx, s, P, ws=ws, out=out)
         ms_synth_kernel += ctx.stats().ms_synth_kernel / reps
 
+    # time domain of the step's spectra: impulse responses at fs = n_t df (16384 samples, 320 kHz)
+    # and received signals for a 2 ms 20-100 kHz chirp
+    Hc = torch.view_as_complex(out)
+    n_t = 16384
+    td_ws = et.Workspace()
+    h_t, dt = et.impulse_response(ctx, s, Hc, n_t, ws=td_ws)
+    L_call = int(round(2e-3 / dt))
+    tt = torch.arange(L_call, dtype=torch.float64, device="cuda") * dt
+    chirp = (torch.sin(2 * math.pi * (20e3 * tt + 0.5 * (80e3 / (L_call * dt)) * tt * tt))
+             * torch.hann_window(L_call, periodic=False, dtype=torch.float64, device="cuda")).float()
+    sig_ws = et.Workspace()
+    et.receiver_signal(ctx, h_t, chirp, dt, ws=sig_ws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        et.impulse_response(ctx, s, Hc, n_t, ws=td_ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_ir = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        et.receiver_signal(ctx, h_t, chirp, dt, ws=sig_ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sig = e0.elapsed_time(e1) / reps
+    del td_ws, sig_ws
+
     # adjoint over the fixed paths of the step (32 receivers x 4096 bins): seeded dL/dconj(H)
     gen = torch.Generator(device="cuda").manual_seed(2024)
     gH = torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda", generator=gen)
@@ -231,6 +258,9 @@ def main():
         "trace_ms": ms_trace, "trace_mrays_bounces_per_s": seg / (ms_trace * 1e-3) / 1e6,
         "synth_ms": ms_synth, "synth_kernel_ms": ms_synth_kernel,
         "synth_g_terms_per_s": terms / (ms_synth * 1e-3) / 1e9, "synth_kernel": kern,
+        "time_domain": {"workload": f"impulse responses of the step's spectra, n_t = {n_t} samples at "
+                                    f"{1 / dt / 1e3:.1f} kHz; received signals for a {L_call}-sample 20-100 kHz chirp",
+                        "impulse_ms": ms_ir, "signal_ms": ms_sig},
         "adjoint": {"workload": "fixed paths of the step, 32 receivers x 4096 bins, seeded dL/dconj(H)",
                     "ms": ms_adj, "kernel_ms": ms_adj_kernel, "kernel": adj_kern,
                     "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,

@@ -223,6 +223,31 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
                             float* spectra, const float* grad_spectra, double* grad_k, double* grad_rx);
 int et_graph_reset(et_ctx* ctx);
 
+/* ------------------------------------------------------------------ time domain
+ * The step after the path: impulse responses from the spectra (Eqs. 5-6, 9-10, 13:
+ * h = F^-1[H]) and received signals (Eq. 14: s = h * s_e).
+ *
+ * Impulse response of receiver m from its spectrum on the grid f_k = f_lo + k df (df =
+ * (f_hi - f_lo) / (F - 1)), sampled at t_n = n dt with dt = 1 / (n_t df), n < n_t:
+ *   h_m(t_n) = 2 df Re sum_k H_m[k] exp(-j phase_sign 2 pi f_k t_n),
+ * the real signal of the one-sided band spectrum; a path of delay tau peaks at t = tau for
+ * either phase sign.  The band-limited response repeats every 1/df (c/df of path length);
+ * n_t sets the sampling (fs = n_t df, at least 2 f_hi for a Nyquist-sampled signal).
+ * spectra: device float [M][F][2]; h: device float [M][n_t]; n_t a power of two with
+ * F <= n_t <= 2^22; *dt_out (host, may be NULL) receives dt.  ET_E_WORKSPACE if ws_bytes is
+ * below et_impulse_response_workspace_size. */
+int et_impulse_response_workspace_size(int32_t M, int32_t n_t, size_t* bytes);
+int et_impulse_response(et_ctx* ctx, int32_t M, int32_t F, double f_lo, double f_hi, int32_t phase_sign,
+                        const float* spectra, int32_t n_t, void* ws, size_t ws_bytes, float* h, double* dt_out);
+
+/* Received signal of every receiver for the emitted call s_e (L samples at the same dt):
+ *   s_m[n] = dt sum_k h_m[k] s_e[n - k],  n < n_t + L - 1,
+ * computed by FFT of length P = the power of two >= n_t + L - 1 (P <= 2^23).
+ * h: device float [M][n_t]; s_e: device float [L]; out: device float [M][n_t + L - 1]. */
+int et_receiver_signal_workspace_size(int32_t M, int32_t n_t, int64_t L, size_t* bytes);
+int et_receiver_signal(et_ctx* ctx, int32_t M, int32_t n_t, const float* h, int64_t L, const float* s_e, double dt,
+                       void* ws, size_t ws_bytes, float* out);
+
 /* ------------------------------------------------------------------ tuning of fused batches
  * Launch shapes kept per context: the workgroups that the record chunks of the synthesis and
  * adjoint kernels aim at, and the grid of the bounce kernels (grid-stride over the active

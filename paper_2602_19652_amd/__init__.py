@@ -131,6 +131,11 @@ def lib():
             "et_get_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
             "et_set_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
             "et_autotune_batch": ([vp, i32, C.POINTER(Job), vp, sz, vp, vp, vp, vp, C.POINTER(Tuning)], C.c_int),
+            "et_impulse_response_workspace_size": ([i32, i32, C.POINTER(sz)], C.c_int),
+            "et_impulse_response": ([vp, i32, i32, C.c_double, C.c_double, i32, vp, i32, vp, sz, vp,
+                                     C.POINTER(C.c_double)], C.c_int),
+            "et_receiver_signal_workspace_size": ([i32, i32, i64, C.POINTER(sz)], C.c_int),
+            "et_receiver_signal": ([vp, i32, i32, vp, i64, vp, C.c_double, vp, sz, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -442,6 +447,42 @@ def synthesize_backward(ctx: Context, sim: Sim, paths: Paths, grad_spectra: torc
     ctx.call("et_synthesize_backward", C.byref(sim.desc), C.byref(paths.desc), _ptr(g), _ptr(buf), buf.numel(),
              _ptr(gk), _ptr(gx))
     return gk, gx
+
+
+def impulse_response(ctx: Context, sim: Sim, spectra: torch.Tensor, n_t: int, ws: Workspace | None = None):
+    """Impulse responses h [M, n_t] (float32) of spectra (complex [M, F] on the sim's grid) and
+    their sample spacing dt: h_m(n dt) = 2 df Re sum_k H_m[k] exp(-j sigma 2 pi f_k n dt)."""
+    ws = ws or Workspace()
+    d = sim.desc
+    H = torch.view_as_real(spectra.to(torch.complex64).contiguous()).contiguous() if spectra.is_complex() \
+        else spectra.contiguous()
+    n = C.c_size_t()
+    rc = lib().et_impulse_response_workspace_size(d.M, n_t, C.byref(n))
+    if rc != 0:
+        raise EchoError(rc, "et_impulse_response_workspace_size")
+    buf = ws.get(n.value)
+    h = torch.empty(d.M, n_t, dtype=torch.float32, device=_dev())
+    dt = C.c_double()
+    ctx.call("et_impulse_response", d.M, d.F, d.f_lo, d.f_hi, d.phase_sign, _ptr(H), n_t, _ptr(buf), buf.numel(),
+             _ptr(h), C.byref(dt))
+    return h, dt.value
+
+
+def receiver_signal(ctx: Context, h: torch.Tensor, s_e: torch.Tensor, dt: float, ws: Workspace | None = None):
+    """Received signals s [M, n_t + L - 1] (float32): s_m[n] = dt sum_k h_m[k] s_e[n - k]."""
+    ws = ws or Workspace()
+    h = h.to(torch.float32).contiguous()
+    s_e = s_e.to(device=h.device, dtype=torch.float32).contiguous()
+    M, n_t = h.shape
+    L = s_e.numel()
+    n = C.c_size_t()
+    rc = lib().et_receiver_signal_workspace_size(M, n_t, L, C.byref(n))
+    if rc != 0:
+        raise EchoError(rc, "et_receiver_signal_workspace_size")
+    buf = ws.get(n.value)
+    out = torch.empty(M, n_t + L - 1, dtype=torch.float32, device=_dev())
+    ctx.call("et_receiver_signal", M, n_t, _ptr(h), L, _ptr(s_e), float(dt), _ptr(buf), buf.numel(), _ptr(out))
+    return out
 
 
 class SpectraFn(torch.autograd.Function):

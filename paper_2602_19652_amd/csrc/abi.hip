@@ -621,6 +621,65 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
   return rc;
 }
 
+namespace {
+void check_time_shape(int32_t M, int32_t n_t) {
+  ET_CHECK(M >= 1, ET_E_INVALID, "need M >= 1 receivers");
+  ET_CHECK(n_t >= 1 && n_t <= (1 << 22) && (n_t & (n_t - 1)) == 0, ET_E_INVALID,
+           "n_t must be a power of two in [1, 2^22]");
+}
+}  // namespace
+
+int et_impulse_response_workspace_size(int32_t M, int32_t n_t, size_t* bytes) {
+  try {
+    if (!bytes) return ET_E_INVALID;
+    check_time_shape(M, n_t);
+    *bytes = impulse_ws_bytes(M, n_t);
+    return ET_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+int et_impulse_response(et_ctx* ctx, int32_t M, int32_t F, double f_lo, double f_hi, int32_t phase_sign,
+                        const float* spectra, int32_t n_t, void* ws, size_t ws_bytes, float* h, double* dt_out) {
+  return guarded(ctx, [&] {
+    check_time_shape(M, n_t);
+    ET_CHECK(F >= 2 && F <= n_t, ET_E_INVALID, "need 2 <= F <= n_t");
+    ET_CHECK(std::isfinite(f_lo) && std::isfinite(f_hi) && f_hi > f_lo && f_lo >= 0, ET_E_INVALID,
+             "frequency grid must satisfy 0 <= f_lo < f_hi");
+    ET_CHECK(phase_sign == 1 || phase_sign == -1, ET_E_INVALID, "phase_sign must be +1 or -1");
+    ET_CHECK(spectra && h, ET_E_INVALID, "spectra or h is NULL");
+    ET_CHECK(ws && ws_bytes >= impulse_ws_bytes(M, n_t), ET_E_WORKSPACE, "workspace too small for et_impulse_response");
+    const double df = (f_hi - f_lo) / (double)(F - 1);
+    impulse_run(M, F, f_lo, df, phase_sign, spectra, n_t, ws, h, ctx->stream);
+    if (dt_out) *dt_out = 1.0 / ((double)n_t * df);
+  });
+}
+
+int et_receiver_signal_workspace_size(int32_t M, int32_t n_t, int64_t L, size_t* bytes) {
+  try {
+    if (!bytes) return ET_E_INVALID;
+    check_time_shape(M, n_t);
+    if (L < 1 || conv_length(n_t, L) > ((int64_t)1 << 23)) return ET_E_INVALID;
+    *bytes = signal_ws_bytes(M, n_t, L);
+    return ET_OK;
+  } catch (const Error& e) {
+    return e.code;
+  }
+}
+
+int et_receiver_signal(et_ctx* ctx, int32_t M, int32_t n_t, const float* h, int64_t L, const float* s_e, double dt,
+                       void* ws, size_t ws_bytes, float* out) {
+  return guarded(ctx, [&] {
+    check_time_shape(M, n_t);
+    ET_CHECK(L >= 1 && conv_length(n_t, L) <= ((int64_t)1 << 23), ET_E_INVALID, "need L >= 1 and n_t + L - 1 <= 2^23");
+    ET_CHECK(std::isfinite(dt) && dt > 0, ET_E_INVALID, "dt must be positive");
+    ET_CHECK(h && s_e && out, ET_E_INVALID, "h, s_e or out is NULL");
+    ET_CHECK(ws && ws_bytes >= signal_ws_bytes(M, n_t, L), ET_E_WORKSPACE, "workspace too small for et_receiver_signal");
+    signal_run(M, n_t, h, L, s_e, dt, ws, out, ctx->stream);
+  });
+}
+
 int et_get_tuning(et_ctx* ctx, et_tuning* out) {
   return guarded(ctx, [&] {
     ET_CHECK(out, ET_E_INVALID, "tuning is NULL");

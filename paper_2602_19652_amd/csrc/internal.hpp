@@ -218,6 +218,15 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
 bool synth_factorised_ok(const et_sim_desc* sim);
 bool synth_bwd_factorised_ok(const et_sim_desc* sim);
 
+// ------------------------------------------------------------------ time domain (timedomain.hip)
+int64_t conv_length(int64_t n_t, int64_t L);
+size_t impulse_ws_bytes(int64_t M, int64_t n_t);
+size_t signal_ws_bytes(int64_t M, int64_t n_t, int64_t L);
+void impulse_run(int64_t M, int64_t F, double f_lo, double df, int sigma, const float* spectra, int64_t n_t, void* ws,
+                 float* h, hipStream_t s);
+void signal_run(int64_t M, int64_t n_t, const float* h, int64_t L, const float* se, double dt, void* ws, float* out,
+                hipStream_t s);
+
 // Launch shapes of the fused batch (the autotuner's knobs): workgroups of the main synthesis
 // and adjoint kernels the record chunks aim at.
 struct BatchTune {

@@ -350,6 +350,55 @@ def test_passive_adjoint_matches_oracle(et, ctx, tiny):
     assert ek <= TOL and ex <= TOL
 
 
+# ----------------------------------------------------------------------------- time domain
+
+@pytest.mark.parametrize("sigma,n_t", [(1, 4096), (-1, 4096), (1, 1024)])
+def test_impulse_response_matches_oracle(et, ctx, tiny, sigma, n_t):
+    """h = F^-1[H] of the tiny scene's spectra (1024 bins 20-100 kHz; n_t = 4096 samples at
+    320 kHz, and the minimum n_t = F) against the oracle's definition."""
+    import torch
+    scene, sim, ref = tiny
+    sim = dict(sim, phase_sign=sigma)
+    H = O.synth(ref, sim)
+    s = et.Sim(sim)
+    h, dt = et.impulse_response(ctx, s, torch.as_tensor(H, dtype=torch.complex64, device="cuda"), n_t)
+    h_ref, dt_ref = O.impulse_response(H.astype(np.complex64), sim, n_t)
+    e = rel_l2(h.cpu().numpy(), h_ref)
+    print(f"impulse response (sigma {sigma}, n_t {n_t}): rel L2 {e:.3e}, dt {dt:.3e} s")
+    assert dt == pytest.approx(dt_ref, rel=1e-15)
+    assert e <= 1e-5
+
+
+def test_receiver_signal_matches_oracle(et, ctx, tiny):
+    """s = h * s_e for a 20-100 kHz chirp of an odd length (the FFT length pads to a power of two)."""
+    import torch
+    scene, sim, ref = tiny
+    H = O.synth(ref, sim)
+    s = et.Sim(sim)
+    h, dt = et.impulse_response(ctx, s, torch.as_tensor(H, dtype=torch.complex64, device="cuda"), 4096)
+    L = 641
+    t = np.arange(L) * dt
+    T = L * dt
+    s_e = np.sin(2 * np.pi * (20e3 * t + 0.5 * (80e3 / T) * t * t)) * np.hanning(L)
+    out = et.receiver_signal(ctx, h, torch.as_tensor(s_e, dtype=torch.float32, device="cuda"), dt)
+    ref_s = O.receiver_signal(h.cpu().numpy().astype(np.float64), s_e.astype(np.float32), dt)
+    e = rel_l2(out.cpu().numpy(), ref_s)
+    print(f"receiver signal: {out.shape[1]} samples, rel L2 {e:.3e}")
+    assert out.shape == (2, 4096 + L - 1)
+    assert e <= 1e-5
+
+
+def test_time_domain_rejects_bad_shapes(et, ctx, tiny):
+    import torch
+    scene, sim, ref = tiny
+    s = et.Sim(sim)
+    H = torch.zeros(2, sim["F"], dtype=torch.complex64, device="cuda")
+    for n_t in (3000, 512):              # not a power of two; shorter than F
+        with pytest.raises(et.EchoError) as e:
+            et.impulse_response(ctx, s, H, n_t)
+        assert e.value.status == -1
+
+
 # ----------------------------------------------------------------------------- errors
 
 def test_invalid_arguments_report_status(et, ctx, tiny):
