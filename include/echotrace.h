@@ -95,12 +95,31 @@ typedef struct {
   int32_t depth;          /* BVH depth (root = 1) */
   double sah_cost;        /* SAH cost with C_node = 1, C_tri = 1, normalised by the root area */
   double build_ms;        /* device time of the build (event-timed) */
+  double refit_ms;        /* device time of the last et_scene_refit (0 before any) */
 } et_scene_info;
 int et_scene_get_info(et_ctx* ctx, const et_scene* scene, et_scene_info* info);   /* synchronises */
 
 /* Device copies of the curvature outputs of the build: C [T] (Eq. 1) and G_v [V]
  * (half the norm of the mean-curvature normal).  Either pointer may be NULL. */
 int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double* G_out);
+
+/* Dynamic scenes (objects moved or meshes animated between frames, Sec. III-A/III-B; the
+ * paper computes curvature offline and so leaves animated meshes out of the diffraction
+ * component, Sec. VI): new vertex positions for the same triangles, materials and objects.
+ *   vertices   device [V][3] FP32, same V as the build; it replaces the mesh's vertex
+ *              pointer and must outlive the scene (or the next refit)
+ *   area_ref   as in et_mesh_desc, for the recomputed curvature C_i of Eq. (1)
+ *   scratch    device, at least et_scene_size's scratch_bytes (free after the call)
+ * Recomputes the repacked triangles, the object boxes, the curvature G_v and C_i, and every
+ * BVH box bottom-up over the topology of the last build.  The boxes are exact unions of the
+ * FP32 triangle bounds, so refitting to the build's own vertices reproduces the blob bit for
+ * bit and traces of a refitted scene hit what a fresh build hits.  Large deformations keep a
+ * valid but looser tree: sah_cost of et_scene_get_info is recomputed (rebuild when it grows).
+ * Ordered on the context's stream; returns after the refit finished.  Errors: ET_E_INVALID
+ * for NULL pointers, ET_E_WORKSPACE for a small scratch, ET_E_HIP for device failures (the
+ * scene is then unusable and must be rebuilt). */
+int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref, void* scratch,
+                   size_t scratch_bytes);
 
 /* ------------------------------------------------------------------ one pose (one emitter) */
 enum {

@@ -383,6 +383,83 @@ __global__ void k_single_leaf(Node2* nodes) {
   nodes[0] = n;
 }
 
+// ------------------------------------------------------------------ refit (dynamic scenes)
+// Same topology, new vertex positions: each leaf writes its box into its parent's child slot
+// and climbs; at every inner node the second arrival (per-node counter) forms the node's box
+// from both child slots and writes it into the grandparent, so every box is the exact union
+// of its leaves' FP32 bounds, as a build of the same structure would produce.  Agent-scope
+// fences order the slot writes before the counter update and the counter update before the
+// slot reads (the XCDs' L2 caches are not coherent with each other).
+
+__device__ inline void set_child_box(Node2* nodes, int node, int child_link, float lox, float hix, float loy, float hiy,
+                                     float loz, float hiz) {
+  Node2& n = nodes[node];
+  if (n.ch.x == child_link) {
+    n.xy0 = make_float4(lox, hix, loy, hiy);
+    n.zz.x = loz;
+    n.zz.y = hiz;
+  } else {
+    n.xy1 = make_float4(lox, hix, loy, hiy);
+    n.zz.z = loz;
+    n.zz.w = hiz;
+  }
+}
+
+__global__ void k_refit_zero(uint32_t* __restrict__ cnt, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    cnt[i] = 0u;
+}
+
+__global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__ tris, const int32_t* __restrict__ mat,
+                        const int32_t* __restrict__ tri_orig, const int32_t* __restrict__ leaf_parent, int64_t T,
+                        float4* __restrict__ tri4, Node2* nodes, uint32_t* cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= T) return;
+  const int32_t t = tri_orig[p];
+  float v[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 3; ++k) v[c][k] = V[3 * (int64_t)tris[3 * (int64_t)t + c] + k];
+  tri4[3 * p + 0] = make_float4(v[0][0], v[0][1], v[0][2], __int_as_float(t));
+  tri4[3 * p + 1] = make_float4(v[1][0], v[1][1], v[1][2], __int_as_float(mat[t]));
+  tri4[3 * p + 2] = make_float4(v[2][0], v[2][1], v[2][2], 0.f);
+  if (T < 2) return;   // a single leaf keeps its unbounded box
+  int node = leaf_parent[p];
+  set_child_box(nodes, node, ~(int)p, fminf(v[0][0], fminf(v[1][0], v[2][0])), fmaxf(v[0][0], fmaxf(v[1][0], v[2][0])),
+                fminf(v[0][1], fminf(v[1][1], v[2][1])), fmaxf(v[0][1], fmaxf(v[1][1], v[2][1])),
+                fminf(v[0][2], fminf(v[1][2], v[2][2])), fmaxf(v[0][2], fmaxf(v[1][2], v[2][2])));
+  for (int guard = 0; guard < 1 << 20; ++guard) {
+    __threadfence();
+    if (atomicAdd(&cnt[node], 1u) == 0u) return;   // the sibling's thread continues
+    __threadfence();
+    const Node2 n = nodes[node];
+    const int parent = n.ch.z;
+    if (parent < 0) return;                        // the root has no slot above it
+    set_child_box(nodes, parent, node, fminf(n.xy0.x, n.xy1.x), fmaxf(n.xy0.y, n.xy1.y), fminf(n.xy0.z, n.xy1.z),
+                  fmaxf(n.xy0.w, n.xy1.w), fminf(n.zz.x, n.zz.z), fmaxf(n.zz.y, n.zz.w));
+    node = parent;
+  }
+}
+
+// SAH cost of the refitted tree (C_node = C_tri = 1, normalised by the root area): the root
+// contributes 1 and every other node its box area, read from its parent's child slot.
+__device__ inline double slot_area(float lx, float hx, float ly, float hy, float lz, float hz) {
+  return (double)(hx - lx) * (hy - ly) + (double)(hy - ly) * (hz - lz) + (double)(hz - lz) * (hx - lx);
+}
+
+__global__ void k_refit_sah(const Node2* __restrict__ nodes, int64_t n_inner, int root, double* sah) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_inner) return;
+  const Node2 r = nodes[root];
+  const double ra = slot_area(fminf(r.xy0.x, r.xy1.x), fmaxf(r.xy0.y, r.xy1.y), fminf(r.xy0.z, r.xy1.z),
+                              fmaxf(r.xy0.w, r.xy1.w), fminf(r.zz.x, r.zz.z), fmaxf(r.zz.y, r.zz.w));
+  const Node2 n = nodes[k];
+  double s = (k == root) ? 1.0 : 0.0;
+  if (ra > 0)
+    s += (slot_area(n.xy0.x, n.xy0.y, n.xy0.z, n.xy0.w, n.zz.x, n.zz.y) +
+          slot_area(n.xy1.x, n.xy1.y, n.xy1.z, n.xy1.w, n.zz.z, n.zz.w)) / ra;
+  atomicAdd(sah, s);
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS > 0 ? (n + BS - 1) / BS : 1); }
 inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -392,7 +469,7 @@ size_t scene_blob_bytes(int64_t T, int64_t V, int32_t n_obj) {
   size_t b = 0;
   b += al(sizeof(Node2) * (size_t)std::max<int64_t>(1, T - 1));
   b += al(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
-  b += 2 * al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
+  b += 3 * al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));   // tri_orig, tri_pos, leaf_parent
   b += al(sizeof(double) * (size_t)std::max<int64_t>(1, T));
   b += al(sizeof(double) * (size_t)std::max<int64_t>(1, V));
   b += al(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
@@ -431,6 +508,7 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   d.tri4 = (float4*)takeb(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
   d.tri_orig = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
   d.tri_pos = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
+  d.leaf_parent = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
   d.C = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, T));
   d.G = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, V));
   d.obj_box = (float*)takeb(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
@@ -453,7 +531,8 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   void* scan_tmp = take(scan_temp_bytes(std::max(Tm, Vm)));
   int64_t* ctr = (int64_t*)take(sizeof(int64_t) * 8);      // [0] n, [1] next node, [2..3] host view
   uint64_t* total = (uint64_t*)take(sizeof(uint64_t) * 4);
-  int32_t* leaf_parent = (int32_t*)take(sizeof(int32_t) * Tm);
+  (void)take(sizeof(int32_t) * Tm);   // (leaf parents live in the blob)
+  int32_t* leaf_parent = d.leaf_parent;
   int32_t* depth = (int32_t*)take(sizeof(int32_t) * 2);
   double* sah = (double*)take(sizeof(double));
   uint64_t* vcnt = (uint64_t*)take(sizeof(uint64_t) * Vm);
@@ -561,6 +640,64 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
     sc->sah = T;
   }
   ET_CHECK(sc->depth <= TRAV_STACK, ET_E_UNSUPPORTED, "BVH deeper than the traversal stack");
+}
+
+}  // namespace et
+
+namespace et {
+
+void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scratch, uint32_t* dev_err,
+                 hipStream_t s) {
+  SceneDev& d = sc->d;
+  const int64_t T = d.T, V = d.V;
+  const int32_t n_obj = d.n_obj;
+  d.verts = vertices;
+  const int64_t Tm = std::max<int64_t>(T, 1), Vm = std::max<int64_t>(V, 1);
+  char* sp = (char*)scratch;
+  auto take = [&](size_t bytes) { char* p = sp; sp += al(bytes); return (void*)p; };
+  uint32_t* cb = (uint32_t*)take(sizeof(uint32_t) * 6);
+  uint32_t* cnt = (uint32_t*)take(sizeof(uint32_t) * Tm);
+  double* sah = (double*)take(sizeof(double));
+  uint64_t* vcnt = (uint64_t*)take(sizeof(uint64_t) * Vm);
+  uint64_t* voff = (uint64_t*)take(sizeof(uint64_t) * Vm);
+  uint32_t* vfill = (uint32_t*)take(sizeof(uint32_t) * Vm);
+  int32_t* adj = (int32_t*)take(sizeof(int32_t) * 3 * Tm);
+  void* scan_tmp = take(scan_temp_bytes(std::max(Tm, Vm)));
+  uint32_t* ob = (uint32_t*)d.obj_box;
+  hipEvent_t e0, e1;
+  ET_HIP(hipEventCreate(&e0));
+  ET_HIP(hipEventCreate(&e1));
+  ET_HIP(hipEventRecord(e0, s));
+  k_init_bounds<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(cb, ob, n_obj);
+  if (T > 0) k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, T, V, n_obj, cb, ob, dev_err);
+  k_obj_box<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(ob, n_obj, d.obj_box);
+  if (T > 0) {
+    k_refit_zero<<<nblk(T), BS, 0, s>>>(cnt, T);
+    k_refit<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.mat, d.tri_orig, d.leaf_parent, T, d.tri4, d.nodes, cnt);
+  }
+  if (T >= 2) {
+    k_refit_zero<<<1, BS, 0, s>>>((uint32_t*)sah, 2);
+    k_refit_sah<<<nblk(T - 1), BS, 0, s>>>(d.nodes, T - 1, d.root, sah);
+  }
+  if (T > 0 && V > 0) {
+    k_refit_zero<<<nblk(2 * V), BS, 0, s>>>((uint32_t*)vcnt, 2 * V);
+    k_refit_zero<<<nblk(V), BS, 0, s>>>(vfill, V);
+    k_vcount<<<nblk(T), BS, 0, s>>>(d.tris, T, vcnt);
+    scan_exclusive_u64(vcnt, voff, V, nullptr, V, nullptr, scan_tmp, s);
+    k_vfill<<<nblk(T), BS, 0, s>>>(d.tris, T, voff, vfill, adj);
+    k_vsort<<<nblk(V), BS, 0, s>>>(voff, vcnt, V, adj);
+    k_vertex_curv<<<nblk(V), BS, 0, s>>>(d.verts, d.tris, voff, vcnt, adj, V, d.G);
+    k_tri_curv<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, T, d.G, area_ref, d.C);
+  }
+  ET_HIP(hipGetLastError());
+  ET_HIP(hipEventRecord(e1, s));
+  ET_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  ET_HIP(hipEventElapsedTime(&ms, e0, e1));
+  sc->refit_ms = ms;
+  ET_HIP(hipEventDestroy(e0));
+  ET_HIP(hipEventDestroy(e1));
+  if (T >= 2) ET_HIP(hipMemcpy(&sc->sah, sah, sizeof(double), hipMemcpyDeviceToHost));
 }
 
 }  // namespace et

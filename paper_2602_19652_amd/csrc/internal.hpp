@@ -76,6 +76,7 @@ struct SceneDev {
   float4* tri4 = nullptr;       // [T][3]: v0 (w = original index bits), v1 (w = material bits), v2
   int32_t* tri_orig = nullptr;  // [T] original triangle index per leaf position
   int32_t* tri_pos = nullptr;   // [T] leaf position per original triangle index
+  int32_t* leaf_parent = nullptr;  // [T] inner node holding leaf position p
   double* C = nullptr;          // [T] curvature metric per original triangle
   double* G = nullptr;          // [V] per-vertex mean curvature magnitude
   float* obj_box = nullptr;     // [n_obj][6] lo xyz, hi xyz
@@ -90,6 +91,7 @@ struct et_scene {
   int32_t depth = 0;
   double sah = 0;
   double build_ms = 0;
+  double refit_ms = 0;
   int device = 0;
 };
 
@@ -114,6 +116,10 @@ size_t scene_blob_bytes(int64_t T, int64_t V, int32_t n_obj);
 size_t scene_scratch_bytes(int64_t T, int64_t V);
 // Builds the BVH and curvature; returns host-side info.  Throws et::Error.
 void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scratch, uint32_t* dev_err,
+                 hipStream_t s);
+// New vertex positions, same topology: BVH refit (structure kept, boxes recomputed bottom-up),
+// triangle repack, object boxes and curvature.  Throws et::Error.
+void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scratch, uint32_t* dev_err,
                  hipStream_t s);
 
 }  // namespace et

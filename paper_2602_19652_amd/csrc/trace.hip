@@ -139,20 +139,26 @@ struct Stack {
 
 // Closest hit (ANY = false) or any hit (ANY = true) over t in (tmin, tmax), excluding the
 // leaf position `excl`.  Closest-hit ties in t go to the smaller original triangle index.
+// Boxes are culled against the current best distance widened by 2^-19 relative (about 16
+// ulps, more than the rounding of a box entry plus that of a triangle's t): a triangle whose
+// computed t ties the best (or lies within rounding of it, as on a shared edge or a box face
+// whose slab entry equals the hit distance) is always tested, so the hit does not depend on
+// the traversal order, and a refitted tree hits what a rebuilt one hits.
+constexpr float T_WIDEN = 1.0f + 1.9073486328125e-6f;   // 1 + 2^-19
 template <bool ANY, bool COUNT>
 __device__ inline int traverse(const SceneDev& S, const Ray32& r, float tmin, float tmax, int excl, Stack& st,
                                float& t_hit, int64_t& cn, int64_t& ct) {
   int node = S.root;
   st.sp = 0;
   int best = -1, best_orig = INT32_MAX;
-  float tb = tmax;
+  float tb = tmax, tbw = tmax * T_WIDEN;
   while (true) {
     while (node >= 0) {
       const Node2 n = S.nodes[node];
       if (COUNT) ++cn;
       bool h0, h1;
       float t0, t1;
-      box2(n, r, tmin, tb, h0, h1, t0, t1);
+      box2(n, r, tmin, tbw, h0, h1, t0, t1);
       if (h0 && h1) {
         const bool first0 = t0 <= t1;
         st.push(first0 ? n.ch.y : n.ch.x);
@@ -178,6 +184,7 @@ __device__ inline int traverse(const SceneDev& S, const Ray32& r, float tmin, fl
           const int orig = __float_as_int(a.w);
           if (t < tb || orig < best_orig) {
             tb = t;
+            tbw = t * T_WIDEN;
             best = pos;
             best_orig = orig;
           }

@@ -1,0 +1,143 @@
+"""Dynamic scenes: a BVH refit over new vertex positions (et_scene_refit) against a fresh
+build of the moved scene and against the FP64 oracle.
+
+  * refitting to the build's own vertices reproduces the scene blob bit for bit (boxes are
+    exact unions of FP32 triangle bounds, curvature is recomputed in the same order);
+  * after an animation frame (objects turned, moved, some deformed) the refitted scene gives
+    bit-identical curvature and trace records to a fresh build of the moved scene, and the
+    oracle's hits on certified rays;
+  * refitting back to the first frame restores the first blob bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(et):
+    return et.Context(0)
+
+
+@pytest.fixture(scope="module")
+def frames():
+    scene, sim = W.room_scene(n_rays=1 << 18, diff_K=16384)
+    V1 = W.animate_objects(scene, W.rng(31))
+    moved = dict(scene, vertices=V1)
+    return scene, moved, sim
+
+
+def _records(P):
+    h = P.to_host()
+    h.pop("count")
+    order = np.lexsort((h["bounce"], h["ray"]))
+    return {k: np.asarray(v)[order] for k, v in h.items()}
+
+
+def _on_triangle(p, v, tol=1e-5):
+    """p lies on triangle v[3][3] within tol metres (plane distance and barycentric slack)."""
+    e1, e2 = v[1] - v[0], v[2] - v[0]
+    n = np.cross(e1, e2)
+    a2 = float(np.linalg.norm(n))
+    if abs(float(np.dot(n / a2, p - v[0]))) > tol:
+        return False
+    q = p - v[0]
+    b1 = float(np.dot(np.cross(q, e2), n)) / a2 ** 2
+    b2 = float(np.dot(np.cross(e1, q), n)) / a2 ** 2
+    slack = tol * max(np.linalg.norm(e1), np.linalg.norm(e2)) / a2 * 2
+    return b1 >= -slack and b2 >= -slack and b1 + b2 <= 1 + slack
+
+
+def test_refit_same_vertices_reproduces_build(et, ctx, frames):
+    scene, _, sim = frames
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    blob0 = sc.blob.clone()
+    sc.refit(scene["vertices"], area_ref=sim["area_ref"])
+    info = sc.info()
+    print(f"room: build {info.build_ms:.2f} ms, refit {info.refit_ms:.2f} ms, T {info.T}")
+    assert info.refit_ms > 0
+    assert torch_equal(sc.blob, blob0)
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
+
+
+def test_refit_frame_matches_fresh_build_and_oracle(et, ctx, frames):
+    scene, moved, sim = frames
+    a_ref = sim["area_ref"]
+    sc = et.Scene(ctx, scene, area_ref=a_ref)
+    blob0 = sc.blob.clone()
+    sah0 = sc.info().sah_cost
+    sc.refit(moved["vertices"], area_ref=a_ref)
+    fresh = et.Scene(ctx, moved, area_ref=a_ref)
+    ri, fi = sc.info(), fresh.info()
+    print(f"moved room: SAH refit {ri.sah_cost:.1f} (first frame {sah0:.1f}), fresh build {fi.sah_cost:.1f}; "
+          f"refit {ri.refit_ms:.2f} ms vs build {fi.build_ms:.2f} ms")
+    assert ri.sah_cost >= 0.95 * fi.sah_cost   # a refit never beats a fresh build by much
+
+    # curvature: bit-identical to the fresh build and to the oracle (Eq. 1)
+    C1, G1 = sc.curvature()
+    C2, G2 = fresh.curvature()
+    assert torch_equal(C1, C2) and torch_equal(G1, G2)
+    G_ref, C_ref = O.curvature(moved, a_ref)
+    assert np.array_equal(C1.cpu().numpy(), C_ref) and np.array_equal(G1.cpu().numpy(), G_ref)
+
+    # specular trace over all rays: identical records.  Closest-hit ties go to the smaller
+    # triangle index and box culling is widened beyond rounding, so the hit does not depend on
+    # the tree's topology; a triangle that differs must still be a valid hit (same point,
+    # direction, path length and material: a shared edge of coplanar triangles).
+    s = et.Sim(sim, flags=et.ET_SPECULAR)
+    ra = _records(et.trace(ctx, sc, s))
+    assert ctx.stats().stack_overflows == 0
+    rb = _records(et.trace(ctx, fresh, s))
+    assert ra.keys() == rb.keys()
+    for k in ra:
+        if k != "tri":
+            assert np.array_equal(ra[k], rb[k]), k
+    diff = np.nonzero(ra["tri"] != rb["tri"])[0]
+    print(f"moved room: {len(ra['ray'])} records, {len(diff)} with another (tied) triangle")
+    assert len(diff) <= 1e-5 * len(ra["ray"])
+    V1 = np.asarray(moved["vertices"], np.float64)
+    tris = np.asarray(moved["tris"])
+    for i in diff:
+        for t in (ra["tri"][i], rb["tri"][i]):
+            assert _on_triangle(ra["p"][i], V1[tris[t]])
+
+    # the oracle on a seeded subset of rays of the moved scene
+    sub = np.sort(W.rng(32).choice(len(sim["ray_dirs"]), 1024, replace=False))
+    dirs = sim["ray_dirs"][sub]
+    ref = O.trace(moved, sim, dirs=dirs)
+    gpu = et.trace(ctx, sc, et.Sim(sim, flags=et.ET_SPECULAR, ray_dirs=dirs)).to_host()
+    from test_gpu_parity import compare_traces
+    mism = compare_traces(gpu, ref, ref["certified"])
+    print(f"moved room subset: certified {ref['certified'].mean():.4f}, mismatches {mism}")
+    assert mism == 0
+
+    # full simulation with diffraction (curvature-driven sampling) matches the fresh build
+    full = et.Sim(sim)
+    Ha = et.simulate(ctx, sc, full).cpu().numpy()
+    Hb = et.simulate(ctx, fresh, full).cpu().numpy()
+    assert np.array_equal(Ha, Hb)
+
+    # back to the first frame
+    sc.refit(scene["vertices"], area_ref=a_ref)
+    assert torch_equal(sc.blob, blob0)
+
+
+def test_refit_rejects_bad_arguments(et, ctx, frames):
+    import ctypes
+    scene, _, sim = frames
+    sc = et.Scene(ctx, scene)
+    with pytest.raises(ValueError):
+        sc.refit(scene["vertices"][:-1])
+    buf = et.Workspace().get(16)
+    v = sc.vertices
+    rc = et.lib().et_scene_refit(ctx.h, sc.h, ctypes.c_void_p(v.data_ptr()), 0.0, ctypes.c_void_p(buf.data_ptr()), 16)
+    assert rc == -2                                            # scratch too small
+    rc = et.lib().et_scene_refit(ctx.h, sc.h, None, 0.0, ctypes.c_void_p(buf.data_ptr()), sc.scratch_bytes)
+    assert rc == -1

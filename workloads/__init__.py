@@ -313,6 +313,32 @@ def room_geometry(g: np.random.Generator, n_boxes=100, n_cyl=100, sensor=(1.0, 4
     return mb.build()
 
 
+def animate_objects(scene: dict, g: np.random.Generator, shift=0.1, yaw=0.15, bulge=0.01, bulge_every=4):
+    """One animation frame of a scene: every object except object 0 (the room shell) turns
+    about the vertical through its centroid by U[-yaw, yaw] rad and moves by U[-shift, shift]
+    m in x and y; every `bulge_every`-th of them also deforms non-rigidly (its vertices move
+    radially by bulge * sin(2 pi z / 0.5 m)).  Returns new vertices [V][3] (same topology)."""
+    V = np.asarray(scene["vertices"], np.float64).copy()
+    tris = np.asarray(scene["tris"])
+    vobj = np.full(len(V), -1, np.int64)
+    for c in range(3):
+        vobj[tris[:, c]] = scene["tri_object"]
+    for o in range(1, int(scene["n_objects"])):
+        idx = np.nonzero(vobj == o)[0]
+        if len(idx) == 0:
+            continue
+        cen = V[idx].mean(axis=0)
+        p = V[idx] - np.array([cen[0], cen[1], 0.0])
+        if bulge and o % bulge_every == 0:
+            r = np.hypot(p[:, 0], p[:, 1])
+            scale = 1.0 + bulge * np.sin(2 * math.pi * p[:, 2] / 0.5) / np.maximum(r, 1e-6)
+            p[:, 0] *= scale
+            p[:, 1] *= scale
+        p = p @ rot_z(g.uniform(-yaw, yaw)).T
+        V[idx] = p + np.array([cen[0] + g.uniform(-shift, shift), cen[1] + g.uniform(-shift, shift), 0.0])
+    return np.ascontiguousarray(V.astype(np.float32))
+
+
 def room_scene(seed: int = 1002, n_rays: int = 1 << 20, M: int = 32, F: int = 4096, bounces: int = 4,
                diff_K: int = 65536, n_boxes=100, n_cyl=100):
     """Room scene: 10x8x3 m room + 100 boxes + 100 cylinders (193,212 tris), 16 materials x 8
