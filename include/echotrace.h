@@ -79,7 +79,8 @@ typedef struct {
 } et_mesh_desc;
 
 /* Byte sizes of the scene blob (kept for the scene's lifetime: BVH nodes, repacked
- * triangles, curvature C_i, object boxes) and of the build scratch (free after build). */
+ * triangles, curvature C_i, object boxes, and what et_scene_refit reads) and of the build
+ * scratch (free after build). */
 int et_scene_size(et_ctx* ctx, const et_mesh_desc* mesh, size_t* blob_bytes, size_t* scratch_bytes);
 
 /* Builds the device acceleration structure (surface-area-driven agglomerative BVH over
@@ -109,17 +110,17 @@ int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double
  *   vertices   device [V][3] FP32, same V as the build; it replaces the mesh's vertex
  *              pointer and must outlive the scene (or the next refit)
  *   area_ref   as in et_mesh_desc, for the recomputed curvature C_i of Eq. (1)
- *   scratch    device, at least et_scene_size's scratch_bytes (free after the call)
  * Recomputes the repacked triangles, the object boxes, the curvature G_v and C_i, and every
- * BVH box bottom-up over the topology of the last build.  The boxes are exact unions of the
- * FP32 triangle bounds, so refitting to the build's own vertices reproduces the blob bit for
- * bit and traces of a refitted scene hit what a fresh build hits.  Large deformations keep a
- * valid but looser tree: sah_cost of et_scene_get_info is recomputed (rebuild when it grows).
- * Ordered on the context's stream; returns after the refit finished.  Errors: ET_E_INVALID
- * for NULL pointers, ET_E_WORKSPACE for a small scratch, ET_E_HIP for device failures (the
- * scene is then unusable and must be rebuilt). */
-int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref, void* scratch,
-                   size_t scratch_bytes);
+ * BVH box bottom-up, one depth level per launch, over the topology of the last build.  It
+ * takes no workspace: what it needs beyond the tree (nodes by depth, the triangles around each
+ * vertex, a few bytes of scratch) was kept in the blob by the build.  The boxes are exact
+ * unions of the FP32 triangle bounds, so refitting to the build's own vertices reproduces the
+ * blob bit for bit and traces of a refitted scene hit what a fresh build hits.  Large
+ * deformations keep a valid but looser tree: sah_cost of et_scene_get_info is recomputed
+ * (rebuild when it grows).  Ordered on the context's stream; returns after the refit
+ * finished; refits of one scene must not overlap.  Errors: ET_E_INVALID for NULL pointers,
+ * ET_E_HIP for device failures (the scene is then unusable and must be rebuilt). */
+int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref);
 
 /* ------------------------------------------------------------------ one pose (one emitter) */
 enum {

@@ -116,7 +116,7 @@ def lib():
             "et_scene_free": ([vp], C.c_int),
             "et_scene_get_info": ([vp, vp, C.POINTER(SceneInfo)], C.c_int),
             "et_scene_curvature": ([vp, vp, vp, vp], C.c_int),
-            "et_scene_refit": ([vp, vp, vp, C.c_double, vp, sz], C.c_int),
+            "et_scene_refit": ([vp, vp, vp, C.c_double], C.c_int),
             "et_workspace_size": ([vp, vp, C.POINTER(SimDesc), C.POINTER(sz)], C.c_int),
             "et_trace": ([vp, vp, C.POINTER(SimDesc), vp, sz, C.POINTER(PathsDesc)], C.c_int),
             "et_synthesize": ([vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp, sz, vp], C.c_int),
@@ -244,7 +244,6 @@ class Scene:
         torch.cuda.synchronize()
         del tmp
         self.h = h
-        self.scratch_bytes = scratch.value
 
     def refit(self, vertices, area_ref: float = 0.0):
         """New vertex positions [V][3] for the same topology (et_scene_refit); keeps the
@@ -255,10 +254,8 @@ class Scene:
             v = _to_dev(vertices, torch.float32)
         if tuple(v.shape) != (self.V, 3):
             raise ValueError(f"vertices must have shape ({self.V}, 3), got {tuple(v.shape)}")
-        tmp = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=_dev())
-        self.ctx.call("et_scene_refit", self.h, _ptr(v), float(area_ref), _ptr(tmp), self.scratch_bytes)
+        self.ctx.call("et_scene_refit", self.h, _ptr(v), float(area_ref))
         self.vertices = v
-        del tmp
 
     def info(self) -> SceneInfo:
         i = SceneInfo()

@@ -313,17 +313,13 @@ int et_scene_free(et_scene* scene) {
   return ET_OK;
 }
 
-int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref, void* scratch,
-                   size_t scratch_bytes) {
+int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref) {
   return guarded(ctx, [&] {
     check_scene(scene);
     ET_CHECK(vertices || scene->d.V == 0, ET_E_INVALID, "vertices is NULL");
-    ET_CHECK(scratch, ET_E_INVALID, "scratch is NULL");
-    ET_CHECK(scratch_bytes >= scene_scratch_bytes(scene->d.T, scene->d.V), ET_E_WORKSPACE, "scene scratch too small");
     ET_CHECK(std::isfinite(area_ref), ET_E_INVALID, "area_ref is not finite");
     ET_CHECK(scene->device == ctx->device, ET_E_INVALID, "scene lives on another device");
-    ET_HIP(hipMemsetAsync(&ctx->ctl->err, 0, sizeof(uint32_t), ctx->stream));
-    scene_refit(scene, vertices, area_ref, scratch, &ctx->ctl->err, ctx->stream);
+    scene_refit(scene, vertices, area_ref, &ctx->ctl->err, ctx->stream);
   });
 }
 

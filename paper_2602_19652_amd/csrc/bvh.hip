@@ -37,21 +37,41 @@ __global__ void k_tri_bounds(const float* __restrict__ V, const int32_t* __restr
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float c[3] = {INFINITY, INFINITY, INFINITY};
   float cm[3] = {-INFINITY, -INFINITY, -INFINITY};
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int32_t key = -1;   // object of a valid triangle, else -1
   if (i < T) {
     int32_t a = tris[3 * i], b = tris[3 * i + 1], cc = tris[3 * i + 2];
     int32_t o = obj[i];
     if (a < 0 || b < 0 || cc < 0 || a >= nV || b >= nV || cc >= nV || o < 0 || o >= n_obj) {
       atomicOr(err, DEV_ERR_INDEX);
     } else {
-      float lo[3], hi[3];
+      key = o;
       for (int k = 0; k < 3; ++k) {
         float x0 = V[3 * (int64_t)a + k], x1 = V[3 * (int64_t)b + k], x2 = V[3 * (int64_t)cc + k];
         lo[k] = fminf(x0, fminf(x1, x2));
         hi[k] = fmaxf(x0, fmaxf(x1, x2));
         c[k] = cm[k] = 0.5f * (lo[k] + hi[k]);
-        atomicMin(&ob[6 * o + k], f2o(lo[k]));
-        atomicMax(&ob[6 * o + 3 + k], f2o(hi[k]));
       }
+    }
+  }
+  // Object boxes: triangles of an object are usually contiguous, so a wave whose lanes all
+  // hold one object reduces its box first and issues 6 atomics instead of 6 per lane.
+  const int32_t key0 = __shfl(key, 0);
+  if (__all(key == key0) && key0 >= 0) {
+    for (int k = 0; k < 3; ++k)
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+      }
+    if ((threadIdx.x & 63) == 0)
+      for (int k = 0; k < 3; ++k) {
+        atomicMin(&ob[6 * key0 + k], f2o(lo[k]));
+        atomicMax(&ob[6 * key0 + 3 + k], f2o(hi[k]));
+      }
+  } else if (key >= 0) {
+    for (int k = 0; k < 3; ++k) {
+      atomicMin(&ob[6 * key + k], f2o(lo[k]));
+      atomicMax(&ob[6 * key + 3 + k], f2o(hi[k]));
     }
   }
   // block reduction of centroid bounds, one atomic per block and axis
@@ -283,29 +303,14 @@ __global__ void k_vcount(const int32_t* __restrict__ tris, int64_t T, uint64_t* 
   for (int c = 0; c < 3; ++c) atomicAdd((unsigned long long*)&cnt[tris[3 * t + c]], 1ull);
 }
 
-__global__ void k_vfill(const int32_t* __restrict__ tris, int64_t T, const uint64_t* __restrict__ offs,
-                        uint32_t* __restrict__ fill, int32_t* __restrict__ adj) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T) return;
-  for (int c = 0; c < 3; ++c) {
-    int32_t v = tris[3 * t + c];
-    uint32_t slot = atomicAdd(&fill[v], 1u);
-    adj[offs[v] + slot] = (int32_t)t;
-  }
-}
-
-__global__ void k_vsort(const uint64_t* __restrict__ offs, const uint64_t* __restrict__ cnt, int64_t V,
-                        int32_t* __restrict__ adj) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  int32_t* a = adj + offs[v];
-  int64_t n = (int64_t)cnt[v];
-  for (int64_t i = 1; i < n; ++i) {   // insertion sort: one-rings are short
-    int32_t x = a[i];
-    int64_t j = i - 1;
-    while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
-    a[j + 1] = x;
-  }
+// (vertex, triangle) pairs in triangle order; a stable sort by vertex leaves each vertex's
+// triangles in ascending order, the order in which the operator below sums them.
+__global__ void k_vkeys(const int32_t* __restrict__ tris, int64_t n3, uint32_t* __restrict__ key,
+                        int32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  key[i] = (uint32_t)tris[i];
+  val[i] = (int32_t)(i / 3);
 }
 
 struct d3 { double x, y, z; };
@@ -384,35 +389,21 @@ __global__ void k_single_leaf(Node2* nodes) {
 }
 
 // ------------------------------------------------------------------ refit (dynamic scenes)
-// Same topology, new vertex positions: each leaf writes its box into its parent's child slot
-// and climbs; at every inner node the second arrival (per-node counter) forms the node's box
-// from both child slots and writes it into the grandparent, so every box is the exact union
-// of its leaves' FP32 bounds, as a build of the same structure would produce.  Agent-scope
-// fences order the slot writes before the counter update and the counter update before the
-// slot reads (the XCDs' L2 caches are not coherent with each other).
+// Same topology, new vertex positions.  The build groups the inner nodes by depth; a refit
+// rewrites the repacked triangles, then visits the levels from the deepest up, one launch per
+// level: each node forms its two child boxes from its children (a leaf's triangle bounds, or
+// the union of an inner child's two slots, final since the previous launch).  Every node
+// writes only its own slots, so no thread waits on or fences against another, and every box
+// is the exact union of its leaves' FP32 bounds, as the build produces it.
 
-__device__ inline void set_child_box(Node2* nodes, int node, int child_link, float lox, float hix, float loy, float hiy,
-                                     float loz, float hiz) {
-  Node2& n = nodes[node];
-  if (n.ch.x == child_link) {
-    n.xy0 = make_float4(lox, hix, loy, hiy);
-    n.zz.x = loz;
-    n.zz.y = hiz;
-  } else {
-    n.xy1 = make_float4(lox, hix, loy, hiy);
-    n.zz.z = loz;
-    n.zz.w = hiz;
-  }
-}
-
-__global__ void k_refit_zero(uint32_t* __restrict__ cnt, int64_t n) {
+__global__ void k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    cnt[i] = 0u;
+    a[i] = v;
 }
 
-__global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__ tris, const int32_t* __restrict__ mat,
-                        const int32_t* __restrict__ tri_orig, const int32_t* __restrict__ leaf_parent, int64_t T,
-                        float4* __restrict__ tri4, Node2* nodes, uint32_t* cnt) {
+__global__ void k_refit_leaves(const float* __restrict__ V, const int32_t* __restrict__ tris,
+                               const int32_t* __restrict__ mat, const int32_t* __restrict__ tri_orig, int64_t T,
+                               float4* __restrict__ tri4) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= T) return;
   const int32_t t = tri_orig[p];
@@ -422,22 +413,52 @@ __global__ void k_refit(const float* __restrict__ V, const int32_t* __restrict__
   tri4[3 * p + 0] = make_float4(v[0][0], v[0][1], v[0][2], __int_as_float(t));
   tri4[3 * p + 1] = make_float4(v[1][0], v[1][1], v[1][2], __int_as_float(mat[t]));
   tri4[3 * p + 2] = make_float4(v[2][0], v[2][1], v[2][2], 0.f);
-  if (T < 2) return;   // a single leaf keeps its unbounded box
-  int node = leaf_parent[p];
-  set_child_box(nodes, node, ~(int)p, fminf(v[0][0], fminf(v[1][0], v[2][0])), fmaxf(v[0][0], fmaxf(v[1][0], v[2][0])),
-                fminf(v[0][1], fminf(v[1][1], v[2][1])), fmaxf(v[0][1], fmaxf(v[1][1], v[2][1])),
-                fminf(v[0][2], fminf(v[1][2], v[2][2])), fmaxf(v[0][2], fmaxf(v[1][2], v[2][2])));
-  for (int guard = 0; guard < 1 << 20; ++guard) {
-    __threadfence();
-    if (atomicAdd(&cnt[node], 1u) == 0u) return;   // the sibling's thread continues
-    __threadfence();
-    const Node2 n = nodes[node];
-    const int parent = n.ch.z;
-    if (parent < 0) return;                        // the root has no slot above it
-    set_child_box(nodes, parent, node, fminf(n.xy0.x, n.xy1.x), fmaxf(n.xy0.y, n.xy1.y), fminf(n.xy0.z, n.xy1.z),
-                  fmaxf(n.xy0.w, n.xy1.w), fminf(n.zz.x, n.zz.z), fmaxf(n.zz.y, n.zz.w));
-    node = parent;
+}
+
+struct Box6 { float lx, hx, ly, hy, lz, hz; };
+
+__device__ inline Box6 child_box(const Node2* nodes, const float4* __restrict__ tri4, int link) {
+  if (link < 0) {
+    const int64_t p = ~(int64_t)link;
+    const float4 a = tri4[3 * p], b = tri4[3 * p + 1], c = tri4[3 * p + 2];
+    return {fminf(a.x, fminf(b.x, c.x)), fmaxf(a.x, fmaxf(b.x, c.x)), fminf(a.y, fminf(b.y, c.y)),
+            fmaxf(a.y, fmaxf(b.y, c.y)), fminf(a.z, fminf(b.z, c.z)), fmaxf(a.z, fmaxf(b.z, c.z))};
   }
+  const Node2 m = nodes[link];
+  return {fminf(m.xy0.x, m.xy1.x), fmaxf(m.xy0.y, m.xy1.y), fminf(m.xy0.z, m.xy1.z),
+          fmaxf(m.xy0.w, m.xy1.w), fminf(m.zz.x, m.zz.z), fmaxf(m.zz.y, m.zz.w)};
+}
+
+__global__ void k_refit_level(const int32_t* __restrict__ level, int64_t n, const float4* __restrict__ tri4,
+                              Node2* nodes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = level[i];
+  const int4 ch = nodes[k].ch;
+  const Box6 b0 = child_box(nodes, tri4, ch.x), b1 = child_box(nodes, tri4, ch.y);
+  nodes[k].xy0 = make_float4(b0.lx, b0.hx, b0.ly, b0.hy);
+  nodes[k].xy1 = make_float4(b1.lx, b1.hx, b1.ly, b1.hy);
+  nodes[k].zz = make_float4(b0.lz, b0.hz, b1.lz, b1.hz);
+}
+
+// Depth of every inner node (root 0) by walking its parent links; histogram per depth.
+template <int NL>
+__global__ void k_node_depth(const Node2* __restrict__ nodes, int64_t n_inner, uint32_t* __restrict__ key,
+                             int32_t* __restrict__ val, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[NL + 1];
+  for (int i = threadIdx.x; i <= NL; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_inner) {
+    int d = 0;
+    for (int node = nodes[k].ch.z; node >= 0 && d < NL; node = nodes[node].ch.z) ++d;
+    key[k] = (uint32_t)d;
+    val[k] = (int32_t)k;
+    atomicAdd(&h[d], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= NL; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 // SAH cost of the refitted tree (C_node = C_tri = 1, normalised by the root area): the root
@@ -448,16 +469,16 @@ __device__ inline double slot_area(float lx, float hx, float ly, float hy, float
 
 __global__ void k_refit_sah(const Node2* __restrict__ nodes, int64_t n_inner, int root, double* sah) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_inner) return;
   const Node2 r = nodes[root];
   const double ra = slot_area(fminf(r.xy0.x, r.xy1.x), fmaxf(r.xy0.y, r.xy1.y), fminf(r.xy0.z, r.xy1.z),
                               fmaxf(r.xy0.w, r.xy1.w), fminf(r.zz.x, r.zz.z), fmaxf(r.zz.y, r.zz.w));
-  const Node2 n = nodes[k];
+  const Node2 n = nodes[k < n_inner ? k : root];
   double s = (k == root) ? 1.0 : 0.0;
-  if (ra > 0)
+  if (ra > 0 && k < n_inner)
     s += (slot_area(n.xy0.x, n.xy0.y, n.xy0.z, n.xy0.w, n.zz.x, n.zz.y) +
           slot_area(n.xy1.x, n.xy1.y, n.xy1.z, n.xy1.w, n.zz.z, n.zz.w)) / ra;
-  atomicAdd(sah, s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(sah, s);
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS > 0 ? (n + BS - 1) / BS : 1); }
@@ -465,14 +486,24 @@ inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
+// [6] u32 centroid bounds, then a double at byte 64; zero between calls, so that a refit to
+// the build's own vertices leaves the whole blob as the build left it
+constexpr size_t REFIT_SCRATCH = 256;
+constexpr int MAX_LEVEL = TRAV_STACK + 1;
+
 size_t scene_blob_bytes(int64_t T, int64_t V, int32_t n_obj) {
   size_t b = 0;
   b += al(sizeof(Node2) * (size_t)std::max<int64_t>(1, T - 1));
   b += al(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
-  b += 3 * al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));   // tri_orig, tri_pos, leaf_parent
+  b += 2 * al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));   // tri_orig, tri_pos
   b += al(sizeof(double) * (size_t)std::max<int64_t>(1, T));
   b += al(sizeof(double) * (size_t)std::max<int64_t>(1, V));
   b += al(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
+  // kept for refits: inner nodes by depth, vertex-triangle lists, refit scratch
+  b += al(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T - 1));
+  b += 2 * al(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, V));
+  b += al(sizeof(int32_t) * 3 * (size_t)std::max<int64_t>(1, T));
+  b += al(REFIT_SCRATCH);
   return b;
 }
 
@@ -490,8 +521,8 @@ size_t scene_scratch_bytes(int64_t T, int64_t V) {
   b += al(sizeof(int64_t) * 8) + al(sizeof(uint64_t) * 4);         // counters, totals
   b += al(sizeof(int32_t) * Tm);                                   // leaf parents
   b += al(sizeof(int32_t) * 2) + al(sizeof(double));               // depth, sah
-  b += 2 * al(sizeof(uint64_t) * Vm) + al(sizeof(uint32_t) * Vm);  // vertex counts / offsets / fill
-  b += al(sizeof(int32_t) * 3 * Tm);                               // adjacency
+  b += al(sizeof(uint32_t) * 3 * Tm) + sort_temp_bytes(3 * Tm, 4);  // vertex-triangle pair keys, sort
+  b += al(sizeof(uint32_t) * (MAX_LEVEL + 1));                     // nodes per depth
   return b;
 }
 
@@ -508,10 +539,14 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   d.tri4 = (float4*)takeb(sizeof(float4) * 3 * (size_t)std::max<int64_t>(1, T));
   d.tri_orig = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
   d.tri_pos = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
-  d.leaf_parent = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T));
   d.C = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, T));
   d.G = (double*)takeb(sizeof(double) * (size_t)std::max<int64_t>(1, V));
   d.obj_box = (float*)takeb(sizeof(float) * 6 * (size_t)std::max<int32_t>(1, n_obj));
+  sc->lvl_nodes = (int32_t*)takeb(sizeof(int32_t) * (size_t)std::max<int64_t>(1, T - 1));
+  sc->vcnt = (uint64_t*)takeb(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, V));
+  sc->voff = (uint64_t*)takeb(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, V));
+  sc->adj = (int32_t*)takeb(sizeof(int32_t) * 3 * (size_t)std::max<int64_t>(1, T));
+  sc->rscratch = takeb(REFIT_SCRATCH);
   // scratch layout
   const int64_t Tm = std::max<int64_t>(T, 1), Vm = std::max<int64_t>(V, 1);
   char* sp = (char*)scratch;
@@ -531,14 +566,15 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   void* scan_tmp = take(scan_temp_bytes(std::max(Tm, Vm)));
   int64_t* ctr = (int64_t*)take(sizeof(int64_t) * 8);      // [0] n, [1] next node, [2..3] host view
   uint64_t* total = (uint64_t*)take(sizeof(uint64_t) * 4);
-  (void)take(sizeof(int32_t) * Tm);   // (leaf parents live in the blob)
-  int32_t* leaf_parent = d.leaf_parent;
+  int32_t* leaf_parent = (int32_t*)take(sizeof(int32_t) * Tm);
   int32_t* depth = (int32_t*)take(sizeof(int32_t) * 2);
   double* sah = (double*)take(sizeof(double));
-  uint64_t* vcnt = (uint64_t*)take(sizeof(uint64_t) * Vm);
-  uint64_t* voff = (uint64_t*)take(sizeof(uint64_t) * Vm);
-  uint32_t* vfill = (uint32_t*)take(sizeof(uint32_t) * Vm);
-  int32_t* adj = (int32_t*)take(sizeof(int32_t) * 3 * Tm);
+  uint32_t* vkey = (uint32_t*)take(sizeof(uint32_t) * 3 * Tm);
+  void* vsort_tmp = take(sort_temp_bytes(3 * Tm, 4));
+  uint32_t* lvl_hist = (uint32_t*)take(sizeof(uint32_t) * (MAX_LEVEL + 1));
+  uint64_t* vcnt = sc->vcnt;
+  uint64_t* voff = sc->voff;
+  int32_t* adj = sc->adj;
   // object boxes live in the blob as floats; build them as ordered uints in the blob memory
   uint32_t* ob = (uint32_t*)d.obj_box;
 
@@ -600,6 +636,10 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
     ET_HIP(hipMemsetAsync(depth, 0, sizeof(int32_t), s));
     ET_HIP(hipMemsetAsync(sah, 0, sizeof(double), s));
     k_depth_sah<<<nblk(T), BS, 0, s>>>(d.nodes, leaf_parent, T, nb, root_id, depth, sah);
+    // inner nodes grouped by depth for refits (stable sort: the order is deterministic)
+    k_fill_u32<<<1, BS, 0, s>>>(lvl_hist, MAX_LEVEL + 1, 0u);
+    k_node_depth<MAX_LEVEL><<<nblk(T - 1), BS, 0, s>>>(d.nodes, T - 1, keys, sc->lvl_nodes, lvl_hist);
+    radix_sort_u32(keys, sc->lvl_nodes, T - 1, 7, sort_tmp, s);
     ET_HIP(hipGetLastError());
     d.root = (int)(T - 2);   // the last node created is the root; packed index = id - T
     sc->n_nodes = T - 1;
@@ -609,14 +649,16 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
     sc->n_nodes = 1;
   }
 
+  k_fill_u32<<<1, BS, 0, s>>>((uint32_t*)sc->rscratch, REFIT_SCRATCH / 4, 0u);
   // curvature (Eq. 1)
   if (T > 0 && V > 0) {
-    ET_HIP(hipMemsetAsync(vcnt, 0, sizeof(uint64_t) * Vm, s));
-    ET_HIP(hipMemsetAsync(vfill, 0, sizeof(uint32_t) * Vm, s));
+    k_fill_u32<<<nblk(2 * V), BS, 0, s>>>((uint32_t*)vcnt, 2 * V, 0u);
     k_vcount<<<nblk(T), BS, 0, s>>>(d.tris, T, vcnt);
     scan_exclusive_u64(vcnt, voff, V, nullptr, V, nullptr, scan_tmp, s);
-    k_vfill<<<nblk(T), BS, 0, s>>>(d.tris, T, voff, vfill, adj);
-    k_vsort<<<nblk(V), BS, 0, s>>>(voff, vcnt, V, adj);
+    k_vkeys<<<nblk(3 * T), BS, 0, s>>>(d.tris, 3 * T, vkey, adj);
+    int vbits = 1;
+    while (vbits < 32 && ((int64_t)1 << vbits) < V) ++vbits;
+    radix_sort_u32(vkey, adj, 3 * T, vbits, vsort_tmp, s);
     k_vertex_curv<<<nblk(V), BS, 0, s>>>(d.verts, d.tris, voff, vcnt, adj, V, d.G);
     k_tri_curv<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, T, d.G, mesh->area_ref, d.C);
     ET_HIP(hipGetLastError());
@@ -635,6 +677,13 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
     ET_HIP(hipMemcpy(&hs, sah, sizeof(double), hipMemcpyDeviceToHost));
     sc->depth = hd;
     sc->sah = hs;
+    std::vector<uint32_t> hist(MAX_LEVEL + 1);
+    ET_HIP(hipMemcpy(hist.data(), lvl_hist, sizeof(uint32_t) * hist.size(), hipMemcpyDeviceToHost));
+    int levels = MAX_LEVEL + 1;
+    while (levels > 0 && hist[levels - 1] == 0) --levels;
+    sc->lvl_off.assign(1, 0);
+    for (int l = 0; l < levels; ++l) sc->lvl_off.push_back(sc->lvl_off.back() + hist[l]);
+    ET_CHECK(sc->lvl_off.back() == T - 1, ET_E_INTERNAL, "BVH level grouping lost nodes");
   } else {
     sc->depth = T;
     sc->sah = T;
@@ -646,23 +695,13 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
 
 namespace et {
 
-void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scratch, uint32_t* dev_err,
-                 hipStream_t s) {
+void scene_refit(et_scene* sc, const float* vertices, double area_ref, uint32_t* dev_err, hipStream_t s) {
   SceneDev& d = sc->d;
   const int64_t T = d.T, V = d.V;
   const int32_t n_obj = d.n_obj;
   d.verts = vertices;
-  const int64_t Tm = std::max<int64_t>(T, 1), Vm = std::max<int64_t>(V, 1);
-  char* sp = (char*)scratch;
-  auto take = [&](size_t bytes) { char* p = sp; sp += al(bytes); return (void*)p; };
-  uint32_t* cb = (uint32_t*)take(sizeof(uint32_t) * 6);
-  uint32_t* cnt = (uint32_t*)take(sizeof(uint32_t) * Tm);
-  double* sah = (double*)take(sizeof(double));
-  uint64_t* vcnt = (uint64_t*)take(sizeof(uint64_t) * Vm);
-  uint64_t* voff = (uint64_t*)take(sizeof(uint64_t) * Vm);
-  uint32_t* vfill = (uint32_t*)take(sizeof(uint32_t) * Vm);
-  int32_t* adj = (int32_t*)take(sizeof(int32_t) * 3 * Tm);
-  void* scan_tmp = take(scan_temp_bytes(std::max(Tm, Vm)));
+  uint32_t* cb = (uint32_t*)sc->rscratch;
+  double* sah = (double*)((char*)sc->rscratch + 64);
   uint32_t* ob = (uint32_t*)d.obj_box;
   hipEvent_t e0, e1;
   ET_HIP(hipEventCreate(&e0));
@@ -671,22 +710,17 @@ void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scr
   k_init_bounds<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(cb, ob, n_obj);
   if (T > 0) k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, T, V, n_obj, cb, ob, dev_err);
   k_obj_box<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(ob, n_obj, d.obj_box);
-  if (T > 0) {
-    k_refit_zero<<<nblk(T), BS, 0, s>>>(cnt, T);
-    k_refit<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.mat, d.tri_orig, d.leaf_parent, T, d.tri4, d.nodes, cnt);
-  }
+  if (T > 0) k_refit_leaves<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.mat, d.tri_orig, T, d.tri4);
   if (T >= 2) {
-    k_refit_zero<<<1, BS, 0, s>>>((uint32_t*)sah, 2);
+    for (int l = (int)sc->lvl_off.size() - 2; l >= 0; --l) {
+      const int64_t a = sc->lvl_off[l], n = sc->lvl_off[l + 1] - a;
+      k_refit_level<<<nblk(n), BS, 0, s>>>(sc->lvl_nodes + a, n, d.tri4, d.nodes);
+    }
+    k_fill_u32<<<1, BS, 0, s>>>((uint32_t*)sah, 2, 0u);
     k_refit_sah<<<nblk(T - 1), BS, 0, s>>>(d.nodes, T - 1, d.root, sah);
   }
-  if (T > 0 && V > 0) {
-    k_refit_zero<<<nblk(2 * V), BS, 0, s>>>((uint32_t*)vcnt, 2 * V);
-    k_refit_zero<<<nblk(V), BS, 0, s>>>(vfill, V);
-    k_vcount<<<nblk(T), BS, 0, s>>>(d.tris, T, vcnt);
-    scan_exclusive_u64(vcnt, voff, V, nullptr, V, nullptr, scan_tmp, s);
-    k_vfill<<<nblk(T), BS, 0, s>>>(d.tris, T, voff, vfill, adj);
-    k_vsort<<<nblk(V), BS, 0, s>>>(voff, vcnt, V, adj);
-    k_vertex_curv<<<nblk(V), BS, 0, s>>>(d.verts, d.tris, voff, vcnt, adj, V, d.G);
+  if (T > 0 && V > 0) {   // the vertex-triangle lists depend on the topology only
+    k_vertex_curv<<<nblk(V), BS, 0, s>>>(d.verts, d.tris, sc->voff, sc->vcnt, sc->adj, V, d.G);
     k_tri_curv<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, T, d.G, area_ref, d.C);
   }
   ET_HIP(hipGetLastError());
@@ -697,7 +731,10 @@ void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scr
   sc->refit_ms = ms;
   ET_HIP(hipEventDestroy(e0));
   ET_HIP(hipEventDestroy(e1));
-  if (T >= 2) ET_HIP(hipMemcpy(&sc->sah, sah, sizeof(double), hipMemcpyDeviceToHost));
+  if (T >= 2) ET_HIP(hipMemcpyAsync(&sc->sah, sah, sizeof(double), hipMemcpyDeviceToHost, s));
+  k_fill_u32<<<1, BS, 0, s>>>((uint32_t*)sc->rscratch, REFIT_SCRATCH / 4, 0u);
+  ET_HIP(hipGetLastError());
+  ET_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace et

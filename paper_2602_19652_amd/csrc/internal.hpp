@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/echotrace.h"
 
@@ -76,7 +77,6 @@ struct SceneDev {
   float4* tri4 = nullptr;       // [T][3]: v0 (w = original index bits), v1 (w = material bits), v2
   int32_t* tri_orig = nullptr;  // [T] original triangle index per leaf position
   int32_t* tri_pos = nullptr;   // [T] leaf position per original triangle index
-  int32_t* leaf_parent = nullptr;  // [T] inner node holding leaf position p
   double* C = nullptr;          // [T] curvature metric per original triangle
   double* G = nullptr;          // [V] per-vertex mean curvature magnitude
   float* obj_box = nullptr;     // [n_obj][6] lo xyz, hi xyz
@@ -93,6 +93,13 @@ struct et_scene {
   double build_ms = 0;
   double refit_ms = 0;
   int device = 0;
+  // what a refit reads besides the tree (device arrays in the blob; level offsets on the host)
+  int32_t* lvl_nodes = nullptr;    // [T-1] inner nodes grouped by depth, root first
+  std::vector<int64_t> lvl_off;    // [levels + 1] start of each depth in lvl_nodes
+  uint64_t* vcnt = nullptr;        // [V] triangles around each vertex
+  uint64_t* voff = nullptr;        // [V] start of each vertex's list in adj
+  int32_t* adj = nullptr;          // [3T] triangles around each vertex, ascending
+  void* rscratch = nullptr;        // refit scratch: centroid bounds, SAH accumulator
 };
 
 namespace et {
@@ -119,7 +126,7 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
                  hipStream_t s);
 // New vertex positions, same topology: BVH refit (structure kept, boxes recomputed bottom-up),
 // triangle repack, object boxes and curvature.  Throws et::Error.
-void scene_refit(et_scene* sc, const float* vertices, double area_ref, void* scratch, uint32_t* dev_err,
+void scene_refit(et_scene* sc, const float* vertices, double area_ref, uint32_t* dev_err,
                  hipStream_t s);
 
 }  // namespace et

@@ -135,9 +135,7 @@ def test_refit_rejects_bad_arguments(et, ctx, frames):
     sc = et.Scene(ctx, scene)
     with pytest.raises(ValueError):
         sc.refit(scene["vertices"][:-1])
-    buf = et.Workspace().get(16)
-    v = sc.vertices
-    rc = et.lib().et_scene_refit(ctx.h, sc.h, ctypes.c_void_p(v.data_ptr()), 0.0, ctypes.c_void_p(buf.data_ptr()), 16)
-    assert rc == -2                                            # scratch too small
-    rc = et.lib().et_scene_refit(ctx.h, sc.h, None, 0.0, ctypes.c_void_p(buf.data_ptr()), sc.scratch_bytes)
-    assert rc == -1
+    v = ctypes.c_void_p(sc.vertices.data_ptr())
+    assert et.lib().et_scene_refit(ctx.h, sc.h, None, 0.0) == -1          # no vertices
+    assert et.lib().et_scene_refit(ctx.h, None, v, 0.0) == -1             # no scene
+    assert et.lib().et_scene_refit(ctx.h, sc.h, v, float("nan")) == -1    # area_ref not finite
