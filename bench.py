@@ -227,6 +227,8 @@ def main():
     trav_bytes = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
                   + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
 
+    dynamic = dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
+
     synth_flops = terms * SYNTH_FLOP_PER_TERM
     synth_tflops = synth_flops / (ms_synth_kernel * 1e-3) / 1e12
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
@@ -268,6 +270,7 @@ def main():
                     "per_unit": f"{ADJ_FLOP_PER_TERM} flop per (visible record, receiver, bin)",
                     "traffic": traffic_for("k_synth_bwd_mfma<false>" if adj_kern == 1 else "k_synth_bwd<false>")},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
+        "dynamic_scene": dynamic,
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
                       "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
@@ -283,6 +286,50 @@ def main():
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(ctx, args)
     print(json.dumps(line))
+
+
+def dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps):
+    """Animated room: one frame in which the 200 objects turn and move (every fourth also
+    deforms).  The tree is refitted (et_scene_refit) or rebuilt; the step then runs on it."""
+    import torch
+    a_ref = sim["area_ref"]
+    V0 = torch.as_tensor(scene["vertices"]).cuda()
+    V1 = torch.as_tensor(W.animate_objects(scene, W.rng(31))).cuda()
+    dev_ms, n = 0.0, 2 * reps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n):
+        sc.refit(V1 if i % 2 == 0 else V0, area_ref=a_ref)
+        dev_ms += sc.info().refit_ms
+    wall_ms = (time.perf_counter() - t0) * 1e3 / n
+    sc.refit(V1, area_ref=a_ref)
+    refit_sah = sc.info().sah_cost
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def step_ms(scn):
+        et.simulate(ctx, scn, s, paths=P, ws=ws, out=out)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            et.simulate(ctx, scn, s, paths=P, ws=ws, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_refitted = step_ms(sc)
+    moved = dict(scene, vertices=V1.cpu().numpy())
+    fresh = et.Scene(ctx, moved, area_ref=a_ref)
+    fi = fresh.info()
+    ms_fresh = step_ms(fresh)
+    del fresh
+    sc.refit(V0, area_ref=a_ref)
+    return {"workload": "room scene, one animation frame: 200 objects turned by up to 0.15 rad and moved by up "
+                        "to 10 cm, every fourth deformed (1 cm radial ripple); same topology",
+            "refit_ms": dev_ms / n, "refit_wall_ms": wall_ms, "build_ms": fi.build_ms,
+            "sah_refit": refit_sah, "sah_rebuilt": fi.sah_cost,
+            "step_ms_refitted": ms_refitted, "step_ms_rebuilt": ms_fresh,
+            "frame_ms_refit": dev_ms / n + ms_refitted, "frame_ms_rebuild": fi.build_ms + ms_fresh}
 
 
 def batched_leg(ctx, args):
