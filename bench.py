@@ -201,6 +201,17 @@ def main():
     ms_sig = e0.elapsed_time(e1) / reps
     del td_ws, sig_ws
 
+    # EQ ray set of the step's size over the whole sphere (collar table, count, centres)
+    eq_ws = et.Workspace()
+    et.eq_directions(ctx, s.desc.N, ws=eq_ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        et.eq_directions(ctx, s.desc.N, ws=eq_ws)
+    torch.cuda.synchronize()
+    ms_eq = (time.perf_counter() - t0) * 1e3 / reps
+    del eq_ws
+
     # adjoint over the fixed paths of the step (32 receivers x 4096 bins): seeded dL/dconj(H)
     gen = torch.Generator(device="cuda").manual_seed(2024)
     gH = torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda", generator=gen)
@@ -263,6 +274,8 @@ def main():
         "time_domain": {"workload": f"impulse responses of the step's spectra, n_t = {n_t} samples at "
                                     f"{1 / dt / 1e3:.1f} kHz; received signals for a {L_call}-sample 20-100 kHz chirp",
                         "impulse_ms": ms_ir, "signal_ms": ms_sig},
+        "ray_set": {"workload": f"EQ sphere partition, {s.desc.N} region centres (two calls: count, then centres)",
+                    "wall_ms": ms_eq},
         "adjoint": {"workload": "fixed paths of the step, 32 receivers x 4096 bins, seeded dL/dconj(H)",
                     "ms": ms_adj, "kernel_ms": ms_adj_kernel, "kernel": adj_kern,
                     "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,

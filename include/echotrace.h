@@ -119,7 +119,7 @@ int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double
  * deformations keep a valid but looser tree: sah_cost of et_scene_get_info is recomputed
  * (rebuild when it grows).  Ordered on the context's stream; returns after the refit
  * finished; refits of one scene must not overlap.  Errors: ET_E_INVALID for NULL pointers,
- * ET_E_HIP for device failures (the scene is then unusable and must be rebuilt). */
+ * ET_E_DEVICE for device failures (the scene is then unusable and must be rebuilt). */
 int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref);
 
 /* ------------------------------------------------------------------ one pose (one emitter) */
@@ -267,6 +267,30 @@ int et_impulse_response(et_ctx* ctx, int32_t M, int32_t F, double f_lo, double f
 int et_receiver_signal_workspace_size(int32_t M, int32_t n_t, int64_t L, size_t* bytes);
 int et_receiver_signal(et_ctx* ctx, int32_t M, int32_t n_t, const float* h, int64_t L, const float* s_e, double dt,
                        void* ws, size_t ws_bytes, float* out);
+
+/* ------------------------------------------------------------------ ray sets (Sec. III-C)
+ * The paper spreads each emitter's rays by the recursive zonal equal-area partition of the
+ * sphere (Leopardi 2006).  EQ(2, N): two polar caps of area A = 4 pi / N, n collars of equal
+ * angular height between them (n = round((pi - 2 theta_c) / sqrt(A))), collar i holding the
+ * rounded share of the cumulative ideal count, every zone boundary at the colatitude whose cap
+ * holds exactly its regions.  A direction is a region centre: the middle colatitude of its
+ * collar, longitudes 2 pi ((j + 1/2) / m_i + offset_i) with each collar turned against the one
+ * above by Leopardi's twist (1/m_{i+1} - 1/m_i)/2 + gcd(m_i, m_{i+1}) / (2 m_i m_{i+1}) turns.
+ * Counts round to the nearest integer with halves (and values within N 2^-36 above a half)
+ * rounded down: a boundary on the equator has an ideal count of exactly (N - 2) / 2.
+ * Directions are in the emitter frame with the polar axis on the boresight +x:
+ * (cos t, sin t cos p, sin t sin p).  Order: the boresight, then collar by collar outward in
+ * increasing longitude, then the backward pole; a cone keeps a prefix of this order.
+ *   N                regions of the whole sphere, 1 <= N <= 2^28
+ *   cone_half_angle  radians in (0, pi]: keep the centres with colatitude <= it
+ *   ws               device workspace of et_eq_directions_workspace_size(N) bytes (collar table)
+ *   dirs             device [capacity][3] FP32, or NULL with capacity 0 to query the count
+ *   count            host out: the number of directions in the cone
+ * Synchronises the stream (the count comes back to the host).  ET_E_CAPACITY (count still
+ * set, nothing written) when dirs is given and the count exceeds capacity. */
+int et_eq_directions_workspace_size(int64_t N, size_t* bytes);
+int et_eq_directions(et_ctx* ctx, int64_t N, double cone_half_angle, void* ws, size_t ws_bytes, float* dirs,
+                     int64_t capacity, int64_t* count);
 
 /* ------------------------------------------------------------------ tuning of fused batches
  * Launch shapes kept per context: the workgroups that the record chunks of the synthesis and

@@ -280,3 +280,98 @@ def receiver_signal(h: np.ndarray, s_e: np.ndarray, dt: float) -> np.ndarray:
     h = np.asarray(h, np.float64)
     s_e = np.asarray(s_e, np.float64)
     return dt * np.stack([np.convolve(row, s_e) for row in np.atleast_2d(h)])
+
+
+# ------------------------------------------------------------------ EQ sphere partition (ray set)
+
+def _cap_area(theta: float) -> float:
+    """Area of the spherical cap of angular radius theta on the unit sphere."""
+    return 2.0 * math.pi * (1.0 - math.cos(theta))
+
+
+def _cap_angle(area: float) -> float:
+    """Angular radius of the cap of the given area (inverse of _cap_area)."""
+    return 2.0 * math.asin(min(1.0, math.sqrt(area / (4.0 * math.pi))))
+
+
+def _round(x: float, N: int) -> int:
+    """Nearest integer to x >= 0, with halves rounded down.  A collar boundary on the equator
+    has an ideal cumulative count of exactly (N - 2) / 2, a half for odd N, which floating
+    point lands on either side of: values within N * 2^-36 above a half count as the half, so
+    that every evaluation order rounds them the same way."""
+    return int(math.floor(x + 0.5 - N * 2.0 ** -36))
+
+
+def eq_zones(N: int):
+    """Recursive zonal equal-area partition EQ(2, N) of the unit sphere (Leopardi 2006; the
+    ray set of Sec. III-C).  Returns (zone boundaries theta_0 = 0 < ... < theta_Z = pi,
+    regions per zone) from the north cap to the south cap.  Steps: two polar caps of the
+    region area A = 4 pi / N; the band between them is cut into n collars of equal angular
+    height, n the rounded ratio of the band's height to the ideal region size sqrt(A); each
+    collar's ideal region count (its area over A) is rounded in order with the rounding error
+    carried into the next collar; the zone boundaries are then placed so that every zone's
+    area is exactly its region count times A."""
+    if N < 1:
+        raise ValueError("N must be >= 1")
+    if N > 1 << 28:
+        raise ValueError("N must be <= 2^28")
+    if N == 1:
+        return [0.0, math.pi], [1]
+    A = 4.0 * math.pi / N
+    theta_c = _cap_angle(A)
+    if N == 2:
+        return [0.0, theta_c, math.pi], [1, 1]
+    delta_i = math.sqrt(A)
+    n = max(1, _round((math.pi - 2.0 * theta_c) / delta_i, N))
+    delta_f = (math.pi - 2.0 * theta_c) / n
+    counts = []
+    carry = 0.0
+    for i in range(1, n + 1):
+        ideal = (_cap_area(theta_c + i * delta_f) - _cap_area(theta_c + (i - 1) * delta_f)) / A
+        m = _round(ideal + carry, N)
+        carry += ideal - m
+        counts.append(m)
+    zones = [1] + counts + [1]
+    bounds = [0.0]
+    acc = 0
+    for m in zones[:-1]:
+        acc += m
+        bounds.append(_cap_angle(acc * A))
+    bounds.append(math.pi)
+    return bounds, zones
+
+
+def eq_circle_offset(n_top: int, n_bot: int) -> float:
+    """Rotation (in turns) of a collar of n_bot regions against the collar of n_top regions
+    above it that keeps the region centres of the two collars apart (Leopardi's twist)."""
+    return (1.0 / n_bot - 1.0 / n_top) / 2.0 + math.gcd(n_top, n_bot) / (2.0 * n_top * n_bot)
+
+
+def eq_directions(N: int, cone_half_angle: float = math.pi) -> np.ndarray:
+    """Centres of the regions of EQ(2, N) as unit vectors about the boresight +x:
+    (cos t, sin t cos p, sin t sin p) with t the colatitude.  Order: north cap, then every
+    collar by increasing longitude, then the south cap.  A collar's centres sit at the
+    middle colatitude of the collar and at longitudes 2 pi ((j + 1/2) / m + offset), the
+    offset of the first collar 0 and each next one turned by eq_circle_offset.  Only the
+    centres with colatitude <= cone_half_angle are returned (a prefix of the order)."""
+    bounds, zones = eq_zones(N)
+    thetas, phis = [0.0], [0.0]
+    offset = 0.0
+    Z = len(zones)
+    for z in range(1, Z):
+        m = zones[z]
+        if z == Z - 1:
+            thetas.append(math.pi)
+            phis.append(0.0)
+            break
+        t = 0.5 * (bounds[z] + bounds[z + 1])
+        for j in range(m):
+            thetas.append(t)
+            phis.append(2.0 * math.pi * (((j + 0.5) / m + offset) % 1.0))
+        if z + 1 < Z - 1:
+            offset = (offset + eq_circle_offset(m, zones[z + 1])) % 1.0
+    th = np.array(thetas)
+    ph = np.array(phis)
+    keep = th <= cone_half_angle
+    th, ph = th[keep], ph[keep]
+    return np.stack([np.cos(th), np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph)], axis=1)

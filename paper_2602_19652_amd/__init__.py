@@ -9,6 +9,7 @@ fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 from dataclasses import dataclass
@@ -117,6 +118,8 @@ def lib():
             "et_scene_get_info": ([vp, vp, C.POINTER(SceneInfo)], C.c_int),
             "et_scene_curvature": ([vp, vp, vp, vp], C.c_int),
             "et_scene_refit": ([vp, vp, vp, C.c_double], C.c_int),
+            "et_eq_directions_workspace_size": ([i64, C.POINTER(sz)], C.c_int),
+            "et_eq_directions": ([vp, i64, C.c_double, vp, sz, vp, i64, C.POINTER(i64)], C.c_int),
             "et_workspace_size": ([vp, vp, C.POINTER(SimDesc), C.POINTER(sz)], C.c_int),
             "et_trace": ([vp, vp, C.POINTER(SimDesc), vp, sz, C.POINTER(PathsDesc)], C.c_int),
             "et_synthesize": ([vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp, sz, vp], C.c_int),
@@ -157,6 +160,8 @@ def _dev() -> torch.device:
 
 
 def _to_dev(a, dtype):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=_dev(), dtype=dtype).contiguous()
     return torch.as_tensor(np.ascontiguousarray(a)).to(device=_dev(), dtype=dtype).contiguous()
 
 
@@ -248,10 +253,7 @@ class Scene:
     def refit(self, vertices, area_ref: float = 0.0):
         """New vertex positions [V][3] for the same topology (et_scene_refit); keeps the
         device copy alive as the scene's vertex array."""
-        if isinstance(vertices, torch.Tensor):
-            v = vertices.to(device=_dev(), dtype=torch.float32).contiguous()
-        else:
-            v = _to_dev(vertices, torch.float32)
+        v = _to_dev(vertices, torch.float32)
         if tuple(v.shape) != (self.V, 3):
             raise ValueError(f"vertices must have shape ({self.V}, 3), got {tuple(v.shape)}")
         self.ctx.call("et_scene_refit", self.h, _ptr(v), float(area_ref))
@@ -496,6 +498,23 @@ def receiver_signal(ctx: Context, h: torch.Tensor, s_e: torch.Tensor, dt: float,
     out = torch.empty(M, n_t + L - 1, dtype=torch.float32, device=_dev())
     ctx.call("et_receiver_signal", M, n_t, _ptr(h), L, _ptr(s_e), float(dt), _ptr(buf), buf.numel(), _ptr(out))
     return out
+
+
+def eq_directions(ctx: Context, N: int, cone_half_angle: float = math.pi, ws: Workspace | None = None) -> torch.Tensor:
+    """Ray directions [count, 3] (float32, emitter frame, boresight +x): the centres of the
+    regions of the equal-area partition EQ(2, N) of the sphere within the cone."""
+    ws = ws or Workspace()
+    n = C.c_size_t()
+    rc = lib().et_eq_directions_workspace_size(int(N), C.byref(n))
+    if rc != 0:
+        raise EchoError(rc, "et_eq_directions_workspace_size")
+    buf = ws.get(n.value)
+    count = C.c_int64()
+    ctx.call("et_eq_directions", int(N), float(cone_half_angle), _ptr(buf), buf.numel(), None, 0, C.byref(count))
+    out = torch.empty(max(count.value, 1), 3, dtype=torch.float32, device=_dev())
+    ctx.call("et_eq_directions", int(N), float(cone_half_angle), _ptr(buf), buf.numel(), _ptr(out), count.value,
+             C.byref(count))
+    return out[:count.value]
 
 
 class SpectraFn(torch.autograd.Function):

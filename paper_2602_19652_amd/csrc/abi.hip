@@ -691,6 +691,31 @@ int et_receiver_signal(et_ctx* ctx, int32_t M, int32_t n_t, const float* h, int6
   });
 }
 
+int et_eq_directions_workspace_size(int64_t N, size_t* bytes) {
+  if (!bytes || N < 1 || N > ((int64_t)1 << 28)) return ET_E_INVALID;
+  *bytes = eq_ws_bytes(eq_plan(N));
+  return ET_OK;
+}
+
+int et_eq_directions(et_ctx* ctx, int64_t N, double cone_half_angle, void* ws, size_t ws_bytes, float* dirs,
+                     int64_t capacity, int64_t* count) {
+  return guarded(ctx, [&] {
+    ET_CHECK(N >= 1 && N <= ((int64_t)1 << 28), ET_E_INVALID, "need 1 <= N <= 2^28");
+    ET_CHECK(std::isfinite(cone_half_angle) && cone_half_angle > 0 && cone_half_angle <= M_PI, ET_E_INVALID,
+             "cone half-angle must lie in (0, pi]");
+    ET_CHECK(count, ET_E_INVALID, "count is NULL");
+    ET_CHECK(dirs || capacity == 0, ET_E_INVALID, "dirs is NULL");
+    ET_CHECK(capacity >= 0, ET_E_INVALID, "negative capacity");
+    const EqPlan p = eq_plan(N);
+    ET_CHECK(ws && ws_bytes >= eq_ws_bytes(p), ET_E_WORKSPACE, "workspace too small for et_eq_directions");
+    const int64_t c = eq_count(p, cone_half_angle, ws, ctx->stream);
+    *count = c;
+    if (!dirs) return;
+    ET_CHECK(c <= capacity, ET_E_CAPACITY, "more directions than capacity");
+    eq_points(p, c, ws, dirs, ctx->stream);
+  });
+}
+
 int et_get_tuning(et_ctx* ctx, et_tuning* out) {
   return guarded(ctx, [&] {
     ET_CHECK(out, ET_E_INVALID, "tuning is NULL");

@@ -232,6 +232,19 @@ bool synth_factorised_ok(const et_sim_desc* sim);
 bool synth_bwd_factorised_ok(const et_sim_desc* sim);
 
 // ------------------------------------------------------------------ time domain (timedomain.hip)
+// ------------------------------------------------------------------ EQ ray sets (eq.hip)
+
+struct EqPlan {
+  int64_t N = 0, n = 0;       // regions, collars
+  double theta_c = 0, delta = 0;   // polar cap colatitude, collar height
+};
+EqPlan eq_plan(int64_t N);
+size_t eq_ws_bytes(const EqPlan& p);
+// Builds the collar table in ws and returns the number of region centres within the cone
+// (synchronises the stream).
+int64_t eq_count(const EqPlan& p, double half_angle, void* ws, hipStream_t s);
+void eq_points(const EqPlan& p, int64_t count, void* ws, float* dirs, hipStream_t s);
+
 int64_t conv_length(int64_t n_t, int64_t L);
 size_t impulse_ws_bytes(int64_t M, int64_t n_t);
 size_t signal_ws_bytes(int64_t M, int64_t n_t, int64_t L);

@@ -423,3 +423,56 @@ def test_invalid_arguments_report_status(et, ctx, tiny):
         ctx.stats()
     assert e.value.status == -3
     assert P.count[0].item() > 4
+
+
+# ----------------------------------------------------------------------------- EQ ray sets
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 10, 33, 100, 1000, 4097, 65536, 1 << 20])
+def test_eq_directions_match_oracle(et, ctx, N):
+    """Region centres of EQ(2, N): the collar counts decide integers, so the sets must have
+    the same size and order; values agree to FP32 rounding of FP64 arithmetic."""
+    D = et.eq_directions(ctx, N).cpu().numpy().astype(np.float64)
+    R = O.eq_directions(N)
+    assert D.shape == R.shape
+    err = float(np.max(np.abs(D - R)))
+    print(f"EQ N={N}: max |diff| {err:.2e}, bitwise-equal fraction {np.mean(D == R.astype(np.float32)):.6f}")
+    assert err <= 1.2e-7
+
+
+def test_eq_cone_and_errors(et, ctx):
+    import ctypes
+    N, a = 1 << 20, math.radians(30.0)
+    R = O.eq_directions(N, a)
+    b, z = O.eq_zones(N)
+    mids = [(b[k] + b[k + 1]) / 2 for k in range(1, len(z) - 1)]
+    assert min(abs(t - a) for t in mids) > 1e-9   # the cone's edge is clear of every collar's centre
+    D = et.eq_directions(ctx, N, a).cpu().numpy()
+    assert D.shape == R.shape
+    assert float(np.max(np.abs(D - R))) <= 1.2e-7
+    n = ctypes.c_size_t()
+    assert et.lib().et_eq_directions_workspace_size(0, ctypes.byref(n)) == -1
+    assert et.lib().et_eq_directions_workspace_size(N, ctypes.byref(n)) == 0
+    ws = et.Workspace().get(n.value)
+    cnt = ctypes.c_int64()
+    out = et.Workspace().get(64)
+    args = (ctypes.c_void_p(ws.data_ptr()), n.value)
+    assert et.lib().et_eq_directions(ctx.h, N, 0.0, *args, None, 0, ctypes.byref(cnt)) == -1
+    assert et.lib().et_eq_directions(ctx.h, N, a, *args, None, 0, None) == -1
+    assert et.lib().et_eq_directions(ctx.h, N, a, ctypes.c_void_p(ws.data_ptr()), 8, None, 0, ctypes.byref(cnt)) == -2
+    rc = et.lib().et_eq_directions(ctx.h, N, a, *args, ctypes.c_void_p(out.data_ptr()), 5, ctypes.byref(cnt))
+    assert rc == -3 and cnt.value == len(R)
+
+
+def test_trace_with_eq_directions(et, ctx, tiny):
+    """The tiny scene traced with the EQ ray set of its 60-degree cone (about 16k rays)."""
+    scene, sim, _ = tiny
+    N, a = 245760, math.radians(30.0)
+    R = O.eq_directions(N, a)
+    D = et.eq_directions(ctx, N, a)
+    assert np.array_equal(D.cpu().numpy(), R.astype(np.float32))
+    ref = O.trace(scene, sim, dirs=R.astype(np.float32))
+    sc = et.Scene(ctx, scene)
+    gpu = et.trace(ctx, sc, et.Sim(sim, ray_dirs=D)).to_host()
+    mism = compare_traces(gpu, ref, ref["certified"])
+    print(f"EQ rays {len(R)}: certified {ref['certified'].mean():.4f}, mismatches {mism}")
+    assert mism == 0

@@ -544,3 +544,71 @@ def test_receiver_signal_is_a_convolution():
     a, b = g.normal(size=9), g.normal(size=9)
     np.testing.assert_allclose(O.receiver_signal(h, 2 * a - b, dt),
                                2 * O.receiver_signal(h, a, dt) - O.receiver_signal(h, b, dt), atol=1e-18)
+
+
+# ----------------------------------------------------------------------------- EQ ray sets (Sec. III-C)
+
+def test_eq_small_sets_closed_forms():
+    """EQ(2, N) worked by hand: N = 1 is the boresight; N = 2 the two hemispheres' poles; for
+    N = 3, 4, 6 the band between the caps (colatitude acos(1 - 2/N)) is lower than the ideal
+    region size sqrt(4 pi / N), so it forms one equatorial collar of N - 2 regions whose
+    centres sit at longitudes 2 pi (j + 1/2) / (N - 2)."""
+    h = math.sqrt(0.5)
+    want = {1: [[1, 0, 0]],
+            2: [[1, 0, 0], [-1, 0, 0]],
+            3: [[1, 0, 0], [0, -1, 0], [-1, 0, 0]],
+            4: [[1, 0, 0], [0, 0, 1], [0, 0, -1], [-1, 0, 0]],
+            6: [[1, 0, 0], [0, h, h], [0, -h, h], [0, -h, -h], [0, h, -h], [-1, 0, 0]]}
+    for N, w in want.items():
+        np.testing.assert_allclose(O.eq_directions(N), np.array(w, float), atol=1e-15)
+
+
+@pytest.mark.parametrize("N", list(range(1, 400)) + [997, 4096, 65537, 1 << 20])
+def test_eq_zones_equal_area_and_carry(N):
+    """Every zone's area (from its boundary colatitudes) is its region count times 4 pi / N,
+    and each collar boundary's cap differs from the cap of the equal-height grid line by at
+    most half a region (the carried rounding)."""
+    b, z = O.eq_zones(N)
+    assert sum(z) == N and min(z) >= 1 and z[0] == 1 and (N == 1 or z[-1] == 1)
+    A = 4 * math.pi / N
+    areas = np.array([2 * math.pi * (math.cos(b[k]) - math.cos(b[k + 1])) for k in range(len(z))])
+    np.testing.assert_allclose(areas, np.array(z) * A, rtol=1e-8, atol=1e-13)
+    if N > 2:
+        tc = math.acos(1 - 2 / N)
+        n = len(z) - 2
+        d = (math.pi - 2 * tc) / n
+        for k in range(1, n + 1):   # boundary k closes zone k - 1
+            grid = 2 * math.pi * (1 - math.cos(tc + (k - 1) * d))
+            cap = 2 * math.pi * (1 - math.cos(b[k]))
+            assert abs(cap - grid) / A <= 0.5 + 1e-6
+
+
+def test_eq_twist_and_order():
+    """Twist closed forms; centres ordered by colatitude with a cone keeping a prefix."""
+    for n in (1, 2, 7, 40):
+        assert O.eq_circle_offset(n, n) == pytest.approx(1 / (2 * n), abs=1e-15)
+    assert O.eq_circle_offset(6, 12) == pytest.approx((1 / 12 - 1 / 6) / 2 + 6 / (2 * 72), abs=1e-15)
+    D = O.eq_directions(5000)
+    assert np.all(np.diff(D[:, 0]) <= 1e-15)
+    for a in (0.3, 1.0, 2.5):
+        C = O.eq_directions(5000, a)
+        k = int(np.sum(D[:, 0] >= math.cos(a) - 1e-12))
+        assert len(C) == k and np.array_equal(C, D[:k])
+    np.testing.assert_allclose(np.linalg.norm(D, axis=1), 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("N", [2000, 20000])
+def test_eq_cap_discrepancy(N):
+    """Equal-area regions make every spherical cap hold its share of centres to
+    O(N^-1/2) with a small constant (seeded random caps: <= 0.35 / sqrt(N); seeded random
+    point sets reach about 1 / sqrt(N))."""
+    D = O.eq_directions(N)
+    g = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(300):
+        ax = g.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        a = g.uniform(0.05, math.pi - 0.05)
+        share = float(np.sum(D @ ax >= math.cos(a))) / N
+        worst = max(worst, abs(share - (1 - math.cos(a)) / 2))
+    assert worst <= 0.35 / math.sqrt(N)
