@@ -186,26 +186,34 @@ def splitmix(key: int, counter: int) -> int:
 
 def diffraction(scene: dict, sim: dict, Ci: np.ndarray, certify: bool = True, kappa: float = KAPPA) -> dict:
     """Section III-D sampler: K candidates drawn from the dithered integer CDF of C_i,
-    filtered by incidence angle and line of sight to the emitter."""
+    filtered by incidence angle and line of sight to the emitter.  With sim["diff_per_mesh"]
+    every mesh (object) with eligible triangles gets its own K candidates from its own CDF
+    (at most sim["diff_max_meshes"] meshes, in increasing object order)."""
     L = lib()
     v = _f32(scene["vertices"]); t = _i32(scene["tris"]); o = _i32(scene["tri_object"])
     K = int(sim["diff_K"])
+    per_mesh = bool(sim.get("diff_per_mesh", False))
+    mm = int(sim.get("diff_max_meshes", 1)) if per_mesh else 1
+    cap = max(K * mm, 1)
     T = len(t)
     q = np.zeros(max(T, 1), np.uint64)
     ne = C.c_int64(0)
-    st = np.zeros(max(K, 1), np.int32); so = np.zeros((max(K, 1), 3)); sr = np.zeros(max(K, 1))
-    sk = np.zeros(max(K, 1), np.uint8); sc = np.zeros(max(K, 1), np.uint8)
+    ns = C.c_int64(0)
+    st = np.zeros(cap, np.int32); so = np.zeros((cap, 3)); sr = np.zeros(cap)
+    sk = np.zeros(cap, np.uint8); sc = np.zeros(cap, np.uint8)
     Ci = _f64(Ci)
     rc = L.orc_diffraction(C.c_int64(len(v)), C.c_int64(T), _p(v), _p(t), _p(o), C.c_int32(int(scene["n_objects"])),
                            _p(Ci), _p(_f64(sim["emitter_pos"])), _p(_f64(sim["emitter_rot"])),
                            C.c_double(math.radians(sim["diff_cone_half_angle_deg"])), C.c_double(sim["diff_tau"]),
                            C.c_uint64(sim["diff_seed"]), C.c_int64(K),
                            C.c_double(math.radians(sim["diff_max_incidence_deg"])), C.c_double(sim["t_eps"]),
-                           C.c_double(kappa if certify else 0.0), _p(q), C.byref(ne), _p(st), _p(so), _p(sr), _p(sk), _p(sc))
-    if rc != 0:
+                           C.c_double(kappa if certify else 0.0), C.c_int(int(per_mesh)), C.c_int64(mm), _p(q),
+                           C.byref(ne), C.byref(ns), _p(st), _p(so), _p(sr), _p(sk), _p(sc))
+    if rc < 0:
         raise ValueError("orc_diffraction failed")
-    return {"q": q[:T], "n_elig": ne.value, "tri": st[:K], "o": so[:K], "r_src": sr[:K], "keep": sk[:K].astype(bool),
-            "certified": sc[:K].astype(bool)}
+    n = ns.value
+    return {"q": q[:T], "n_elig": ne.value, "tri": st[:n], "o": so[:n], "r_src": sr[:n], "keep": sk[:n].astype(bool),
+            "certified": sc[:n].astype(bool), "truncated": rc == 1}
 
 
 def diffraction_records(scene: dict, samples: dict) -> dict:

@@ -583,22 +583,28 @@ uint64_t orc_splitmix(uint64_t key, uint64_t counter) {
 
 static double u01(uint64_t x) { return (double)(x >> 11) * 0x1p-53; }
 
-typedef struct { uint64_t q; int64_t i; } qi_t;
+typedef struct { uint64_t q; int64_t i; int32_t o; } qi_t;
 static int cmp_qi(const void* a, const void* b) {
   const qi_t* x = (const qi_t*)a;
   const qi_t* y = (const qi_t*)b;
   if (x->q != y->q) return x->q > y->q ? -1 : 1;   /* weight descending */
   return x->i < y->i ? -1 : (x->i > y->i);          /* index ascending */
 }
+static int cmp_oqi(const void* a, const void* b) {   /* mesh first, then as cmp_qi */
+  const qi_t* x = (const qi_t*)a;
+  const qi_t* y = (const qi_t*)b;
+  if (x->o != y->o) return x->o < y->o ? -1 : 1;
+  return cmp_qi(a, b);
+}
 
 int orc_diffraction(int64_t V, int64_t T, const float* verts, const int32_t* tris, const int32_t* tri_obj,
                     int32_t n_obj, const double* C, const double* emitter_pos, const double* emitter_rot,
                     double cone_half_angle, double tau, uint64_t seed, int64_t K, double max_incidence,
-                    double t_eps, double kappa,
-                    uint64_t* q_out, int64_t* n_elig, int32_t* samp_tri, double* samp_o, double* samp_r,
-                    uint8_t* samp_keep, uint8_t* samp_certified) {
+                    double t_eps, double kappa, int per_mesh, int64_t max_meshes,
+                    uint64_t* q_out, int64_t* n_elig, int64_t* n_samples, int32_t* samp_tri, double* samp_o,
+                    double* samp_r, uint8_t* samp_keep, uint8_t* samp_certified) {
   (void)V;
-  if (T < 0 || n_obj < 1 || K < 0) return -1;
+  if (T < 0 || n_obj < 1 || K < 0 || (per_mesh && max_meshes < 1)) return -1;
   v3 s = ld3d(emitter_pos);
   v3 axis = rot(emitter_rot, mk(1, 0, 0));
   /* objects inside the emitter's field of view: bounding sphere of the object's box meets the cone */
@@ -634,23 +640,39 @@ int orc_diffraction(int64_t V, int64_t T, const float* verts, const int32_t* tri
     if (cmax > 0.0 && oel[tri_obj[t]] && C[t] > 0.0 && C[t] >= tau * cmax) {
       /* dithered integer weight: stochastic rounding of (C/Cmax) * 2^32 */
       q = (uint64_t)floor(C[t] / cmax * 4294967296.0 + u01(orc_splitmix(kd, (uint64_t)t)));
-      if (q > 0) { list[ne].q = q; list[ne].i = t; ++ne; }
+      if (q > 0) { list[ne].q = q; list[ne].i = t; list[ne].o = tri_obj[t]; ++ne; }
     }
     if (q_out) q_out[t] = q;
   }
   *n_elig = ne;
-  qsort(list, (size_t)ne, sizeof(qi_t), cmp_qi);
+  /* the triangles sorted by weight (per mesh: grouped by mesh first); one CDF per group,
+   * the running sums restarting at every group */
+  qsort(list, (size_t)ne, sizeof(qi_t), per_mesh ? cmp_oqi : cmp_qi);
+  int64_t* gstart = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne + 1));
+  int64_t ng = 0;
+  for (int64_t j = 0; j < ne; ++j)
+    if (j == 0 || (per_mesh && list[j].o != list[j - 1].o)) gstart[ng++] = j;
+  gstart[ng] = ne;
+  int truncated = 0;
+  if (per_mesh && ng > max_meshes) { ng = max_meshes; truncated = 1; }
   uint64_t* W = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(ne > 0 ? ne : 1));
-  uint64_t acc = 0;
-  for (int64_t j = 0; j < ne; ++j) { acc += list[j].q; W[j] = acc; }
+  for (int64_t g = 0; g < ng; ++g) {
+    uint64_t acc = 0;
+    for (int64_t j = gstart[g]; j < gstart[g + 1]; ++j) { acc += list[j].q; W[j] = acc; }
+  }
+  const int64_t n_draw = per_mesh ? K * ng : K;
+  *n_samples = n_draw;
   tri_t* tr = make_tris(T, verts, tris);
   const double cos_max = cos(max_incidence);
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int64_t k = 0; k < K; ++k) {
+  for (int64_t k = 0; k < n_draw; ++k) {
     if (ne == 0) { samp_tri[k] = -1; samp_keep[k] = 0; if (samp_certified) samp_certified[k] = 1; continue; }
+    const int64_t g = per_mesh ? k / K : 0;   /* the group (mesh) this draw belongs to */
+    const int64_t j0 = gstart[g], j1 = gstart[g + 1];
+    const uint64_t acc = W[j1 - 1];
     uint64_t U = orc_splitmix(ks, 3 * (uint64_t)k);
     uint64_t idx = (uint64_t)(((unsigned __int128)U * (unsigned __int128)acc) >> 64);
-    int64_t a = 0, b = ne;            /* first position with W > idx */
+    int64_t a = j0, b = j1;           /* first position of the group with W > idx */
     while (a < b) { int64_t mid = (a + b) / 2; if (W[mid] > idx) b = mid; else a = mid + 1; }
     int64_t t = list[a].i;
     double u1 = u01(orc_splitmix(ks, 3 * (uint64_t)k + 1)), u2 = u01(orc_splitmix(ks, 3 * (uint64_t)k + 2));
@@ -675,6 +697,6 @@ int orc_diffraction(int64_t V, int64_t T, const float* verts, const int32_t* tri
     samp_keep[k] = (uint8_t)keep;
     if (samp_certified) samp_certified[k] = (uint8_t)cert;
   }
-  free(lo); free(hi); free(oel); free(list); free(W); free(tr);
-  return 0;
+  free(lo); free(hi); free(oel); free(list); free(W); free(tr); free(gstart);
+  return truncated;
 }

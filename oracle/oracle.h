@@ -74,13 +74,17 @@ int orc_curvature(int64_t V, int64_t T, const float* verts, const int32_t* tris,
 uint64_t orc_splitmix(uint64_t key, uint64_t counter);
 
 /* Section III-D: curvature-importance Monte Carlo diffraction candidates, dithered
- * integer CDF, line-of-sight and incidence-angle filters.  Writes K samples. */
+ * integer CDF, line-of-sight and incidence-angle filters.  per_mesh = 0: K samples from one
+ * CDF over all eligible triangles.  per_mesh = 1: K samples for each mesh (object) with
+ * eligible triangles, in increasing object order, each from its own CDF; at most max_meshes
+ * meshes (returns 1 when more are eligible).  *n_samples receives the number written; the
+ * sample arrays hold K (or K * max_meshes) entries. */
 int orc_diffraction(int64_t V, int64_t T, const float* verts, const int32_t* tris, const int32_t* tri_obj,
                     int32_t n_obj, const double* C, const double* emitter_pos, const double* emitter_rot,
                     double cone_half_angle, double tau, uint64_t seed, int64_t K, double max_incidence,
-                    double t_eps, double kappa,
-                    uint64_t* q_out, int64_t* n_elig, int32_t* samp_tri, double* samp_o, double* samp_r,
-                    uint8_t* samp_keep, uint8_t* samp_certified);
+                    double t_eps, double kappa, int per_mesh, int64_t max_meshes,
+                    uint64_t* q_out, int64_t* n_elig, int64_t* n_samples, int32_t* samp_tri, double* samp_o,
+                    double* samp_r, uint8_t* samp_keep, uint8_t* samp_certified);
 
 #ifdef __cplusplus
 }

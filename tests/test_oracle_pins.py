@@ -359,6 +359,44 @@ def test_diffraction_filters():
     assert s2["n_elig"] == 0 and not s2["keep"].any()
 
 
+def test_diffraction_per_mesh_allocation():
+    """Sec. III-D, a fixed number of candidates per mesh: every mesh with eligible triangles
+    gets K draws from its own CDF (chi-square per mesh), in increasing object order; one mesh
+    alone reproduces the global sampler draw for draw; a cap on the meshes truncates."""
+    from scipy.stats import chisquare
+    scene = _boxes_scene()
+    G, C = O.curvature(scene, W.median_triangle_area(scene))
+    K = 30000
+    sim = _sim(diff_K=K, diff_seed=99, diff_tau=0.0, diff_cone_half_angle_deg=90.0, diff_per_mesh=True,
+               diff_max_meshes=scene["n_objects"])
+    s = O.diffraction(scene, sim, C, certify=False)
+    q = s["q"].astype(np.float64)
+    obj = scene["tri_object"]
+    meshes = sorted(set(obj[q > 0].tolist()))
+    assert len(meshes) == scene["n_objects"] == 6 and not s["truncated"]
+    assert len(s["tri"]) == K * len(meshes)
+    for r, o in enumerate(meshes):
+        tri = s["tri"][r * K:(r + 1) * K]
+        assert np.all(obj[tri] == o)
+        sel = (q > 0) & (obj == o)
+        counts = np.bincount(tri, minlength=len(q))[sel]
+        expect = q[sel] / q[sel].sum() * K
+        big = expect >= 5
+        ob, ex = counts[big], expect[big]
+        if (~big).any():
+            ob, ex = np.append(ob, counts[~big].sum()), np.append(ex, expect[~big].sum())
+        assert chisquare(ob, ex).pvalue > 1e-4
+    # a single mesh: the per-mesh sampler is the global one
+    one = dict(scene, tri_object=np.zeros_like(obj), n_objects=1)
+    a = O.diffraction(one, sim, C, certify=False)
+    b = O.diffraction(one, dict(sim, diff_per_mesh=False), C, certify=False)
+    assert np.array_equal(a["tri"], b["tri"]) and np.array_equal(a["o"], b["o"])
+    # at most two meshes: the first two by object id
+    c = O.diffraction(scene, dict(sim, diff_max_meshes=2), C, certify=False)
+    assert c["truncated"] and len(c["tri"]) == 2 * K
+    assert np.array_equal(c["tri"], s["tri"][:2 * K])
+
+
 # ---------------------------------------------------------------------------------------- adjoint
 
 def _loss(rec, sim, Hstar):
