@@ -127,9 +127,14 @@ enum {
   ET_SPECULAR = 1u << 0,      /* trace rays (Algorithm 1) and synthesise their records */
   ET_DIFFRACTION = 1u << 1,   /* draw diff_K curvature-importance samples (Sec. III-D) */
   ET_SYNTH_DIRECT = 1u << 2,  /* force the per-term synthesis and adjoint kernels (no factorised MFMA path) */
-  ET_PASSIVE = 1u << 3        /* passive component: direct emitter -> receiver path per receiver,
+  ET_PASSIVE = 1u << 3,       /* passive component: direct emitter -> receiver path per receiver,
                                  P(f) = L_geo L_atm I_p e^{j omega r / c} (Eqs. 11-13), with a
                                  line-of-sight test from the emitter to each receiver */
+  ET_DIFF_PER_MESH = 1u << 4  /* with ET_DIFFRACTION: diff_K candidates for every mesh (object)
+                                 with eligible triangles, each from the mesh's own curvature CDF
+                                 (Sec. III-D); meshes in increasing object order, draws numbered
+                                 mesh-major; at most diff_max_meshes meshes (more: the first ones,
+                                 and ET_E_CAPACITY at et_get_stats) */
 };
 
 typedef struct {
@@ -163,8 +168,10 @@ typedef struct {
   double diff_tau;              /* eligibility: C_i >= tau * max C */
   double diff_max_incidence;    /* incidence limit between normal and source direction */
   double diff_cone_half_angle;  /* emitter field of view for object eligibility */
-  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT | ET_PASSIVE */
+  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT | ET_PASSIVE | ET_DIFF_PER_MESH */
   const float* passive_coef;    /* device [Bk] source magnitude I_p per band (ET_PASSIVE), >= 0 */
+  int64_t diff_max_meshes;      /* ET_DIFF_PER_MESH: meshes that may receive candidates (sizes the
+                                   records and workspace: diff_K * diff_max_meshes draws) */
 } et_sim_desc;
 
 /* Path records (hit buffer B of Algorithm 1 plus diffraction points and the passive

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libechotrace.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "echotrace.h")
 
-ET_SPECULAR, ET_DIFFRACTION, ET_SYNTH_DIRECT, ET_PASSIVE = 1, 2, 4, 8
+ET_SPECULAR, ET_DIFFRACTION, ET_SYNTH_DIRECT, ET_PASSIVE, ET_DIFF_PER_MESH = 1, 2, 4, 8, 16
 STATUS = {0: "ET_OK", -1: "ET_E_INVALID", -2: "ET_E_WORKSPACE", -3: "ET_E_CAPACITY", -4: "ET_E_DEVICE",
           -5: "ET_E_UNSUPPORTED", -6: "ET_E_INTERNAL"}
 
@@ -50,7 +50,7 @@ class SimDesc(C.Structure):
                 ("lobe_beta", C.c_void_p), ("diff_coef", C.c_void_p), ("Bd", C.c_int32), ("El", C.c_int32),
                 ("Az", C.c_int32), ("directivity", C.c_void_p), ("diff_K", C.c_int64), ("diff_seed", C.c_uint64),
                 ("diff_tau", C.c_double), ("diff_max_incidence", C.c_double), ("diff_cone_half_angle", C.c_double),
-                ("flags", C.c_uint32), ("passive_coef", C.c_void_p)]
+                ("flags", C.c_uint32), ("passive_coef", C.c_void_p), ("diff_max_meshes", C.c_int64)]
 
 
 class PathsDesc(C.Structure):
@@ -302,7 +302,8 @@ class Sim:
         self.passive_coef = None if pc is None else _to_dev(pc, torch.float32)
         if flags is None:
             flags = (ET_SPECULAR | (ET_DIFFRACTION if sim.get("diff_K", 0) > 0 else 0)
-                     | (ET_PASSIVE if pc is not None else 0))
+                     | (ET_PASSIVE if pc is not None else 0)
+                     | (ET_DIFF_PER_MESH if sim.get("diff_per_mesh", False) else 0))
         d = SimDesc()
         d.emitter_pos[:] = [float(x) for x in np.asarray(sim["emitter_pos"], float)]
         d.emitter_rot[:] = [float(x) for x in np.asarray(sim["emitter_rot"], float).ravel()]
@@ -324,6 +325,7 @@ class Sim:
         d.diff_max_incidence = float(np.radians(sim.get("diff_max_incidence_deg", 80.0)))
         d.diff_cone_half_angle = float(np.radians(sim.get("diff_cone_half_angle_deg", 90.0)))
         d.flags = int(flags)
+        d.diff_max_meshes = int(sim.get("diff_max_meshes", 1))
         self.desc = d
         self.refresh()
 
@@ -344,11 +346,15 @@ class Sim:
         return self.desc.F
 
     def capacity(self) -> int:
+        """Records a trace can produce at most (sizes Paths)."""
+        d = self.desc
         n = 0
-        if self.desc.flags & ET_SPECULAR:
-            n += self.desc.N * self.desc.max_bounces
-        if self.desc.flags & ET_DIFFRACTION:
-            n += self.desc.diff_K
+        if d.flags & ET_SPECULAR:
+            n += d.N * d.max_bounces
+        if d.flags & ET_DIFFRACTION:
+            n += d.diff_K * (d.diff_max_meshes if d.flags & ET_DIFF_PER_MESH else 1)
+        if d.flags & ET_PASSIVE:
+            n += d.M
         return max(n, 1)
 
 

@@ -91,6 +91,10 @@ void validate_sim(const et_sim_desc* s, bool need_rays) {
     ET_CHECK(std::isfinite(s->t_eps) && s->t_eps >= 0, ET_E_INVALID, "t_eps must be finite and >= 0");
     if (s->flags & ET_DIFFRACTION) {
       ET_CHECK(s->diff_K >= 0 && s->diff_K < (int64_t)1 << 31, ET_E_INVALID, "diff_K out of range");
+      if (s->flags & ET_DIFF_PER_MESH)
+        ET_CHECK(s->diff_max_meshes >= 1 && s->diff_max_meshes < (int64_t)1 << 31 &&
+                     s->diff_K * s->diff_max_meshes < (int64_t)1 << 31,
+                 ET_E_INVALID, "per-mesh diffraction needs 1 <= diff_max_meshes and diff_K * diff_max_meshes < 2^31");
       ET_CHECK(std::isfinite(s->diff_tau) && std::isfinite(s->diff_max_incidence) &&
                    std::isfinite(s->diff_cone_half_angle),
                ET_E_INVALID, "diffraction parameters not finite");
@@ -106,10 +110,16 @@ void validate_paths(const et_paths* p) {
            ET_E_INVALID, "a path array is NULL");
 }
 
+// Diffraction draws at most: diff_K, or diff_K per mesh for at most diff_max_meshes meshes.
+int64_t diff_draws_max(const et_sim_desc* s) {
+  if (!(s->flags & ET_DIFFRACTION)) return 0;
+  return s->diff_K * ((s->flags & ET_DIFF_PER_MESH) ? s->diff_max_meshes : 1);
+}
+
 int64_t records_upper_bound(const et_sim_desc* s) {
   int64_t n = 0;
   if (s->flags & ET_SPECULAR) n += s->N * (int64_t)s->max_bounces;
-  if (s->flags & ET_DIFFRACTION) n += s->diff_K;
+  n += diff_draws_max(s);
   if (s->flags & ET_PASSIVE) n += s->M;
   return n;
 }
@@ -137,7 +147,7 @@ struct WsPlan {
 WsPlan plan(const et_scene* sc, const et_sim_desc* s, int64_t cap) {
   WsPlan w;
   const int64_t N = (s->flags & ET_SPECULAR) ? s->N : 0;
-  const int64_t K = (s->flags & ET_DIFFRACTION) ? s->diff_K : 0;
+  const int64_t K = diff_draws_max(s);
   if (sc) w.trace = al(trace_ws_layout(N, sc->d.T, sc->d.n_obj, K, nullptr, nullptr));
   w.synth = al(synth_ws_layout(s, cap, nullptr, nullptr));
   w.bwd = al(synth_bwd_ws_layout(s, cap, nullptr, nullptr));
@@ -185,8 +195,8 @@ void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* w
   ET_CHECK(ws || w.trace == 0, ET_E_INVALID, "workspace is NULL");
   ET_CHECK(ws_bytes >= w.trace, ET_E_WORKSPACE, "workspace too small for et_trace");
   TraceWS tw;
-  trace_ws_layout((sim->flags & ET_SPECULAR) ? sim->N : 0, sc->d.T, sc->d.n_obj,
-                  (sim->flags & ET_DIFFRACTION) ? sim->diff_K : 0, (char*)ws, &tw);
+  trace_ws_layout((sim->flags & ET_SPECULAR) ? sim->N : 0, sc->d.T, sc->d.n_obj, diff_draws_max(sim), (char*)ws,
+                  &tw);
   ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
   trace_run(sc->d, sim, paths, tw, ctx->ctl, ctx->counting, ctx->stream);
   ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
@@ -504,7 +514,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     const WsPlan w = plan(jobs[j].scene, s, cap);
     TraceWS tw;
     trace_ws_layout((s->flags & ET_SPECULAR) ? s->N : 0, jobs[j].scene->d.T, jobs[j].scene->d.n_obj,
-                    (s->flags & ET_DIFFRACTION) ? s->diff_K : 0, (char*)ws, &tw);
+                    diff_draws_max(s), (char*)ws, &tw);
     trace_run(jobs[j].scene->d, s, &P, tw, ctx->ctl, false, ctx->stream);
     k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
     SynthWS sw;

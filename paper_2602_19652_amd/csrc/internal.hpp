@@ -151,6 +151,8 @@ struct Ctl {
   int64_t cnt[6];            // traversal work counters (nodes/tris closest, nodes/tris any, rays c/a)
   int64_t n_rec;             // records to synthesise
   int64_t n_vis;             // of which visible (compacted index list)
+  int64_t n_groups;          // diffraction CDF groups (1, or the meshes with eligible triangles)
+  int64_t n_draw;            // diffraction draws (K, or K per mesh)
 };
 
 struct TraceWS {
@@ -185,6 +187,8 @@ struct TraceWS {
   double* sr;
   uint64_t* skeep;
   uint64_t* soffs;
+  uint64_t* goffs;    // [T] group ranks (per-mesh CDFs)
+  int64_t* gstart;    // [T + 1] first sorted position of each group
 };
 
 // Workspace layout of et_trace.  base == nullptr: only computes the size.

@@ -493,8 +493,10 @@ struct DiffArgs {
   double tau;
   double cos_max;
   uint64_t seed;
-  int64_t K;
+  int64_t K;            // draws (per mesh with per_mesh)
   double t_eps;
+  int per_mesh;
+  int64_t max_meshes;
 };
 
 __global__ void k_obj_fov(SceneDev S, DiffArgs a, uint8_t* oel) {
@@ -540,22 +542,52 @@ __global__ void k_qweight(SceneDev S, DiffArgs a, const uint8_t* __restrict__ oe
   flag[t] = qq > 0 ? 1ull : 0ull;
 }
 
-__global__ void k_elig_keys(SceneDev S, const uint64_t* __restrict__ q, const uint64_t* __restrict__ flag,
+// Sort keys of the eligible triangles, listed in increasing index.  One CDF: weight
+// descending, then index ascending.  Per mesh: the mesh first, then weight descending; the
+// stable sort keeps increasing indices among equal weights.
+__global__ void k_elig_keys(SceneDev S, int per_mesh, const uint64_t* __restrict__ q, const uint64_t* __restrict__ flag,
                             const uint64_t* __restrict__ offs, uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= S.T || !flag[t]) return;
   const int64_t p = (int64_t)offs[t];
-  // ascending order of this key = weight descending, then index ascending
-  keys[p] = ((4294967296ull - q[t]) << 31) | (uint64_t)t;
+  keys[p] = per_mesh ? ((uint64_t)S.obj[t] << 32) | (4294967296ull - q[t])
+                     : ((4294967296ull - q[t]) << 31) | (uint64_t)t;
   vals[p] = (int32_t)t;
 }
 
 __global__ void k_elig_count(Ctl* ctl) { ctl->n_elig = (int64_t)ctl->tot[1]; }
 
-__global__ void k_sorted_q(const uint64_t* __restrict__ keys, const Ctl* ctl, uint64_t* __restrict__ qs) {
+__global__ void k_sorted_q(const uint64_t* __restrict__ keys, int per_mesh, const Ctl* ctl, uint64_t* __restrict__ qs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ctl->n_elig) return;
-  qs[i] = 4294967296ull - (keys[i] >> 31);
+  qs[i] = 4294967296ull - (per_mesh ? (keys[i] & 0xffffffffull) : (keys[i] >> 31));
+}
+
+// Group starts in the sorted list: a group per mesh (per_mesh), else one group.
+__global__ void k_group_flags(const uint64_t* __restrict__ keys, int per_mesh, const Ctl* ctl,
+                              uint64_t* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctl->n_elig) return;
+  flag[i] = (i == 0 || (per_mesh && (keys[i] >> 32) != (keys[i - 1] >> 32))) ? 1ull : 0ull;
+}
+
+__global__ void k_group_starts(const uint64_t* __restrict__ flag, const uint64_t* __restrict__ rank, const Ctl* ctl,
+                               int64_t* __restrict__ gstart) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ctl->n_elig && flag[i]) gstart[rank[i]] = i;
+}
+
+// Group count and draws; more meshes than max_meshes keeps the first ones and reports a
+// capacity error.
+__global__ void k_group_count(Ctl* ctl, DiffArgs a, int64_t* __restrict__ gstart) {
+  int64_t g = (int64_t)ctl->tot[2];
+  if (a.per_mesh && g > a.max_meshes) {
+    atomicOr(&ctl->err, DEV_ERR_CAPACITY);
+    g = a.max_meshes;
+  }
+  gstart[g] = ctl->n_elig;
+  ctl->n_groups = g;
+  ctl->n_draw = a.per_mesh ? a.K * g : (ctl->n_elig > 0 ? a.K : 0);
 }
 
 __global__ __launch_bounds__(BS) void k_diff_sample(SceneDev S, DiffArgs a, const uint64_t* __restrict__ W_ex,
@@ -569,21 +601,24 @@ __global__ __launch_bounds__(BS) void k_diff_sample(SceneDev S, DiffArgs a, cons
   st.glob = w.gstack + gtid;
   st.gstride = w.gstack_threads;
   st.overflow = 0;
-  const int64_t ne = ctl->n_elig;
-  const uint64_t total = ctl->tot[2];
+  const int64_t n_draw = ctl->n_draw;
   int64_t dummy0 = 0, dummy1 = 0, rays = 0;
-  for (int64_t k = gtid; k < a.K; k += stride) {
+  for (int64_t k = gtid; k < n_draw; k += stride) {
     uint64_t keep = 0;
     w.stri[k] = -1;
-    if (ne > 0) {
+    {
+      // this draw's group (its mesh, or the one CDF) and the group's running sums
+      const int64_t g = a.per_mesh ? k / a.K : 0;
+      const int64_t j0 = w.gstart[g], j1 = w.gstart[g + 1];
+      const uint64_t base = W_ex[j0], total = W_ex[j1 - 1] + qs[j1 - 1] - base;
       const uint64_t ks = a.seed ^ 2ull;
       const uint64_t U = splitmix(ks, 3ull * (uint64_t)k);
       const uint64_t idx = __umul64hi(U, total);
-      // first position whose inclusive prefix exceeds idx
-      int64_t lo = 0, hi = ne;
+      // first position of the group whose inclusive running sum exceeds idx
+      int64_t lo = j0, hi = j1;
       while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (W_ex[mid] + qs[mid] > idx) hi = mid; else lo = mid + 1;
+        if (W_ex[mid] + qs[mid] - base > idx) hi = mid; else lo = mid + 1;
       }
       const int32_t t = vals[lo];
       const double u1 = u01(splitmix(ks, 3ull * (uint64_t)k + 1ull)), u2 = u01(splitmix(ks, 3ull * (uint64_t)k + 2ull));
@@ -628,7 +663,8 @@ __global__ __launch_bounds__(BS) void k_diff_sample(SceneDev S, DiffArgs a, cons
 
 __global__ void k_diff_scatter(SceneDev S, DiffArgs a, TraceWS w, Ctl* ctl, et_paths P) {
   const int64_t base = ctl->rec_base;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.K; k += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t n_draw = ctl->n_draw;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_draw; k += (int64_t)gridDim.x * blockDim.x) {
     if (!w.skeep[k]) continue;
     const int64_t ri = base + (int64_t)w.soffs[k];
     if (ri >= P.capacity) { atomicOr(&ctl->err, DEV_ERR_CAPACITY); continue; }
@@ -748,6 +784,8 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
     x.sr = (double*)take(sizeof(double) * Km);
     x.skeep = (uint64_t*)take(sizeof(uint64_t) * Km);
     x.soffs = (uint64_t*)take(sizeof(uint64_t) * Km);
+    x.goffs = (uint64_t*)take(sizeof(uint64_t) * Tm);
+    x.gstart = (int64_t*)take(sizeof(int64_t) * (Tm + 1));
   }
   if (w) *w = x;
   return off;
@@ -859,19 +897,29 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     d.seed = sim->diff_seed;
     d.K = sim->diff_K;
     d.t_eps = sim->t_eps;
+    d.per_mesh = (sim->flags & ET_DIFF_PER_MESH) ? 1 : 0;
+    d.max_meshes = d.per_mesh ? sim->diff_max_meshes : 1;
+    const int64_t max_draw = d.K * d.max_meshes;
+    int obj_bits = 1;
+    while (obj_bits < 31 && ((int64_t)1 << obj_bits) < S.n_obj) ++obj_bits;
     k_obj_fov<<<nblk_full(S.n_obj), BS, 0, s>>>(S, d, w.oel);
     k_cmax<<<nblk_full(S.T), BS, 0, s>>>(S, w.oel, ctl);
     k_qweight<<<nblk_full(S.T), BS, 0, s>>>(S, d, w.oel, ctl, w.dq, w.dflags);
     scan_exclusive_u64(w.dflags, w.doffs, S.T, nullptr, S.T, &ctl->tot[1], w.scan_tmp, s);
-    k_elig_keys<<<nblk_full(S.T), BS, 0, s>>>(S, w.dq, w.dflags, w.doffs, w.dkeys, w.dvals);
+    k_elig_keys<<<nblk_full(S.T), BS, 0, s>>>(S, d.per_mesh, w.dq, w.dflags, w.doffs, w.dkeys, w.dvals);
     k_elig_count<<<1, 1, 0, s>>>(ctl);
-    radix_sort_u64(w.dkeys, w.dvals, 0, &ctl->n_elig, S.T, 64, w.sort_tmp, s);
+    radix_sort_u64(w.dkeys, w.dvals, 0, &ctl->n_elig, S.T, d.per_mesh ? 32 + obj_bits : 64, w.sort_tmp, s);
     // weights in sorted order, then their exclusive prefix sums (the CDF) and total
-    k_sorted_q<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, ctl, w.dq);
-    scan_exclusive_u64(w.dq, w.doffs, 0, &ctl->n_elig, S.T, &ctl->tot[2], w.scan_tmp, s);
-    k_diff_sample<<<nblk(d.K), BS, 0, s>>>(S, d, w.doffs, w.dq, w.dvals, w, ctl);
-    scan_exclusive_u64(w.skeep, w.soffs, d.K, nullptr, d.K, &ctl->tot[3], w.scan_tmp, s);
-    k_diff_scatter<<<nblk(d.K), BS, 0, s>>>(S, d, w, ctl, P);
+    k_sorted_q<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, d.per_mesh, ctl, w.dq);
+    scan_exclusive_u64(w.dq, w.doffs, 0, &ctl->n_elig, S.T, nullptr, w.scan_tmp, s);
+    // groups of the sorted list (meshes, or one) and the number of draws
+    k_group_flags<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, d.per_mesh, ctl, w.dflags);
+    scan_exclusive_u64(w.dflags, w.goffs, 0, &ctl->n_elig, S.T, &ctl->tot[2], w.scan_tmp, s);
+    k_group_starts<<<nblk_full(S.T), BS, 0, s>>>(w.dflags, w.goffs, ctl, w.gstart);
+    k_group_count<<<1, 1, 0, s>>>(ctl, d, w.gstart);
+    k_diff_sample<<<nblk(max_draw), BS, 0, s>>>(S, d, w.doffs, w.dq, w.dvals, w, ctl);
+    scan_exclusive_u64(w.skeep, w.soffs, 0, &ctl->n_draw, max_draw, &ctl->tot[3], w.scan_tmp, s);
+    k_diff_scatter<<<nblk(max_draw), BS, 0, s>>>(S, d, w, ctl, P);
     ET_HIP(hipGetLastError());
   }
   const int32_t n_passive = (sim->flags & ET_PASSIVE) ? sim->M : 0;

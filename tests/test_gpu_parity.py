@@ -211,22 +211,35 @@ def test_synthesis_isolation_room(et, ctx, room_small, direct):
 
 # ----------------------------------------------------------------------------- diffraction
 
-def test_diffraction_samples_match(et, ctx):
+def _diffraction_case(per_mesh, max_meshes=None):
     g = W.rng(31)
     scene = W.room_geometry(g, n_boxes=30, n_cyl=30)
     a_ref = W.median_triangle_area(scene)
     sim = W.make_sim(emitter_pos=[1.0, 4.0, 1.2], emitter_rot=np.eye(3), rx_pos=[[1.0, 4.02, 1.2]],
                      ray_dirs=np.zeros((0, 3)), max_bounces=1, f_lo=20e3, f_hi=100e3, F=256,
                      refl_k=np.full((16, 8), 0.8), lobe_beta=np.full((16, 8), 0.1), diff_coef=np.full((16, 8), 0.2),
-                     diff_K=8192, diff_seed=1234, diff_tau=0.1, diff_max_incidence_deg=80.0, diff_cone_half_angle_deg=90.0)
+                     diff_K=512 if per_mesh else 8192, diff_seed=1234, diff_tau=0.1, diff_max_incidence_deg=80.0,
+                     diff_cone_half_angle_deg=90.0, diff_per_mesh=per_mesh,
+                     diff_max_meshes=max_meshes or scene["n_objects"])
+    return scene, sim, a_ref
+
+
+@pytest.mark.parametrize("per_mesh", [False, True])
+def test_diffraction_samples_match(et, ctx, per_mesh):
+    """One CDF (diff_K draws) or a CDF per mesh (diff_K draws for each of the meshes with
+    eligible triangles, Sec. III-D): the GPU's kept samples against the oracle's."""
+    scene, sim, a_ref = _diffraction_case(per_mesh)
     _, C_ref = O.curvature(scene, a_ref)
     ref = O.diffraction(scene, sim, C_ref)
     sc = et.Scene(ctx, scene, area_ref=a_ref)
-    s = et.Sim(sim, flags=et.ET_DIFFRACTION)
+    s = et.Sim(sim, flags=et.ET_DIFFRACTION | (et.ET_DIFF_PER_MESH if per_mesh else 0))
     P = et.trace(ctx, sc, s)
     st = ctx.stats()
     gpu = P.to_host()
     assert st.diff_eligible == ref["n_elig"]
+    if per_mesh:
+        print(f"per-mesh: {len(ref['tri']) // sim['diff_K']} meshes x {sim['diff_K']} draws")
+        assert len(ref["tri"]) > sim["diff_K"] and not ref["truncated"]
     kept = np.nonzero(ref["keep"])[0]
     # GPU records: kept samples in sample order, ray field = sample index
     g_idx = gpu["ray"]
@@ -243,6 +256,26 @@ def test_diffraction_samples_match(et, ctx):
         assert gpu["tri"][i] == ref["tri"][k]
         assert np.array_equal(gpu["p"][i], ref["o"][k])          # same FP64 operations: bit-equal
         assert gpu["rtot"][i] == ref["r_src"][k]
+
+
+def test_diffraction_per_mesh_cap(et, ctx):
+    """More eligible meshes than diff_max_meshes: the first meshes keep their draws (the same
+    as without the cap) and the trace reports a capacity error."""
+    scene, sim, a_ref = _diffraction_case(True, max_meshes=3)
+    _, C_ref = O.curvature(scene, a_ref)
+    ref = O.diffraction(scene, sim, C_ref)
+    assert ref["truncated"] and len(ref["tri"]) == 3 * sim["diff_K"]
+    sc = et.Scene(ctx, scene, area_ref=a_ref)
+    s = et.Sim(sim, flags=et.ET_DIFFRACTION | et.ET_DIFF_PER_MESH)
+    P = et.trace(ctx, sc, s)
+    with pytest.raises(et.EchoError) as e:
+        ctx.stats()
+    assert e.value.status == -3
+    gpu = P.to_host()
+    kept = np.nonzero(ref["keep"] & ref["certified"])[0]
+    g_idx = gpu["ray"]
+    assert g_idx.max() < 3 * sim["diff_K"]
+    assert set(kept.tolist()) <= set(g_idx.tolist())
 
 
 # ----------------------------------------------------------------------------- adjoint
