@@ -250,6 +250,20 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
                             float* spectra, const float* grad_spectra, double* grad_k, double* grad_rx);
 int et_graph_reset(et_ctx* ctx);
 
+/* ------------------------------------------------------------------ several emitters
+ * Simultaneous sources (the paper's multi-emitter scenes): S emitters in one scene heard by
+ * one receiver array.  Propagation is linear, so the received spectrum is the sum of every
+ * emitter's (Eq. 6 summed over the sources): H_m = sum_s H_m^(s).  sims is an array of S
+ * descriptors that share rx_pos (the same device pointer), M, F, f_lo, f_hi and phase_sign;
+ * poses, rays, bounces, components (ET_SPECULAR, ET_DIFFRACTION, ET_PASSIVE) and materials may
+ * differ.  The emitters run as the jobs of a batch (fused when all are specular-only), each
+ * into its own spectra in the workspace, then one kernel sums them in emitter order, so the
+ * result is bit-reproducible.  spectra: device float [M][F][2]. */
+int et_emitters_workspace_size(et_ctx* ctx, const et_scene* scene, int32_t S, const et_sim_desc* sims,
+                               size_t* bytes);
+int et_simulate_emitters(et_ctx* ctx, const et_scene* scene, int32_t S, const et_sim_desc* sims, void* ws,
+                         size_t ws_bytes, float* spectra);
+
 /* ------------------------------------------------------------------ time domain
  * The step after the path: impulse responses from the spectra (Eqs. 5-6, 9-10, 13:
  * h = F^-1[H]) and received signals (Eq. 14: s = h * s_e).

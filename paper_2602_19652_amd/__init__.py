@@ -119,6 +119,8 @@ def lib():
             "et_scene_curvature": ([vp, vp, vp, vp], C.c_int),
             "et_scene_refit": ([vp, vp, vp, C.c_double], C.c_int),
             "et_eq_directions_workspace_size": ([i64, C.POINTER(sz)], C.c_int),
+            "et_emitters_workspace_size": ([vp, vp, i32, vp, C.POINTER(sz)], C.c_int),
+            "et_simulate_emitters": ([vp, vp, i32, vp, vp, sz, vp], C.c_int),
             "et_eq_directions": ([vp, i64, C.c_double, vp, sz, vp, i64, C.POINTER(i64)], C.c_int),
             "et_workspace_size": ([vp, vp, C.POINTER(SimDesc), C.POINTER(sz)], C.c_int),
             "et_trace": ([vp, vp, C.POINTER(SimDesc), vp, sz, C.POINTER(PathsDesc)], C.c_int),
@@ -504,6 +506,22 @@ def receiver_signal(ctx: Context, h: torch.Tensor, s_e: torch.Tensor, dt: float,
     out = torch.empty(M, n_t + L - 1, dtype=torch.float32, device=_dev())
     ctx.call("et_receiver_signal", M, n_t, _ptr(h), L, _ptr(s_e), float(dt), _ptr(buf), buf.numel(), _ptr(out))
     return out
+
+
+def simulate_emitters(ctx: Context, scene: Scene, sims: list, ws: Workspace | None = None,
+                      out: torch.Tensor | None = None):
+    """Spectra complex64 [M, F] of several simultaneous emitters (et_simulate_emitters): the
+    sum over the emitters of each one's spectra.  The Sim objects must share their receiver
+    tensor (rx_pos), M, F and the frequency grid."""
+    ws = ws or Workspace()
+    arr = (SimDesc * len(sims))(*[s.desc for s in sims])
+    n = C.c_size_t()
+    ctx.call("et_emitters_workspace_size", scene.h, len(sims), C.cast(arr, C.c_void_p), C.byref(n))
+    buf = ws.get(n.value)
+    M, F = sims[0].M, sims[0].F
+    out = out if out is not None else torch.empty(M, F, 2, dtype=torch.float32, device=_dev())
+    ctx.call("et_simulate_emitters", scene.h, len(sims), C.cast(arr, C.c_void_p), _ptr(buf), buf.numel(), _ptr(out))
+    return torch.view_as_complex(out)
 
 
 def eq_directions(ctx: Context, N: int, cone_half_angle: float = math.pi, ws: Workspace | None = None) -> torch.Tensor:

@@ -584,6 +584,54 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
   });
 }
 
+// Several simultaneous emitters over one scene and one receiver array: the emitters run as
+// the jobs of a batch (fused when all are specular-only) into per-emitter spectra in the
+// workspace, which one kernel sums in emitter order.
+size_t emitters_batch_bytes(et_ctx* ctx, int32_t S, const et_job* jobs) {
+  return batch_fused(S, jobs) ? fused_plan(ctx, S, jobs).total : sequential_bytes(S, jobs);
+}
+
+void emitters_check(const et_scene* scene, int32_t S, const et_sim_desc* sims) {
+  check_scene(scene);
+  ET_CHECK(S >= 1 && sims, ET_E_INVALID, "need S >= 1 emitters");
+  for (int e = 0; e < S; ++e) {
+    validate_sim(&sims[e], true);
+    const et_sim_desc& a = sims[0];
+    const et_sim_desc& b = sims[e];
+    ET_CHECK(b.M == a.M && b.F == a.F && b.f_lo == a.f_lo && b.f_hi == a.f_hi && b.phase_sign == a.phase_sign &&
+                 b.rx_pos == a.rx_pos,
+             ET_E_INVALID, "emitters must share the receivers (rx_pos), M, F, the frequency grid and the phase sign");
+  }
+}
+
+int et_emitters_workspace_size(et_ctx* ctx, const et_scene* scene, int32_t S, const et_sim_desc* sims,
+                               size_t* bytes) {
+  return guarded(ctx, [&] {
+    emitters_check(scene, S, sims);
+    ET_CHECK(bytes, ET_E_INVALID, "bytes is NULL");
+    std::vector<et_job> jobs(S);
+    for (int e = 0; e < S; ++e) jobs[e] = et_job{scene, &sims[e]};
+    *bytes = al(sizeof(float) * 2 * (size_t)S * sims[0].M * sims[0].F) + emitters_batch_bytes(ctx, S, jobs.data());
+  });
+}
+
+int et_simulate_emitters(et_ctx* ctx, const et_scene* scene, int32_t S, const et_sim_desc* sims, void* ws,
+                         size_t ws_bytes, float* spectra) {
+  return guarded(ctx, [&] {
+    emitters_check(scene, S, sims);
+    ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
+    std::vector<et_job> jobs(S);
+    for (int e = 0; e < S; ++e) jobs[e] = et_job{scene, &sims[e]};
+    const size_t per = al(sizeof(float) * 2 * (size_t)S * sims[0].M * sims[0].F);
+    const size_t need = per + emitters_batch_bytes(ctx, S, jobs.data());
+    ET_CHECK(ws && ws_bytes >= need, ET_E_WORKSPACE, "workspace too small for et_simulate_emitters");
+    ctx->timed = 0;
+    float* each = (float*)ws;
+    batch_impl(ctx, S, jobs.data(), (char*)ws + per, ws_bytes - per, each, nullptr, nullptr, nullptr, false);
+    sum_spectra(each, S, (int64_t)2 * sims[0].M * sims[0].F, spectra, ctx->stream);
+  });
+}
+
 int et_graph_reset(et_ctx* ctx) {
   return guarded(ctx, [&] {
     if (ctx->graph_exec) { ET_HIP(hipGraphExecDestroy(ctx->graph_exec)); ctx->graph_exec = nullptr; }

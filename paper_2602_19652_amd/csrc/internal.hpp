@@ -236,6 +236,9 @@ bool synth_factorised_ok(const et_sim_desc* sim);
 bool synth_bwd_factorised_ok(const et_sim_desc* sim);
 
 // ------------------------------------------------------------------ time domain (timedomain.hip)
+// out[i] = sum over j < J (in order) of in[j][i], i < n (synth.hip)
+void sum_spectra(const float* in, int32_t J, int64_t n, float* out, hipStream_t s);
+
 // ------------------------------------------------------------------ EQ ray sets (eq.hip)
 
 struct EqPlan {

@@ -1431,4 +1431,18 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
   return w.mf ? 1 : 2;
 }
 
+__global__ void k_sum_spectra(const float* __restrict__ in, int32_t J, int64_t n, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int32_t j = 0; j < J; ++j) acc += in[(size_t)j * n + i];
+    out[i] = acc;
+  }
+}
+
+void sum_spectra(const float* in, int32_t J, int64_t n, float* out, hipStream_t s) {
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
+  k_sum_spectra<<<grid, 256, 0, s>>>(in, J, n, out);
+  ET_HIP(hipGetLastError());
+}
+
 }  // namespace et

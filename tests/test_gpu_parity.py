@@ -509,3 +509,57 @@ def test_trace_with_eq_directions(et, ctx, tiny):
     mism = compare_traces(gpu, ref, ref["certified"])
     print(f"EQ rays {len(R)}: certified {ref['certified'].mean():.4f}, mismatches {mism}")
     assert mism == 0
+
+
+# ----------------------------------------------------------------------------- several emitters
+
+def _emitter_sims(sim, scene_rot_deg=(0.0, 12.0, -8.0), pos=((0, 0, 0), (0.0, 0.4, 0.15), (0.2, -0.3, -0.1))):
+    out = []
+    for a, p in zip(scene_rot_deg, pos):
+        c, s = math.cos(math.radians(a)), math.sin(math.radians(a))
+        out.append(dict(sim, emitter_pos=np.array(p, float), emitter_rot=np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])))
+    return out
+
+
+def test_emitters_sum_matches_oracle(et, ctx, tiny):
+    """Three simultaneous emitters (specular, fused batch): the spectra equal the sum of the
+    oracle's per-emitter spectra on each emitter's certified rays."""
+    scene, sim, _ = tiny
+    sims = _emitter_sims(sim)
+    H_ref = 0
+    gs = []
+    for se in sims:
+        ref = O.trace(scene, se)
+        dirs = se["ray_dirs"][ref["certified"]]
+        H_ref = H_ref + O.synth(O.trace(scene, se, dirs=dirs), se)
+        gs.append(et.Sim(se, ray_dirs=dirs))
+    for g in gs[1:]:
+        g.rx_pos = gs[0].rx_pos
+        g.refresh()
+    sc = et.Scene(ctx, scene)
+    H = et.simulate_emitters(ctx, sc, gs).cpu().numpy()
+    e = rel_l2(H, H_ref)
+    each = sum(et.simulate(ctx, sc, g).cpu().numpy().astype(np.complex128) for g in gs)
+    print(f"3 emitters: rel L2 vs oracle {e:.3e}, vs sum of single-emitter calls {rel_l2(H, each):.3e}")
+    assert e <= TOL
+    assert rel_l2(H, each) <= 1e-6
+
+
+def test_emitters_with_diffraction_and_passive(et, ctx, tiny):
+    """Emitters with diffraction and the passive component run job after job; the sum equals
+    the single-emitter calls, and mismatched receivers are rejected."""
+    scene, sim, _ = tiny
+    sims = _emitter_sims(dict(sim, diff_K=4096, diff_seed=3, diff_tau=0.05, passive_coef=np.full(8, 0.5, np.float32)))
+    gs = [et.Sim(se) for se in sims]
+    for g in gs[1:]:
+        g.rx_pos = gs[0].rx_pos
+        g.refresh()
+    sc = et.Scene(ctx, scene, area_ref=W.median_triangle_area(scene))
+    H = et.simulate_emitters(ctx, sc, gs).cpu().numpy()
+    each = sum(et.simulate(ctx, sc, g).cpu().numpy().astype(np.complex128) for g in gs)
+    print(f"3 emitters with diffraction + passive: rel L2 vs single calls {rel_l2(H, each):.3e}")
+    assert rel_l2(H, each) <= 1e-6
+    other = et.Sim(sims[1])
+    with pytest.raises(et.EchoError) as e:
+        et.simulate_emitters(ctx, sc, [gs[0], other])
+    assert e.value.status == -1
