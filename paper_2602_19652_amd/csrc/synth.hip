@@ -818,7 +818,7 @@ struct __align__(16) BwdBuf {
   double kinv2[256];         // per (material, band): 2 / k (0 where k = 0)
 };
 
-template <bool BATCH>
+template <bool BATCH, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                         ChunkTab ct, et_paths P, const int32_t* __restrict__ idx,
                                                         const Ctl* ctl, const float* __restrict__ g,
@@ -836,11 +836,11 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
-  // wave -> block of 16 rows; a tile of at most 32 rows (two blocks) gives each wave pair one
-  // block and each wave of a pair one of the stage's two record blocks
-  const bool split = nk1 <= 32;
-  const int rbw = split ? (wv & 1) : wv;
-  const int nbw = split ? (wv >> 1) : -1;
+  // wave -> block of 16 rows; SPLIT (a tile of at most 32 rows, two blocks) gives each wave
+  // pair one block and each wave of a pair one of the stage's two record blocks
+  constexpr int NB = SPLIT ? 1 : 2;              // record blocks of 16 per wave and stage
+  const int rbw = SPLIT ? (wv & 1) : wv;
+  const int nb0 = SPLIT ? (wv >> 1) : 0;
   // A operands: rows k1 = 16 rbw + lane % 16 of G, columns k2 = 4 ks + lane / 16, as Gauss forms
   float ga[3][16];
   const int r1g = rbw * 16 + (lane & 15);
@@ -874,33 +874,32 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0], BS68,
              &bb.Y[0][0][0], &bb.Y[1][0][0], BS68, wscr[wv]);
     __syncthreads();
-    floatx4 acc[6][2];
+    floatx4 acc[6][NB];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) acc[i][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) {
       const int kk = 4 * ks + (lane >> 4);
       const float w2 = (float)kk;
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        if (nbw >= 0 && nb != nbw) continue;
-        const int nn = nb * 16 + (lane & 15);
+      for (int j = 0; j < NB; ++j) {
+        const int nn = (nb0 + j) * 16 + (lane & 15);
         const float yr = bb.Y[0][nn][kk], yi = bb.Y[1][nn][kk];
         const float b0 = yr, b1 = yi - yr, b2 = yr + yi;
-        acc[0][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], b0, acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], b1, acc[1][nb], 0, 0, 0);
-        acc[2][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], b2, acc[2][nb], 0, 0, 0);
-        acc[3][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], w2 * b0, acc[3][nb], 0, 0, 0);
-        acc[4][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], w2 * b1, acc[4][nb], 0, 0, 0);
-        acc[5][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], w2 * b2, acc[5][nb], 0, 0, 0);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], b0, acc[0][j], 0, 0, 0);
+        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], b1, acc[1][j], 0, 0, 0);
+        acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], b2, acc[2][j], 0, 0, 0);
+        acc[3][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], w2 * b0, acc[3][j], 0, 0, 0);
+        acc[4][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], w2 * b1, acc[4][j], 0, 0, 0);
+        acc[5][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], w2 * b2, acc[5][j], 0, 0, 0);
       }
     }
-    // accumulator (nb, v) of lane l: row 16 rbw + 4 (l / 16) + v, record 16 nb + l % 16
+    // accumulator (j, v) of lane l: row 16 rbw + 4 (l / 16) + v, record 16 (nb0 + j) + l % 16
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      if (nbw >= 0 && nb != nbw) continue;
+    for (int j = 0; j < NB; ++j) {
+      const int nb = nb0 + j;
       const int n = nb * 16 + (lane & 15);
       const int r10 = rbw * 16 + (lane >> 4) * 4;   // this lane's four rows r10 .. r10 + 3
       const float4 x4r = *reinterpret_cast<const float4*>(&bb.X[0][n][r10]);
@@ -910,8 +909,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       float s1r = 0.f, s1i = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float zr = acc[0][nb][v] - acc[2][nb][v], zi = acc[0][nb][v] + acc[1][nb][v];
-        const float wr = acc[3][nb][v] - acc[5][nb][v], wi = acc[3][nb][v] + acc[4][nb][v];
+        const float zr = acc[0][j][v] - acc[2][j][v], zi = acc[0][j][v] + acc[1][j][v];
+        const float wr = acc[3][j][v] - acc[5][j][v], wi = acc[3][j][v] + acc[4][j][v];
         const float xr = xrv[v], xi = xiv[v];
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
         const float fr = frow0 + (float)(r10 + v) * df64;
@@ -934,7 +933,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       const float gc1 = __shfl(q.gc1, src);
       const float glx = __shfl(q.glx, src), gly = __shfl(q.gly, src), glz = __shfl(q.glz, src);
       double s1r = 0.0, s1i = 0.0;
-      const int ngroups = split ? 8 : 16;   // row groups of 4 written this stage
+      const int ngroups = SPLIT ? 8 : 16;   // row groups of 4 written this stage
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (j + 8 * h >= ngroups) continue;
@@ -1277,8 +1276,12 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);
-    k_synth_bwd_mfma<false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra, ws.gpart_x,
-                                                 ws.gpart_k);
+    if (sim->F / K2 <= 32)
+      k_synth_bwd_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra,
+                                                         ws.gpart_x, ws.gpart_k);
+    else
+      k_synth_bwd_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra,
+                                                          ws.gpart_x, ws.gpart_k);
   } else {
     dim3 grid(ws.gchunks, sim->M);
     const size_t shm = sizeof(float2) * (size_t)sim->F;
@@ -1415,7 +1418,10 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[2], s));
     if (w.mf_bwd) {
       dim3 grid(w.chunks_bwd, s0->M, w.T1);
-      k_synth_bwd_mfma<true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
+      if (s0->F / K2 <= 32)
+        k_synth_bwd_mfma<true, true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
+      else
+        k_synth_bwd_mfma<true, false><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
     } else {
       dim3 grid(w.chunks_bwd, s0->M);
       k_synth_bwd<true><<<grid, GB, sizeof(float2) * (size_t)s0->F, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,
