@@ -452,17 +452,31 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
 // and columns 32 h2 + [0, 32), Gauss forms built as the operands are loaded.
 template <int NK>
 __device__ inline void contract(const GaussBuf& buf, int kk0, int xrow0, int h2, int lane, floatx4 (&acc)[3][2][2]) {
+  const int cc = lane & 15;
+  // operands of step kq + 1 are read from LDS before the matrix products of step kq issue,
+  // so their latency hides behind those products
+  float nxr[2], nxi[2], nyr[2], nyi[2];
+  auto load = [&](int kq) {
+    const int rr = kk0 + 4 * kq + (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      nxr[i] = buf.X[0][rr][xrow0 + i * 16 + cc];
+      nxi[i] = buf.X[1][rr][xrow0 + i * 16 + cc];
+      nyr[i] = buf.Y[0][rr][h2 * 32 + i * 16 + cc];
+      nyi[i] = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
+    }
+  };
+  load(0);
 #pragma unroll
   for (int kq = 0; kq < NK; ++kq) {
-    const int rr = kk0 + 4 * kq + (lane >> 4), cc = lane & 15;
     float av[3][2], bv[3][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const float xr = buf.X[0][rr][xrow0 + i * 16 + cc], xi = buf.X[1][rr][xrow0 + i * 16 + cc];
-      const float yr = buf.Y[0][rr][h2 * 32 + i * 16 + cc], yi = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
+      const float xr = nxr[i], xi = nxi[i], yr = nyr[i], yi = nyi[i];
       av[0][i] = xr + xi; av[1][i] = xr; av[2][i] = xi;
       bv[0][i] = yr; bv[1][i] = yi - yr; bv[2][i] = yr + yi;
     }
+    if (kq + 1 < NK) load(kq + 1);
 #pragma unroll
     for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
@@ -948,8 +962,21 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         double sb = 0.0;
         if (b < a.Bk) {
           const int sg = st.bseg[b];
-          if (sg >= 0)
-            for (int r1 = st.s0[sg]; r1 < st.s1[sg]; ++r1) sb += (double)bb.R0[n][r1];
+          if (sg >= 0) {
+            // the band's rows in four interleaved FP32 partial sums (independent LDS reads),
+            // combined in a fixed order
+            const int e = st.s1[sg];
+            int r1 = st.s0[sg];
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+            for (; r1 + 4 <= e; r1 += 4) {
+              p0 += bb.R0[n][r1];
+              p1 += bb.R0[n][r1 + 1];
+              p2 += bb.R0[n][r1 + 2];
+              p3 += bb.R0[n][r1 + 3];
+            }
+            for (; r1 < e; ++r1) p0 += bb.R0[n][r1];
+            sb = (double)((p0 + p1) + (p2 + p3));
+          }
         }
         s0 += sb;
         double kvv = 0.0;

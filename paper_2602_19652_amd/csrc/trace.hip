@@ -241,6 +241,8 @@ __global__ void k_trace_init(Ctl* ctl, int64_t N) {
   ctl->cmax_bits = 0;
   ctl->n_elig = 0;
   ctl->diff_kept = 0;
+  ctl->n_groups = 0;
+  ctl->n_draw = 0;
   for (int i = 0; i < 4; ++i) ctl->tot[i] = 0;
   for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
 }
