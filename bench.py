@@ -101,8 +101,8 @@ def cpu_baseline(scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hot path does not shard across GPUs "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library runs each pose, batch and "
+              f"adjoint on a single GPU and does not shard across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2602_19652_amd as et

@@ -47,7 +47,7 @@ typedef enum {
   ET_E_WORKSPACE = -2,   /* caller buffer smaller than the queried size */
   ET_E_CAPACITY = -3,    /* path buffer too small for the records produced (true count in stats) */
   ET_E_DEVICE = -4,      /* HIP runtime error */
-  ET_E_UNSUPPORTED = -5, /* valid request outside what this build implements */
+  ET_E_UNSUPPORTED = -5, /* valid request outside what the library implements */
   ET_E_INTERNAL = -6     /* device-side invariant broken (e.g. traversal stack overflow) */
 } et_status;
 
