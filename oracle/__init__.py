@@ -84,15 +84,21 @@ def trace(scene: dict, sim: dict, dirs=None, certify: bool = True, kappa: float 
     n = C.c_int64(0)
     v = _f32(scene["vertices"]); t = _i32(scene["tris"]); m = _i32(scene["tri_material"])
     ep = _f64(sim["emitter_pos"]); er = _f64(sim["emitter_rot"]); xr = _f64(sim["x_ref"])
+    per_rx = bool(sim.get("per_rx_visibility", False))
+    rx = _f64(sim["rx_pos"])
+    rxvis = np.zeros(cap, np.uint64) if per_rx else None
     rc = L.orc_trace(C.c_int64(len(v)), C.c_int64(len(t)), _p(v), _p(t), _p(m), _p(ep), _p(er), C.c_int64(N), _p(dirs),
                      C.c_int32(B), C.c_double(sim["max_distance"]), _p(xr), C.c_double(sim["t_eps"]),
                      C.c_double(kappa if certify else 0.0), C.c_double(mu_g), C.c_int64(cap), C.byref(n),
                      _p(out["ray"]), _p(out["bounce"]), _p(out["tri"]), _p(out["mat"]), _p(out["p"]), _p(out["din"]),
-                     _p(out["dout"]), _p(out["rtot"]), _p(out["vis"]), _p(cert), _p(nseg))
+                     _p(out["dout"]), _p(out["rtot"]), _p(out["vis"]), _p(cert), _p(nseg),
+                     C.c_int32(len(rx)), _p(rx), _p(rxvis))
     if rc != 0:
         raise ValueError(f"orc_trace failed ({rc})")
     k = n.value
     res = {key: val[:k].copy() for key, val in out.items()}
+    if per_rx:
+        res["rxvis"] = rxvis[:k].copy()
     res["kind"] = np.zeros(k, np.uint8)
     res["certified"] = cert[:N].astype(bool)
     res["nseg"] = nseg[:N].copy()
@@ -101,7 +107,10 @@ def trace(scene: dict, sim: dict, dirs=None, certify: bool = True, kappa: float 
 
 def synth(rec: dict, sim: dict, bins=None, M_subset=None) -> np.ndarray:
     """Eqs. (2)-(4) and (7)-(8): complex spectra [M, nk] (complex128) by direct summation.
-    `bins` selects frequency indices (default all F); `M_subset` selects receivers."""
+    `bins` selects frequency indices (default all F); `M_subset` selects receivers.
+    sim["per_rx_visibility"]: per-receiver line of sight from rec["rxvis"] (bit m: receiver
+    m); sim["path_product"]: specular magnitudes as the product of k over the ray's
+    reflections so far (rec["ray"], rec["bounce"])."""
     L = lib()
     F = int(sim["F"])
     k_list = np.arange(F, dtype=np.int32) if bins is None else _i32(bins)
@@ -129,13 +138,19 @@ def synth(rec: dict, sim: dict, bins=None, M_subset=None) -> np.ndarray:
     Q, Bk = k.shape
     pc = sim.get("passive_coef")
     pc = None if pc is None else _f32(pc)
+    rxvis = None
+    if sim.get("per_rx_visibility", False):
+        rxvis = np.ascontiguousarray(rec["rxvis"], np.uint64) if n else np.zeros(1, np.uint64)
+    pp = bool(sim.get("path_product", False))
+    rray = _i32(rec["ray"]) if (pp and n) else (np.zeros(1, np.int32) if pp else None)
+    rbnc = _i32(rec["bounce"]) if (pp and n) else (np.zeros(1, np.int32) if pp else None)
     out = np.zeros((M, len(k_list), 2))
     rc = L.orc_synth(C.c_int64(n), _p(p), _p(dout), _p(rt), _p(mat), _p(kind), _p(vis), C.c_int32(M), _p(rx), _p(rr),
                      C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]), C.c_int32(F), C.c_int32(len(k_list)), _p(k_list),
                      C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
                      C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
                      _p(k), _p(b), _p(dc), C.c_int32(Bd), C.c_int32(El), C.c_int32(Az), _p(D), _p(pc), _p(rx_id),
-                     _p(out))
+                     _p(out), _p(rxvis), _p(rray), _p(rbnc), C.c_int(int(pp)))
     if rc != 0:
         raise ValueError(f"orc_synth failed ({rc})")
     return out[..., 0] + 1j * out[..., 1]
@@ -147,6 +162,8 @@ def grad(rec: dict, sim: dict, g: np.ndarray):
     L = lib()
     if sim.get("directivity") is not None:
         raise ValueError("gradient with directivity is not defined here")
+    if sim.get("path_product", False):
+        raise ValueError("gradient with the path-product reading is not defined here")
     F = int(sim["F"])
     rx = _f64(sim["rx_pos"])
     M = len(rx)
@@ -159,11 +176,12 @@ def grad(rec: dict, sim: dict, g: np.ndarray):
     vis = np.ascontiguousarray(rec.get("vis", np.ones(n, np.uint8)), np.uint8)
     pc = sim.get("passive_coef")
     pc = None if pc is None else _f32(pc)
+    rxvis = np.ascontiguousarray(rec["rxvis"], np.uint64) if sim.get("per_rx_visibility", False) else None
     rc = L.orc_grad(C.c_int64(n), _p(_f64(rec["p"])), _p(_f64(rec["dout"])), _p(_f64(rec["rtot"])), _p(_i32(rec["mat"])),
                     _p(kind), _p(vis), C.c_int32(M), _p(rx), C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]),
                     C.c_int32(F), C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
                     C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
-                    _p(k), _p(b), _p(dc), _p(pc), _p(gg), _p(gk), _p(gx))
+                    _p(k), _p(b), _p(dc), _p(pc), _p(gg), _p(gk), _p(gx), _p(rxvis))
     if rc != 0:
         raise ValueError(f"orc_grad failed ({rc})")
     return gk, gx

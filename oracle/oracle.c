@@ -219,9 +219,10 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
               double kappa, double mu_g, int64_t capacity,
               int64_t* n_rec, int32_t* rec_ray, int32_t* rec_bounce, int32_t* rec_tri, int32_t* rec_mat,
               double* rec_p, double* rec_din, double* rec_dout, double* rec_rtot, uint8_t* rec_vis,
-              uint8_t* ray_certified, int32_t* ray_nseg) {
+              uint8_t* ray_certified, int32_t* ray_nseg, int32_t M, const double* rx_pos, uint64_t* rec_rxvis) {
   (void)V;
   if (N < 0 || T < 0 || max_bounces < 1 || capacity < N * (int64_t)max_bounces) return -1;
+  if (rec_rxvis && (M < 1 || M > 64 || !rx_pos)) return -1;
   tri_t* tr = make_tris(T, verts, tris);
   const int B = max_bounces;
   /* per-ray fixed slots, compacted afterwards in (ray, bounce) order */
@@ -231,6 +232,7 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
   double* s_dout = (double*)malloc(sizeof(double) * 3 * (size_t)(N * B + 1));
   double* s_r = (double*)malloc(sizeof(double) * (size_t)(N * B + 1));
   uint8_t* s_vis = (uint8_t*)malloc((size_t)(N * B + 1));
+  uint64_t* s_rxvis = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(N * B + 1));
   int32_t* s_cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N + 1));
   v3 s = ld3d(emitter_pos);
   v3 xr = ld3d(x_ref);
@@ -254,12 +256,27 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
       v3 n = tr[h].n;
       v3 dr = sub(d, scl(n, 2.0 * dot(d, n)));              /* specular reflection */
       rtot = (j == 0) ? norm(sub(p, s)) : rtot + t;         /* path length to the hit */
-      /* line-of-sight ray from the hit point toward the receiver reference point */
-      v3 w = sub(xr, p);
-      double L = norm(w);
-      v3 dv = scl(w, 1.0 / L);
-      int blocked = any_hit(p, dv, tr, T, h, t_eps, L - t_eps);
-      if (certify && cert && anyhit_marginal(p, dv, tr, T, h, t_eps, L - t_eps, kappa)) cert = 0;
+      int blocked;
+      uint64_t bits = 0;
+      if (!rec_rxvis) {
+        /* line-of-sight ray from the hit point toward the receiver reference point */
+        v3 w = sub(xr, p);
+        double L = norm(w);
+        v3 dv = scl(w, 1.0 / L);
+        blocked = any_hit(p, dv, tr, T, h, t_eps, L - t_eps);
+        if (certify && cert && anyhit_marginal(p, dv, tr, T, h, t_eps, L - t_eps, kappa)) cert = 0;
+      } else {
+        /* per-receiver variant: one line-of-sight ray from the hit point to every receiver */
+        for (int32_t m = 0; m < M; ++m) {
+          v3 w = sub(ld3d(rx_pos + 3 * m), p);
+          double L = norm(w);
+          v3 dv = scl(w, 1.0 / L);
+          int bl = any_hit(p, dv, tr, T, h, t_eps, L - t_eps);
+          if (certify && cert && anyhit_marginal(p, dv, tr, T, h, t_eps, L - t_eps, kappa)) cert = 0;
+          if (!bl) bits |= 1ull << m;
+        }
+        blocked = bits == 0;
+      }
       int64_t slot = i * B + cnt;
       s_tri[slot] = (int32_t)h;
       st3(s_p + 3 * slot, p);
@@ -267,6 +284,7 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
       st3(s_dout + 3 * slot, dr);
       s_r[slot] = rtot;
       s_vis[slot] = (uint8_t)(!blocked);
+      s_rxvis[slot] = bits;
       ++cnt;
       if (isfinite(max_distance) && fabs(rtot - max_distance) < kappa * 0x1p-24 * fmax(1.0, rtot)) cert = 0;
       if (rtot >= max_distance) break;
@@ -291,11 +309,12 @@ int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, con
       memcpy(rec_dout + 3 * w, s_dout + 3 * slot, 3 * sizeof(double));
       rec_rtot[w] = s_r[slot];
       rec_vis[w] = s_vis[slot];
+      if (rec_rxvis) rec_rxvis[w] = s_rxvis[slot];
       ++w;
     }
   }
   *n_rec = w;
-  free(s_tri); free(s_p); free(s_din); free(s_dout); free(s_r); free(s_vis); free(s_cnt); free(tr);
+  free(s_tri); free(s_p); free(s_din); free(s_dout); free(s_r); free(s_vis); free(s_rxvis); free(s_cnt); free(tr);
   return 0;
 }
 
@@ -365,17 +384,52 @@ static pair_t pair_setup(v3 p, v3 dout, double rtot, int kind, v3 xm) {
   return q;
 }
 
+/* Path-product reading of the reflection magnitude (the alternative to "k of the hit
+ * triangle only"): a specular record at reflection n carries the product of k(T_j, band) over
+ * its ray's reflections j <= n.  kp[n][b] for specular records (others unused), from the
+ * records' ray and reflection indices: the specular records grouped by ray in increasing
+ * reflection order, running products along each ray. */
+typedef struct { int32_t ray, bounce; int64_t n; } rb_t;
+static int cmp_rb(const void* a, const void* b) {
+  const rb_t* x = (const rb_t*)a;
+  const rb_t* y = (const rb_t*)b;
+  if (x->ray != y->ray) return x->ray < y->ray ? -1 : 1;
+  return x->bounce < y->bounce ? -1 : (x->bounce > y->bounce);
+}
+static double* path_k_products(int64_t n_rec, const uint8_t* kind, const int32_t* mat, const int32_t* ray,
+                               const int32_t* bounce, int32_t Bk, const float* refl_k) {
+  double* kp = (double*)calloc((size_t)(n_rec > 0 ? n_rec : 1) * Bk, sizeof(double));
+  rb_t* list = (rb_t*)malloc(sizeof(rb_t) * (size_t)(n_rec > 0 ? n_rec : 1));
+  int64_t ns = 0;
+  for (int64_t n = 0; n < n_rec; ++n)
+    if (!kind || kind[n] == 0) { list[ns].ray = ray[n]; list[ns].bounce = bounce[n]; list[ns].n = n; ++ns; }
+  qsort(list, (size_t)ns, sizeof(rb_t), cmp_rb);
+  for (int64_t i = 0; i < ns; ++i) {
+    const int64_t n = list[i].n;
+    const int first = i == 0 || list[i - 1].ray != list[i].ray;
+    for (int b = 0; b < Bk; ++b) {
+      const double prev = first ? 1.0 : kp[list[i - 1].n * Bk + b];
+      kp[n * Bk + b] = prev * (double)refl_k[mat[n] * Bk + b];
+    }
+  }
+  free(list);
+  return kp;
+}
+
 int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* rtot, const int32_t* mat,
               const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos, const double* rx_rot,
               double f_lo, double f_hi, int32_t F, int32_t nk, const int32_t* k_list,
               double c, double A0, double A1, double p_s, int32_t sigma,
               int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
               int32_t Bd, int32_t El, int32_t Az, const float* directivity, const float* passive_coef,
-              const int32_t* rx_id, double* out) {
+              const int32_t* rx_id, double* out, const uint64_t* rxvis, const int32_t* rec_ray,
+              const int32_t* rec_bounce, int path_product) {
   if (M < 1 || F < 1 || nk < 1 || Q < 1 || Bk < 1) return -1;
   if (directivity && (Bd < 1 || El < 1 || Az < 1)) return -1;
+  if (path_product && (!rec_ray || !rec_bounce)) return -1;
   for (int64_t n = 0; n < n_rec; ++n)
     if (kind && kind[n] == 2 && !passive_coef) return -1;   /* passive records need I_p */
+  double* kp = path_product ? path_k_products(n_rec, kind, mat, rec_ray, rec_bounce, Bk, refl_k) : NULL;
   const double df = F > 1 ? (f_hi - f_lo) / (double)(F - 1) : 0.0;
   const int KB = 64;
   const int nkb = (nk + KB - 1) / KB;
@@ -388,10 +442,11 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
       memset(acc, 0, sizeof(acc));
       v3 xm = ld3d(rx_pos + 3 * m);
       double Dg[64];
+      const int gm = rx_id ? rx_id[m] : m;   /* receiver index of the full array */
       for (int64_t n = 0; n < n_rec; ++n) {
-        if (vis && !vis[n]) continue;
+        if (rxvis ? !((rxvis[n] >> gm) & 1ull) : (vis && !vis[n])) continue;
         int kd = kind ? kind[n] : 0;
-        if (kd == 2 && mat[n] != (rx_id ? rx_id[m] : m)) continue;   /* passive: its own receiver only */
+        if (kd == 2 && mat[n] != gm) continue;   /* passive: its own receiver only */
         v3 pn = ld3d(p + 3 * n);
         pair_t q = pair_setup(pn, kd == 0 ? ld3d(dout + 3 * n) : mk(1, 0, 0), rtot[n], kd, xm);
         if (directivity) {
@@ -411,7 +466,8 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
           double I;
           if (kd == 0) {
             double bt = (double)beta[mat[n] * Bk + b];
-            I = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt)) * (double)refl_k[mat[n] * Bk + b];
+            double kv = kp ? kp[n * Bk + b] : (double)refl_k[mat[n] * Bk + b];
+            I = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt)) * kv;
           } else if (kd == 1) {
             I = (double)diff_coef[mat[n] * Bk + b];
           } else {
@@ -431,6 +487,7 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
       }
     }
   }
+  free(kp);
   return 0;
 }
 
@@ -440,7 +497,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const float* passive_coef, const double* g, double* grad_k, double* grad_x) {
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis) {
   if (M < 1 || F < 1 || Q < 1 || Bk < 1 || Bk > 64) return -1;
   for (int64_t n = 0; n < n_rec; ++n)
     if (kind && kind[n] == 2 && !passive_coef) return -1;   /* passive records need I_p */
@@ -454,7 +511,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
     v3 gx = mk(0, 0, 0);
     double* gk = gk_m + (size_t)m * Q * Bk;
     for (int64_t n = 0; n < n_rec; ++n) {
-      if (vis && !vis[n]) continue;
+      if (rxvis ? !((rxvis[n] >> m) & 1ull) : (vis && !vis[n])) continue;
       int kd = kind ? kind[n] : 0;
       if (kd == 2 && mat[n] != m) continue;   /* passive: its own receiver only */
       v3 pn = ld3d(p + 3 * n);

@@ -28,36 +28,45 @@ extern "C" {
 /* Algorithm 1 (with the readings listed in the design notes): brute-force FP64
  * closest-hit tracing of N rays, per-hit visibility ray toward x_ref, and the
  * per-segment margin predicate that certifies a ray as free of near-ties.
- * Records are written in (ray, bounce) order; capacity must be >= N*B. */
+ * Records are written in (ray, bounce) order; capacity must be >= N*B.  With rec_rxvis
+ * (non-NULL; 1 <= M <= 64 receivers at rx_pos) the visibility ray toward x_ref is replaced by
+ * one line-of-sight ray to each receiver: bit m of rec_rxvis[n] says receiver m sees the
+ * point, rec_vis[n] whether any does. */
 int orc_trace(int64_t V, int64_t T, const float* verts, const int32_t* tris, const int32_t* tri_mat,
               const double* emitter_pos, const double* emitter_rot, int64_t N, const float* dirs,
               int32_t max_bounces, double max_distance, const double* x_ref, double t_eps,
               double kappa, double mu_g, int64_t capacity,
               int64_t* n_rec, int32_t* rec_ray, int32_t* rec_bounce, int32_t* rec_tri, int32_t* rec_mat,
               double* rec_p, double* rec_din, double* rec_dout, double* rec_rtot, uint8_t* rec_vis,
-              uint8_t* ray_certified, int32_t* ray_nseg);
+              uint8_t* ray_certified, int32_t* ray_nseg, int32_t M, const double* rx_pos, uint64_t* rec_rxvis);
 
 /* Eqs. (2)-(4) and (7)-(8): direct spectral sum over records for the listed bins.
  * kind[n] = 0 specular (uses dout, lobe, refl_k), 1 diffraction (uses diff_coef),
  * 2 passive (the emitter itself as the point, rtot 0, passive_coef [Bk]; it reaches only
  * the receiver whose id equals mat[n]; rx_id[m] gives the ids of the rx_pos rows, NULL
- * for 0..M-1).  Records with vis[n]==0 contribute nothing.  out is [M][nk][2] (re, im). */
+ * for 0..M-1).  Records with vis[n]==0 contribute nothing; with rxvis (per-receiver line of
+ * sight, bit r for receiver id r) record n reaches receiver id r only when that bit is set.
+ * path_product: a specular record's reflection magnitude is the product of k over its ray's
+ * reflections up to it (rec_ray, rec_bounce identify them) instead of its own triangle's k.
+ * out is [M][nk][2] (re, im). */
 int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* rtot, const int32_t* mat,
               const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos, const double* rx_rot,
               double f_lo, double f_hi, int32_t F, int32_t nk, const int32_t* k_list,
               double c, double A0, double A1, double p_s, int32_t sigma,
               int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
               int32_t Bd, int32_t El, int32_t Az, const float* directivity, const float* passive_coef,
-              const int32_t* rx_id, double* out);
+              const int32_t* rx_id, double* out, const uint64_t* rxvis, const int32_t* rec_ray,
+              const int32_t* rec_bounce, int path_product);
 
 /* Analytic gradient of L = sum_{m,k} |H_mk - H*_mk|^2 given g = H - H* ([M][F][2]),
  * with respect to refl_k [Q][Bk] and the receiver positions [M][3], over fixed records.
- * Receiver directivity is not an input of this gradient. */
+ * Receiver directivity and the path-product reading are not inputs of this gradient;
+ * rxvis as in orc_synth. */
 int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* rtot, const int32_t* mat,
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const float* passive_coef, const double* g, double* grad_k, double* grad_x);
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis);
 
 /* Passive component: line of sight from the emitter to each receiver (vis[M]) and whether
  * that decision is certified against FP32 traversal (certified[M], may be NULL). */

@@ -650,3 +650,71 @@ def test_eq_cap_discrepancy(N):
         share = float(np.sum(D @ ax >= math.cos(a))) / N
         worst = max(worst, abs(share - (1 - math.cos(a)) / 2))
     assert worst <= 0.35 / math.sqrt(N)
+
+
+# ----------------------------------------------------------------------------- alternative readings
+
+def test_path_product_between_parallel_walls():
+    """Path-product reading of the reflection magnitude: a ray bouncing along x between the
+    walls x = 10 (material 1, hit first) and x = 0 (material 0) carries, at its n-th record,
+    k1^ceil(n/2) k0^floor(n/2) times the literal value (k of the hit triangle only)."""
+    mb = W.MeshBuilder()
+    v, t = W.quad_grid_box([0, 0, 0], [10.0, 8.0, 3.0], 1)
+    xs = v[t].mean(axis=1)[:, 0]
+    for tri, xc in zip(t, xs):   # one object per triangle: material by the wall it lies on
+        mb.add(v[tri], np.array([[0, 1, 2]]), 1 if abs(xc - 10.0) < 1e-9 else 0)
+    scene = mb.build()
+    k0, k1 = 0.8, 0.55
+    sim = _sim(emitter_pos=[5.0, 4.3, 1.1], x_ref=[5.0, 4.3, 1.1], rx_pos=[[4.0, 4.3, 1.1]],
+               ray_dirs=[[1, 0, 0]], max_bounces=6, F=64,
+               refl_k=np.array([[k0] * 8, [k1] * 8]), lobe_beta=np.full((2, 8), 1e6),
+               diff_coef=np.full((2, 8), 0.1))
+    rec = O.trace(scene, sim)
+    assert len(rec["rtot"]) == 6 and list(rec["mat"]) == [1, 0, 1, 0, 1, 0]
+    for i in range(6):
+        one = {k: v[i:i + 1] for k, v in rec.items() if k not in ("certified", "nseg")}
+        one["vis"] = np.ones(1, np.uint8)
+        lit = O.synth(one, sim)
+        pp = O.synth(one, dict(sim, path_product=True))
+        # a single record alone has no earlier reflections of its ray in the list: literal value
+        np.testing.assert_allclose(pp, lit, rtol=1e-13)
+    full = {k: v for k, v in rec.items() if k not in ("certified", "nseg")}
+    full["vis"] = np.ones(6, np.uint8)
+    for n in range(6):
+        # spectra of the first n + 1 records minus the first n: record n alone, in context
+        def part(s, upto):
+            sub = {k: v[:upto] for k, v in full.items()}
+            return O.synth(sub, s) if upto else 0
+        lit_n = part(sim, n + 1) - part(sim, n)
+        pp_n = part(dict(sim, path_product=True), n + 1) - part(dict(sim, path_product=True), n)
+        kf0, kf1 = float(np.float32(k0)), float(np.float32(k1))   # the tables are FP32
+        want = kf1 ** math.ceil(n / 2) * kf0 ** (n // 2)
+        np.testing.assert_allclose(pp_n, want * lit_n, rtol=1e-10, atol=1e-18)
+
+
+def test_per_receiver_visibility_equals_reference_point_tests():
+    """Per-receiver line of sight: bit m of a record equals the reference-point test with
+    x_ref placed at receiver m; a screen in front of one receiver makes the bits differ, and the
+    spectrum of receiver m uses exactly the records its bit admits."""
+    mb = W.MeshBuilder()
+    mb.add(np.array([[4, -3, -2], [4, 3, -2], [4, 3, 2], [4, -3, 2]], float), np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    mb.add(np.array([[1.5, 0.05, -0.6], [1.5, 0.8, -0.6], [1.5, 0.8, 0.6], [1.5, 0.05, 0.6]], float),
+           np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    scene = mb.build()
+    g = W.rng(4)
+    rx = np.array([[0.0, 0.3, 0.0], [0.0, -0.3, 0.0]])
+    sim = _sim(emitter_pos=[0, 0, 0], rx_pos=rx, ray_dirs=W.cone_directions(g, 4000, math.radians(30)),
+               max_bounces=2, F=64, refl_k=np.full((1, 8), 0.9), lobe_beta=np.full((1, 8), 0.3),
+               diff_coef=np.full((1, 8), 0.1), per_rx_visibility=True)
+    per = O.trace(scene, sim)
+    bits = per["rxvis"]
+    for m in range(2):
+        lit = O.trace(scene, dict(sim, per_rx_visibility=False, x_ref=rx[m]))
+        assert np.array_equal(lit["ray"], per["ray"]) and np.array_equal(lit["bounce"], per["bounce"])
+        assert np.array_equal(((bits >> np.uint64(m)) & np.uint64(1)).astype(np.uint8), lit["vis"])
+        H_per = O.synth(per, sim, M_subset=[m])
+        H_lit = O.synth(lit, dict(sim, per_rx_visibility=False), M_subset=[m])
+        np.testing.assert_allclose(H_per, H_lit, rtol=1e-12, atol=1e-20)
+    b0, b1 = bits & np.uint64(1), (bits >> np.uint64(1)) & np.uint64(1)
+    assert np.any(b0 != b1)
+    assert np.array_equal(per["vis"], ((b0 | b1) > 0).astype(np.uint8))

@@ -222,7 +222,7 @@ def make_sim(*, emitter_pos, emitter_rot, rx_pos, ray_dirs, max_bounces, f_lo, f
              c=C_SOUND, atm_a0=0.0, atm_a1=A1_DB_PER_M_HZ, spreading_p=2.0, phase_sign=1,
              diff_K=0, diff_seed=0, diff_tau=0.1, diff_max_incidence_deg=80.0,
              diff_cone_half_angle_deg=90.0, x_ref=None, t_eps=1e-5, passive_coef=None, diff_per_mesh=False,
-             diff_max_meshes=1) -> dict:
+             diff_max_meshes=1, path_product=False, per_rx_visibility=False) -> dict:
     rx_pos = np.ascontiguousarray(np.asarray(rx_pos, dtype=np.float64).reshape(-1, 3))
     M = len(rx_pos)
     if rx_rot is None:
@@ -248,6 +248,7 @@ def make_sim(*, emitter_pos, emitter_rot, rx_pos, ray_dirs, max_bounces, f_lo, f
         "diff_max_incidence_deg": float(diff_max_incidence_deg),
         "diff_cone_half_angle_deg": float(diff_cone_half_angle_deg),
         "diff_per_mesh": bool(diff_per_mesh), "diff_max_meshes": int(diff_max_meshes),
+        "path_product": bool(path_product), "per_rx_visibility": bool(per_rx_visibility),
         "passive_coef": None if passive_coef is None else np.ascontiguousarray(np.asarray(passive_coef, np.float32)),
     }
 
