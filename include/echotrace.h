@@ -130,11 +130,22 @@ enum {
   ET_PASSIVE = 1u << 3,       /* passive component: direct emitter -> receiver path per receiver,
                                  P(f) = L_geo L_atm I_p e^{j omega r / c} (Eqs. 11-13), with a
                                  line-of-sight test from the emitter to each receiver */
-  ET_DIFF_PER_MESH = 1u << 4  /* with ET_DIFFRACTION: diff_K candidates for every mesh (object)
+  ET_DIFF_PER_MESH = 1u << 4, /* with ET_DIFFRACTION: diff_K candidates for every mesh (object)
                                  with eligible triangles, each from the mesh's own curvature CDF
                                  (Sec. III-D); meshes in increasing object order, draws numbered
                                  mesh-major; at most diff_max_meshes meshes (more: the first ones,
                                  and ET_E_CAPACITY at et_get_stats) */
+  ET_PATH_PRODUCT = 1u << 5,  /* alternative reading of Eq. (2): a specular record's magnitude uses
+                                 the product of k over its ray's reflections up to it (the default
+                                 uses its own triangle's k).  et_trace fills paths->prev; synthesis
+                                 needs it.  Not differentiable here (the adjoint reports
+                                 ET_E_UNSUPPORTED).  Records of one pose < 2^31. */
+  ET_PER_RX_VISIBILITY = 1u << 6  /* alternative reading of Algorithm 1's visibility ray: one line of
+                                 sight from every hit to every receiver (M <= 64) instead of one
+                                 toward x_ref; et_trace fills paths->rx_vis (bit m: receiver m sees
+                                 the point); synthesis and adjoint pair a record with receiver m
+                                 only when its bit is set.  Diffraction records have every bit set
+                                 (no receiver-side test), passive ones their own receiver's. */
 };
 
 typedef struct {
@@ -192,9 +203,12 @@ typedef struct {
   int32_t* mat;       /* [cap] material of the triangle */
   int32_t* ray;       /* [cap] ray index (specular) or sample index (diffraction) */
   uint8_t* bounce;    /* [cap] reflection index within the ray */
-  uint8_t* flags;     /* [cap] bit0 visible (line of sight); bits 1-2 kind: 0 specular,
-                         1 diffraction, 2 passive */
+  uint8_t* flags;     /* [cap] bit0 visible (line of sight; with ET_PER_RX_VISIBILITY: seen by
+                         any receiver); bits 1-2 kind: 0 specular, 1 diffraction, 2 passive */
   int64_t* count;     /* device int64[4] */
+  int64_t* prev;      /* [cap] or NULL: index of the same ray's previous specular record, -1 at
+                         its first reflection (written when not NULL; ET_PATH_PRODUCT needs it) */
+  uint64_t* rx_vis;   /* [cap] or NULL: per-receiver line-of-sight bits (ET_PER_RX_VISIBILITY) */
 } et_paths;
 
 /* Workspace bytes for et_trace / et_synthesize / et_simulate with this descriptor. */

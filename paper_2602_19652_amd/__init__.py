@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libechotrace.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "echotrace.h")
 
 ET_SPECULAR, ET_DIFFRACTION, ET_SYNTH_DIRECT, ET_PASSIVE, ET_DIFF_PER_MESH = 1, 2, 4, 8, 16
+ET_PATH_PRODUCT, ET_PER_RX_VISIBILITY = 32, 64
 STATUS = {0: "ET_OK", -1: "ET_E_INVALID", -2: "ET_E_WORKSPACE", -3: "ET_E_CAPACITY", -4: "ET_E_DEVICE",
           -5: "ET_E_UNSUPPORTED", -6: "ET_E_INTERNAL"}
 
@@ -56,7 +57,7 @@ class SimDesc(C.Structure):
 class PathsDesc(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("p", C.c_void_p), ("dout", C.c_void_p), ("rtot", C.c_void_p),
                 ("tri", C.c_void_p), ("mat", C.c_void_p), ("ray", C.c_void_p), ("bounce", C.c_void_p),
-                ("flags", C.c_void_p), ("count", C.c_void_p)]
+                ("flags", C.c_void_p), ("count", C.c_void_p), ("prev", C.c_void_p), ("rx_vis", C.c_void_p)]
 
 
 class SceneInfo(C.Structure):
@@ -305,7 +306,9 @@ class Sim:
         if flags is None:
             flags = (ET_SPECULAR | (ET_DIFFRACTION if sim.get("diff_K", 0) > 0 else 0)
                      | (ET_PASSIVE if pc is not None else 0)
-                     | (ET_DIFF_PER_MESH if sim.get("diff_per_mesh", False) else 0))
+                     | (ET_DIFF_PER_MESH if sim.get("diff_per_mesh", False) else 0)
+                     | (ET_PATH_PRODUCT if sim.get("path_product", False) else 0)
+                     | (ET_PER_RX_VISIBILITY if sim.get("per_rx_visibility", False) else 0))
         d = SimDesc()
         d.emitter_pos[:] = [float(x) for x in np.asarray(sim["emitter_pos"], float)]
         d.emitter_rot[:] = [float(x) for x in np.asarray(sim["emitter_rot"], float).ravel()]
@@ -378,8 +381,11 @@ class Paths:
         self.bounce = torch.zeros(cap, dtype=torch.uint8, device=dev)
         self.flags = torch.zeros(cap, dtype=torch.uint8, device=dev)
         self.count = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.prev = torch.full((cap,), -1, dtype=torch.int64, device=dev)
+        self.rx_vis = torch.zeros(cap, dtype=torch.int64, device=dev)   # uint64 bits
         self.desc = PathsDesc(cap, *[_ptr(t).value for t in (self.p, self.dout, self.rtot, self.tri, self.mat, self.ray,
-                                                             self.bounce, self.flags, self.count)])
+                                                             self.bounce, self.flags, self.count, self.prev,
+                                                             self.rx_vis)])
 
     @classmethod
     def from_records(cls, rec: dict) -> "Paths":
@@ -396,6 +402,8 @@ class Paths:
             vis = np.asarray(rec.get("vis", np.ones(n)), np.uint8) & 1
             kind = np.asarray(rec.get("kind", np.zeros(n)), np.uint8) & 3
             P.flags[:n] = torch.as_tensor(vis | (kind << 1))
+            if "rxvis" in rec:
+                P.rx_vis[:n] = torch.as_tensor(np.asarray(rec["rxvis"], np.uint64).view(np.int64))
         P.count[0] = n
         P.count[1] = n
         return P
@@ -410,6 +418,7 @@ class Paths:
                 "rtot": self.rtot[:n].cpu().numpy(), "tri": self.tri[:n].cpu().numpy(), "mat": self.mat[:n].cpu().numpy(),
                 "ray": self.ray[:n].cpu().numpy(), "bounce": self.bounce[:n].cpu().numpy().astype(np.int32),
                 "vis": (fl & 1).astype(np.uint8), "kind": ((fl >> 1) & 3).astype(np.uint8),
+                "prev": self.prev[:n].cpu().numpy(), "rxvis": self.rx_vis[:n].cpu().numpy().view(np.uint64),
                 "count": self.count[:4].cpu().numpy()}
 
 

@@ -110,6 +110,18 @@ void validate_paths(const et_paths* p) {
            ET_E_INVALID, "a path array is NULL");
 }
 
+// The arrays the alternative readings need, for calls that write or read them.
+void validate_readings(const et_sim_desc* s, const et_paths* p) {
+  if (s->flags & ET_PATH_PRODUCT) {
+    ET_CHECK(p->capacity == 0 || p->prev, ET_E_INVALID, "ET_PATH_PRODUCT needs paths->prev");
+    ET_CHECK(p->capacity < ((int64_t)1 << 31), ET_E_UNSUPPORTED, "ET_PATH_PRODUCT needs fewer than 2^31 records");
+  }
+  if (s->flags & ET_PER_RX_VISIBILITY) {
+    ET_CHECK(p->capacity == 0 || p->rx_vis, ET_E_INVALID, "ET_PER_RX_VISIBILITY needs paths->rx_vis");
+    ET_CHECK(s->M <= 64, ET_E_UNSUPPORTED, "ET_PER_RX_VISIBILITY supports at most 64 receivers");
+  }
+}
+
 // Diffraction draws at most: diff_K, or diff_K per mesh for at most diff_max_meshes meshes.
 int64_t diff_draws_max(const et_sim_desc* s) {
   if (!(s->flags & ET_DIFFRACTION)) return 0;
@@ -126,8 +138,8 @@ int64_t records_upper_bound(const et_sim_desc* s) {
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
-size_t paths_bytes(int64_t cap) {
-  return al(cap * (24 + 12 + 8 + 4 + 4 + 4 + 1 + 1)) + al(8 * sizeof(int64_t)) + 8 * 256;
+size_t paths_bytes(int64_t cap) {   // the arrays of carve_paths, each aligned to 256 bytes
+  return al(cap * (24 + 12 + 8 + 4 + 4 + 4 + 1 + 1 + 8 + 8)) + al(8 * sizeof(int64_t)) + 10 * 256;
 }
 
 // A batch runs fused (all rays in shared bounce kernels, all records in shared synthesis
@@ -135,7 +147,7 @@ size_t paths_bytes(int64_t cap) {
 bool batch_fused(int32_t J, const et_job* jobs) {
   if (J > 65536) return false;   // the ray sort keys hold the job in 16 bits
   for (int32_t j = 0; j < J; ++j)
-    if (jobs[j].sim->flags & (ET_DIFFRACTION | ET_PASSIVE)) return false;
+    if (jobs[j].sim->flags & (ET_DIFFRACTION | ET_PASSIVE | ET_PATH_PRODUCT | ET_PER_RX_VISIBILITY)) return false;
   return true;
 }
 
@@ -191,6 +203,7 @@ void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* w
   check_scene(sc);
   validate_sim(sim, true);
   validate_paths(paths);
+  validate_readings(sim, paths);
   const WsPlan w = plan(sc, sim, std::max<int64_t>(paths->capacity, records_upper_bound(sim)));
   ET_CHECK(ws || w.trace == 0, ET_E_INVALID, "workspace is NULL");
   ET_CHECK(ws_bytes >= w.trace, ET_E_WORKSPACE, "workspace too small for et_trace");
@@ -208,6 +221,7 @@ void synth_impl(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void
                 bool from_trace) {
   validate_sim(sim, false);
   validate_paths(paths);
+  validate_readings(sim, paths);
   ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
   SynthWS sw;
   const size_t need = synth_ws_layout(sim, std::max<int64_t>(paths->capacity, 1), nullptr, nullptr);
@@ -405,8 +419,10 @@ int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* 
   return guarded(ctx, [&] {
     validate_sim(sim, false);
     validate_paths(paths);
+    validate_readings(sim, paths);
     ET_CHECK(grad_spectra && grad_k && grad_rx, ET_E_INVALID, "gradient pointer is NULL");
     ET_CHECK(!sim->directivity, ET_E_UNSUPPORTED, "the adjoint does not support receiver directivity");
+    ET_CHECK(!(sim->flags & ET_PATH_PRODUCT), ET_E_UNSUPPORTED, "the adjoint does not support ET_PATH_PRODUCT");
     ET_CHECK(sim->Bk <= 16 && sim->Q * sim->Bk <= 256, ET_E_UNSUPPORTED, "adjoint needs Bk <= 16 and Q*Bk <= 256");
     ET_CHECK(sim->F <= 12288, ET_E_UNSUPPORTED, "adjoint keeps dL/dH of one receiver in LDS: F <= 12288");
     SynthWS sw;
@@ -451,6 +467,8 @@ et_paths carve_paths(char*& p, int64_t cap) {
   P.bounce = (uint8_t*)take(cap);
   P.flags = (uint8_t*)take(cap);
   P.count = (int64_t*)take(8 * sizeof(int64_t));
+  P.prev = (int64_t*)take(sizeof(int64_t) * cap);
+  P.rx_vis = (uint64_t*)take(sizeof(uint64_t) * cap);
   return P;
 }
 
@@ -467,8 +485,10 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     ET_CHECK(s->M == s0->M && s->F == s0->F && s->Q == s0->Q && s->Bk == s0->Bk, ET_E_INVALID,
              "jobs of a batch must share M, F, Q and Bk");
     if (grad_spectra)
-      ET_CHECK(!s->directivity && s->Bk <= 16 && s->Q * s->Bk <= 256 && s->F <= 12288, ET_E_UNSUPPORTED,
-               "adjoint limits exceeded");
+      ET_CHECK(!s->directivity && !(s->flags & ET_PATH_PRODUCT) && s->Bk <= 16 && s->Q * s->Bk <= 256 &&
+                   s->F <= 12288,
+               ET_E_UNSUPPORTED, "adjoint limits exceeded");
+    if (s->flags & ET_PER_RX_VISIBILITY) ET_CHECK(s->M <= 64, ET_E_UNSUPPORTED, "ET_PER_RX_VISIBILITY: M <= 64");
   }
   if (grad_spectra) ET_CHECK(grad_k && grad_rx, ET_E_INVALID, "gradient outputs are NULL");
   size_t need = 0;

@@ -160,12 +160,13 @@ struct TraceWS {
   double* st[2][7];
   int32_t* prev[2];
   int32_t* ray[2];
+  int64_t* prec[2];          // record index of the ray's previous reflection (-1 before the first)
   // per-slot bounce results
   double* rp[3];
   double* rd[3];
   double* rr;
   int32_t* rpos;
-  uint8_t* rvis;
+  uint64_t* rvis;            // line of sight: 0/1, or receiver bits (per-receiver reading)
   uint64_t* flags;
   uint64_t* offs;
   void* scan_tmp;
@@ -221,6 +222,8 @@ struct SynthWS {
   float* lc;
   float* ld;
   float* lp;                 // [Bk] log2 I_p (passive component)
+  float* plk;                // [cap][Bk] path-product reading: log2 k over each record's path (or log2 I_d)
+  float* plc;                // [cap][Bk] path-product reading: each record's lobe coefficient
 };
 size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws);
 // returns 1 for the factorised MFMA kernel, 2 for the direct kernel

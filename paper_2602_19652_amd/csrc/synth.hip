@@ -58,6 +58,9 @@ struct SynthArgs {
   const float* ld;         // [Q][Bk] log2 I_d
   const float* pcoef;      // [Bk] passive source magnitude I_p (NULL without the passive component)
   const float* lp;         // [Bk] log2 I_p
+  int32_t rec_rows;        // 1 (path-product reading): lk, lc, ld have a row per record and a
+                           // record's `mat` in the kernels is its index; 0: a row per material
+  const uint64_t* rxv;     // per-receiver line of sight [records] (NULL: the records' visible bit)
 };
 
 SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
@@ -78,6 +81,8 @@ SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
   a.kbase = -(a.A0 + a.A1 * a.f_lo) / 20.0 * LOG2_10;
   a.kslope = -a.A1 * a.df / 20.0 * LOG2_10;
   a.pcoef = (sim->flags & ET_PASSIVE) ? sim->passive_coef : nullptr;
+  a.rec_rows = 0;
+  a.rxv = nullptr;
   return a;
 }
 
@@ -89,7 +94,7 @@ struct Pair {
   double r, l;
   double u[3];
   float gamma;
-  int mat;
+  int mat;           // row of the band tables: the material, or the record (rec_rows)
   int kind;
 };
 
@@ -120,6 +125,7 @@ __device__ inline float dir_gain(const float* tab, int El, int Az, float vx, flo
 __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t n, int m, Pair& q) {
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return false;
+  if (a.rxv && !((a.rxv[n] >> m) & 1ull)) return false;   // per-receiver line of sight
   q.kind = (fl >> 1) & 3;
   if (q.kind == 2 && P.mat[n] != m) return false;
   const double px = P.p[3 * n], py = P.p[3 * n + 1], pz = P.p[3 * n + 2];
@@ -132,7 +138,7 @@ __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t
   q.cb = sc * a.df;
   q.base = (float)(-a.ps * log2(q.r) - (a.A0 + a.A1 * a.f_lo) * q.r / 20.0 * LOG2_10);
   q.slope = (float)(-a.A1 * a.df * q.r / 20.0 * LOG2_10);
-  q.mat = P.mat[n];
+  q.mat = a.rec_rows ? (int)n : P.mat[n];
   q.gamma = 0.f;
   if (q.kind == 0) {
     const float dx = P.dout[3 * n], dy = P.dout[3 * n + 1], dz = P.dout[3 * n + 2];
@@ -146,7 +152,7 @@ __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t
 // log2 of the band factor: k exp(-gamma^2 / (2 beta^2)) (specular), I_d (diffraction) or
 // I_p (passive)
 __device__ inline float band_log2_v(const SynthArgs& a, int kind, int mat, float gamma, int b) {
-  const int i = mat * a.Bk + b;
+  const int64_t i = (int64_t)mat * a.Bk + b;
   return kind == 0 ? a.lk[i] - gamma * gamma * a.lc[i] : kind == 1 ? a.ld[i] : a.lp[b];
 }
 
@@ -164,7 +170,9 @@ __global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld, floa
   band_table_entry(a, i, lk, lc, ld, lp);
 }
 
-__device__ inline float band_log2(const SynthArgs& a, const Pair& q, int b) { return band_log2_v(a, q.kind, q.mat, q.gamma, b); }
+__device__ inline float band_log2(const SynthArgs& a, const Pair& q, int b) {
+  return band_log2_v(a, q.kind, q.mat, q.gamma, b);
+}
 
 // direction of arrival in the receiver frame: v = R_m^T (p - x_m) / l = -R_m^T u
 __device__ inline void arrival(const SynthArgs& a, const Pair& q, int m, float& vx, float& vy, float& vz) {
@@ -265,7 +273,7 @@ struct PairLean {
   uint32_t a32, bx32, by32;
   float base, slope, gamma;
   float vx, vy, vz;
-  int mat, kind;
+  int mat, kind;         // mat: row of the band tables (the material, or the record: rec_rows)
   // GRAD: receiver-gradient coefficients, d/dx_m of (ln A + j phi) = (c1 + c2 f + j c3 f) u - lobe
   float gux, guy, guz;   // u = (x_m - p) / l
   float gc1;             // -p / r - ln10 a0 / 20
@@ -284,6 +292,7 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   const int64_t n = idx[e];
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return;
+  if (a.rxv && !((a.rxv[n] >> m) & 1ull)) return;   // per-receiver line of sight
   const int kind = (fl >> 1) & 3;
   if (kind == 2 && P.mat[n] != m) return;   // a passive record reaches its own receiver only
   q.kind = kind;
@@ -297,7 +306,7 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   q.by32 = q32(cb);
   q.base = -(float)a.ps * log2f((float)r) + (float)(r * a.kbase);
   q.slope = (float)(r * a.kslope);
-  q.mat = P.mat[n];
+  q.mat = a.rec_rows ? (int)n : P.mat[n];
   const double il = 1.0 / l;
   const float ux = (float)(wx * il), uy = (float)(wy * il), uz = (float)(wz * il);
   if (q.kind == 0) {
@@ -1081,6 +1090,52 @@ void build_tables(SynthArgs& a, const SynthWS& ws, hipStream_t s) {
   k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld, ws.lp);
 }
 
+// Path-product reading: band tables with a row per record.  Specular record n: the sum of
+// log2 k over its ray's specular records up to n (itself and its predecessors through prev)
+// and its own lobe coefficient; a diffraction record: its material's log2 I_d.
+__global__ void k_path_tables(et_paths P, SynthArgs a, const Ctl* ctl, float* __restrict__ plk,
+                              float* __restrict__ plc) {
+  const int Bk = a.Bk;
+  const int64_t n_rec = ctl->n_rec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rec * Bk;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = i / Bk;
+    const int b = (int)(i - n * Bk);
+    const int kind = (P.flags[n] >> 1) & 3;
+    const int mat = P.mat[n];
+    float s = 0.f, lobe = 0.f;
+    if (kind == 0) {
+      lobe = a.lc[mat * Bk + b];
+      int64_t r = n;
+      for (int guard = 0; guard < 256 && r >= 0; ++guard) {   // a ray has at most 255 reflections
+        s += a.lk[P.mat[r] * Bk + b];
+        const int64_t pr = P.prev[r];
+        r = pr < r ? pr : -1;                                    // predecessors have smaller indices
+      }
+    } else if (kind == 1) {
+      s = a.ld[mat * Bk + b];
+    }
+    plk[i] = s;
+    plc[i] = lobe;
+  }
+}
+
+// Per-receiver line of sight and the path-product reading for one pose's synthesis.
+void set_readings(SynthArgs& a, const et_sim_desc* sim, const et_paths& P, const SynthWS& ws, Ctl* ctl,
+                  hipStream_t s) {
+  a.rxv = (sim->flags & ET_PER_RX_VISIBILITY) ? P.rx_vis : nullptr;
+  if (sim->flags & ET_PATH_PRODUCT) {
+    const int64_t n = ws.cap * sim->Bk;
+    k_path_tables<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)), 256, 0, s>>>(
+        P, a, ctl, ws.plk, ws.plc);
+    ET_HIP(hipGetLastError());
+    a.lk = ws.plk;
+    a.lc = ws.plc;
+    a.ld = ws.plk;
+    a.rec_rows = 1;
+  }
+}
+
 size_t table_ws(const et_sim_desc* sim, char* base, size_t off, SynthWS& w) {
   const size_t n = (size_t)sim->Q * sim->Bk;
   w.lk = (float*)(base ? base + off : nullptr);
@@ -1236,6 +1291,12 @@ size_t synth_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS*
   off += al(sizeof(float) * 2 * (size_t)P * sim->M * sim->F);
   off = vis_ws(cap, base, off, &w.vflags, &w.voffs, &w.vidx, &w.vscan);
   off = table_ws(sim, base, off, w);
+  if (sim->flags & ET_PATH_PRODUCT) {
+    w.plk = (float*)(base ? base + off : nullptr);
+    off += al(sizeof(float) * (size_t)cap * sim->Bk);
+    w.plc = (float*)(base ? base + off : nullptr);
+    off += al(sizeof(float) * (size_t)cap * sim->Bk);
+  }
   if (ws) *ws = w;
   return off;
 }
@@ -1247,6 +1308,7 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   const et_paths P = *paths;
   build_vis(P, ws, ws.cap, ctl, s);
   build_tables(a, ws, s);
+  set_readings(a, sim, P, ws, ctl, s);
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     const int K1 = sim->F / K2;
@@ -1300,6 +1362,7 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   const et_paths P = *paths;
   build_vis(P, ws, ws.cap, ctl, s);
   build_tables(a, ws, s);
+  a.rxv = (sim->flags & ET_PER_RX_VISIBILITY) ? P.rx_vis : nullptr;   // (no path product in the adjoint)
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);

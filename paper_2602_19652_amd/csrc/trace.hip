@@ -342,12 +342,15 @@ __global__ void k_ray_init(PoseArgs a0, const float* __restrict__ dirs0, const T
   w.st[0][6][i] = 0.0;
   w.prev[0][i] = -1;
   w.ray[0][i] = tag;
+  w.prec[0][i] = -1;
 }
 
 // BATCH: each ray reads its scene and pose from the job table (the ray field is the job).
-template <bool COUNT, bool BATCH>
+// PERRX: one line-of-sight ray from the hit to each of the M receivers at rxp (bit m of the
+// result) instead of one toward the pose's reference point.
+template <bool COUNT, bool BATCH, bool PERRX>
 __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w,
-                                               Ctl* ctl, int j) {
+                                               Ctl* ctl, int j, const double* __restrict__ rxp, int32_t M) {
   __shared__ int lds_stack[TRAV_LDS_STACK * BS];
   const int cur = j & 1;
   const int64_t n = ctl->n_active[cur];
@@ -390,22 +393,29 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
       const double px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
       const double rnew = (j == 0) ? dnorm3(px - a.s[0], py - a.s[1], pz - a.s[2]) : rtot + t;
       const double rx = dx - 2.0 * dn * nx, ry = dy - 2.0 * dn * ny, rz = dz - 2.0 * dn * nz;
-      // line of sight from the hit point toward the receiver reference point
-      const double wx = a.xref[0] - px, wy = a.xref[1] - py, wz = a.xref[2] - pz;
-      const double L = dnorm3(wx, wy, wz);
-      int vis = 1;
-      if (L > 2.0 * a.t_eps) {
-        const Ray32 rv = make_ray(px, py, pz, wx / L, wy / L, wz / L);
-        float tv;
-        const int blk = traverse<true, COUNT>(S, rv, teps, (float)(L - a.t_eps), pos, st, tv, cn_a, ct_a);
-        vis = blk < 0;
-        ++rays_a;
+      uint64_t vis = 0;
+      const int n_los = PERRX ? M : 1;
+      for (int m = 0; m < n_los; ++m) {
+        // line of sight from the hit point toward the receiver reference point (or receiver m)
+        const double tx = PERRX ? rxp[3 * m] : a.xref[0], ty = PERRX ? rxp[3 * m + 1] : a.xref[1],
+                     tz = PERRX ? rxp[3 * m + 2] : a.xref[2];
+        const double wx = tx - px, wy = ty - py, wz = tz - pz;
+        const double L = dnorm3(wx, wy, wz);
+        bool v = true;
+        if (L > 2.0 * a.t_eps) {
+          const Ray32 rv = make_ray(px, py, pz, wx / L, wy / L, wz / L);
+          float tv;
+          const int blk = traverse<true, COUNT>(S, rv, teps, (float)(L - a.t_eps), pos, st, tv, cn_a, ct_a);
+          v = blk < 0;
+          ++rays_a;
+        }
+        if (v) vis |= 1ull << m;
       }
       w.rp[0][i] = px; w.rp[1][i] = py; w.rp[2][i] = pz;
       w.rd[0][i] = rx; w.rd[1][i] = ry; w.rd[2][i] = rz;
       w.rr[i] = rnew;
       w.rpos[i] = pos;
-      w.rvis[i] = (uint8_t)vis;
+      w.rvis[i] = vis;
       const bool cont = (j + 1 < a.B) && !(rnew >= a.maxd);
       flag = 1ull | ((uint64_t)cont << 32);
     }
@@ -423,7 +433,8 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
 }
 
 template <bool BATCH>
-__global__ void k_scatter(SceneDev S, const TraceJob* __restrict__ jobs, TraceWS w, Ctl* ctl, et_paths P, int j) {
+__global__ void k_scatter(SceneDev S, const TraceJob* __restrict__ jobs, TraceWS w, Ctl* ctl, et_paths P, int j,
+                          int perrx) {
   const int cur = j & 1, nxt = cur ^ 1;
   const int64_t n = ctl->n_active[cur];
   const int64_t base = ctl->rec_base;
@@ -449,7 +460,9 @@ __global__ void k_scatter(SceneDev S, const TraceJob* __restrict__ jobs, TraceWS
       P.mat[ri] = matp[orig];
       P.ray[ri] = w.ray[cur][i];
       P.bounce[ri] = (uint8_t)j;
-      P.flags[ri] = w.rvis[i];
+      P.flags[ri] = w.rvis[i] != 0 ? 1 : 0;
+      if (P.prev) P.prev[ri] = w.prec[cur][i];
+      if (perrx) P.rx_vis[ri] = w.rvis[i];
     } else {
       atomicOr(&ctl->err, DEV_ERR_CAPACITY);
     }
@@ -460,6 +473,7 @@ __global__ void k_scatter(SceneDev S, const TraceJob* __restrict__ jobs, TraceWS
       w.st[nxt][6][k] = w.rr[i];
       w.prev[nxt][k] = pos;
       w.ray[nxt][k] = w.ray[cur][i];
+      w.prec[nxt][k] = ri;
     }
   }
 }
@@ -499,6 +513,7 @@ struct DiffArgs {
   double t_eps;
   int per_mesh;
   int64_t max_meshes;
+  uint64_t rx_all;      // per-receiver reading: every receiver's bit (no receiver-side test), else 0
 };
 
 __global__ void k_obj_fov(SceneDev S, DiffArgs a, uint8_t* oel) {
@@ -679,6 +694,8 @@ __global__ void k_diff_scatter(SceneDev S, DiffArgs a, TraceWS w, Ctl* ctl, et_p
     P.ray[ri] = (int32_t)k;
     P.bounce[ri] = 0;
     P.flags[ri] = 3;   // visible | diffraction
+    if (P.prev) P.prev[ri] = -1;
+    if (a.rx_all) P.rx_vis[ri] = a.rx_all;
   }
 }
 
@@ -688,7 +705,7 @@ __global__ void k_diff_scatter(SceneDev S, DiffArgs a, TraceWS w, Ctl* ctl, et_p
 // excluded) and one record per receiver after the specular and diffraction records: the
 // emitter as the point, path 0, the receiver in `mat` and `ray`, kind 2 in the flags.
 __global__ __launch_bounds__(BS) void k_passive(SceneDev S, PoseArgs a, const double* __restrict__ rx, int32_t M,
-                                                int diff, TraceWS w, Ctl* ctl, et_paths P) {
+                                                int diff, TraceWS w, Ctl* ctl, et_paths P, int perrx) {
   __shared__ int lds_stack[TRAV_LDS_STACK * BS];
   const int64_t gtid = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * BS;
@@ -719,6 +736,8 @@ __global__ __launch_bounds__(BS) void k_passive(SceneDev S, PoseArgs a, const do
       P.ray[ri] = (int32_t)m;
       P.bounce[ri] = 0;
       P.flags[ri] = (uint8_t)(vis | 4);   // visible | kind 2
+      if (P.prev) P.prev[ri] = -1;
+      if (perrx) P.rx_vis[ri] = vis && m < 64 ? 1ull << m : 0ull;
     } else {
       atomicOr(&ctl->err, DEV_ERR_CAPACITY);
     }
@@ -759,12 +778,13 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
     for (int k = 0; k < 7; ++k) x.st[b][k] = (double*)take(sizeof(double) * Nm);
     x.prev[b] = (int32_t*)take(sizeof(int32_t) * Nm);
     x.ray[b] = (int32_t*)take(sizeof(int32_t) * Nm);
+    x.prec[b] = (int64_t*)take(sizeof(int64_t) * Nm);
   }
   for (int k = 0; k < 3; ++k) x.rp[k] = (double*)take(sizeof(double) * Nm);
   for (int k = 0; k < 3; ++k) x.rd[k] = (double*)take(sizeof(double) * Nm);
   x.rr = (double*)take(sizeof(double) * Nm);
   x.rpos = (int32_t*)take(sizeof(int32_t) * Nm);
-  x.rvis = (uint8_t*)take(Nm);
+  x.rvis = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.flags = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.offs = (uint64_t*)take(sizeof(uint64_t) * Nm);
   x.scan_tmp = take(scan_temp_bytes(std::max(std::max(Nm, Tm), Km)));
@@ -852,10 +872,10 @@ void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_pat
     }
     k_ray_init<true><<<nblk_full(N), BS, 0, s>>>(all, nullptr, dj, J, sorted ? w.rperm : nullptr, w, ctl);
     for (int j = 0; j < B; ++j) {
-      if (counting) k_bounce<true, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
-      else k_bounce<false, true><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j);
+      if (counting) k_bounce<true, true, false><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j, nullptr, 0);
+      else k_bounce<false, true, false><<<gb, BS, 0, s>>>(SceneDev{}, all, dj, w, ctl, j, nullptr, 0);
       scan_exclusive_u64(w.flags, w.offs, 0, &ctl->n_active[j & 1], N, &ctl->tot[0], w.scan_tmp, s);
-      k_scatter<true><<<nblk(N), BS, 0, s>>>(SceneDev{}, dj, w, ctl, P, j);
+      k_scatter<true><<<nblk(N), BS, 0, s>>>(SceneDev{}, dj, w, ctl, P, j, 0);
       k_bounce_epi<<<1, 1, 0, s>>>(ctl, j);
       ET_HIP(hipGetLastError());
     }
@@ -868,6 +888,7 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
                bool counting, hipStream_t s) {
   const PoseArgs a = pose_args(sim);
   const et_paths P = *paths;
+  const bool perrx = (sim->flags & ET_PER_RX_VISIBILITY) != 0;
   k_trace_init<<<1, 1, 0, s>>>(ctl, a.N);
   ET_HIP(hipGetLastError());
   if (a.N > 0 && S.T > 0) {
@@ -878,10 +899,17 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     }
     k_ray_init<false><<<nblk_full(a.N), BS, 0, s>>>(a, sim->ray_dirs, nullptr, 0, sorted ? w.rperm : nullptr, w, ctl);
     for (int j = 0; j < a.B; ++j) {
-      if (counting) k_bounce<true, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
-      else k_bounce<false, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j);
+      const double* rx = sim->rx_pos;
+      const int32_t M = sim->M;
+      if (perrx) {
+        if (counting) k_bounce<true, false, true><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j, rx, M);
+        else k_bounce<false, false, true><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j, rx, M);
+      } else {
+        if (counting) k_bounce<true, false, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j, nullptr, 0);
+        else k_bounce<false, false, false><<<nblk(a.N), BS, 0, s>>>(S, a, nullptr, w, ctl, j, nullptr, 0);
+      }
       scan_exclusive_u64(w.flags, w.offs, 0, &ctl->n_active[j & 1], a.N, &ctl->tot[0], w.scan_tmp, s);
-      k_scatter<false><<<nblk(a.N), BS, 0, s>>>(S, nullptr, w, ctl, P, j);
+      k_scatter<false><<<nblk(a.N), BS, 0, s>>>(S, nullptr, w, ctl, P, j, perrx ? 1 : 0);
       k_bounce_epi<<<1, 1, 0, s>>>(ctl, j);
       ET_HIP(hipGetLastError());
     }
@@ -900,6 +928,7 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     d.K = sim->diff_K;
     d.t_eps = sim->t_eps;
     d.per_mesh = (sim->flags & ET_DIFF_PER_MESH) ? 1 : 0;
+    d.rx_all = perrx ? (sim->M >= 64 ? ~0ull : (1ull << sim->M) - 1ull) : 0ull;
     d.max_meshes = d.per_mesh ? sim->diff_max_meshes : 1;
     const int64_t max_draw = d.K * d.max_meshes;
     int obj_bits = 1;
@@ -926,7 +955,7 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
   }
   const int32_t n_passive = (sim->flags & ET_PASSIVE) ? sim->M : 0;
   if (n_passive > 0)
-    k_passive<<<nblk(n_passive), BS, 0, s>>>(S, a, sim->rx_pos, n_passive, diff ? 1 : 0, w, ctl, P);
+    k_passive<<<nblk(n_passive), BS, 0, s>>>(S, a, sim->rx_pos, n_passive, diff ? 1 : 0, w, ctl, P, perrx ? 1 : 0);
   k_trace_final<<<1, 1, 0, s>>>(ctl, P, diff ? 1 : 0, n_passive);
   ET_HIP(hipGetLastError());
 }

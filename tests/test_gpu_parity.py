@@ -563,3 +563,101 @@ def test_emitters_with_diffraction_and_passive(et, ctx, tiny):
     with pytest.raises(et.EchoError) as e:
         et.simulate_emitters(ctx, sc, [gs[0], other])
     assert e.value.status == -1
+
+
+# ----------------------------------------------------------------------------- alternative readings
+
+def _screen_scene():
+    """A wall 4 m ahead and a small screen that hides part of it from the receiver at +y."""
+    mb = W.MeshBuilder()
+    mb.add(np.array([[4, -3, -2], [4, 3, -2], [4, 3, 2], [4, -3, 2]], float), np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    mb.add(np.array([[1.5, 0.05, -0.6], [1.5, 0.8, -0.6], [1.5, 0.8, 0.6], [1.5, 0.05, 0.6]], float),
+           np.array([[0, 1, 2], [0, 2, 3]]), 1)
+    return mb.build()
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_path_product_matches_oracle(et, ctx, direct):
+    """Path-product reading (k multiplied over every reflection of the ray): records chain
+    through prev, and the spectra match the oracle's on certified rays, both kernels."""
+    scene = _screen_scene()
+    g = W.rng(12)
+    k = np.array([[0.9, 0.8, 0.85, 0.7, 0.95, 0.6, 0.75, 0.5], [0.4, 0.5, 0.6, 0.7, 0.3, 0.9, 0.2, 0.8]], np.float32)
+    sim = W.make_sim(emitter_pos=[0, 0, 0], emitter_rot=np.eye(3), rx_pos=[[0, 0.3, 0], [0, -0.3, 0]],
+                     ray_dirs=W.cone_directions(g, 8192, math.radians(35)), max_bounces=4, f_lo=20e3, f_hi=100e3,
+                     F=1024, refl_k=k, lobe_beta=np.full((2, 8), 0.3, np.float32),
+                     diff_coef=np.full((2, 8), 0.1, np.float32), path_product=True)
+    ref = O.trace(scene, sim)
+    dirs = sim["ray_dirs"][ref["certified"]]
+    ref_c = O.trace(scene, sim, dirs=dirs)
+    H_ref = O.synth(ref_c, sim)
+    assert np.any(ref_c["bounce"] > 0)
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim, ray_dirs=dirs, flags=et.ET_SPECULAR | et.ET_PATH_PRODUCT | (et.ET_SYNTH_DIRECT if direct else 0))
+    P = et.trace(ctx, sc, s)
+    H = et.synthesize(ctx, s, P).cpu().numpy()
+    h = P.to_host()
+    # every record after a ray's first reflection points at that ray's previous reflection
+    for i in np.nonzero(h["bounce"] > 0)[0][:2000]:
+        j = h["prev"][i]
+        assert 0 <= j < i and h["ray"][j] == h["ray"][i] and h["bounce"][j] == h["bounce"][i] - 1
+    assert np.all(h["prev"][h["bounce"] == 0] == -1)
+    e = rel_l2(H, H_ref)
+    lit = O.synth(ref_c, dict(sim, path_product=False))
+    print(f"path product ({'direct' if direct else 'factorised'}): rel L2 {e:.3e} "
+          f"(literal reading differs by {rel_l2(lit, H_ref):.2e})")
+    assert ctx.stats().synth_kernel == (2 if direct else 1)
+    assert e <= TOL
+    with pytest.raises(et.EchoError) as ex:
+        et.synthesize_backward(ctx, s, P, torch_randn_like(H))
+    assert ex.value.status == -5
+
+
+def torch_randn_like(H):
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(3)
+    return torch.randn(H.shape, dtype=torch.complex64, device="cuda", generator=g)
+
+
+def test_per_receiver_visibility_matches_oracle(et, ctx):
+    """Per-receiver line of sight: the receiver bits of every certified ray's records, the
+    spectra and the adjoint match the oracle's; a fused batch of such jobs equals single calls."""
+    scene = _screen_scene()
+    g = W.rng(13)
+    sim = W.make_sim(emitter_pos=[0, 0, 0], emitter_rot=np.eye(3), rx_pos=[[0, 0.3, 0], [0, -0.3, 0]],
+                     ray_dirs=W.cone_directions(g, 8192, math.radians(35)), max_bounces=3, f_lo=20e3, f_hi=100e3,
+                     F=512, refl_k=np.full((2, 8), 0.9, np.float32), lobe_beta=np.full((2, 8), 0.3, np.float32),
+                     diff_coef=np.full((2, 8), 0.1, np.float32), per_rx_visibility=True)
+    ref = O.trace(scene, sim)
+    dirs = sim["ray_dirs"][ref["certified"]]
+    ref_c = O.trace(scene, sim, dirs=dirs)
+    b = ref_c["rxvis"]
+    assert np.any((b & np.uint64(1)) != ((b >> np.uint64(1)) & np.uint64(1)))
+    sc = et.Scene(ctx, scene)
+    s = et.Sim(sim, ray_dirs=dirs)
+    assert s.desc.flags & et.ET_PER_RX_VISIBILITY
+    P = et.trace(ctx, sc, s)
+    h = P.to_host()
+    order_g = np.lexsort((h["bounce"], h["ray"]))
+    order_o = np.lexsort((ref_c["bounce"], ref_c["ray"]))
+    assert np.array_equal(h["ray"][order_g], ref_c["ray"][order_o])
+    assert np.array_equal(h["rxvis"][order_g], ref_c["rxvis"][order_o])
+    H = et.synthesize(ctx, s, P).cpu().numpy()
+    H_ref = O.synth(ref_c, sim)
+    e = rel_l2(H, H_ref)
+    # the adjoint over the same records
+    rng = np.random.default_rng(5)
+    gH = (rng.normal(size=H.shape) + 1j * rng.normal(size=H.shape)).astype(np.complex64)
+    import torch
+    gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(gH).cuda())
+    gk_ref, gx_ref = O.grad(ref_c, sim, gH.astype(np.complex128))
+    ek, ex = rel_l2(gk.cpu().numpy(), gk_ref), rel_l2(gx.cpu().numpy(), gx_ref)
+    print(f"per-receiver visibility: spectra rel L2 {e:.3e}, dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    assert e <= TOL and ek <= TOL and ex <= TOL
+    # two such emitters run as batch jobs (job after job): their sum equals single calls
+    s2 = et.Sim(dict(sim, emitter_pos=np.array([0.1, 0.0, 0.05])), ray_dirs=dirs)
+    s2.rx_pos = s.rx_pos
+    s2.refresh()
+    Hs = et.simulate_emitters(ctx, sc, [s, s2]).cpu().numpy()
+    each = et.simulate(ctx, sc, s).cpu().numpy().astype(np.complex128) + et.simulate(ctx, sc, s2).cpu().numpy()
+    assert rel_l2(Hs, each) <= 1e-6
