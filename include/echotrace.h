@@ -179,7 +179,8 @@ typedef struct {
   double diff_tau;              /* eligibility: C_i >= tau * max C */
   double diff_max_incidence;    /* incidence limit between normal and source direction */
   double diff_cone_half_angle;  /* emitter field of view for object eligibility */
-  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT | ET_PASSIVE | ET_DIFF_PER_MESH */
+  uint32_t flags;               /* ET_SPECULAR | ET_DIFFRACTION | ET_SYNTH_DIRECT | ET_PASSIVE | ET_DIFF_PER_MESH |
+                                   ET_PATH_PRODUCT | ET_PER_RX_VISIBILITY */
   const float* passive_coef;    /* device [Bk] source magnitude I_p per band (ET_PASSIVE), >= 0 */
   int64_t diff_max_meshes;      /* ET_DIFF_PER_MESH: meshes that may receive candidates (sizes the
                                    records and workspace: diff_K * diff_max_meshes draws) */
@@ -214,8 +215,10 @@ typedef struct {
 /* Workspace bytes for et_trace / et_synthesize / et_simulate with this descriptor. */
 int et_workspace_size(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, size_t* bytes);
 
-/* Algorithm 1 (+ diffraction sampling if ET_DIFFRACTION): fills `paths`.  Records beyond
- * capacity are dropped and the call reports ET_E_CAPACITY at the next et_get_stats. */
+/* Algorithm 1 (+ diffraction sampling if ET_DIFFRACTION, + the passive component if
+ * ET_PASSIVE): fills `paths` (and paths->prev when not NULL, paths->rx_vis with
+ * ET_PER_RX_VISIBILITY).  Records beyond capacity are dropped and the call reports
+ * ET_E_CAPACITY at the next et_get_stats. */
 int et_trace(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, void* ws, size_t ws_bytes,
              const et_paths* paths);
 
