@@ -4,10 +4,13 @@
 // m at x_m, with r = rtot + |x_m - p| and f_k = f_lo + k df:
 //   H_m[k] += A_nmk exp(j 2 pi sigma f_k r / c)
 //   A_nmk = r^-p 10^(-(a0 + a1 f_k) r / 20) * I[b(k)] * D_m[bd(k)]
-//   I[b] = k_qb exp(-gamma^2 / (2 beta_qb^2)) (specular),  I_d,qb (diffraction)
+//   I[b] = k_qb exp(-gamma^2 / (2 beta_qb^2)) (specular),  I_d,qb (diffraction),  I_p,b (passive)
 // where gamma is the angle between d' and the direction from p to x_m.  Records whose
 // line-of-sight ray was blocked contribute nothing; a first pass compacts the indices of
-// the visible records so that no kernel spends work on the others.
+// the visible records so that no kernel spends work on the others.  Two alternative
+// readings switch per pose: the path product (k_qb replaced by the product of k over the
+// ray's reflections so far, through per-record band tables) and per-receiver line of sight
+// (a record reaches receiver m only when its bit m is set).
 //
 // Precision: the receiver leg, total path and the delay in cycles at f_lo and per bin are
 // FP64 (the phase needs the path to ~1e-8 m at 100-200 kHz); sin/cos/exp2 and the
@@ -120,8 +123,8 @@ __device__ inline float dir_gain(const float* tab, int El, int Az, float vx, flo
   return (1.f - te) * a0 + te * a1;
 }
 
-// Returns false if the record does not contribute to receiver m (not visible, or a passive
-// record of another receiver).
+// Returns false if the record does not contribute to receiver m (not visible, hidden from
+// receiver m under the per-receiver line of sight, or a passive record of another receiver).
 __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t n, int m, Pair& q) {
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return false;
