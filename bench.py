@@ -270,8 +270,8 @@ def main():
                 "kernel_ms": ms_synth_kernel, "algorithmic_flop_per_launch": synth_flops,
                 "per_unit": f"{SYNTH_FLOP_PER_TERM} flop per (visible record, receiver, bin)"}
     else:
-        roof = {"kernel": "k_bounce<false, false>", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false>")}
+        roof = {"kernel": "k_bounce<false, false, false>", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false, false>")}
     line = {
         "metric": METRIC,
         "value": seg / (ms_step * 1e-3) / 1e6,
@@ -299,14 +299,15 @@ def main():
                     "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,
                     "kernel_tflops_algorithmic": adj_tflops, "frac_of_mfma_peak": adj_tflops / PEAK_MFMA_F32_TFLOPS,
                     "per_unit": f"{ADJ_FLOP_PER_TERM} flop per (visible record, receiver, bin)",
-                    "traffic": traffic_for("k_synth_bwd_mfma<false>" if adj_kern == 1 else "k_synth_bwd<false>")},
+                    "traffic": traffic_for(f"k_synth_bwd_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}>"
+                                           if adj_kern == 1 else "k_synth_bwd<false>")},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "dynamic_scene": dynamic,
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
                       "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
                       "algorithmic_bytes": trav_bytes, "effective_GBs": trace_gbs,
-                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false>")},
+                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false, false>")},
         "roofline": roof,
         "cpu_baseline": None,
     }
