@@ -4,9 +4,12 @@
  * Computes what the SonoTraceUE paper (Jansen & Steckel, arXiv 2602.19652) computes per
  * frame: rays emitted from a sensor pose are traced through a triangle-mesh scene with
  * specular bounces (Sec. III-C, Algorithm 1), curvature-importance Monte Carlo
- * diffraction points are drawn (Sec. III-D), and every path becomes a complex
- * contribution to each receiver's transfer function (Eqs. 2-4 specular, Eqs. 7-8
- * diffraction).  Scene in, per-receiver spectra out.
+ * diffraction points are drawn (Sec. III-D), the direct emitter-receiver paths of the
+ * passive component are tested (Sec. III-E), and every path becomes a complex
+ * contribution to each receiver's transfer function (Eqs. 2-4 specular, 7-8 diffraction,
+ * 11-13 passive).  Scene in, per-receiver spectra out; then impulse responses and received
+ * signals (Sec. III-F).  Around that: batches of poses and scenes, several emitters, the
+ * adjoint of the synthesis, equal-area ray sets and BVH refits for dynamic scenes.
  *
  * Conventions
  *  - Every call returns an int status (et_status); no exception crosses the ABI.
@@ -22,9 +25,9 @@
  *  - A context is used by one host thread at a time.  Scenes are immutable after build
  *    and may be shared by contexts on the same device.
  *  - Host-side validation (shapes, null pointers, ranges of scalar parameters) runs
- *    before any launch; array contents on the device are trusted, except that index
- *    arrays are range-checked on the device during scene build (ET_E_INVALID reported
- *    by et_get_stats via the error word).
+ *    before any launch; array contents on the device are trusted, except that the mesh's
+ *    index arrays are range-checked on the device during scene build (which then returns
+ *    ET_E_INVALID).
  *  - Angles are radians, lengths metres, frequencies Hz.  Rotation matrices are 3x3
  *    row-major, their columns are the local axes expressed in world coordinates
  *    (world = R * local).
@@ -39,7 +42,7 @@
 extern "C" {
 #endif
 
-#define ET_ABI_VERSION 2
+#define ET_ABI_VERSION 3
 
 typedef enum {
   ET_OK = 0,

@@ -11,7 +11,7 @@
  *   - per-point magnitude and transfer function: Eqs. (2)-(4)
  *   - curvature metric: Section III-B, Eq. (1), Meyer et al. 2003 operator
  *   - Monte Carlo diffraction and its transfer function: Section III-D, Eqs. (7)-(8)
- *   - passive component (direct emitter-receiver path): its section, Eqs. (11)-(13)
+ *   - passive component (direct emitter-receiver path): Section III-E, Eqs. (11)-(13)
  *
  * All arithmetic is IEEE double, compiled with -ffp-contract=off.  Brute force: no
  * acceleration structure anywhere.  Every function returns 0 on success, a negative

@@ -1,4 +1,5 @@
-// Time-domain signals: impulse responses from the spectra (Eqs. 5-6, 9-10, 13: h = F^-1[H])
+// Time-domain signals (Sec. III-F): impulse responses from the spectra (Eqs. 5-6, 9-10, 13:
+// h = F^-1[H])
 // and received signals (Eq. 14: s = h * s_e).
 //
 // Impulse response of receiver m on t_n = n dt, dt = 1 / (n_t df), n < n_t:
