@@ -1,6 +1,5 @@
 // Time-domain signals (Sec. III-F): impulse responses from the spectra (Eqs. 5-6, 9-10, 13:
-// h = F^-1[H])
-// and received signals (Eq. 14: s = h * s_e).
+// h = F^-1[H]) and received signals (Eq. 14: s = h * s_e).
 //
 // Impulse response of receiver m on t_n = n dt, dt = 1 / (n_t df), n < n_t:
 //   h_m(t_n) = 2 df Re[ e^{-j sigma 2 pi f_lo t_n} sum_{k<F} H_m[k] e^{-j sigma 2 pi k n / n_t} ],
