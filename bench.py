@@ -255,6 +255,7 @@ def main():
                   + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
 
     dynamic = dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
+    other_configs = configs_leg(ctx, et, W, reps)
 
     synth_flops = terms * SYNTH_FLOP_PER_TERM
     synth_tflops = synth_flops / (ms_synth_kernel * 1e-3) / 1e12
@@ -303,6 +304,7 @@ def main():
                                            if adj_kern == 1 else "k_synth_bwd<false>")},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "dynamic_scene": dynamic,
+        "other_configs": other_configs,
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
                       "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
@@ -318,6 +320,39 @@ def main():
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(ctx, args)
     print(json.dumps(line))
+
+
+def configs_leg(ctx, et, W, reps):
+    """The step on the other single-pose workloads: the tiny wall + sphere scene (16,384
+    rays, <=3 reflection points, 2 receivers, 1024 bins) and the foliage scene (1M
+    triangles, 2^22 rays, <=6 reflection points, 2 receivers with directivity, 8192 bins)."""
+    import torch
+    res = {}
+    for name, (scene_c, sim_c) in (("tiny", W.tiny_scene()), ("foliage", W.foliage_scene())):
+        sc_c = et.Scene(ctx, scene_c, area_ref=W.median_triangle_area(scene_c))
+        s_c = et.Sim(sim_c)
+        P_c = et.Paths(s_c.capacity())
+        ws_c = et.Workspace()
+        out_c = torch.empty(s_c.M, s_c.F, 2, dtype=torch.float32, device="cuda")
+        et.simulate(ctx, sc_c, s_c, paths=P_c, ws=ws_c, out=out_c)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            et.simulate(ctx, sc_c, s_c, paths=P_c, ws=ws_c, out=out_c)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st = ctx.stats()
+        n_vis = int((P_c.flags[:st.records] & 1).sum().item())
+        res[name] = {"triangles": len(scene_c["tris"]), "rays": s_c.desc.N, "receivers": s_c.M, "bins": s_c.F,
+                     "ms_per_step": ms, "mrays_bounces_per_s": st.segments / (ms * 1e-3) / 1e6,
+                     "trace_ms": st.ms_trace, "synth_kernel_ms": st.ms_synth_kernel, "synth_kernel": st.synth_kernel,
+                     "g_terms_per_s": n_vis * s_c.M * s_c.F / (ms * 1e-3) / 1e9, "build_ms": sc_c.info().build_ms}
+        del P_c, ws_c, sc_c
+        torch.cuda.empty_cache()
+    return res
 
 
 def dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps):
