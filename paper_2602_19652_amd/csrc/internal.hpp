@@ -61,7 +61,10 @@ struct __align__(16) NodeB {
   int right;
 };
 
-constexpr int TRAV_LDS_STACK = 32;     // per-lane stack entries held in LDS
+// per-lane stack entries held in LDS: 26 KB per 256-thread block, so six blocks (six waves
+// per SIMD) fit the compute unit's 160 KB
+constexpr int TRAV_LDS_STACK = 26;
+constexpr int TRAV_WAVES_PER_SIMD = 6;
 constexpr int TRAV_STACK = 64;         // total per-lane entries (rest in global memory)
 constexpr int TRAV_BLOCK = 256;
 constexpr int PLOC_RADIUS = 16;

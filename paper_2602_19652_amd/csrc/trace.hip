@@ -135,10 +135,14 @@ struct Stack {
     else { ++overflow; return; }
     ++sp;
   }
+  // The global part is read as a non-temporal load, so the compiler keeps the two reads apart
+  // (an LDS read in the common case) rather than merging them into one generic (flat) load
+  // that waits on both memory counters.
   __device__ inline int pop() {
     if (sp == 0) return EMPTY;
     --sp;
-    return sp < TRAV_LDS_STACK ? lds[sp * BS] : glob[(int64_t)(sp - TRAV_LDS_STACK) * gstride];
+    if (sp < TRAV_LDS_STACK) return lds[sp * BS];
+    return __builtin_nontemporal_load(glob + (int64_t)(sp - TRAV_LDS_STACK) * gstride);
   }
 };
 
@@ -353,8 +357,10 @@ __global__ void k_ray_init(PoseArgs a0, const float* __restrict__ dirs0, const T
 // BATCH: each ray reads its scene and pose from the job table (the ray field is the job).
 // PERRX: one line-of-sight ray from the hit to each of the M receivers at rxp (bit m of the
 // result) instead of one toward the pose's reference point.
+// Six waves per SIMD (the register budget that asks for, 80, holds the kernel without spills):
+// measured 7% faster on the room's trace and 15% on foliage's than five.
 template <bool COUNT, bool BATCH, bool PERRX>
-__global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(TRAV_WAVES_PER_SIMD))) void k_bounce(SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w,
                                                Ctl* ctl, int j, const double* __restrict__ rxp, int32_t M) {
   __shared__ int lds_stack[TRAV_LDS_STACK * BS];
   const int cur = j & 1;
@@ -368,6 +374,24 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
   st.overflow = 0;
   int64_t cn_c = 0, ct_c = 0, cn_a = 0, ct_a = 0, rays_a = 0;
   for (int64_t i = gtid; i < n; i += stride) {
+    int pos;
+    float th = INFINITY;
+    {
+      SceneDev S = S0;
+      float teps = (float)a0.t_eps;
+      if (BATCH) {
+        const TraceJob* tj = jobs + w.ray[cur][i];
+        S = tj->S;
+        teps = (float)tj->a.t_eps;
+      }
+      const Ray32 r = make_ray(w.st[cur][0][i], w.st[cur][1][i], w.st[cur][2][i], w.st[cur][3][i], w.st[cur][4][i],
+                               w.st[cur][5][i]);
+      pos = (!BATCH || S.T > 0) ? traverse<false, COUNT>(S, r, teps, INFINITY, w.prev[cur][i], st, th, cn_c, ct_c) : -1;
+    }
+    // The FP64 ray state (and a batch ray's job) is read again after the traversal instead of
+    // being held in registers through it; the compiler barrier keeps the two reads apart, so
+    // the traversal loop runs with fewer live registers (more waves per SIMD).
+    __asm__ volatile("" ::: "memory");
     SceneDev S = S0;
     PoseArgs a = a0;
     if (BATCH) {
@@ -379,10 +403,6 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
     const double ox = w.st[cur][0][i], oy = w.st[cur][1][i], oz = w.st[cur][2][i];
     const double dx = w.st[cur][3][i], dy = w.st[cur][4][i], dz = w.st[cur][5][i];
     const double rtot = w.st[cur][6][i];
-    const int prev = w.prev[cur][i];
-    const Ray32 r = make_ray(ox, oy, oz, dx, dy, dz);
-    float th = INFINITY;
-    const int pos = (!BATCH || S.T > 0) ? traverse<false, COUNT>(S, r, teps, INFINITY, prev, st, th, cn_c, ct_c) : -1;
     uint64_t flag = 0;
     if (pos >= 0) {
       // FP64 refinement on the chosen triangle: plane intersection, normal, reflection
@@ -398,6 +418,13 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
       const double px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
       const double rnew = (j == 0) ? dnorm3(px - a.s[0], py - a.s[1], pz - a.s[2]) : rtot + t;
       const double rx = dx - 2.0 * dn * nx, ry = dy - 2.0 * dn * ny, rz = dz - 2.0 * dn * nz;
+      // the bounce's results leave registers before the line-of-sight traversal
+      w.rp[0][i] = px; w.rp[1][i] = py; w.rp[2][i] = pz;
+      w.rd[0][i] = rx; w.rd[1][i] = ry; w.rd[2][i] = rz;
+      w.rr[i] = rnew;
+      w.rpos[i] = pos;
+      const bool cont = (j + 1 < a.B) && !(rnew >= a.maxd);
+      flag = 1ull | ((uint64_t)cont << 32);
       uint64_t vis = 0;
       const int n_los = PERRX ? M : 1;
       for (int m = 0; m < n_los; ++m) {
@@ -416,13 +443,7 @@ __global__ __launch_bounds__(BS) void k_bounce(SceneDev S0, PoseArgs a0, const T
         }
         if (v) vis |= 1ull << m;
       }
-      w.rp[0][i] = px; w.rp[1][i] = py; w.rp[2][i] = pz;
-      w.rd[0][i] = rx; w.rd[1][i] = ry; w.rd[2][i] = rz;
-      w.rr[i] = rnew;
-      w.rpos[i] = pos;
       w.rvis[i] = vis;
-      const bool cont = (j + 1 < a.B) && !(rnew >= a.maxd);
-      flag = 1ull | ((uint64_t)cont << 32);
     }
     w.flags[i] = flag;
   }
