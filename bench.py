@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=1024, help="rays of the oracle's bounded sample")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baselines (for rocprofv3)")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the dynamic-scene and other-workload legs (a kernel trace then holds only the "
+                         "room step's synthesis launches)")
     ap.add_argument("--batch-poses", type=int, default=256, help="poses of the batch leg (0 with 0 scenes skips it)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-rays", type=int, default=1 << 18)
@@ -254,8 +257,8 @@ def main():
     trav_bytes = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
                   + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
 
-    dynamic = dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
-    other_configs = configs_leg(ctx, et, W, reps)
+    dynamic = None if args.no_extra_legs else dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
+    other_configs = None if args.no_extra_legs else configs_leg(ctx, et, W, reps)
 
     synth_flops = terms * SYNTH_FLOP_PER_TERM
     synth_tflops = synth_flops / (ms_synth_kernel * 1e-3) / 1e12
