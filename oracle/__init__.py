@@ -160,14 +160,17 @@ def grad(rec: dict, sim: dict, g: np.ndarray):
     """Analytic gradient of L = sum |H - H*|^2 with g = H - H* (complex [M, F]):
     returns (dL/d refl_k [Q, Bk], dL/d rx_pos [M, 3])."""
     L = lib()
-    if sim.get("directivity") is not None:
-        raise ValueError("gradient with directivity is not defined here")
     if sim.get("path_product", False):
         raise ValueError("gradient with the path-product reading is not defined here")
     F = int(sim["F"])
-    rx = _f64(sim["rx_pos"])
+    rx = _f64(sim["rx_pos"]); rr = _f64(sim["rx_rot"])
     M = len(rx)
     n = len(rec["rtot"])
+    D = sim.get("directivity")
+    Bd = El = Az = 0
+    if D is not None:
+        D = _f32(D)
+        _, Bd, El, Az = D.shape
     gg = np.ascontiguousarray(np.stack([g.real, g.imag], -1), np.float64)
     k = _f32(sim["refl_k"]); b = _f32(sim["lobe_beta"]); dc = _f32(sim["diff_coef"])
     Q, Bk = k.shape
@@ -181,7 +184,8 @@ def grad(rec: dict, sim: dict, g: np.ndarray):
                     _p(kind), _p(vis), C.c_int32(M), _p(rx), C.c_double(sim["f_lo"]), C.c_double(sim["f_hi"]),
                     C.c_int32(F), C.c_double(sim["c"]), C.c_double(sim["atm_a0"]), C.c_double(sim["atm_a1"]),
                     C.c_double(sim["spreading_p"]), C.c_int32(sim["phase_sign"]), C.c_int32(Q), C.c_int32(Bk),
-                    _p(k), _p(b), _p(dc), _p(pc), _p(gg), _p(gk), _p(gx), _p(rxvis))
+                    _p(k), _p(b), _p(dc), _p(pc), _p(gg), _p(gk), _p(gx), _p(rxvis), _p(rr), C.c_int32(Bd),
+                    C.c_int32(El), C.c_int32(Az), _p(D))
     if rc != 0:
         raise ValueError(f"orc_grad failed ({rc})")
     return gk, gx

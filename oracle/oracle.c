@@ -349,8 +349,11 @@ int orc_passive(int64_t V, int64_t T, const float* verts, const int32_t* tris, c
 /* ------------------------------------------------------------------ synthesis */
 
 /* Receiver directivity: real gain per band, cell-centred az/el grid in the receiver
- * frame (az from -pi, el from -pi/2), bilinear, azimuth periodic, elevation clamped. */
-static double directivity_gain(const float* tab, int El, int Az, v3 v) {
+ * frame (az from -pi, el from -pi/2), bilinear, azimuth periodic, elevation clamped.
+ * With dv != NULL also the gradient of the gain with respect to the direction v: the
+ * derivative of the bilinear interpolant inside the cell that holds v (zero across the
+ * clamped elevation rows; undefined on the poles, where it is set to zero). */
+static double directivity_gain_dv(const float* tab, int El, int Az, v3 v, v3* dv) {
   double az = atan2(v.y, v.x);
   double el = atan2(v.z, hypot(v.x, v.y));
   double fa = (az + M_PI) / (2.0 * M_PI) * Az - 0.5;
@@ -360,12 +363,33 @@ static double directivity_gain(const float* tab, int El, int Az, v3 v) {
   double fe = (el + 0.5 * M_PI) / M_PI * El - 0.5;
   long j0, j1;
   double te;
+  int inner = 0;
   if (fe <= 0.0) { j0 = j1 = 0; te = 0.0; }
   else if (fe >= El - 1) { j0 = j1 = El - 1; te = 0.0; }
-  else { j0 = (long)floor(fe); j1 = j0 + 1; te = fe - (double)j0; }
+  else { j0 = (long)floor(fe); j1 = j0 + 1; te = fe - (double)j0; inner = 1; }
   double a0 = (1.0 - ta) * tab[j0 * Az + i0] + ta * tab[j0 * Az + i1];
   double a1 = (1.0 - ta) * tab[j1 * Az + i0] + ta * tab[j1 * Az + i1];
+  if (dv) {
+    /* dD/daz and dD/del through the cell coordinates fa = (az + pi) Az / 2pi - 1/2 and
+     * fe = (el + pi/2) El / pi - 1/2, then az = atan2(y, x) and el = atan2(z, rho) */
+    double dfa = (1.0 - te) * ((double)tab[j0 * Az + i1] - tab[j0 * Az + i0]) +
+                 te * ((double)tab[j1 * Az + i1] - tab[j1 * Az + i0]);
+    double dfe = inner ? a1 - a0 : 0.0;
+    double daz = dfa * Az / (2.0 * M_PI), del = dfe * El / M_PI;
+    double rho2 = v.x * v.x + v.y * v.y, rho = sqrt(rho2), n2 = rho2 + v.z * v.z;
+    if (rho2 > 0.0) {
+      dv->x = -daz * v.y / rho2 - del * v.x * v.z / (rho * n2);
+      dv->y = daz * v.x / rho2 - del * v.y * v.z / (rho * n2);
+      dv->z = del * rho / n2;
+    } else {
+      *dv = mk(0, 0, 0);
+    }
+  }
   return (1.0 - te) * a0 + te * a1;
+}
+
+static double directivity_gain(const float* tab, int El, int Az, v3 v) {
+  return directivity_gain_dv(tab, El, Az, v, NULL);
 }
 
 typedef struct {
@@ -497,8 +521,10 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis) {
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis,
+             const double* rx_rot, int32_t Bd, int32_t El, int32_t Az, const float* directivity) {
   if (M < 1 || F < 1 || Q < 1 || Bk < 1 || Bk > 64) return -1;
+  if (directivity && (Bd < 1 || Bd > 64 || El < 1 || Az < 1)) return -1;
   for (int64_t n = 0; n < n_rec; ++n)
     if (kind && kind[n] == 2 && !passive_coef) return -1;   /* passive records need I_p */
   const double df = F > 1 ? (f_hi - f_lo) / (double)(F - 1) : 0.0;
@@ -518,8 +544,18 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
       v3 dn = kd == 0 ? ld3d(dout + 3 * n) : mk(1, 0, 0);
       pair_t q = pair_setup(pn, dn, rtot[n], kd, xm);
       double Lgeo = pow(q.r, -p_s);
-      double Sb[2 * 64];
+      double Sb[2 * 64], Sd[64], Dg[64];
+      v3 dDg[64];
       memset(Sb, 0, sizeof(double) * 2 * Bk);
+      const double* Rm = rx_rot ? rx_rot + 9 * m : NULL;
+      if (directivity) {
+        /* gain per directivity band and its gradient in the receiver frame (as in orc_synth) */
+        v3 vl = Rm ? rotT(Rm, scl(q.u, -1.0)) : scl(q.u, -1.0);
+        for (int d = 0; d < Bd; ++d) {
+          Dg[d] = directivity_gain_dv(directivity + ((size_t)m * Bd + d) * (size_t)El * Az, El, Az, vl, &dDg[d]);
+          Sd[d] = 0.0;
+        }
+      }
       double S1r = 0, S1i = 0;
       for (int64_t k = 0; k < F; ++k) {
         double f = f_lo + (double)k * df;
@@ -535,6 +571,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
           I = (double)passive_coef[b];
         }
         double A = Lgeo * Latm * I;
+        if (directivity) A *= Dg[(k * Bd) / F];
         double cyc = (double)sigma * f * q.r / c;
         double ph = 2.0 * M_PI * (cyc - floor(cyc));
         double Tr = A * cos(ph), Ti = A * sin(ph);
@@ -543,6 +580,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
         double zr = gr * Tr + gi * Ti, zi = gr * Ti - gi * Tr;
         Sb[2 * b] += zr;
         Sb[2 * b + 1] += zi;
+        if (directivity) Sd[(k * Bd) / F] += zr;
         S1r += f * zr;
         S1i += f * zi;
       }
@@ -566,6 +604,18 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
           if (kv != 0.0) gk[mat[n] * Bk + b] += 2.0 * Sb[2 * b] / kv;
         }
         grad = sub(grad, scl(dg2, 2.0 * wsum));
+      }
+      if (directivity) {
+        /* d ln D_d / dx_m: v = -R^T u and du/dx_m = (I - u u^T) / l, so the gradient in x is
+         * -(I - u u^T) R (dD_d/dv) / (l D_d) */
+        v3 gv = mk(0, 0, 0);
+        for (int d = 0; d < Bd; ++d)
+          if (Dg[d] != 0.0) gv = add(gv, scl(dDg[d], Sd[d] / Dg[d]));
+        v3 w = Rm ? mk(Rm[0] * gv.x + Rm[1] * gv.y + Rm[2] * gv.z, Rm[3] * gv.x + Rm[4] * gv.y + Rm[5] * gv.z,
+                       Rm[6] * gv.x + Rm[7] * gv.y + Rm[8] * gv.z)
+                  : gv;
+        v3 wp = sub(w, scl(q.u, dot(q.u, w)));
+        grad = sub(grad, scl(wp, 2.0 / q.l));
       }
       gx = add(gx, grad);
     }

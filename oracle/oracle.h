@@ -60,13 +60,15 @@ int orc_synth(int64_t n_rec, const double* p, const double* dout, const double* 
 
 /* Analytic gradient of L = sum_{m,k} |H_mk - H*_mk|^2 given g = H - H* ([M][F][2]),
  * with respect to refl_k [Q][Bk] and the receiver positions [M][3], over fixed records.
- * Receiver directivity and the path-product reading are not inputs of this gradient;
- * rxvis as in orc_synth. */
+ * Receiver directivity (rx_rot, Bd, El, Az, directivity as in orc_synth; NULL for none)
+ * enters the receiver gradient through the direction of arrival; the path-product reading
+ * is not an input of this gradient; rxvis as in orc_synth. */
 int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* rtot, const int32_t* mat,
              const uint8_t* kind, const uint8_t* vis, int32_t M, const double* rx_pos,
              double f_lo, double f_hi, int32_t F, double c, double A0, double A1, double p_s, int32_t sigma,
              int32_t Q, int32_t Bk, const float* refl_k, const float* beta, const float* diff_coef,
-             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis);
+             const float* passive_coef, const double* g, double* grad_k, double* grad_x, const uint64_t* rxvis,
+             const double* rx_rot, int32_t Bd, int32_t El, int32_t Az, const float* directivity);
 
 /* Passive component: line of sight from the emitter to each receiver (vis[M]) and whether
  * that decision is certified against FP32 traversal (certified[M], may be NULL). */
