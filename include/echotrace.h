@@ -238,7 +238,11 @@ int et_simulate(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, cons
 /* Adjoint of et_synthesize over fixed records: given grad_spectra = dL/dH* as complex64
  * [M][F][2] (for L = sum |H - H_target|^2 this is H - H_target), writes dL/d refl_k as
  * double [Q][Bk] and dL/d rx_pos as double [M][3] (device, overwritten).  Records keep
- * their hit points and visibility ("fixed ray paths").  Directivity must be NULL. */
+ * their hit points and visibility ("fixed ray paths").  With receiver directivity the
+ * receiver gradient includes the change of each band's gain with the direction of arrival
+ * (the gradient of the bilinear table inside the cell that holds the direction; the receiver
+ * orientations rx_rot are not differentiated); such calls run the per-term kernel.
+ * ET_E_UNSUPPORTED for ET_PATH_PRODUCT, Bk > 16, Q*Bk > 256 or F > 12288. */
 int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, const float* grad_spectra,
                            void* ws, size_t ws_bytes, double* grad_k, double* grad_rx);
 

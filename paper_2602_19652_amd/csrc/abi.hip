@@ -421,7 +421,6 @@ int et_synthesize_backward(et_ctx* ctx, const et_sim_desc* sim, const et_paths* 
     validate_paths(paths);
     validate_readings(sim, paths);
     ET_CHECK(grad_spectra && grad_k && grad_rx, ET_E_INVALID, "gradient pointer is NULL");
-    ET_CHECK(!sim->directivity, ET_E_UNSUPPORTED, "the adjoint does not support receiver directivity");
     ET_CHECK(!(sim->flags & ET_PATH_PRODUCT), ET_E_UNSUPPORTED, "the adjoint does not support ET_PATH_PRODUCT");
     ET_CHECK(sim->Bk <= 16 && sim->Q * sim->Bk <= 256, ET_E_UNSUPPORTED, "adjoint needs Bk <= 16 and Q*Bk <= 256");
     ET_CHECK(sim->F <= 12288, ET_E_UNSUPPORTED, "adjoint keeps dL/dH of one receiver in LDS: F <= 12288");
@@ -485,7 +484,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     ET_CHECK(s->M == s0->M && s->F == s0->F && s->Q == s0->Q && s->Bk == s0->Bk, ET_E_INVALID,
              "jobs of a batch must share M, F, Q and Bk");
     if (grad_spectra)
-      ET_CHECK(!s->directivity && !(s->flags & ET_PATH_PRODUCT) && s->Bk <= 16 && s->Q * s->Bk <= 256 &&
+      ET_CHECK(!(s->flags & ET_PATH_PRODUCT) && s->Bk <= 16 && s->Q * s->Bk <= 256 &&
                    s->F <= 12288,
                ET_E_UNSUPPORTED, "adjoint limits exceeded");
     if (s->flags & ET_PER_RX_VISIBILITY) ET_CHECK(s->M <= 64, ET_E_UNSUPPORTED, "ET_PER_RX_VISIBILITY: M <= 64");

@@ -123,6 +123,46 @@ __device__ inline float dir_gain(const float* tab, int El, int Az, float vx, flo
   return (1.f - te) * a0 + te * a1;
 }
 
+// The gain of dir_gain and its gradient (gx, gy, gz) with respect to the direction v: the
+// derivative of the bilinear interpolant inside the cell that holds v, through
+// fa = (az + pi) Az / 2pi - 1/2, fe = (el + pi/2) El / pi - 1/2, az = atan2(y, x) and
+// el = atan2(z, rho); zero across the clamped elevation rows and on the poles.
+__device__ inline float dir_gain_dv(const float* tab, int El, int Az, float vx, float vy, float vz, float& gx,
+                                    float& gy, float& gz) {
+  const float az = atan2f(vy, vx);
+  const float rho2 = vx * vx + vy * vy, rho = sqrtf(rho2);
+  const float el = atan2f(vz, rho);
+  float fa = (az + PI_F) / (2.0f * PI_F) * (float)Az - 0.5f;
+  float fe = (el + 0.5f * PI_F) / PI_F * (float)El - 0.5f;
+  if (!(fa == fa)) fa = 0.f;
+  if (!(fe == fe)) fe = 0.f;
+  const float fl = floorf(fa);
+  const float ta = fa - fl;
+  int i0 = (int)fl % Az;
+  if (i0 < 0) i0 += Az;
+  const int i1 = (i0 + 1) % Az;
+  int j0, j1;
+  float te;
+  bool inner = false;
+  if (fe <= 0.f) { j0 = j1 = 0; te = 0.f; }
+  else if (fe >= (float)(El - 1)) { j0 = j1 = El - 1; te = 0.f; }
+  else { j0 = min((int)floorf(fe), El - 1); j1 = min(j0 + 1, El - 1); te = fe - (float)j0; inner = true; }
+  const float t00 = tab[j0 * Az + i0], t01 = tab[j0 * Az + i1], t10 = tab[j1 * Az + i0], t11 = tab[j1 * Az + i1];
+  const float a0 = (1.f - ta) * t00 + ta * t01;
+  const float a1 = (1.f - ta) * t10 + ta * t11;
+  const float daz = ((1.f - te) * (t01 - t00) + te * (t11 - t10)) * (float)Az / (2.0f * PI_F);
+  const float del = inner ? (a1 - a0) * (float)El / PI_F : 0.f;
+  const float n2 = rho2 + vz * vz;
+  if (rho2 > 0.f && n2 > 0.f) {
+    gx = -daz * vy / rho2 - del * vx * vz / (rho * n2);
+    gy = daz * vx / rho2 - del * vy * vz / (rho * n2);
+    gz = del * rho / n2;
+  } else {
+    gx = gy = gz = 0.f;
+  }
+  return (1.f - te) * a0 + te * a1;
+}
+
 // Returns false if the record does not contribute to receiver m (not visible, hidden from
 // receiver m under the per-receiver line of sight, or a passive record of another receiver).
 __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t n, int m, Pair& q) {
@@ -719,35 +759,58 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
       // block of GANCHOR bins the FP32 sums carry the small weights (k - ka); blocks combine
       // in FP64 as S1 += f_ka sum z + df sum (k - ka) z.
       double s1r = 0.0, s1i = 0.0;
+      // receiver directivity: direction of arrival in the receiver frame, and the sum over
+      // directivity bands d of Re(S_d) grad_v ln D_d(v)
+      float vx = 0.f, vy = 0.f, vz = 0.f;
+      if (a.Bd) arrival(a, q, m, vx, vy, vz);
+      double gvx = 0.0, gvy = 0.0, gvz = 0.0;
       for (int b = 0; b < a.Bk; ++b) {
         const int k0 = (int)(((int64_t)b * a.F + a.Bk - 1) / a.Bk);
         const int k1 = (int)(((int64_t)(b + 1) * a.F + a.Bk - 1) / a.Bk);
         const float blog = band_log2(a, q, b);
         double sbr = 0.0;
-        for (int ka = k0; ka < k1; ka += GANCHOR) {
-          const int ke = min(ka + GANCHOR, k1);
-          const float rev = (float)frac(q.c0 + (double)ka * q.cb);
-          const float amp = exp2f(q.base + (float)ka * q.slope + blog);
-          float tr = amp * __builtin_amdgcn_cosf(rev), ti = amp * __builtin_amdgcn_sinf(rev);
-          float w = 0.f;
-          float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
-          for (int k = ka; k < ke; ++k) {
-            const float2 gg = gl[k];
-            const float zr = gg.x * tr + gg.y * ti;   // Re(conj(g) T)
-            const float zi = gg.x * ti - gg.y * tr;   // Im(conj(g) T)
-            c0r += zr;
-            c0i += zi;
-            c1r += w * zr;
-            c1i += w * zi;
-            const float nr = tr * wr - ti * wi;
-            ti = tr * wi + ti * wr;
-            tr = nr;
-            w += 1.f;
+        // the band's bins in runs of one directivity band (one run without directivity)
+        for (int ks = k0; ks < k1;) {
+          int kr = k1;
+          float dlog = 0.f, dgx = 0.f, dgy = 0.f, dgz = 0.f;
+          if (a.Bd) {
+            const int d = (int)(((int64_t)ks * a.Bd) / a.F);
+            kr = min(k1, (int)(((int64_t)(d + 1) * a.F + a.Bd - 1) / a.Bd));
+            const float D = dir_gain_dv(a.dir + ((size_t)m * a.Bd + d) * a.El * a.Az, a.El, a.Az, vx, vy, vz, dgx,
+                                        dgy, dgz);
+            dlog = log2f(D);
+            const float iD = D > 0.f ? 1.f / D : 0.f;
+            dgx *= iD; dgy *= iD; dgz *= iD;
           }
-          const double fa = a.f_lo + (double)ka * a.df;
-          sbr += (double)c0r;
-          s1r += fa * (double)c0r + a.df * (double)c1r;
-          s1i += fa * (double)c0i + a.df * (double)c1i;
+          double srun = 0.0;
+          for (int ka = ks; ka < kr; ka += GANCHOR) {
+            const int ke = min(ka + GANCHOR, kr);
+            const float rev = (float)frac(q.c0 + (double)ka * q.cb);
+            const float amp = exp2f(q.base + (float)ka * q.slope + blog + dlog);
+            float tr = amp * __builtin_amdgcn_cosf(rev), ti = amp * __builtin_amdgcn_sinf(rev);
+            float w = 0.f;
+            float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
+            for (int k = ka; k < ke; ++k) {
+              const float2 gg = gl[k];
+              const float zr = gg.x * tr + gg.y * ti;   // Re(conj(g) T)
+              const float zi = gg.x * ti - gg.y * tr;   // Im(conj(g) T)
+              c0r += zr;
+              c0i += zi;
+              c1r += w * zr;
+              c1i += w * zi;
+              const float nr = tr * wr - ti * wi;
+              ti = tr * wi + ti * wr;
+              tr = nr;
+              w += 1.f;
+            }
+            const double fa = a.f_lo + (double)ka * a.df;
+            srun += (double)c0r;
+            s1r += fa * (double)c0r + a.df * (double)c1r;
+            s1i += fa * (double)c0i + a.df * (double)c1i;
+          }
+          sbr += srun;
+          gvx += srun * (double)dgx; gvy += srun * (double)dgy; gvz += srun * (double)dgz;
+          ks = kr;
         }
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb)
@@ -787,6 +850,21 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
           double kv = b < a.Bk ? (double)a.refl_k[q.mat * a.Bk + b] : 0.0;
           sb[b] = kv != 0.0 ? 2.0 * sb[b] / kv : 0.0;
         }
+      }
+      if (a.Bd) {
+        // v = -R^T u and du/dx_m = (I - u u^T) / l: d ln D / dx_m = -(I - u u^T) R grad_v ln D / l
+        double w0 = gvx, w1 = gvy, w2 = gvz;
+        if (a.rx_rot) {
+          const double* R = a.rx_rot + 9 * m;
+          w0 = R[0] * gvx + R[1] * gvy + R[2] * gvz;
+          w1 = R[3] * gvx + R[4] * gvy + R[5] * gvz;
+          w2 = R[6] * gvx + R[7] * gvy + R[8] * gvz;
+        }
+        const double uw = q.u[0] * w0 + q.u[1] * w1 + q.u[2] * w2;
+        const double c = 2.0 / q.l;
+        g0 -= c * (w0 - uw * q.u[0]);
+        g1 -= c * (w1 - uw * q.u[1]);
+        g2 -= c * (w2 - uw * q.u[2]);
       }
       gx0 += g0; gx1 += g1; gx2 += g2;
     }
