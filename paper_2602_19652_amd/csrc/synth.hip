@@ -265,15 +265,36 @@ __device__ inline bool batch_chunk(const ChunkTab& ct, int64_t c, int& j, int64_
 }
 
 // Common prologue: the workgroup's arguments and record range, plain or batched.
+// Workgroup -> (record chunk, receiver, tile).  Workgroups reach the eight XCDs in turn (linear
+// id mod 8).  With a chunk count that is a multiple of 8 the linear id reads as (chunk group,
+// receiver and tile, XCD): every XCD works through its chunks one at a time with all receivers
+// and tiles of a chunk together, so they share that XCD's L2 for the chunk's records.  Other
+// chunk counts keep the grid's own coordinates.
+__device__ inline void block_coords(int& p, int& m, int& t) {
+  const int64_t nx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+  if (nx % 8 != 0) {
+    p = blockIdx.x; m = blockIdx.y; t = blockIdx.z;
+    return;
+  }
+  const int64_t L = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const int64_t q = L >> 3, inner = ny * nz;
+  const int64_t mt = q % inner;
+  p = (int)((q / inner) * 8 + (L & 7));
+  m = (int)(mt % ny);
+  t = (int)(mt / ny);
+}
+
 #define SYNTH_RESOLVE()                                                      \
+  int bp, bm, bt;                                                            \
+  block_coords(bp, bm, bt);                                                  \
   SynthArgs a = a0;                                                          \
   int64_t lo, hi;                                                            \
   int jb = 0;                                                                \
   if (BATCH) {                                                               \
-    if (!batch_chunk(ct, blockIdx.x, jb, lo, hi)) return;                    \
+    if (!batch_chunk(ct, bp, jb, lo, hi)) return;                            \
     a = jobs[jb];                                                            \
   } else {                                                                   \
-    chunk_range(ctl->n_vis, a.P, blockIdx.x, lo, hi);                        \
+    chunk_range(ctl->n_vis, a.P, bp, lo, hi);                                \
   }
 
 // ------------------------------------------------------------------ visible-record list
@@ -553,7 +574,7 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArg
   __shared__ __align__(16) GaussBuf buf;
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
-  const int p = blockIdx.x, m = blockIdx.y, k1t = blockIdx.z;
+  const int p = bp, m = bm, k1t = bt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = a.F / K2;
   const int k1_0 = k1t * KT1;
@@ -645,9 +666,9 @@ __global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a0, const SynthAr
                                                      float* __restrict__ part) {
   SYNTH_RESOLVE();
   __shared__ DirectLds L;
-  const int p = blockIdx.x, m = blockIdx.y;
+  const int p = bp, m = bm;
   const int tid = threadIdx.x;
-  const int kbase = blockIdx.z * DTILE + tid * DPT;
+  const int kbase = bt * DTILE + tid * DPT;
   int bk[DPT], bd[DPT];
 #pragma unroll
   for (int i = 0; i < DPT; ++i) {
@@ -734,7 +755,7 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
   __shared__ double kval[16][GB];
   __shared__ int kmat[GB];
   __shared__ double kacc[16 * 16];
-  const int p = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
+  const int p = bp, m = bm, tid = threadIdx.x;
   for (int k = tid; k < a.F; k += GB) gl[k] = make_float2(g[((size_t)m * a.F + k) * 2], g[((size_t)m * a.F + k) * 2 + 1]);
   for (int i = tid; i < a.Q * a.Bk; i += GB) kacc[i] = 0.0;
   double gx0 = 0, gx1 = 0, gx2 = 0;
@@ -933,7 +954,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
   __shared__ double red[256];
-  const int p = blockIdx.x, m = blockIdx.y, k1t = blockIdx.z;
+  const int p = bp, m = bm, k1t = bt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = a.F / K2;
   const int k1_0 = k1t * KT1;
