@@ -1144,19 +1144,32 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   if (tid < QB) gpk[slot * QB + tid] = kacc;
 }
 
-__global__ void k_bwd_reduce(const double* __restrict__ gpx, const double* __restrict__ gpk, int32_t P, int32_t M,
-                             int32_t QB, double* __restrict__ grad_k, double* __restrict__ grad_x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < QB) {
-    double s = 0.0;
-    for (int p = 0; p < P; ++p)
-      for (int m = 0; m < M; ++m) s += gpk[((size_t)p * M + m) * QB + i];
-    grad_k[i] = s;
+// One workgroup per output value (QB band coefficients, then 3 M receiver coordinates): its
+// threads sum fixed strided subsets of the partials in FP64 and a fixed-shape tree in LDS adds
+// the 256 sums, so the result does not depend on scheduling.
+constexpr int RED_T = 256;
+__global__ __launch_bounds__(RED_T) void k_bwd_reduce(const double* __restrict__ gpx, const double* __restrict__ gpk,
+                                                      int32_t P, int32_t M, int32_t QB, double* __restrict__ grad_k,
+                                                      double* __restrict__ grad_x) {
+  __shared__ double red[RED_T];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  if (o < QB) {
+    const int64_t n = (int64_t)P * M;   // partial (p, m) at gpk[((p M) + m) QB + o]
+    for (int64_t e = tid; e < n; e += RED_T) s += gpk[e * QB + o];
+  } else {
+    const int i = o - QB;               // coordinate i = 3 m + c at gpx[p 3 M + i]
+    for (int64_t p = tid; p < P; p += RED_T) s += gpx[p * M * 3 + i];
   }
-  if (i < M * 3) {
-    double s = 0.0;
-    for (int p = 0; p < P; ++p) s += gpx[(size_t)p * M * 3 + i];
-    grad_x[i] = s;
+  red[tid] = s;
+  __syncthreads();
+  for (int h = RED_T / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (o < QB) grad_k[o] = red[0];
+    else grad_x[o - QB] = red[0];
   }
 }
 
@@ -1484,8 +1497,7 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   }
   if (ke) ET_HIP(hipEventRecord(ke, s));
   const int QB = sim->Q * sim->Bk;
-  const int n = std::max(QB, sim->M * 3);
-  k_bwd_reduce<<<(n + 255) / 256, 256, 0, s>>>(ws.gpart_x, ws.gpart_k, ws.gchunks * ws.gtiles, sim->M, QB, grad_k,
+  k_bwd_reduce<<<QB + 3 * sim->M, RED_T, 0, s>>>(ws.gpart_x, ws.gpart_k, ws.gchunks * ws.gtiles, sim->M, QB, grad_k,
                                                 grad_rx);
   ET_HIP(hipGetLastError());
   return mf ? 1 : 2;
