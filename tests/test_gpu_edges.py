@@ -128,3 +128,105 @@ def test_255_bounces_in_a_closed_room(et, ctx):
           f"mismatches {mism}")
     assert per_ray.max() == 255
     assert mism == 0
+
+
+# ----------------------------------------------------------------------------- maximum sizes
+
+def _tiny_materials(scene, sim, Q, Bk, F, n_rays, seed):
+    """The tiny scene with Q materials drawn per triangle and Bk bands."""
+    g = W.rng(seed)
+    scene = dict(scene, tri_material=g.integers(0, Q, len(scene["tris"])).astype(np.int32))
+    sim = dict(sim, F=F, ray_dirs=sim["ray_dirs"][:n_rays],
+               refl_k=g.uniform(0.3, 0.99, (Q, Bk)).astype(np.float32),
+               lobe_beta=g.uniform(0.05, 0.3, (Q, Bk)).astype(np.float32),
+               diff_coef=g.uniform(0.05, 0.3, (Q, Bk)).astype(np.float32))
+    return scene, sim, g
+
+
+def test_adjoint_at_its_limits(et, ctx):
+    """The adjoint at the largest accepted shape (12288 bins, 16 bands, 16 materials, so
+    Q Bk = 256) against the oracle gradient; one step past each limit is refused with
+    ET_E_UNSUPPORTED."""
+    import torch
+    base_scene, base_sim = W.tiny_scene(n_rays=1024)
+    scene, sim, g = _tiny_materials(base_scene, base_sim, 16, 16, 12288, 1024, 51)
+    ref = O.trace(scene, sim, certify=False)
+    hidden = dict(sim, refl_k=g.uniform(0.3, 0.99, (16, 16)).astype(np.float32))
+    H_star = O.synth(ref, hidden)
+    H = O.synth(ref, sim)
+    gk_ref, gx_ref = O.grad(ref, sim, H - H_star)
+    P = et.Paths.from_records(ref)
+    gk, gx = et.synthesize_backward(ctx, et.Sim(sim), P, torch.as_tensor(H - H_star).to("cuda"))
+    st = ctx.stats()
+    ek, ex = rel_l2(gk.cpu().numpy(), gk_ref), rel_l2(gx.cpu().numpy(), gx_ref)
+    print(f"adjoint at F=12288, Q=Bk=16 (kernel {st.adjoint_kernel}, {len(ref['rtot'])} records): "
+          f"dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    assert st.adjoint_kernel == 1
+    assert ek <= TOL and ex <= TOL
+    over = [dict(sim, F=12352),                                                        # F > 12288
+            dict(sim, refl_k=np.full((16, 17), 0.5, np.float32), lobe_beta=np.full((16, 17), 0.2, np.float32),
+                 diff_coef=np.full((16, 17), 0.1, np.float32)),                      # Bk > 16
+            dict(sim, refl_k=np.full((17, 16), 0.5, np.float32), lobe_beta=np.full((17, 16), 0.2, np.float32),
+                 diff_coef=np.full((17, 16), 0.1, np.float32))]                      # Q Bk > 256
+    for bad in over:
+        s = et.Sim(bad)
+        gb = torch.zeros(s.M, s.F, dtype=torch.complex64, device="cuda")
+        with pytest.raises(et.EchoError) as err:
+            et.synthesize_backward(ctx, s, P, gb)
+        assert err.value.status == -5
+
+
+@pytest.mark.parametrize("F", [4096, 65536])
+def test_synthesis_with_64_bands(et, ctx, F):
+    """The largest band tables: 64 material bands and a 64-band receiver directivity.  At
+    4096 bins every 64-bin row is its own band (more segments per tile than the factorised
+    kernel holds, so the per-term kernel runs); at 65536 bins the bands span 1024 bins and the
+    factorised kernel runs over 16 tiles.  Sampled bins against the oracle."""
+    base_scene, base_sim = W.tiny_scene(n_rays=2048)
+    scene, sim, g = _tiny_materials(base_scene, base_sim, 3, 64, F, 2048, 52)
+    sim = dict(sim, directivity=W.directivity_table(g, len(sim["rx_pos"]), Bd=64, El=16, Az=32), f_hi=200e3)
+    ref = O.trace(scene, sim, certify=False)
+    bins = np.sort(W.rng(9).choice(F, 96, replace=False))
+    H_ref = O.synth(ref, sim, bins=bins)
+    H = et.synthesize(ctx, et.Sim(sim), et.Paths.from_records(ref)).cpu().numpy()
+    st = ctx.stats()
+    e = rel_l2(H[:, bins], H_ref)
+    print(f"64 bands, F={F}: kernel {st.synth_kernel}, rel L2 {e:.3e}")
+    assert st.synth_kernel == (2 if F == 4096 else 1)
+    assert e <= TOL
+
+
+def test_per_receiver_visibility_at_64_receivers(et, ctx):
+    """Per-receiver line of sight at its limit of 64 receivers (a ring of 64 around the
+    emitter, the screen scene hiding part of the wall from some of them): every certified
+    record's 64 receiver bits equal the oracle's; 65 receivers are refused."""
+    from test_gpu_parity import _screen_scene
+    import math
+    scene = _screen_scene()
+    g = W.rng(14)
+    ang = np.linspace(0, 2 * math.pi, 64, endpoint=False)
+    rx = np.stack([np.zeros(64), 0.35 * np.cos(ang), 0.35 * np.sin(ang)], 1)
+    sim = W.make_sim(emitter_pos=[0, 0, 0], emitter_rot=np.eye(3), rx_pos=rx,
+                     ray_dirs=W.cone_directions(g, 4096, math.radians(35)), max_bounces=3, f_lo=20e3, f_hi=100e3,
+                     F=256, refl_k=np.full((2, 8), 0.9, np.float32), lobe_beta=np.full((2, 8), 0.3, np.float32),
+                     diff_coef=np.full((2, 8), 0.1, np.float32), per_rx_visibility=True)
+    ref = O.trace(scene, sim)
+    dirs = sim["ray_dirs"][ref["certified"]]
+    ref_c = O.trace(scene, sim, dirs=dirs)
+    bits = ref_c["rxvis"]
+    assert np.any(bits != bits[0]) and np.any(bits >> np.uint64(63))
+    sc = et.Scene(ctx, scene)
+    P = et.trace(ctx, sc, et.Sim(sim, ray_dirs=dirs))
+    h = P.to_host()
+    order_g = np.lexsort((h["bounce"], h["ray"]))
+    order_o = np.lexsort((ref_c["bounce"], ref_c["ray"]))
+    assert np.array_equal(h["ray"][order_g], ref_c["ray"][order_o])
+    assert np.array_equal(h["rxvis"][order_g], ref_c["rxvis"][order_o])
+    print(f"64 receivers: {len(bits)} records, {np.mean([bin(int(b)).count('1') for b in bits]):.1f} receivers "
+          f"in sight per record")
+    rx65 = np.concatenate([rx, [[0.0, 0.0, 0.5]]])
+    s65 = et.Sim(dict(sim, rx_pos=rx65, rx_rot=np.repeat(np.eye(3)[None], 65, axis=0),
+                      x_ref=rx65.mean(0)), ray_dirs=dirs)
+    with pytest.raises(et.EchoError) as err:
+        et.trace(ctx, sc, s65)
+    assert err.value.status == -5
