@@ -604,25 +604,25 @@ __global__ void k_qweight(SceneDev S, DiffArgs a, const uint8_t* __restrict__ oe
   flag[t] = qq > 0 ? 1ull : 0ull;
 }
 
-// Sort keys of the eligible triangles, listed in increasing index.  One CDF: weight
-// descending, then index ascending.  Per mesh: the mesh first, then weight descending; the
-// stable sort keeps increasing indices among equal weights.
+// Sort keys of the eligible triangles, listed in increasing index: weight descending (one
+// CDF), or the mesh first and then weight descending (per mesh).  The radix sort is stable,
+// so equal weights keep increasing indices without the index in the key (32 key bits, four
+// passes, for one CDF).
 __global__ void k_elig_keys(SceneDev S, int per_mesh, const uint64_t* __restrict__ q, const uint64_t* __restrict__ flag,
                             const uint64_t* __restrict__ offs, uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= S.T || !flag[t]) return;
   const int64_t p = (int64_t)offs[t];
-  keys[p] = per_mesh ? ((uint64_t)S.obj[t] << 32) | (4294967296ull - q[t])
-                     : ((4294967296ull - q[t]) << 31) | (uint64_t)t;
+  keys[p] = per_mesh ? ((uint64_t)S.obj[t] << 32) | (4294967296ull - q[t]) : (4294967296ull - q[t]);
   vals[p] = (int32_t)t;
 }
 
 __global__ void k_elig_count(Ctl* ctl) { ctl->n_elig = (int64_t)ctl->tot[1]; }
 
-__global__ void k_sorted_q(const uint64_t* __restrict__ keys, int per_mesh, const Ctl* ctl, uint64_t* __restrict__ qs) {
+__global__ void k_sorted_q(const uint64_t* __restrict__ keys, const Ctl* ctl, uint64_t* __restrict__ qs) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ctl->n_elig) return;
-  qs[i] = 4294967296ull - (per_mesh ? (keys[i] & 0xffffffffull) : (keys[i] >> 31));
+  qs[i] = 4294967296ull - (keys[i] & 0xffffffffull);
 }
 
 // Group starts in the sorted list: a group per mesh (per_mesh), else one group.
@@ -1013,9 +1013,9 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     scan_exclusive_u64(w.dflags, w.doffs, S.T, nullptr, S.T, &ctl->tot[1], w.scan_tmp, s);
     k_elig_keys<<<nblk_full(S.T), BS, 0, s>>>(S, d.per_mesh, w.dq, w.dflags, w.doffs, w.dkeys, w.dvals);
     k_elig_count<<<1, 1, 0, s>>>(ctl);
-    radix_sort_u64(w.dkeys, w.dvals, 0, &ctl->n_elig, S.T, d.per_mesh ? 32 + obj_bits : 64, w.sort_tmp, s);
+    radix_sort_u64(w.dkeys, w.dvals, 0, &ctl->n_elig, S.T, d.per_mesh ? 32 + obj_bits : 32, w.sort_tmp, s);
     // weights in sorted order, then their exclusive prefix sums (the CDF) and total
-    k_sorted_q<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, d.per_mesh, ctl, w.dq);
+    k_sorted_q<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, ctl, w.dq);
     scan_exclusive_u64(w.dq, w.doffs, 0, &ctl->n_elig, S.T, nullptr, w.scan_tmp, s);
     // groups of the sorted list (meshes, or one) and the number of draws
     k_group_flags<<<nblk_full(S.T), BS, 0, s>>>(w.dkeys, d.per_mesh, ctl, w.dflags);
