@@ -579,13 +579,20 @@ __global__ void k_obj_fov(SceneDev S, DiffArgs a, uint8_t* oel) {
   oel[o] = psi <= a.cone + asin(rad / dist);
 }
 
+// Largest C_i over the field-of-view objects: positive doubles order as their bit patterns, so
+// a wave takes the maximum of the bits by shuffles and issues one atomic.
 __global__ void k_cmax(SceneDev S, const uint8_t* __restrict__ oel, Ctl* ctl) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= S.T) return;
-  if (oel[S.obj[t]]) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  long long v = 0;
+  if (t < S.T && oel[S.obj[t]]) {
     const double c = S.C[t];
-    if (c > 0.0) atomicMax((unsigned long long*)&ctl->cmax_bits, (unsigned long long)__double_as_longlong(c));
+    if (c > 0.0) v = __double_as_longlong(c);
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    const long long o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax((unsigned long long*)&ctl->cmax_bits, (unsigned long long)v);
 }
 
 __global__ void k_qweight(SceneDev S, DiffArgs a, const uint8_t* __restrict__ oel, const Ctl* ctl,
