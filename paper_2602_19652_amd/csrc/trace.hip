@@ -379,8 +379,9 @@ __global__ void k_ray_init(PoseArgs a0, const float* __restrict__ dirs0, const T
 // Six waves per SIMD (the register budget that asks for, 80, holds the kernel without spills):
 // measured 7% faster on the room's trace and 15% on foliage's than five.
 template <bool COUNT, bool BATCH, bool PERRX>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(TRAV_WAVES_PER_SIMD))) void k_bounce(SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w,
-                                               Ctl* ctl, int j, const double* __restrict__ rxp, int32_t M) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(TRAV_WAVES_PER_SIMD))) void k_bounce(
+    SceneDev S0, PoseArgs a0, const TraceJob* __restrict__ jobs, TraceWS w, Ctl* ctl, int j,
+    const double* __restrict__ rxp, int32_t M) {
   __shared__ int lds_stack[TRAV_LDS_STACK * BS];
   const int cur = j & 1;
   const int64_t n = ctl->n_active[cur];
