@@ -193,8 +193,8 @@ typedef struct {
  * component), caller-owned device SoA arrays of `capacity` entries.  Order: specular
  * records bounce-major (all bounce-0 hits, then bounce 1, ...); within a bounce the rays
  * follow the library's traversal order (ray order, or sorted by direction when there are
- * more rays than threads in the traversal grid; deterministic either way; `ray` names each
- * record's ray).  Kept diffraction samples follow in sample order, then with ET_PASSIVE one
+ * more rays than the device holds threads of the traversal kernel at once; deterministic
+ * either way; `ray` names each record's ray).  Kept diffraction samples follow in sample order, then with ET_PASSIVE one
  * record per receiver m (the emitter as the point, rtot 0, mat = ray = m) that reaches
  * receiver m only.  count (device int64[4]) = {records, specular, diffraction, segments};
  * passive records = records - specular - diffraction. */
