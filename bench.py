@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=1024, help="rays of the oracle's bounded sample")
+    ap.add_argument("--cpu-rays", type=int, default=32768, help="rays of the oracle's bounded sample (about 10 s of host work)")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baselines (for rocprofv3)")
     ap.add_argument("--no-extra-legs", action="store_true",
                     help="skip the dynamic-scene and other-workload legs (a kernel trace then holds only the "
