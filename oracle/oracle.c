@@ -544,9 +544,10 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
       v3 dn = kd == 0 ? ld3d(dout + 3 * n) : mk(1, 0, 0);
       pair_t q = pair_setup(pn, dn, rtot[n], kd, xm);
       double Lgeo = pow(q.r, -p_s);
-      double Sb[2 * 64], Sd[64], Dg[64];
+      double Sb[2 * 64], Sk[64], Sd[64], Dg[64];
       v3 dDg[64];
       memset(Sb, 0, sizeof(double) * 2 * Bk);
+      memset(Sk, 0, sizeof(double) * Bk);
       const double* Rm = rx_rot ? rx_rot + 9 * m : NULL;
       if (directivity) {
         /* gain per directivity band and its gradient in the receiver frame (as in orc_synth) */
@@ -561,10 +562,11 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
         double f = f_lo + (double)k * df;
         int64_t b = (k * Bk) / F;
         double Latm = pow(10.0, -(A0 + A1 * f) * q.r / 20.0);
-        double I;
+        double I, lobe = 0.0;
         if (kd == 0) {
           double bt = (double)beta[mat[n] * Bk + b];
-          I = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt)) * (double)refl_k[mat[n] * Bk + b];
+          lobe = exp(-(q.gamma * q.gamma) / (2.0 * bt * bt));
+          I = lobe * (double)refl_k[mat[n] * Bk + b];
         } else if (kd == 1) {
           I = (double)diff_coef[mat[n] * Bk + b];
         } else {
@@ -578,6 +580,12 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
         double gr = g[2 * ((size_t)m * F + k)], gi = g[2 * ((size_t)m * F + k) + 1];
         /* conj(g) * T */
         double zr = gr * Tr + gi * Ti, zi = gr * Ti - gi * Tr;
+        if (kd == 0) {
+          /* H is linear in k (Eq. 2): dT/dk is T with the factor k left out, also where k = 0 */
+          double Ak = Lgeo * Latm * lobe;
+          if (directivity) Ak *= Dg[(k * Bd) / F];
+          Sk[b] += gr * Ak * cos(ph) + gi * Ak * sin(ph);
+        }
         Sb[2 * b] += zr;
         Sb[2 * b + 1] += zi;
         if (directivity) Sd[(k * Bd) / F] += zr;
@@ -600,8 +608,7 @@ int orc_grad(int64_t n_rec, const double* p, const double* dout, const double* r
         for (int b = 0; b < Bk; ++b) {
           double bt = (double)beta[mat[n] * Bk + b];
           wsum += Sb[2 * b] / (2.0 * bt * bt);
-          double kv = (double)refl_k[mat[n] * Bk + b];
-          if (kv != 0.0) gk[mat[n] * Bk + b] += 2.0 * Sb[2 * b] / kv;
+          gk[mat[n] * Bk + b] += 2.0 * Sk[b];
         }
         grad = sub(grad, scl(dg2, 2.0 * wsum));
       }

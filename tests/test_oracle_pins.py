@@ -169,6 +169,45 @@ def test_box_room_unfolding():
     assert checked > 180
 
 
+def test_max_distance_between_parallel_walls():
+    """Algorithm 1 records a hit and then stops the ray once its path reaches MaxDistance.
+    Between walls x = 0 and x = D with the emitter at x = e, a ray at angle theta to the x axis
+    reaches its n-th wall after r_n = ((D - e) + (n - 1) D) / cos(theta); the ray keeps exactly
+    the records up to the first r_n >= MaxDistance (or max_bounces of them)."""
+    D, e = 3.0, 1.0
+    mb = W.MeshBuilder()
+    for x in (0.0, D):
+        mb.add(np.array([[x, -50, -50], [x, 50, -50], [x, 50, 50], [x, -50, 50]], float),
+               np.array([[0, 1, 2], [0, 2, 3]]), 0)
+    scene = mb.build()
+    th = np.radians([0.0, 17.0, 41.0])
+    dirs = np.stack([np.cos(th), np.sin(th) * 0.6, np.sin(th) * 0.8], 1).astype(np.float32)
+    B = 8
+    for md in (0.5, 4.0, 6.5, 13.9, 40.0, math.inf):
+        sim = _sim(emitter_pos=[e, 0.1, -0.2], ray_dirs=dirs, max_bounces=B, max_distance=md,
+                   rx_pos=[[e, 0.12, -0.2]])
+        rec = O.trace(scene, sim)
+        for i in range(len(dirs)):
+            d = dirs[i].astype(np.float64)
+            c = d[0] / np.linalg.norm(d)
+            r = ((D - e) + np.arange(B) * D) / c
+            n = int(np.argmax(r >= md)) + 1 if np.any(r >= md) else B
+            sel = rec["ray"] == i
+            assert sel.sum() == n, (md, i)
+            np.testing.assert_allclose(rec["rtot"][sel], r[:n], rtol=1e-12)
+            assert rec["certified"][i]
+    # a path that reaches MaxDistance within the FP32 margin is not certified
+    sim = _sim(emitter_pos=[e, 0.1, -0.2], ray_dirs=dirs[:1], max_bounces=B, max_distance=5.0 * (1 + 1e-9),
+               rx_pos=[[e, 0.12, -0.2]])
+    rec = O.trace(scene, sim)
+    assert not rec["certified"][0]
+    # an exact tie stops the ray (r >= MaxDistance): along the axis the paths 2 and 5 are exact
+    sim = _sim(emitter_pos=[e, 0.1, -0.2], ray_dirs=dirs[:1], max_bounces=B, max_distance=5.0,
+               rx_pos=[[e, 0.12, -0.2]])
+    rec = O.trace(scene, sim)
+    assert list(rec["rtot"]) == [2.0, 5.0]
+
+
 # ---------------------------------------------------------------------------------------- reciprocity
 
 def test_reciprocity_single_point():
@@ -265,6 +304,89 @@ def test_curvature_flat_plane():
     assert np.all(G[~interior] > 1e-3)                    # open boundary: one-sided cotangents
     inner_tri = interior[t].all(1)
     assert np.all(C[inner_tri] == 0)
+
+
+def _fan(apex, rim):
+    """One-ring of the vertex `apex` (index 0): triangles (apex, rim[i], rim[i + 1]), closed."""
+    v = np.vstack([apex, rim]).astype(np.float32)
+    n = len(rim)
+    t = np.array([[0, 1 + i, 1 + (i + 1) % n] for i in range(n)], np.int32)
+    return v, t
+
+
+def _ring_area(v, t, apex):
+    w = np.asarray(v, np.float64).copy()
+    w[0] = apex
+    a = w[t[:, 1]] - w[t[:, 0]]
+    b = w[t[:, 2]] - w[t[:, 0]]
+    return 0.5 * np.sum(np.linalg.norm(np.cross(a, b), axis=1))
+
+
+def _angles(v, t):
+    """Interior angles [T][3] (radians) at the triangles' three corners, FP64."""
+    w = np.asarray(v, np.float64)
+    out = np.zeros((len(t), 3))
+    for c in range(3):
+        a = w[t[:, (c + 1) % 3]] - w[t[:, c]]
+        b = w[t[:, (c + 2) % 3]] - w[t[:, c]]
+        out[:, c] = np.arctan2(np.linalg.norm(np.cross(a, b), axis=1), np.sum(a * b, axis=1))
+    return out
+
+
+def test_curvature_regular_pyramid_apex_closed_forms():
+    """Apex of a regular pyramid (n rim vertices at radius R, apex height h): the cotangent
+    operator of Eq. (1) (Meyer et al.) gives |K| = |grad of the one-ring area| / A_mixed.
+    Non-obtuse one-ring (n = 6): the Voronoi areas give G = 2h / (R^2 + h^2).  Obtuse apex
+    (n = 3, h^2 < R^2 / 2): A_mixed = half the ring's area, G = h / (R^2 cos^2(pi/3) + h^2)."""
+    R = 1.0
+    for n, h, expect in ((6, 0.45, lambda h: 2 * h / (R * R + h * h)),
+                         (3, 0.30, lambda h: h / (R * R * math.cos(math.pi / 3) ** 2 + h * h))):
+        ang = 2 * math.pi * np.arange(n) / n
+        rim = np.stack([R * np.cos(ang), R * np.sin(ang), np.zeros(n)], 1)
+        v, t = _fan([0, 0, h], rim)
+        h32 = float(v[0, 2])   # the FP32 apex the oracle sees (the rim is exact in FP32 up to rounding)
+        G, _ = O.curvature({"vertices": v, "tris": t}, 1.0)
+        A = _angles(v, t)
+        if n == 3:
+            assert np.all(A[:, 0] > math.pi / 2)            # obtuse at the apex
+        else:
+            assert np.all(A < math.pi / 2)
+        # closed form on the FP32 geometry: rim radius and apex height as stored
+        R32 = float(np.mean(np.linalg.norm(v[1:, :2].astype(np.float64), axis=1)))
+        if n == 6:
+            want = 2 * h32 / (R32 * R32 + h32 * h32)
+        else:
+            want = h32 / (R32 * R32 * math.cos(math.pi / 3) ** 2 + h32 * h32)
+        np.testing.assert_allclose(G[0], want, rtol=1e-6)
+        assert abs(want - expect(h)) < 1e-6 * want
+
+
+def test_curvature_obtuse_one_ring_mixed_area():
+    """A one-ring whose triangles are all obtuse, some at the centre vertex and some at a rim
+    vertex.  Meyer et al.'s mixed area is then area/2 for a triangle obtuse at the vertex and
+    area/4 for one obtuse elsewhere; the cotangent sum is twice the gradient of the ring's area
+    with respect to the vertex (central differences of plain triangle areas here), so
+    G = |grad A_ring| / (2 A_mixed).  Swapping the two weights changes G by far more than the
+    tolerance."""
+    phi = np.radians([0.0, 140.0, 195.0, 250.0, 305.0])
+    r = np.array([1.0, 1.0, 0.3, 1.0, 0.3])
+    rim = np.stack([r * np.cos(phi), r * np.sin(phi), np.array([0.0, 0.02, -0.01, 0.03, -0.02])], 1)
+    v, t = _fan([0.0, 0.0, 0.05], rim)
+    A = _angles(v, t)
+    obt_c = A[:, 0] > math.pi / 2
+    obt_o = (A[:, 1:] > math.pi / 2).any(1)
+    assert np.all(obt_c | obt_o) and obt_c.any() and obt_o.any()
+    assert np.min(np.abs(A - math.pi / 2)) > 0.1          # clear of right angles
+    w = np.asarray(v, np.float64)
+    area = 0.5 * np.linalg.norm(np.cross(w[t[:, 1]] - w[t[:, 0]], w[t[:, 2]] - w[t[:, 0]]), axis=1)
+    a_mixed = np.sum(np.where(obt_c, area / 2, area / 4))
+    hd = 1e-6
+    grad = np.array([(_ring_area(v, t, w[0] + hd * e) - _ring_area(v, t, w[0] - hd * e)) / (2 * hd) for e in np.eye(3)])
+    want = np.linalg.norm(grad) / (2 * a_mixed)
+    G, _ = O.curvature({"vertices": v, "tris": t}, 1.0)
+    swapped = np.linalg.norm(grad) / (2 * np.sum(np.where(obt_c, area / 4, area / 2)))
+    assert abs(swapped - want) > 0.05 * want
+    np.testing.assert_allclose(G[0], want, rtol=1e-7)
 
 
 def test_curvature_box_edges():
@@ -437,6 +559,29 @@ def test_adjoint_matches_finite_differences():
             np.testing.assert_allclose(gx[m, a], fd, rtol=1e-5, atol=1e-9 * max(1.0, abs(fd)))
 
 
+def test_adjoint_at_zero_coefficients_matches_finite_differences():
+    """H is linear in k (Eq. 2), so dL/dk_qb does not vanish where k_qb = 0: central
+    differences of L in FP64 (k - h < 0 included, the magnitude is linear through zero) match
+    the analytic gradient at bands whose coefficient is exactly zero and at the others."""
+    scene, sim = W.tiny_scene(n_rays=48, F=64)
+    g = W.rng(33)
+    k = g.uniform(0.3, 0.99, (1, 8)).astype(np.float32)
+    k[0, 2] = 0.0
+    k[0, 5] = 0.0
+    sim = dict(sim, refl_k=k, lobe_beta=np.ascontiguousarray(g.uniform(0.1, 0.3, (1, 8)).astype(np.float32)))
+    rec = O.trace(scene, sim)
+    Hstar = O.synth(rec, dict(sim, refl_k=g.uniform(0.3, 0.99, (1, 8)).astype(np.float32)))
+    gk, _ = O.grad(rec, sim, O.synth(rec, sim) - Hstar)
+    h = 1e-3
+    for b in range(8):
+        kp = k.copy(); kp[0, b] += h
+        km = k.copy(); km[0, b] -= h
+        dk = float(kp[0, b]) - float(km[0, b])      # the FP32 steps actually taken
+        fd = (_loss(rec, dict(sim, refl_k=kp), Hstar) - _loss(rec, dict(sim, refl_k=km), Hstar)) / dk
+        np.testing.assert_allclose(gk[0, b], fd, rtol=1e-6, atol=1e-12)
+    assert abs(gk[0, 2]) > 1e-3 * np.max(np.abs(gk)) and abs(gk[0, 5]) > 1e-3 * np.max(np.abs(gk))
+
+
 def test_directivity_adjoint_matches_finite_differences():
     """With receiver directivity (a rough random 64 x 32 table per band and receiver, rotated
     receiver frames), central differences of L with respect to every receiver coordinate match
@@ -469,6 +614,73 @@ def test_directivity_adjoint_matches_finite_differences():
             sm = dict(sim); sm["rx_pos"] = sim["rx_pos"].copy(); sm["rx_pos"][m, a] -= h
             fd = (_loss(rec, sp, Hstar) - _loss(rec, sm, Hstar)) / (2 * h)
             np.testing.assert_allclose(gx[m, a], fd, rtol=1e-5, atol=1e-9 * max(1.0, abs(fd)))
+
+
+def _directivity_probe(table, v_local, rx, R):
+    """|H| of one secondary-source record seen by a receiver at rx with frame R, arriving from
+    the receiver-frame direction v_local: with no spreading, no absorption and I_d = 1 every
+    bin's magnitude is the receiver gain of its directivity band (F = Bd bins, one per band)."""
+    M, Bd, El, Az = table.shape
+    v = np.asarray(v_local, np.float64)
+    p = np.asarray(rx, np.float64) + 1.7 * (np.asarray(R) @ (v / np.linalg.norm(v)))
+    rec = {"p": p[None], "dout": np.zeros((1, 3)), "rtot": np.array([0.3]), "mat": np.zeros(1, np.int32),
+           "kind": np.ones(1, np.uint8), "vis": np.ones(1, np.uint8)}
+    sim = _sim(rx_pos=[rx], rx_rot=np.asarray(R)[None], F=Bd, f_lo=40e3, f_hi=41e3, spreading_p=0.0, atm_a1=0.0,
+               diff_coef=np.ones((1, 1)), refl_k=np.ones((1, 1)), lobe_beta=np.ones((1, 1)), directivity=table)
+    return np.abs(O.synth(rec, sim)[0])
+
+
+def _cell_dir(az, el):
+    return [math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)]
+
+
+def test_directivity_lookup_cell_centres_and_between():
+    """Receiver directivity (the receiver transfer function of the signal-generation section,
+    read as a real gain on a cell-centred azimuth/elevation grid in the receiver frame, bilinear,
+    periodic in azimuth, clamped in elevation), seen through a receiver turned by a known yaw and
+    pitch:
+      * at the centre of cell (i, j) (az = -pi + (i + 1/2) 2pi/Az, el = -pi/2 + (j + 1/2) pi/El)
+        the gain is the table entry itself;
+      * a table linear in the cell-centre angles is reproduced exactly in between;
+      * across the azimuth seam (between the last and the first centre) it interpolates the two;
+      * beyond the outermost elevation centre it keeps that row's value."""
+    El, Az, Bd = 8, 16, 2
+    yaw, pitch = 0.7, -0.4
+    rz = np.array([[math.cos(yaw), -math.sin(yaw), 0], [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]])
+    ry = np.array([[math.cos(pitch), 0, math.sin(pitch)], [0, 1, 0], [-math.sin(pitch), 0, math.cos(pitch)]])
+    R = rz @ ry
+    rx = [0.3, -0.2, 0.5]
+    da, de = 2 * math.pi / Az, math.pi / El
+    az_c = -math.pi + (np.arange(Az) + 0.5) * da
+    el_c = -math.pi / 2 + (np.arange(El) + 0.5) * de
+    g = W.rng(17)
+    rough = g.uniform(0.2, 1.0, (1, Bd, El, Az)).astype(np.float32)
+    for (i, j) in [(0, 0), (3, 5), (15, 7), (8, 2), (11, 4)]:
+        got = _directivity_probe(rough, _cell_dir(az_c[i], el_c[j]), rx, R)
+        np.testing.assert_allclose(got, rough[0, :, j, i], rtol=1e-9)
+    # a table linear in the centre angles: D = a + b az + c el (band 1 with other coefficients)
+    coef = [(1.5, 0.05, 0.1), (2.0, -0.07, 0.2)]
+    lin = np.zeros((1, Bd, El, Az), np.float32)
+    for b, (a0, a1, a2) in enumerate(coef):
+        lin[0, b] = a0 + a1 * az_c[None, :] + a2 * el_c[:, None]
+    for az, el in [(0.3, 0.2), (-1.1, -0.9), (2.5, 1.1), (-2.9, 0.05)]:
+        got = _directivity_probe(lin, _cell_dir(az, el), rx, R)
+        # bilinear interpolation of the stored FP32 samples of a linear function is that function
+        # (up to the FP32 rounding of the samples)
+        want = np.array([a0 + a1 * az + a2 * el for (a0, a1, a2) in coef])
+        np.testing.assert_allclose(got, want, rtol=3e-7)
+    # azimuth seam: a quarter of the way from the last centre (pi - da/2) to the first (-pi + da/2)
+    saw = np.zeros((1, Bd, El, Az), np.float32)
+    saw[0, :, :, :] = np.arange(Az, dtype=np.float32)[None, None, :] + 100 * np.arange(El, dtype=np.float32)[None, :, None]
+    got = _directivity_probe(saw, _cell_dir(math.pi - da / 4, el_c[3]), rx, R)
+    np.testing.assert_allclose(got, 0.75 * (Az - 1) + 0.25 * 0 + 300, rtol=1e-9)
+    got = _directivity_probe(saw, _cell_dir(-math.pi + da / 4, el_c[3]), rx, R)
+    np.testing.assert_allclose(got, 0.25 * (Az - 1) + 0.75 * 0 + 300, rtol=1e-9)
+    # elevation beyond the top and bottom centres: clamped to those rows
+    got = _directivity_probe(lin, _cell_dir(0.4, math.pi / 2 - de / 5), rx, R)
+    np.testing.assert_allclose(got, [a0 + a1 * 0.4 + a2 * el_c[-1] for (a0, a1, a2) in coef], rtol=3e-7)
+    got = _directivity_probe(lin, _cell_dir(-0.6, -math.pi / 2 + de / 3), rx, R)
+    np.testing.assert_allclose(got, [a0 - a1 * 0.6 + a2 * el_c[0] for (a0, a1, a2) in coef], rtol=3e-7)
 
 
 def test_spectrum_linear_in_band_coefficients():
