@@ -25,9 +25,11 @@
  *  - A context is used by one host thread at a time.  Scenes are immutable after build
  *    and may be shared by contexts on the same device.
  *  - Host-side validation (shapes, null pointers, ranges of scalar parameters) runs
- *    before any launch; array contents on the device are trusted, except that the mesh's
- *    index arrays are range-checked on the device during scene build (which then returns
- *    ET_E_INVALID).
+ *    before any launch; array contents on the device are trusted, except that the mesh is
+ *    checked on the device during scene build (vertex and object indices in range, materials
+ *    >= 0, finite coordinates of the vertices that triangles use; otherwise ET_E_INVALID) and
+ *    a trace refuses a pose whose band tables have fewer rows (Q) than the scene's largest
+ *    material index needs (ET_E_INVALID).
  *  - Angles are radians, lengths metres, frequencies Hz.  Rotation matrices are 3x3
  *    row-major, their columns are the local axes expressed in world coordinates
  *    (world = R * local).
@@ -121,8 +123,10 @@ int et_scene_curvature(et_ctx* ctx, const et_scene* scene, double* C_out, double
  * blob bit for bit and traces of a refitted scene hit what a fresh build hits.  Large
  * deformations keep a valid but looser tree: sah_cost of et_scene_get_info is recomputed
  * (rebuild when it grows).  Ordered on the context's stream; returns after the refit
- * finished; refits of one scene must not overlap.  Errors: ET_E_INVALID for NULL pointers,
- * ET_E_DEVICE for device failures (the scene is then unusable and must be rebuilt). */
+ * finished; refits of one scene must not overlap.  Errors: ET_E_INVALID for NULL pointers and
+ * for a non-finite coordinate of a vertex that a triangle uses (the scene must then be refitted
+ * to finite vertices before it is traced again), ET_E_DEVICE for device failures (the scene is
+ * then unusable and must be rebuilt). */
 int et_scene_refit(et_ctx* ctx, et_scene* scene, const float* vertices, double area_ref);
 
 /* ------------------------------------------------------------------ one pose (one emitter) */
@@ -384,6 +388,14 @@ int et_get_stats(et_ctx* ctx, et_stats* out);   /* synchronises the context stre
 int et_set_counting(et_ctx* ctx, int enable);
 typedef struct { int64_t nodes_closest, tris_closest, nodes_any, tris_any, rays_closest, rays_any; } et_counters;
 int et_get_counters(et_ctx* ctx, et_counters* out);
+
+/* Test hook for the overflow path of the traversal stack (normally unreachable: 64 entries per
+ * lane hold any tree this library builds for up to 2^31 triangles in practice).  Limits the
+ * per-lane stack of later traces on this context to `entries` (1 .. 64; 0 restores 64).  A
+ * traversal that needs more drops the subtrees that do not fit, so those rays may miss their
+ * true hits; every kernel still completes, and et_get_stats reports the dropped pushes in
+ * stack_overflows with status ET_E_INTERNAL.  ET_E_INVALID outside [0, 64]. */
+int et_set_stack_limit(et_ctx* ctx, int32_t entries);
 
 #ifdef __cplusplus
 }

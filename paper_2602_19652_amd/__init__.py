@@ -28,9 +28,10 @@ STATUS = {0: "ET_OK", -1: "ET_E_INVALID", -2: "ET_E_WORKSPACE", -3: "ET_E_CAPACI
 
 
 class EchoError(RuntimeError):
-    def __init__(self, status: int, msg: str):
+    def __init__(self, status: int, msg: str, stats=None):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+        self.stats = stats     # the statistics of a failing et_get_stats (deferred device-side status)
 
 
 # ------------------------------------------------------------------ ABI structs
@@ -135,6 +136,7 @@ def lib():
             "et_get_stats": ([vp, C.POINTER(Stats)], C.c_int),
             "et_set_counting": ([vp, C.c_int], C.c_int),
             "et_get_counters": ([vp, C.POINTER(Counters)], C.c_int),
+            "et_set_stack_limit": ([vp, i32], C.c_int),
             "et_get_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
             "et_set_tuning": ([vp, C.POINTER(Tuning)], C.c_int),
             "et_autotune_batch": ([vp, i32, C.POINTER(Job), vp, sz, vp, vp, vp, vp, C.POINTER(Tuning)], C.c_int),
@@ -196,7 +198,7 @@ class Context:
         st = Stats()
         rc = lib().et_get_stats(self.h, C.byref(st))
         if rc != 0:
-            raise EchoError(rc, f"et_get_stats: {lib().et_last_error(self.h).decode()} (status {st.status})")
+            raise EchoError(rc, f"et_get_stats: {lib().et_last_error(self.h).decode()} (status {st.status})", st)
         return st
 
     def counters(self) -> Counters:
@@ -206,6 +208,10 @@ class Context:
 
     def set_counting(self, on: bool):
         self.call("et_set_counting", 1 if on else 0)
+
+    def set_stack_limit(self, entries: int):
+        """Test hook: per-lane traversal stack entries for later traces (0 restores the full stack)."""
+        self.call("et_set_stack_limit", int(entries))
 
     def tuning(self) -> Tuning:
         t = Tuning()

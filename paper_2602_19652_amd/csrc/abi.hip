@@ -18,6 +18,7 @@ struct et_ctx {
   std::string last_error;
   Ctl* ctl = nullptr;                 // device control block (the only library allocation)
   bool counting = false;
+  int32_t stack_cap = TRAV_STACK;     // per-lane traversal stack entries (et_set_stack_limit)
   hipEvent_t ev[12] = {};
   uint32_t timed = 0;   // event pairs holding the last calls' times (TM_* bits)
   int synth_kernel = 0;
@@ -199,9 +200,15 @@ size_t sequential_bytes(int32_t J, const et_job* jobs) {
 
 void check_scene(const et_scene* sc) { ET_CHECK(sc, ET_E_INVALID, "scene is NULL"); }
 
+// The scene's materials index the pose's band tables.
+void check_materials(const et_scene* sc, const et_sim_desc* sim) {
+  ET_CHECK(sc->max_mat < sim->Q, ET_E_INVALID, "a triangle's material is >= Q (the band tables' rows)");
+}
+
 void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* ws, size_t ws_bytes, const et_paths* paths) {
   check_scene(sc);
   validate_sim(sim, true);
+  check_materials(sc, sim);
   validate_paths(paths);
   validate_readings(sim, paths);
   const WsPlan w = plan(sc, sim, std::max<int64_t>(paths->capacity, records_upper_bound(sim)));
@@ -210,6 +217,7 @@ void trace_impl(et_ctx* ctx, const et_scene* sc, const et_sim_desc* sim, void* w
   TraceWS tw;
   trace_ws_layout((sim->flags & ET_SPECULAR) ? sim->N : 0, sc->d.T, sc->d.n_obj, diff_draws_max(sim), (char*)ws,
                   &tw);
+  tw.stack_cap = ctx->stack_cap;
   ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
   trace_run(sc->d, sim, paths, tw, ctx->ctl, ctx->counting, ctx->stream);
   ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
@@ -480,6 +488,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
   for (int j = 0; j < J; ++j) {
     check_scene(jobs[j].scene);
     validate_sim(jobs[j].sim, true);
+    check_materials(jobs[j].scene, jobs[j].sim);
     const et_sim_desc* s = jobs[j].sim;
     ET_CHECK(s->M == s0->M && s->F == s0->F && s->Q == s0->Q && s->Bk == s0->Bk, ET_E_INVALID,
              "jobs of a batch must share M, F, Q and Bk");
@@ -501,6 +510,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     base += f.tj;
     TraceWS tw;
     trace_ws_layout(f.N, 0, 0, 0, base, &tw, TUNE_MAX_TRACE_BLOCKS);
+    tw.stack_cap = ctx->stack_cap;
     base += f.tw;
     char* pp = base;
     et_paths P = carve_paths(pp, f.cap);
@@ -534,6 +544,7 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     TraceWS tw;
     trace_ws_layout((s->flags & ET_SPECULAR) ? s->N : 0, jobs[j].scene->d.T, jobs[j].scene->d.n_obj,
                     diff_draws_max(s), (char*)ws, &tw);
+    tw.stack_cap = ctx->stack_cap;
     trace_run(jobs[j].scene->d, s, &P, tw, ctx->ctl, false, ctx->stream);
     k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
     SynthWS sw;
@@ -615,6 +626,7 @@ void emitters_check(const et_scene* scene, int32_t S, const et_sim_desc* sims) {
   ET_CHECK(S >= 1 && sims, ET_E_INVALID, "need S >= 1 emitters");
   for (int e = 0; e < S; ++e) {
     validate_sim(&sims[e], true);
+    check_materials(scene, &sims[e]);
     const et_sim_desc& a = sims[0];
     const et_sim_desc& b = sims[e];
     ET_CHECK(b.M == a.M && b.F == a.F && b.f_lo == a.f_lo && b.f_hi == a.f_hi && b.phase_sign == a.phase_sign &&
@@ -869,6 +881,13 @@ int et_set_counting(et_ctx* ctx, int enable) {
   if (!ctx) return ET_E_INVALID;
   ctx->counting = enable != 0;
   return ET_OK;
+}
+
+int et_set_stack_limit(et_ctx* ctx, int32_t entries) {
+  return guarded(ctx, [&] {
+    ET_CHECK(entries >= 0 && entries <= TRAV_STACK, ET_E_INVALID, "stack limit must be in [0, 64]");
+    ctx->stack_cap = entries == 0 ? TRAV_STACK : entries;
+  });
 }
 
 int et_get_counters(et_ctx* ctx, et_counters* out) {

@@ -31,14 +31,22 @@ __global__ void k_init_bounds(uint32_t* cb, uint32_t* ob, int32_t n_obj) {
   if (i < n_obj * 6) ob[i] = ((i % 6) < 3) ? 0xffffffffu : 0u;
 }
 
+// Triangle bounds (centroid bounds, object boxes) and the device checks of the mesh: vertex and
+// object indices in range, finite vertex coordinates, materials >= 0 (their largest value goes
+// to *mat_max when mat_max is not NULL, for the host's check against a pose's tables).
 __global__ void k_tri_bounds(const float* __restrict__ V, const int32_t* __restrict__ tris,
-                             const int32_t* __restrict__ obj, int64_t T, int64_t nV, int32_t n_obj,
-                             uint32_t* cb, uint32_t* ob, uint32_t* err) {
+                             const int32_t* __restrict__ obj, const int32_t* __restrict__ mat, int64_t T, int64_t nV,
+                             int32_t n_obj, uint32_t* cb, uint32_t* ob, uint32_t* err, int32_t* mat_max) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float c[3] = {INFINITY, INFINITY, INFINITY};
   float cm[3] = {-INFINITY, -INFINITY, -INFINITY};
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int32_t key = -1;   // object of a valid triangle, else -1
+  if (i < T && mat_max) {
+    const int32_t q = mat[i];
+    if (q < 0) atomicOr(err, DEV_ERR_INDEX);
+    else atomicMax(mat_max, q);
+  }
   if (i < T) {
     int32_t a = tris[3 * i], b = tris[3 * i + 1], cc = tris[3 * i + 2];
     int32_t o = obj[i];
@@ -46,11 +54,21 @@ __global__ void k_tri_bounds(const float* __restrict__ V, const int32_t* __restr
       atomicOr(err, DEV_ERR_INDEX);
     } else {
       key = o;
+      bool finite = true;
       for (int k = 0; k < 3; ++k) {
         float x0 = V[3 * (int64_t)a + k], x1 = V[3 * (int64_t)b + k], x2 = V[3 * (int64_t)cc + k];
+        finite = finite && isfinite(x0) && isfinite(x1) && isfinite(x2);
         lo[k] = fminf(x0, fminf(x1, x2));
         hi[k] = fmaxf(x0, fmaxf(x1, x2));
         c[k] = cm[k] = 0.5f * (lo[k] + hi[k]);
+      }
+      if (!finite) {   // a NaN or infinite coordinate: no box, and the call reports it
+        atomicOr(err, DEV_ERR_VERTEX);
+        key = -1;
+        for (int k = 0; k < 3; ++k) {
+          c[k] = lo[k] = INFINITY;
+          cm[k] = hi[k] = -INFINITY;
+        }
       }
     }
   }
@@ -396,6 +414,9 @@ __global__ void k_single_leaf(Node2* nodes) {
 // writes only its own slots, so no thread waits on or fences against another, and every box
 // is the exact union of its leaves' FP32 bounds, as the build produces it.
 
+// Clears some bits of the deferred error word (the others keep what earlier calls reported).
+__global__ void k_clear_bits(uint32_t* err, uint32_t bits) { atomicAnd(err, ~bits); }
+
 __global__ void k_fill_u32(uint32_t* __restrict__ a, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
@@ -552,8 +573,7 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   char* sp = (char*)scratch;
   auto take = [&](size_t bytes) { char* p = sp; sp += al(bytes); return (void*)p; };
   uint32_t* cb = (uint32_t*)take(sizeof(uint32_t) * 6);
-  uint32_t* ob_unused = (uint32_t*)take(sizeof(uint32_t) * 6);
-  (void)ob_unused;
+  int32_t* mat_max = (int32_t*)take(sizeof(uint32_t) * 6);   // [0]: largest material index
   uint32_t* keys = (uint32_t*)take(sizeof(uint32_t) * Tm);
   int32_t* perm = (int32_t*)take(sizeof(int32_t) * Tm);
   void* sort_tmp = take(sort_temp_bytes(Tm, 4));
@@ -584,16 +604,22 @@ void scene_build(et_scene* sc, const et_mesh_desc* mesh, void* blob, void* scrat
   ET_HIP(hipEventRecord(e0, s));
 
   k_init_bounds<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(cb, ob, n_obj);
+  k_fill_u32<<<1, 1, 0, s>>>((uint32_t*)mat_max, 1, 0u);
   if (T > 0) {
-    k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, T, V, n_obj, cb, ob, dev_err);
+    k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, d.mat, T, V, n_obj, cb, ob, dev_err, mat_max);
   }
   k_obj_box<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(ob, n_obj, d.obj_box);
   ET_HIP(hipGetLastError());
   // the index check must pass before any kernel dereferences triangle indices
   uint32_t herr = 0;
+  int32_t hmat = 0;
   ET_HIP(hipMemcpyAsync(&herr, dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  ET_HIP(hipMemcpyAsync(&hmat, mat_max, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   ET_HIP(hipStreamSynchronize(s));
-  ET_CHECK(!(herr & DEV_ERR_INDEX), ET_E_INVALID, "mesh index out of range (triangle vertex or object index)");
+  ET_CHECK(!(herr & DEV_ERR_INDEX), ET_E_INVALID,
+           "mesh index out of range (triangle vertex or object index, or a negative material)");
+  ET_CHECK(!(herr & DEV_ERR_VERTEX), ET_E_INVALID, "non-finite vertex coordinate in a triangle");
+  sc->max_mat = T > 0 ? hmat : -1;
 
   int64_t h_ctr[2] = {0, 0};
   if (T >= 1) {
@@ -707,8 +733,9 @@ void scene_refit(et_scene* sc, const float* vertices, double area_ref, uint32_t*
   ET_HIP(hipEventCreate(&e0));
   ET_HIP(hipEventCreate(&e1));
   ET_HIP(hipEventRecord(e0, s));
+  k_clear_bits<<<1, 1, 0, s>>>(dev_err, DEV_ERR_VERTEX);
   k_init_bounds<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(cb, ob, n_obj);
-  if (T > 0) k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, T, V, n_obj, cb, ob, dev_err);
+  if (T > 0) k_tri_bounds<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.obj, d.mat, T, V, n_obj, cb, ob, dev_err, nullptr);
   k_obj_box<<<nblk(6 * (int64_t)std::max(n_obj, 1)), BS, 0, s>>>(ob, n_obj, d.obj_box);
   if (T > 0) k_refit_leaves<<<nblk(T), BS, 0, s>>>(d.verts, d.tris, d.mat, d.tri_orig, T, d.tri4);
   if (T >= 2) {
@@ -734,7 +761,13 @@ void scene_refit(et_scene* sc, const float* vertices, double area_ref, uint32_t*
   if (T >= 2) ET_HIP(hipMemcpyAsync(&sc->sah, sah, sizeof(double), hipMemcpyDeviceToHost, s));
   k_fill_u32<<<1, BS, 0, s>>>((uint32_t*)sc->rscratch, REFIT_SCRATCH / 4, 0u);
   ET_HIP(hipGetLastError());
+  uint32_t herr = 0;
+  ET_HIP(hipMemcpyAsync(&herr, dev_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  k_clear_bits<<<1, 1, 0, s>>>(dev_err, DEV_ERR_VERTEX);   // reported by this call's status only
+  ET_HIP(hipGetLastError());
   ET_HIP(hipStreamSynchronize(s));
+  ET_CHECK(!(herr & DEV_ERR_VERTEX), ET_E_INVALID,
+           "non-finite vertex coordinate in a triangle (refit again with finite vertices before tracing)");
 }
 
 }  // namespace et

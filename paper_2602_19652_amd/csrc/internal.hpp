@@ -39,6 +39,7 @@ enum : uint32_t {
   DEV_ERR_CAPACITY = 1u << 2,   // record capacity exceeded
   DEV_ERR_RAYDIR = 1u << 3,     // zero / non-finite ray direction
   DEV_ERR_BUILD = 1u << 4,      // BVH build invariant broken
+  DEV_ERR_VERTEX = 1u << 5,     // non-finite coordinate of a vertex that a triangle uses
 };
 
 // ------------------------------------------------------------------ BVH layout
@@ -96,6 +97,7 @@ struct et_scene {
   double build_ms = 0;
   double refit_ms = 0;
   int device = 0;
+  int32_t max_mat = -1;            // largest material index of the mesh (-1: no triangles)
   // what a refit reads besides the tree (device arrays in the blob; level offsets on the host)
   int32_t* lvl_nodes = nullptr;    // [T-1] inner nodes grouped by depth, root first
   std::vector<int64_t> lvl_off;    // [levels + 1] start of each depth in lvl_nodes
@@ -178,6 +180,7 @@ struct TraceWS {
   void* rsort_tmp;
   int32_t* gstack;           // global part of the traversal stacks
   int64_t gstack_threads;
+  int32_t stack_cap;         // per-lane stack entries in use (TRAV_STACK; lower only to test overflows)
   // diffraction
   uint8_t* oel;
   uint64_t* dkeys;

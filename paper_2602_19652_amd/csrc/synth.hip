@@ -194,9 +194,11 @@ __device__ inline bool pair_setup(const SynthArgs& a, const et_paths& P, int64_t
 
 // log2 of the band factor: k exp(-gamma^2 / (2 beta^2)) (specular), I_d (diffraction) or
 // I_p (passive)
+// KFREE: specular records without the factor k (the adjoint's dH/dk, H being linear in k).
+template <bool KFREE = false>
 __device__ inline float band_log2_v(const SynthArgs& a, int kind, int mat, float gamma, int b) {
   const int64_t i = (int64_t)mat * a.Bk + b;
-  return kind == 0 ? a.lk[i] - gamma * gamma * a.lc[i] : kind == 1 ? a.ld[i] : a.lp[b];
+  return kind == 0 ? (KFREE ? 0.f : a.lk[i]) - gamma * gamma * a.lc[i] : kind == 1 ? a.ld[i] : a.lp[b];
 }
 
 __device__ inline void band_table_entry(const SynthArgs& a, int i, float* lk, float* lc, float* ld, float* lp) {
@@ -463,6 +465,8 @@ __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x
 // One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
 // nseg band segments cover the tile; this lane's row lies in segment myseg.
 // X lands at xr/xi[record * xs + k1], Y at yr/yi[record * ys + k2].
+// KFREE: the specular band factor leaves out k (see band_log2_v).
+template <bool KFREE = false>
 __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
                                 int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi, int xs,
                                 float* yr, float* yi, int ys, WaveScratch& W) {
@@ -492,7 +496,7 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
     if (i < RPW * nseg) {
       float f = 0.f;
       if (b_r != -INFINITY) {
-        float lb = band_log2_v(a, k_r, m_r, g_r, st.sb[sg]);
+        float lb = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[sg]);
         if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
         f = exp2f(lb);
       }
@@ -788,8 +792,11 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
       for (int b = 0; b < a.Bk; ++b) {
         const int k0 = (int)(((int64_t)b * a.F + a.Bk - 1) / a.Bk);
         const int k1 = (int)(((int64_t)(b + 1) * a.F + a.Bk - 1) / a.Bk);
-        const float blog = band_log2(a, q, b);
-        double sbr = 0.0;
+        // specular records: the band's terms without the factor k (H is linear in k, Eq. 2, so
+        // this sum is dH/dk also where k = 0); k multiplies the band's share of the other sums
+        const float blog = q.kind == 0 ? -q.gamma * q.gamma * a.lc[(int64_t)q.mat * a.Bk + b] : band_log2(a, q, b);
+        const double kf = q.kind == 0 ? (double)a.refl_k[(int64_t)q.mat * a.Bk + b] : 1.0;
+        double sbr = 0.0, b1r = 0.0, b1i = 0.0, bgx = 0.0, bgy = 0.0, bgz = 0.0;
         // the band's bins in runs of one directivity band (one run without directivity)
         for (int ks = k0; ks < k1;) {
           int kr = k1;
@@ -826,21 +833,25 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
             }
             const double fa = a.f_lo + (double)ka * a.df;
             srun += (double)c0r;
-            s1r += fa * (double)c0r + a.df * (double)c1r;
-            s1i += fa * (double)c0i + a.df * (double)c1i;
+            b1r += fa * (double)c0r + a.df * (double)c1r;
+            b1i += fa * (double)c0i + a.df * (double)c1i;
           }
           sbr += srun;
-          gvx += srun * (double)dgx; gvy += srun * (double)dgy; gvz += srun * (double)dgz;
+          bgx += srun * (double)dgx; bgy += srun * (double)dgy; bgz += srun * (double)dgz;
           ks = kr;
         }
+        s1r += kf * b1r;
+        s1i += kf * b1i;
+        gvx += kf * bgx; gvy += kf * bgy; gvz += kf * bgz;
 #pragma unroll
         for (int bb = 0; bb < 16; ++bb)
           if (bb == b) sb[bb] = sbr;
       }
+      // sb: band sums without k for specular records; s0 = sum over bands of k * sb
       double s0 = 0;
 #pragma unroll
       for (int b = 0; b < 16; ++b)
-        if (b < a.Bk) s0 += sb[b];
+        if (b < a.Bk) s0 += (q.kind == 0 ? (double)a.refl_k[(int64_t)q.mat * a.Bk + b] : 1.0) * sb[b];
       // d(ln A + j phi)/dx_m = [(-p/r - ln10 (a0 + a1 f)/20) + j sigma 2 pi f / c] u - d(gamma^2)/dx / (2 beta^2)
       const double cu = (-a.ps / q.r - ln10 * a.A0 / 20.0) * s0 - ln10 * a.A1 / 20.0 * (double)s1r -
                         (double)a.sigma * 2.0 * M_PI / a.c * (double)s1i;
@@ -862,15 +873,13 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
         for (int b = 0; b < 16; ++b) {
           if (b < a.Bk) {
             const double bt = (double)a.beta[q.mat * a.Bk + b];
-            wsum += sb[b] / (2.0 * bt * bt);
+            wsum += (double)a.refl_k[q.mat * a.Bk + b] * sb[b] / (2.0 * bt * bt);
           }
         }
         g0 -= 2.0 * wsum * d0; g1 -= 2.0 * wsum * d1; g2 -= 2.0 * wsum * d2;
+        // dL/dk of the record's (material, band): 2 Re sum conj(g) dT/dk
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          double kv = b < a.Bk ? (double)a.refl_k[q.mat * a.Bk + b] : 0.0;
-          sb[b] = kv != 0.0 ? 2.0 * sb[b] / kv : 0.0;
-        }
+        for (int b = 0; b < 16; ++b) sb[b] = 2.0 * sb[b];
       }
       if (a.Bd) {
         // v = -R^T u and du/dx_m = (I - u u^T) / l: d ln D / dx_m = -(I - u u^T) R grad_v ln D / l
@@ -932,15 +941,18 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 // contiguous, and 16-byte accesses of four consecutive rows are conflict-free per quarter wave.
 constexpr int BS68 = 68;
 
+// X carries the band factor without k for specular records: Re(X Z) summed over a band's rows
+// is then dH/dk of that band (also where k = 0), and k enters the other sums per row.
 struct __align__(16) BwdBuf {
   float X[2][RB][BS68];      // [re/im][record][k1]
   float Y[2][RB][BS68];      // [re/im][record][k2]
   float R0[RB][BS68];        // Re(X Z) per (record, row)
-  float2 R1[RB][17];         // sum over 4 rows of X (f Z + df Z') per (record, row group)
+  float2 R1[RB][17];         // sum over 4 rows of k X (f Z + df Z') per (record, row group)
   double kv[RB][17];         // dL/dk contribution per (record, band)
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
   double lobe_w[256];        // per (material, band): 1 / (2 beta^2)
-  double kinv2[256];         // per (material, band): 2 / k (0 where k = 0)
+  float kf[256 + 16];        // per (material, band): k; then a row of ones (records of other kinds)
+  int32_t recb[RB];          // per record of the stage: its row of kf (mat Bk, or the ones row)
 };
 
 template <bool BATCH, bool SPLIT>
@@ -988,16 +1000,33 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
   for (int i = tid; i < a.Q; i += 256) bb.kmask[0][i] = bb.kmask[1][i] = 0u;   // first used after two barriers
   for (int i = tid; i < QB; i += 256) {
-    const double bt = (double)a.beta[i], kk = (double)a.refl_k[i];
+    const double bt = (double)a.beta[i];
     bb.lobe_w[i] = 1.0 / (2.0 * bt * bt);
-    bb.kinv2[i] = kk != 0.0 ? 2.0 / kk : 0.0;
+    bb.kf[i] = a.refl_k[i];
+  }
+  if (tid < a.Bk) bb.kf[QB + tid] = 1.f;
+  // material band of each of this lane's four epilogue rows (rows past the grid: the last band)
+  int rband[4];
+  {
+    const int r10 = rbw * 16 + (lane >> 4) * 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t kr = (int64_t)min(k1_0 + r10 + v, K1 - 1) * K2;
+      rband[v] = (int)((kr * a.Bk) / a.F);
+    }
   }
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0], BS68,
-             &bb.Y[0][0][0], &bb.Y[1][0][0], BS68, wscr[wv]);
+    generate<true>(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0], BS68,
+                   &bb.Y[0][0][0], &bb.Y[1][0][0], BS68, wscr[wv]);
+    {
+      // each generated record's row of k factors
+      const int src = t * RPW + (lane & 7);
+      const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
+      if (lane < RPW) bb.recb[wv * RPW + lane] = k_r == 0 ? m_r * a.Bk : QB;
+    }
     __syncthreads();
     floatx4 acc[6][NB];
 #pragma unroll
@@ -1030,6 +1059,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       const float4 x4r = *reinterpret_cast<const float4*>(&bb.X[0][n][r10]);
       const float4 x4i = *reinterpret_cast<const float4*>(&bb.X[1][n][r10]);
       const float xrv[4] = {x4r.x, x4r.y, x4r.z, x4r.w}, xiv[4] = {x4i.x, x4i.y, x4i.z, x4i.w};
+      const float* kfr = bb.kf + bb.recb[n];
       float crv[4];
       float s1r = 0.f, s1i = 0.f;
 #pragma unroll
@@ -1039,9 +1069,10 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         const float xr = xrv[v], xi = xiv[v];
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
         const float fr = frow0 + (float)(r10 + v) * df64;
+        const float kv = kfr[rband[v]];
         crv[v] = cr;
-        s1r += fr * cr + dff * (xr * wr - xi * wi);
-        s1i += fr * ci + dff * (xr * wi + xi * wr);
+        s1r += kv * (fr * cr + dff * (xr * wr - xi * wi));
+        s1i += kv * (fr * ci + dff * (xr * wi + xi * wr));
       }
       *reinterpret_cast<float4*>(&bb.R0[n][r10]) = make_float4(crv[0], crv[1], crv[2], crv[3]);
       bb.R1[n][rbw * 4 + (lane >> 4)] = make_float2(s1r, s1i);
@@ -1089,11 +1120,15 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
             sb = (double)((p0 + p1) + (p2 + p3));
           }
         }
-        s0 += sb;
+        // sb leaves out k for specular records: k sb is the band's share of H's sums, 2 sb its dL/dk
         double kvv = 0.0;
-        if (valid && kind == 0 && b < a.Bk) {
-          wl += sb * bb.lobe_w[mat * a.Bk + b];
-          kvv = sb * bb.kinv2[mat * a.Bk + b];
+        if (b < a.Bk) {
+          const double kb = kind == 0 ? (double)bb.kf[mat * a.Bk + b] : 1.0;
+          s0 += kb * sb;
+          if (valid && kind == 0) {
+            wl += kb * sb * bb.lobe_w[mat * a.Bk + b];
+            kvv = 2.0 * sb;
+          }
         }
         bb.kv[n][b] = kvv;
       }

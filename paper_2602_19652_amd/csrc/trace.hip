@@ -129,11 +129,13 @@ struct Stack {
   int* glob;       // this lane's global column: entry i at glob[i * gstride]
   int64_t gstride;
   int sp;
+  int cap;         // entries in use: TRAV_STACK (lower only when a test forces overflows)
   int overflow;
+  // A push beyond the cap drops the subtree (counted; the traversal still ends normally).
   __device__ inline void push(int v) {
+    if (sp >= cap) { ++overflow; return; }
     if (sp < TRAV_LDS_STACK) lds[sp * BS] = v;
-    else if (sp < TRAV_STACK) glob[(int64_t)(sp - TRAV_LDS_STACK) * gstride] = v;
-    else { ++overflow; return; }
+    else glob[(int64_t)(sp - TRAV_LDS_STACK) * gstride] = v;
     ++sp;
   }
   // The global part is read as a non-temporal load, so the compiler keeps the two reads apart
@@ -391,6 +393,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(TRAV_WAVES_P
   st.lds = lds_stack + threadIdx.x;
   st.glob = w.gstack + gtid;
   st.gstride = w.gstack_threads;
+  st.cap = w.stack_cap;
   st.overflow = 0;
   int64_t cn_c = 0, ct_c = 0, cn_a = 0, ct_a = 0, rays_a = 0;
   for (int64_t i = gtid; i < n; i += stride) {
@@ -648,14 +651,16 @@ __global__ void k_group_starts(const uint64_t* __restrict__ flag, const uint64_t
 }
 
 // Group count and draws; more meshes than max_meshes keeps the first ones and reports a
-// capacity error.
+// capacity error.  The last kept group ends where the first dropped one starts (its entry of
+// gstart is already that start), so only an untruncated list gets the end marker n_elig.
 __global__ void k_group_count(Ctl* ctl, DiffArgs a, int64_t* __restrict__ gstart) {
   int64_t g = (int64_t)ctl->tot[2];
   if (a.per_mesh && g > a.max_meshes) {
     atomicOr(&ctl->err, DEV_ERR_CAPACITY);
     g = a.max_meshes;
+  } else {
+    gstart[g] = ctl->n_elig;
   }
-  gstart[g] = ctl->n_elig;
   ctl->n_groups = g;
   ctl->n_draw = a.per_mesh ? a.K * g : (ctl->n_elig > 0 ? a.K : 0);
 }
@@ -670,6 +675,7 @@ __global__ __launch_bounds__(BS) void k_diff_sample(SceneDev S, DiffArgs a, cons
   st.lds = lds_stack + threadIdx.x;
   st.glob = w.gstack + gtid;
   st.gstride = w.gstack_threads;
+  st.cap = w.stack_cap;
   st.overflow = 0;
   const int64_t n_draw = ctl->n_draw;
   int64_t dummy0 = 0, dummy1 = 0, rays = 0;
@@ -766,6 +772,7 @@ __global__ __launch_bounds__(BS) void k_passive(SceneDev S, PoseArgs a, const do
   st.lds = lds_stack + threadIdx.x;
   st.glob = w.gstack + gtid;
   st.gstride = w.gstack_threads;
+  st.cap = w.stack_cap;
   st.overflow = 0;
   const int64_t base = ctl->rec_base + (diff ? (int64_t)ctl->tot[3] : 0);
   int64_t dummy0 = 0, dummy1 = 0, rays = 0;
@@ -850,6 +857,7 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
                                               : std::max<int64_t>(nblk(std::max<int64_t>(N, 1)), nblk(std::max<int64_t>(K, 1)));
   x.gstack_threads = stack_blocks * BS;
   x.gstack = (int32_t*)take(sizeof(int32_t) * (size_t)(TRAV_STACK - TRAV_LDS_STACK) * (size_t)x.gstack_threads);
+  x.stack_cap = TRAV_STACK;
   if (K > 0) {
     x.oel = (uint8_t*)take((size_t)std::max<int32_t>(n_obj, 1));
     x.dkeys = (uint64_t*)take(sizeof(uint64_t) * Tm);

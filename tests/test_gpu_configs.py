@@ -9,6 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from test_gpu_parity import check_spectra
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -63,10 +64,12 @@ def test_foliage_synthesis_with_directivity(et, ctx, foliage, direct):
     assert st.synth_kernel == (2 if direct else 1)
     bins = np.sort(W.rng(6).choice(sim["F"], 128, replace=False))
     H_ref = O.synth(ref, sim, bins=bins)
-    e = rel_l2(H[:, bins], H_ref)
-    print(f"foliage synthesis ({'direct' if direct else 'factorised'}, directivity): rel L2 {e:.3e} "
-          f"over {len(ref['rtot'])} records")
-    assert e <= TOL
+    check_spectra(H[:, bins], H_ref, f"foliage synthesis ({'direct' if direct else 'factorised'}, directivity), "
+                  f"{len(ref['rtot'])} records, 128 sampled bins")
+    # every bin of both receivers for 256 of the records
+    rec = {k: v[:256] for k, v in ref.items() if k not in ("certified", "nseg")}
+    H = et.synthesize(ctx, s, et.Paths.from_records(rec)).cpu().numpy()
+    check_spectra(H, O.synth(rec, sim), f"foliage synthesis, all 8192 bins, {len(rec['rtot'])} records")
 
 
 # ----------------------------------------------------------------------------- batches
@@ -115,17 +118,58 @@ def test_batch_fused_matches_plain_and_graph(et, ctx, batch_small):
             assert np.array_equal(Hg, Hb), f"graph replay {rep} differs"
             et.simulate(ctx, scenes[0], sims[0])          # unrelated eager work between replays
             torch.cuda.synchronize()
-    # one job against the oracle (certified rays only)
-    j0 = b.jobs[0]
-    ref = O.trace(b.scenes[j0.scene_index], j0.sim)
-    dirs = j0.sim["ray_dirs"][ref["certified"]]
-    ref_c = O.trace(b.scenes[j0.scene_index], j0.sim, dirs=dirs)
-    bins = np.arange(0, 2048, 64)
-    H_ref = O.synth(ref_c, j0.sim, bins=bins)
-    Hc = et.simulate(ctx, scenes[j0.scene_index], et.Sim(j0.sim, flags=et.ET_SPECULAR, ray_dirs=dirs)).cpu().numpy()
-    e = rel_l2(Hc[:, bins], H_ref)
-    print(f"batch job 0 vs oracle on certified rays ({ref['certified'].mean():.4f}): rel L2 {e:.3e}")
-    assert e <= TOL
+
+
+def _certified_records(rec):
+    """The records of the rays the oracle certified (record arrays only)."""
+    keep = rec["certified"][rec["ray"]]
+    return {k: v[keep] for k, v in rec.items() if k not in ("certified", "nseg")}
+
+
+def test_batch_fused_matches_oracle_per_job(et, ctx, batch_small):
+    """Every job of a fused batch (6 poses in the room and the 4 uneven scenes, uneven ray
+    counts) on its oracle-certified rays: the fused forward's spectra (eager, and graph replays
+    with eager work between them) against the oracle's per job and per receiver, and the fused
+    adjoint's dL/dk and dL/dx_m per job against the oracle gradient for a seeded dL/dconj(H)."""
+    import torch
+    b = batch_small
+    scenes = [et.Scene(ctx, s) for s in b.scenes]
+    sims, recs, psims = [], [], []
+    for i, j in enumerate(b.jobs):
+        n = 384 - 29 * i
+        sim = dict(j.sim, ray_dirs=j.sim["ray_dirs"][:n])
+        ref = O.trace(b.scenes[j.scene_index], sim)
+        dirs = sim["ray_dirs"][ref["certified"]]
+        recs.append(_certified_records(ref))
+        psims.append(sim)
+        sims.append(et.Sim(sim, flags=et.ET_SPECULAR, ray_dirs=dirs))
+    batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+    J, M, F = len(b.jobs), sims[0].M, sims[0].F
+    gen = np.random.default_rng(44)
+    g = (gen.normal(size=(J, M, F)) + 1j * gen.normal(size=(J, M, F))).astype(np.complex64)
+    gd = torch.as_tensor(g).cuda()
+    Hb = batch.run(grad_spectra=gd).cpu().numpy()
+    assert ctx.stats().adjoint_kernel == 1
+    gk_b, gx_b = batch.grad_k.cpu().numpy(), batch.grad_rx.cpu().numpy()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep in range(2):
+            Hg = batch.run(grad_spectra=gd, graph=True).cpu().numpy()
+            torch.cuda.synchronize()
+            assert np.array_equal(Hg, Hb), f"graph replay {rep} differs from the eager batch"
+            assert np.array_equal(batch.grad_k.cpu().numpy(), gk_b) and np.array_equal(batch.grad_rx.cpu().numpy(), gx_b)
+            et.simulate(ctx, scenes[0], sims[0])
+            torch.cuda.synchronize()
+    worst = 0.0
+    for i, j in enumerate(b.jobs):
+        H_ref = O.synth(recs[i], psims[i])
+        e = check_spectra(Hb[i], H_ref, f"batch job {i} (scene {j.scene_index}, {len(recs[i]['rtot'])} records)")
+        gk_ref, gx_ref = O.grad(recs[i], psims[i], g[i].astype(np.complex128))
+        ek, ex = rel_l2(gk_b[i], gk_ref), rel_l2(gx_b[i], gx_ref)
+        print(f"batch job {i}: adjoint dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+        assert ek <= TOL and ex <= TOL
+        worst = max(worst, e, ek, ex)
+    print(f"fused batch vs oracle: worst relative error over {J} jobs {worst:.3e}")
 
 
 def test_batch_fused_adjoint_matches_per_job(et, ctx, batch_small):

@@ -37,20 +37,6 @@ def _records(P):
     return {k: np.asarray(v)[order] for k, v in h.items()}
 
 
-def _on_triangle(p, v, tol=1e-5):
-    """p lies on triangle v[3][3] within tol metres (plane distance and barycentric slack)."""
-    e1, e2 = v[1] - v[0], v[2] - v[0]
-    n = np.cross(e1, e2)
-    a2 = float(np.linalg.norm(n))
-    if abs(float(np.dot(n / a2, p - v[0]))) > tol:
-        return False
-    q = p - v[0]
-    b1 = float(np.dot(np.cross(q, e2), n)) / a2 ** 2
-    b2 = float(np.dot(np.cross(e1, q), n)) / a2 ** 2
-    slack = tol * max(np.linalg.norm(e1), np.linalg.norm(e2)) / a2 * 2
-    return b1 >= -slack and b2 >= -slack and b1 + b2 <= 1 + slack
-
-
 def test_refit_same_vertices_reproduces_build(et, ctx, frames):
     scene, _, sim = frames
     sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
@@ -87,10 +73,9 @@ def test_refit_frame_matches_fresh_build_and_oracle(et, ctx, frames):
     G_ref, C_ref = O.curvature(moved, a_ref)
     assert np.array_equal(C1.cpu().numpy(), C_ref) and np.array_equal(G1.cpu().numpy(), G_ref)
 
-    # specular trace over all rays: identical records.  Closest-hit ties go to the smaller
-    # triangle index and box culling is widened beyond rounding, so the hit does not depend on
-    # the tree's topology; a triangle that differs must still be a valid hit (same point,
-    # direction, path length and material: a shared edge of coplanar triangles).
+    # specular trace over all rays: identical records, triangles included.  Closest-hit ties go
+    # to the smaller triangle index and box culling is widened beyond rounding, so the hit does
+    # not depend on the tree's topology.
     s = et.Sim(sim, flags=et.ET_SPECULAR)
     ra = _records(et.trace(ctx, sc, s))
     assert ctx.stats().stack_overflows == 0
@@ -101,12 +86,7 @@ def test_refit_frame_matches_fresh_build_and_oracle(et, ctx, frames):
             assert np.array_equal(ra[k], rb[k]), k
     diff = np.nonzero(ra["tri"] != rb["tri"])[0]
     print(f"moved room: {len(ra['ray'])} records, {len(diff)} with another (tied) triangle")
-    assert len(diff) <= 1e-5 * len(ra["ray"])
-    V1 = np.asarray(moved["vertices"], np.float64)
-    tris = np.asarray(moved["tris"])
-    for i in diff:
-        for t in (ra["tri"][i], rb["tri"][i]):
-            assert _on_triangle(ra["p"][i], V1[tris[t]])
+    assert len(diff) == 0
 
     # the oracle on a seeded subset of rays of the moved scene
     sub = np.sort(W.rng(32).choice(len(sim["ray_dirs"]), 1024, replace=False))
