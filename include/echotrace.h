@@ -235,6 +235,20 @@ int et_trace(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, void* w
 int et_synthesize(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, void* ws, size_t ws_bytes,
                   float* spectra);
 
+/* For callers that cannot allocate device memory or hand over a workspace (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): et_synthesize with the
+ * same inputs and output, but no workspace.  Its band tables and per-chunk partial spectra live
+ * in a 64 MiB scratch array that the library keeps in each GPU's memory from the first
+ * et_create on that device until the process ends, and its kernels walk every record (hidden
+ * ones contribute nothing) instead of a compacted list of the visible ones.  The call allocates
+ * nothing.  Limits: the tables (4 Q Bk + Bk floats) and one record chunk's partial spectra
+ * (8 M F bytes) must fit in the scratch (ET_E_UNSUPPORTED otherwise, e.g. beyond M F = 8 M);
+ * ET_PATH_PRODUCT is refused (ET_E_UNSUPPORTED: it needs per-record tables).  Every call on a
+ * device uses that device's one scratch and leaves its contents there: calls that overlap on
+ * one GPU (other streams, contexts or threads) race and must be serialised by the caller.
+ * Results equal et_synthesize's up to the FP32 order of the per-chunk sums. */
+int et_synthesize_noalloc(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, float* spectra);
+
 /* et_trace followed by et_synthesize. */
 int et_simulate(et_ctx* ctx, const et_scene* scene, const et_sim_desc* sim, const et_paths* paths, void* ws,
                 size_t ws_bytes, float* spectra);

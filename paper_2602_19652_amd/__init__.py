@@ -128,6 +128,7 @@ def lib():
             "et_trace": ([vp, vp, C.POINTER(SimDesc), vp, sz, C.POINTER(PathsDesc)], C.c_int),
             "et_synthesize": ([vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp, sz, vp], C.c_int),
             "et_simulate": ([vp, vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp, sz, vp], C.c_int),
+            "et_synthesize_noalloc": ([vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp], C.c_int),
             "et_synthesize_backward": ([vp, C.POINTER(SimDesc), C.POINTER(PathsDesc), vp, vp, sz, vp, vp], C.c_int),
             "et_batch_workspace_size": ([vp, i32, C.POINTER(Job), C.POINTER(sz)], C.c_int),
             "et_simulate_batch": ([vp, i32, C.POINTER(Job), vp, sz, vp, vp, vp, vp], C.c_int),
@@ -460,6 +461,13 @@ def synthesize(ctx: Context, sim: Sim, paths: Paths, ws: Workspace | None = None
     buf = ws.get(workspace_size(ctx, None, sim))
     out = out if out is not None else torch.empty(sim.M, sim.F, 2, dtype=torch.float32, device=_dev())
     ctx.call("et_synthesize", C.byref(sim.desc), C.byref(paths.desc), _ptr(buf), buf.numel(), _ptr(out))
+    return torch.view_as_complex(out)
+
+
+def synthesize_noalloc(ctx: Context, sim: Sim, paths: Paths, out: torch.Tensor):
+    """et_synthesize_noalloc: spectra into the caller's float32 [M, F, 2] tensor `out` without a
+    workspace (the library's per-device scratch); returns the complex64 [M, F] view."""
+    ctx.call("et_synthesize_noalloc", C.byref(sim.desc), C.byref(paths.desc), _ptr(out))
     return torch.view_as_complex(out)
 
 

@@ -26,7 +26,7 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-SOURCES = ["prims.hip", "bvh.hip", "trace.hip", "synth.hip", "timedomain.hip", "eq.hip", "abi.hip"]
+SOURCES = ["prims.hip", "bvh.hip", "trace.hip", "synth.hip", "timedomain.hip", "eq.hip", "noalloc.hip", "abi.hip"]
 
 
 def _compile(src: str) -> str:

@@ -280,6 +280,7 @@ int et_create(int device, void* hip_stream, et_ctx** out) {
     ET_HIP(hipMalloc(&c->ctl, sizeof(Ctl)));
     ET_HIP(hipMemset(c->ctl, 0, sizeof(Ctl)));
     for (auto& e : c->ev) ET_HIP(hipEventCreate(&e));
+    noalloc_init(device);   // this device's address of the allocation-free calls' scratch
   } catch (const Error& e) {
     delete c;
     return e.code;
@@ -403,6 +404,24 @@ int et_synthesize(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, vo
     k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
     ET_HIP(hipGetLastError());
     synth_impl(ctx, sim, paths, ws, ws_bytes, spectra, false);
+  });
+}
+
+int et_synthesize_noalloc(et_ctx* ctx, const et_sim_desc* sim, const et_paths* paths, float* spectra) {
+  return guarded(ctx, [&] {
+    validate_paths(paths);
+    validate_sim(sim, false);
+    validate_readings(sim, paths);
+    ET_CHECK(spectra, ET_E_INVALID, "spectra is NULL");
+    ctx->timed = 0;
+    void* buf = noalloc_scratch(ctx->device);
+    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, paths->count, paths->capacity);
+    ET_HIP(hipGetLastError());
+    ET_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+    ctx->synth_kernel = synth_run_noalloc(sim, paths, buf, NOALLOC_SCRATCH_BYTES, ctx->ctl, spectra, ctx->stream,
+                                          ctx->ev[8], ctx->ev[9]);
+    ET_HIP(hipEventRecord(ctx->ev[5], ctx->stream));
+    ctx->timed |= TM_SYNTH | TM_SYNTH_K;
   });
 }
 

@@ -244,6 +244,19 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
 bool synth_factorised_ok(const et_sim_desc* sim);
 bool synth_bwd_factorised_ok(const et_sim_desc* sim);
 
+// Synthesis without a workspace (et_synthesize_noalloc): band tables and partial spectra in
+// `buf` (bytes), every record walked (no visible-record list).  Throws ET_E_UNSUPPORTED when the
+// tables and one record chunk's partial spectra do not fit.
+int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, size_t bytes, Ctl* ctl,
+                      float* spectra, hipStream_t s, hipEvent_t kb = nullptr, hipEvent_t ke = nullptr);
+
+// ------------------------------------------------------------------ device scratch (noalloc.hip)
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+// Takes the scratch array's address on `device` (current) once; called at context creation.
+void noalloc_init(int device);
+// The scratch address on `device` (noalloc_init must have run there).
+void* noalloc_scratch(int device);
+
 // ------------------------------------------------------------------ time domain (timedomain.hip)
 // out[i] = sum over j < J (in order) of in[j][i], i < n (synth.hip)
 void sum_spectra(const float* in, int32_t J, int64_t n, float* out, hipStream_t s);

@@ -315,6 +315,7 @@ __global__ void k_vis_scatter(const uint64_t* __restrict__ flags, const uint64_t
 }
 
 __global__ void k_vis_count(Ctl* ctl) { ctl->n_vis = (int64_t)ctl->tot[3]; }
+__global__ void k_vis_all(Ctl* ctl) { ctl->n_vis = ctl->n_rec; }   // no list: the kernels walk every record
 
 // ------------------------------------------------------------------ factorised MFMA kernel
 
@@ -355,7 +356,7 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   q.mat = q.kind = 0;
   if (GRAD) q.gux = q.guy = q.guz = q.gc1 = q.glx = q.gly = q.glz = 0.f;
   if (e >= hi) return;
-  const int64_t n = idx[e];
+  const int64_t n = idx ? (int64_t)idx[e] : e;   // no list: every record (hidden ones skipped here)
   const uint8_t fl = P.flags[n];
   if (!(fl & 1)) return;
   if (a.rxv && !((a.rxv[n] >> m) & 1ull)) return;   // per-receiver line of sight
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(DB) void k_synth_direct(SynthArgs a0, const SynthAr
     if (tid < DRB) {
       const int64_t e = n0 + tid;
       Pair q;
-      if (e < hi && pair_setup(a, P, idx[e], m, q)) {
+      if (e < hi && pair_setup(a, P, idx ? (int64_t)idx[e] : e, m, q)) {
         // integer phase accumulator (Q0.32 cycles): phase_k = a32 + k b32 mod 2^32
         L.a32[tid] = (uint32_t)(uint64_t)llrint(frac(q.c0) * 4294967296.0);
         L.b32[tid] = (uint32_t)(uint64_t)llrint(frac(q.cb) * 4294967296.0);
@@ -1474,6 +1475,47 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   if (ke) ET_HIP(hipEventRecord(ke, s));
   const int64_t MF2 = (int64_t)sim->M * sim->F * 2;
   k_reduce_partials<<<(unsigned)std::min<int64_t>((MF2 + 255) / 256, 4096), 256, 0, s>>>(ws.partial, ws.P, MF2, spectra);
+  ET_HIP(hipGetLastError());
+  return mf ? 1 : 2;
+}
+
+int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, size_t bytes, Ctl* ctl,
+                      float* spectra, hipStream_t s, hipEvent_t kb, hipEvent_t ke) {
+  ET_CHECK(!(sim->flags & ET_PATH_PRODUCT), ET_E_UNSUPPORTED,
+           "ET_PATH_PRODUCT needs per-record tables (a workspace): use et_synthesize");
+  const bool mf = synth_factorised_ok(sim);
+  const int64_t cap = std::max<int64_t>(paths->capacity, 1);
+  SynthWS w{};
+  const size_t tables = table_ws(sim, nullptr, 0, w);
+  const size_t chunk = al(sizeof(float) * 2 * (size_t)sim->M * sim->F);
+  ET_CHECK(tables + chunk <= bytes, ET_E_UNSUPPORTED,
+           "receivers x bins too large for the device scratch of the allocation-free call");
+  // record chunks: the usual choice, as many as the scratch holds, a multiple of 8 above 8
+  int64_t P = std::min<int64_t>(choose_P(sim, cap, mf), (int64_t)((bytes - tables) / chunk));
+  if (P > 8) P = P / 8 * 8;
+  char* base = (char*)buf;
+  table_ws(sim, base, 0, w);
+  w.partial = (float*)(base + tables);
+  w.P = (int)P;
+  w.cap = cap;
+  SynthArgs a = make_args(sim, w.P);
+  const et_paths Pth = *paths;
+  k_vis_all<<<1, 1, 0, s>>>(ctl);
+  build_tables(a, w, s);
+  a.rxv = (sim->flags & ET_PER_RX_VISIBILITY) ? Pth.rx_vis : nullptr;
+  if (kb) ET_HIP(hipEventRecord(kb, s));
+  if (mf) {
+    const int K1 = sim->F / K2;
+    dim3 grid(w.P, sim->M, (K1 + KT1 - 1) / KT1);
+    if (K1 <= 32) k_synth_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
+    else k_synth_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
+  } else {
+    dim3 grid(w.P, sim->M, (sim->F + DTILE - 1) / DTILE);
+    k_synth_direct<false><<<grid, DB, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
+  }
+  if (ke) ET_HIP(hipEventRecord(ke, s));
+  const int64_t MF2 = (int64_t)sim->M * sim->F * 2;
+  k_reduce_partials<<<(unsigned)std::min<int64_t>((MF2 + 255) / 256, 4096), 256, 0, s>>>(w.partial, w.P, MF2, spectra);
   ET_HIP(hipGetLastError());
   return mf ? 1 : 2;
 }
