@@ -395,3 +395,118 @@ def test_gradient_descent_recovers_hidden_coefficients(et, ctx, diff_paths):
     assert well.sum() >= 0.5 * ident.sum()
     assert res <= 1e-5
     assert err_w <= 1e-3
+
+
+# ----------------------------------------------------------------------------- differentiation at the stated sizes
+
+@pytest.fixture(scope="module")
+def d_instance(et, ctx):
+    """The differentiation workload: the room scene's fixed specular paths (diffraction off),
+    traced on the GPU, 32 receivers; hidden band coefficients from the workload's seed."""
+    scene, sim = W.room_scene(n_rays=1 << 20, diff_K=0)
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    k_star = W.rng(1005).uniform(0.3, 0.99, (16, 8)).astype(np.float32)
+    return scene, sim, sc, k_star
+
+
+def test_d_reduced_instance_all_parameters(et, ctx, d_instance):
+    """Reduced instance: 2^14 of the room's rays, 256 bins, all 224 parameters (16 x 8 band
+    coefficients and 32 x 3 receiver coordinates).  The GPU adjoint against the FP64 oracle's
+    gradient, and that gradient against central differences of the FP64 loss for every
+    parameter: for k exact (H is linear in k, so the difference needs only the band's bins and
+    the material's records), for x_m with h = 1e-6 m over receiver m's spectrum."""
+    import torch
+    scene, sim, sc, k_star = d_instance
+    sim = dict(sim, F=256)
+    sub = np.sort(W.rng(1006).choice(len(sim["ray_dirs"]), 1 << 14, replace=False))
+    k0 = np.full((16, 8), 0.5, np.float32)
+    simk = dict(sim, refl_k=k0)
+    s = et.Sim(simk, flags=et.ET_SPECULAR, ray_dirs=sim["ray_dirs"][sub])
+    P = et.trace(ctx, sc, s)
+    rec = P.to_host()
+    H_star = O.synth(rec, dict(sim, refl_k=k_star))
+    H = O.synth(rec, simk)
+    gR = H - H_star
+    gk_ref, gx_ref = O.grad(rec, simk, gR)
+    gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(gR.astype(np.complex64)).cuda())
+    gk, gx = gk.cpu().numpy(), gx.cpu().numpy()
+    ek, ex = rel_l2(gk, gk_ref), rel_l2(gx, gx_ref)
+    wk = float(np.max(np.abs(gk - gk_ref)) / np.max(np.abs(gk_ref)))
+    wx = float(np.max(np.abs(gx - gx_ref)) / np.max(np.abs(gx_ref)))
+    print(f"D reduced ({len(rec['rtot'])} records, 32 x 256): GPU vs oracle gradient dL/dk {ek:.3e} (worst entry "
+          f"{wk:.3e} of the largest), dL/dx {ex:.3e} (worst {wx:.3e})")
+    assert ek <= TOL and ex <= TOL and wk <= TOL and wx <= TOL
+    # the oracle gradient against central differences, all 224 parameters
+    h = 1e-6
+    F, Bk = sim["F"], 8
+    worst_k = worst_x = 0.0
+    for q in range(16):
+        sel = rec["mat"] == q
+        recq = {kk: v[sel] for kk, v in rec.items() if hasattr(v, "__len__") and len(v) == len(sel)}
+        for b in range(Bk):
+            bins = np.arange(F)[(np.arange(F) * Bk) // F == b].astype(np.int32)
+            e = np.zeros((16, Bk), np.float32)
+            e[q, b] = 1.0
+            E = O.synth(recq, dict(simk, refl_k=e), bins=bins) if sel.any() else np.zeros((32, len(bins)))
+            Lp = np.sum(np.abs(gR[:, bins] + h * E) ** 2)
+            Lm = np.sum(np.abs(gR[:, bins] - h * E) ** 2)
+            fd = (Lp - Lm) / (2 * h)
+            worst_k = max(worst_k, abs(fd - gk_ref[q, b]) / np.max(np.abs(gk_ref)))
+    for m in range(32):
+        for a in range(3):
+            Ls = []
+            for sgn in (1, -1):
+                xp = simk["rx_pos"].copy()
+                xp[m, a] += sgn * h
+                Hm = O.synth(rec, dict(simk, rx_pos=xp), M_subset=[m])
+                Ls.append(np.sum(np.abs(Hm[0] - H_star[m]) ** 2))
+            fd = (Ls[0] - Ls[1]) / (2 * h)
+            worst_x = max(worst_x, abs(fd - gx_ref[m, a]) / np.max(np.abs(gx_ref)))
+    print(f"D reduced: oracle gradient vs central differences, worst over 128 k entries {worst_k:.2e}, over 96 "
+          f"receiver coordinates {worst_x:.2e} (of the largest entry)")
+    assert worst_k <= 1e-6 and worst_x <= 1e-5
+
+
+def test_d_full_instance_directional_derivatives(et, ctx, d_instance):
+    """Full instance: the room step's fixed specular paths (2^20 rays), 32 receivers x 4096
+    bins.  The oracle evaluates the loss on a seeded subset of 16 bins (the full sum is 5.5e11
+    FP64 terms), so the loss is L = sum over those bins of |H - H*|^2, and the GPU adjoint is fed
+    dL/dconj(H) = H - H* on them and zero elsewhere.  The GPU forward matches the oracle on the
+    16 bins; 8 directional derivatives (4 along receiver coordinates, central differences with
+    h = 1e-6 m; 4 along band coefficients, exact by linearity) match the adjoint's."""
+    import torch
+    scene, sim, sc, k_star = d_instance
+    g = W.rng(1007)
+    k0 = g.uniform(0.4, 0.8, (16, 8)).astype(np.float32)
+    simk = dict(sim, refl_k=k0)
+    s = et.Sim(simk, flags=et.ET_SPECULAR)
+    P = et.trace(ctx, sc, s)
+    rec = P.to_host()
+    bins = np.sort(g.choice(sim["F"], 16, replace=False)).astype(np.int32)
+    H_gpu = et.synthesize(ctx, s, P).cpu().numpy()
+    H = O.synth(rec, simk, bins=bins)
+    check_spectra(H_gpu[:, bins], H, f"D full ({len(rec['rtot'])} records): GPU forward vs oracle on 16 bins")
+    H_star = O.synth(rec, dict(simk, refl_k=k_star), bins=bins)
+    gR = H - H_star
+    gfull = np.zeros((32, sim["F"]), np.complex64)
+    gfull[:, bins] = gR
+    gk, gx = et.synthesize_backward(ctx, s, P, torch.as_tensor(gfull).cuda())
+    gk, gx = gk.cpu().numpy(), gx.cpu().numpy()
+
+    def loss(k, x):
+        return float(np.sum(np.abs(O.synth(rec, dict(simk, refl_k=k, rx_pos=x), bins=bins) - H_star) ** 2))
+    h = 1e-6
+    x0 = simk["rx_pos"]
+    for t in range(4):
+        dx = g.normal(size=x0.shape) * 0.01
+        fd = (loss(k0, x0 + h * dx) - loss(k0, x0 - h * dx)) / (2 * h)
+        an = float(np.sum(gx * dx))
+        print(f"D full, receiver direction {t}: adjoint {an:.6e}, central difference {fd:.6e}")
+        assert abs(an - fd) <= 1e-3 * abs(fd)
+    for t in range(4):
+        dk = g.normal(size=k0.shape).astype(np.float32)
+        dH = O.synth(rec, dict(simk, refl_k=dk), bins=bins)
+        ex = float(np.sum(2 * np.real(np.conj(gR) * dH)))   # exact: L is quadratic in k
+        an = float(np.sum(gk * dk.astype(np.float64)))
+        print(f"D full, coefficient direction {t}: adjoint {an:.6e}, exact {ex:.6e}")
+        assert abs(an - ex) <= 1e-4 * abs(ex)
