@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define ET_ABI_VERSION 3
+#define ET_ABI_VERSION 4
 
 typedef enum {
   ET_OK = 0,
@@ -270,7 +270,9 @@ typedef struct {
   const et_sim_desc* sim;       /* per-job descriptor (M, F, B, Q, Bk equal across jobs) */
 } et_job;
 
-/* Workspace for a batch (all jobs' rays and records and the synthesis scratch). */
+/* Workspace for a batch: fused (specular-only) batches run in job waves (et_tuning.wave_rays) and
+ * need one wave's rays, records and synthesis scratch; other batches run job after job and need
+ * the largest job's scratch plus every job's records. */
 int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes);
 
 /* Traces and synthesises J jobs (poses and scenes may all differ; M, F, Q and Bk are shared).
@@ -363,8 +365,12 @@ typedef struct {
   int32_t synth_wgs;      /* 64 .. 4096 */
   int32_t adjoint_wgs;    /* 64 .. 4096 */
   int32_t trace_blocks;   /* 64 .. 4096 */
-  int32_t reserved0;
-  double ms_trace, ms_synth, ms_adjoint;   /* event times of the chosen shape (et_autotune_batch) */
+  int32_t wave_rays;      /* rays per job wave of a fused batch: >= 1024, or 0 for the default 2^23.
+                             Jobs run in waves of consecutive jobs whose rays add up to at most this
+                             (a larger job forms its own wave); the workspace holds one wave's rays
+                             and records, so et_batch_workspace_size depends on it */
+  double ms_trace, ms_synth, ms_adjoint;   /* event times of the chosen shape (et_autotune_batch),
+                                              summed over the waves */
 } et_tuning;
 int et_get_tuning(et_ctx* ctx, et_tuning* out);
 int et_set_tuning(et_ctx* ctx, const et_tuning* t);   /* ET_E_INVALID outside the ranges */

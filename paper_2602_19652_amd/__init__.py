@@ -86,7 +86,7 @@ class Job(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("synth_wgs", C.c_int32), ("adjoint_wgs", C.c_int32), ("trace_blocks", C.c_int32),
-                ("reserved0", C.c_int32), ("ms_trace", C.c_double), ("ms_synth", C.c_double),
+                ("wave_rays", C.c_int32), ("ms_trace", C.c_double), ("ms_synth", C.c_double),
                 ("ms_adjoint", C.c_double)]
 
 
@@ -219,8 +219,8 @@ class Context:
         self.call("et_get_tuning", C.byref(t))
         return t
 
-    def set_tuning(self, synth_wgs: int, adjoint_wgs: int, trace_blocks: int):
-        t = Tuning(synth_wgs=synth_wgs, adjoint_wgs=adjoint_wgs, trace_blocks=trace_blocks)
+    def set_tuning(self, synth_wgs: int, adjoint_wgs: int, trace_blocks: int, wave_rays: int = 0):
+        t = Tuning(synth_wgs=synth_wgs, adjoint_wgs=adjoint_wgs, trace_blocks=trace_blocks, wave_rays=wave_rays)
         self.call("et_set_tuning", C.byref(t))
 
     def close(self):

@@ -10,7 +10,7 @@
 using namespace et;
 
 // which of the context's event pairs hold times of the last calls
-enum : uint32_t { TM_TRACE = 1, TM_SYNTH = 2, TM_ADJ = 4, TM_SYNTH_K = 8, TM_ADJ_K = 16 };
+enum : uint32_t { TM_TRACE = 1, TM_SYNTH = 2, TM_ADJ = 4, TM_SYNTH_K = 8, TM_ADJ_K = 16, TM_WAVES = 32 };
 
 struct et_ctx {
   int device = 0;
@@ -21,6 +21,8 @@ struct et_ctx {
   int32_t stack_cap = TRAV_STACK;     // per-lane traversal stack entries (et_set_stack_limit)
   hipEvent_t ev[12] = {};
   uint32_t timed = 0;   // event pairs holding the last calls' times (TM_* bits)
+  std::vector<hipEvent_t> wave_ev;   // fused batches: per job wave, trace / synthesis / adjoint pairs
+  int32_t waves_timed = 0;           // waves of the last timed fused batch (TM_WAVES)
   int synth_kernel = 0;
   et::BatchTune tune;
   int adjoint_kernel = 0;
@@ -169,20 +171,50 @@ WsPlan plan(const et_scene* sc, const et_sim_desc* s, int64_t cap) {
 
 // Workspace of a fused batch: trace job table, ray state of all jobs, records of all jobs,
 // synthesis scratch (visible list sorted by job, chunk tables, partial spectra, gradients).
+// Job waves of a fused batch: consecutive jobs whose rays add up to at most wave_rays (a job
+// with more rays forms a wave of its own).  Each wave is traced, synthesised and differentiated
+// by the fused kernels in the same workspace, so the workspace holds one wave's rays and records.
+struct Wave {
+  int32_t j0, n;
+  int64_t N, cap;
+};
+
+std::vector<Wave> job_waves(int32_t J, const et_job* jobs, int64_t wave_rays) {
+  std::vector<Wave> w;
+  Wave cur{0, 0, 0, 0};
+  for (int32_t j = 0; j < J; ++j) {
+    const int64_t nr = (jobs[j].sim->flags & ET_SPECULAR) ? jobs[j].sim->N : 0;
+    if (cur.n > 0 && cur.N + nr > wave_rays) {
+      w.push_back(cur);
+      cur = Wave{j, 0, 0, 0};
+    }
+    ++cur.n;
+    cur.N += nr;
+    cur.cap += records_upper_bound(jobs[j].sim);
+  }
+  w.push_back(cur);
+  return w;
+}
+
+// Workspace of a fused batch: each part sized for the largest wave.
 struct FusedPlan {
+  std::vector<Wave> waves;
   int64_t N = 0, cap = 0;
   size_t tj = 0, tw = 0, pp = 0, sy = 0, total = 0;
 };
 
 FusedPlan fused_plan(et_ctx* ctx, int32_t J, const et_job* jobs) {
   FusedPlan f;
-  f.N = trace_batch_rays(J, jobs);
-  for (int32_t j = 0; j < J; ++j) f.cap += records_upper_bound(jobs[j].sim);
-  f.cap = std::max<int64_t>(f.cap, 1);
-  f.tj = al(trace_batch_jobs_bytes(J));
+  f.waves = job_waves(J, jobs, ctx->tune.wave_rays);
+  for (const Wave& w : f.waves) {
+    const int64_t cap = std::max<int64_t>(w.cap, 1);
+    f.N = std::max(f.N, w.N);
+    f.cap = std::max(f.cap, cap);
+    f.tj = std::max(f.tj, al(trace_batch_jobs_bytes(w.n)));
+    f.sy = std::max(f.sy, al(synth_batch_ws_layout(w.n, jobs + w.j0, cap, ctx->tune, true, nullptr, nullptr)));
+  }
   f.tw = al(trace_ws_layout(f.N, 0, 0, 0, nullptr, nullptr, TUNE_MAX_TRACE_BLOCKS));
   f.pp = al(paths_bytes(f.cap));
-  f.sy = al(synth_batch_ws_layout(J, jobs, f.cap, ctx->tune, true, nullptr, nullptr));
   f.total = f.tj + f.tw + f.pp + f.sy;
   return f;
 }
@@ -199,6 +231,21 @@ size_t sequential_bytes(int32_t J, const et_job* jobs) {
 }
 
 void check_scene(const et_scene* sc) { ET_CHECK(sc, ET_E_INVALID, "scene is NULL"); }
+
+// Phase times of the last timed fused batch, summed over its job waves: trace, synthesis
+// kernel, adjoint kernel (ms; the stream must have completed the batch).
+void wave_phase_ms(et_ctx* ctx, double* t) {
+  t[0] = t[1] = t[2] = 0.0;
+  for (int32_t w = 0; w < ctx->waves_timed; ++w) {
+    const hipEvent_t* e = ctx->wave_ev.data() + 6 * w;
+    float ms = 0.f;
+    for (int p = 0; p < 3; ++p) {
+      if (p == 2 && !(ctx->timed & TM_ADJ_K)) break;
+      ET_HIP(hipEventElapsedTime(&ms, e[2 * p], e[2 * p + 1]));
+      t[p] += ms;
+    }
+  }
+}
 
 // The scene's materials index the pose's band tables.
 void check_materials(const et_scene* sc, const et_sim_desc* sim) {
@@ -296,6 +343,7 @@ int et_destroy(et_ctx* ctx) {
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->wave_ev) (void)hipEventDestroy(e);
   if (ctx->ctl) (void)hipFree(ctx->ctl);
   delete ctx;
   return ET_OK;
@@ -527,25 +575,50 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     char* base = (char*)ws;
     void* dj = base;
     base += f.tj;
-    TraceWS tw;
-    trace_ws_layout(f.N, 0, 0, 0, base, &tw, TUNE_MAX_TRACE_BLOCKS);
-    tw.stack_cap = ctx->stack_cap;
+    char* twb = base;
     base += f.tw;
-    char* pp = base;
-    et_paths P = carve_paths(pp, f.cap);
+    char* ppb = base;
     base += f.pp;
-    SynthBatchWS sw;
-    synth_batch_ws_layout(J, jobs, f.cap, ctx->tune, true, base, &sw);
-    if (timed) ET_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
-    trace_batch_run(J, jobs, dj, &P, tw, ctx->ctl, ctx->counting, ctx->tune.trace_blocks, ctx->stream);
-    if (timed) ET_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-    k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
-    int ak = 0;
-    const hipEvent_t kev[4] = {ctx->ev[8], ctx->ev[9], ctx->ev[10], ctx->ev[11]};
-    ctx->synth_kernel = synth_batch_run(J, jobs, &P, sw, ctx->ctl, spectra, grad_spectra, grad_k, grad_rx, &ak,
-                                        timed ? kev : nullptr, ctx->stream);
-    if (grad_spectra) ctx->adjoint_kernel = ak;
-    ctx->timed = timed ? (TM_TRACE | TM_SYNTH_K | (grad_spectra ? TM_ADJ_K : 0u)) : 0u;
+    char* syb = base;
+    const size_t MF2 = (size_t)s0->M * s0->F * 2;
+    const size_t QB = (size_t)s0->Q * s0->Bk;
+    const size_t nw = f.waves.size();
+    // timed: three event pairs per wave (trace, synthesis kernel, adjoint kernel)
+    if (timed)
+      while (ctx->wave_ev.size() < 6 * nw) {
+        hipEvent_t e;
+        ET_HIP(hipEventCreate(&e));
+        ctx->wave_ev.push_back(e);
+      }
+    for (size_t wi = 0; wi < nw; ++wi) {
+      const Wave& wv = f.waves[wi];
+      const et_job* wj = jobs + wv.j0;
+      const int64_t cap = std::max<int64_t>(wv.cap, 1);
+      TraceWS tw;
+      trace_ws_layout(wv.N, 0, 0, 0, twb, &tw, TUNE_MAX_TRACE_BLOCKS);
+      tw.stack_cap = ctx->stack_cap;
+      char* pp = ppb;
+      et_paths P = carve_paths(pp, cap);
+      SynthBatchWS sw;
+      synth_batch_ws_layout(wv.n, wj, cap, ctx->tune, true, syb, &sw);
+      hipEvent_t* ev = timed ? ctx->wave_ev.data() + 6 * wi : nullptr;
+      if (ev) ET_HIP(hipEventRecord(ev[0], ctx->stream));
+      trace_batch_run(wv.n, wj, dj, &P, tw, ctx->ctl, ctx->counting, ctx->tune.trace_blocks, ctx->stream, wi > 0);
+      if (ev) ET_HIP(hipEventRecord(ev[1], ctx->stream));
+      k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
+      int ak = 0;
+      const hipEvent_t kev[4] = {ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
+                                 ev ? ev[5] : nullptr};
+      ctx->synth_kernel =
+          synth_batch_run(wv.n, wj, &P, sw, ctx->ctl, spectra + (size_t)wv.j0 * MF2,
+                          grad_spectra ? grad_spectra + (size_t)wv.j0 * MF2 : nullptr,
+                          grad_spectra ? grad_k + (size_t)wv.j0 * QB : nullptr,
+                          grad_spectra ? grad_rx + (size_t)wv.j0 * s0->M * 3 : nullptr, &ak, ev ? kev : nullptr,
+                          ctx->stream);
+      if (grad_spectra) ctx->adjoint_kernel = ak;
+    }
+    ctx->waves_timed = timed ? (int32_t)nw : 0;
+    ctx->timed = timed ? (TM_WAVES | TM_TRACE | TM_SYNTH_K | (grad_spectra ? TM_ADJ_K : 0u)) : 0u;
     return;
   }
   size_t mx = 0;
@@ -607,6 +680,7 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
     key.push_back((uint64_t)(uintptr_t)grad_rx);
     key.push_back(((uint64_t)(uint32_t)ctx->tune.synth_wgs << 32) | (uint32_t)ctx->tune.adjoint_wgs);
     key.push_back((uint64_t)(uint32_t)ctx->tune.trace_blocks);
+    key.push_back((uint64_t)ctx->tune.wave_rays);
     for (int j = 0; j < J; ++j) {
       key.push_back((uint64_t)(uintptr_t)jobs[j].scene);
       const uint64_t* w = reinterpret_cast<const uint64_t*>(jobs[j].sim);
@@ -697,8 +771,8 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
     Ctl h;
     ET_HIP(hipMemcpy(&h, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
-    out->records = h.rec_base + h.diff_kept;
-    out->specular = h.rec_base;
+    out->records = h.rec_prev + h.rec_base + h.diff_kept;
+    out->specular = h.rec_prev + h.rec_base;
     out->diffraction = h.diff_kept;
     out->segments = h.seg;
     out->shadow_rays = h.shadow;
@@ -712,15 +786,23 @@ int et_get_stats(et_ctx* ctx, et_stats* out) {
       out->passive = cnt[0] - cnt[1] - cnt[2];
     }
     float ms = 0;
-    auto pair = [&](uint32_t bit, int a, int b, double& dst) {
-      if ((ctx->timed & bit) && hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) == hipSuccess) dst = ms;
-    };
-    pair(TM_TRACE, 0, 1, out->ms_trace);
-    pair(TM_SYNTH, 4, 5, out->ms_synth);
-    pair(TM_SYNTH_K, 8, 9, out->ms_synth_kernel);
-    pair(TM_ADJ, 6, 7, out->ms_adjoint);
-    if ((ctx->timed & TM_ADJ_K) && hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]) == hipSuccess)
-      out->ms_adjoint_kernel = ms;
+    if (ctx->timed & TM_WAVES) {
+      double t[3];
+      wave_phase_ms(ctx, t);
+      out->ms_trace = t[0];
+      out->ms_synth_kernel = t[1];
+      out->ms_adjoint_kernel = t[2];
+    } else {
+      auto pair = [&](uint32_t bit, int a, int b, double& dst) {
+        if ((ctx->timed & bit) && hipEventElapsedTime(&ms, ctx->ev[a], ctx->ev[b]) == hipSuccess) dst = ms;
+      };
+      pair(TM_TRACE, 0, 1, out->ms_trace);
+      pair(TM_SYNTH, 4, 5, out->ms_synth);
+      pair(TM_SYNTH_K, 8, 9, out->ms_synth_kernel);
+      pair(TM_ADJ, 6, 7, out->ms_adjoint);
+      if ((ctx->timed & TM_ADJ_K) && hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]) == hipSuccess)
+        out->ms_adjoint_kernel = ms;
+    }
     out->adjoint_kernel = ctx->adjoint_kernel;
     uint32_t err = h.err;
     out->status = ET_OK;
@@ -831,6 +913,7 @@ int et_get_tuning(et_ctx* ctx, et_tuning* out) {
     out->synth_wgs = ctx->tune.synth_wgs;
     out->adjoint_wgs = ctx->tune.adjoint_wgs;
     out->trace_blocks = ctx->tune.trace_blocks;
+    out->wave_rays = (int32_t)ctx->tune.wave_rays;
   });
 }
 
@@ -841,9 +924,11 @@ int et_set_tuning(et_ctx* ctx, const et_tuning* t) {
     ET_CHECK(in(t->synth_wgs, TUNE_MAX_WGS) && in(t->adjoint_wgs, TUNE_MAX_WGS) &&
                  in(t->trace_blocks, TUNE_MAX_TRACE_BLOCKS),
              ET_E_INVALID, "tuning values must lie in 64 .. 4096");
+    ET_CHECK(t->wave_rays == 0 || t->wave_rays >= MIN_WAVE_RAYS, ET_E_INVALID, "wave_rays must be 0 or >= 1024");
     ctx->tune.synth_wgs = t->synth_wgs;
     ctx->tune.adjoint_wgs = t->adjoint_wgs;
     ctx->tune.trace_blocks = t->trace_blocks;
+    ctx->tune.wave_rays = t->wave_rays == 0 ? BatchTune{}.wave_rays : (int64_t)t->wave_rays;
   });
 }
 
@@ -862,16 +947,7 @@ int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
     auto run = [&](double* t) {
       batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx, true);
       ET_HIP(hipStreamSynchronize(ctx->stream));
-      float ms = 0.f;
-      ET_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
-      t[0] = ms;
-      ET_HIP(hipEventElapsedTime(&ms, ctx->ev[8], ctx->ev[9]));
-      t[1] = ms;
-      t[2] = 0.0;
-      if (grad_spectra) {
-        ET_HIP(hipEventElapsedTime(&ms, ctx->ev[10], ctx->ev[11]));
-        t[2] = ms;
-      }
+      wave_phase_ms(ctx, t);
     };
     double t[3], best[3] = {INFINITY, INFINITY, INFINITY};
     BatchTune pick = ctx->tune;
@@ -890,6 +966,7 @@ int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
     out->synth_wgs = pick.synth_wgs;
     out->adjoint_wgs = pick.adjoint_wgs;
     out->trace_blocks = pick.trace_blocks;
+    out->wave_rays = (int32_t)pick.wave_rays;
     out->ms_trace = t[0];
     out->ms_synth = t[1];
     out->ms_adjoint = t[2];

@@ -146,6 +146,7 @@ struct Ctl {
   uint32_t pad0;
   int64_t n_active[2];       // active rays of the current / next bounce
   int64_t rec_base;          // specular records produced so far (may exceed capacity)
+  int64_t rec_prev;          // specular records of the earlier job waves of a batch
   int64_t seg;               // closest-hit segments traced
   int64_t shadow;            // line-of-sight rays traced
   int64_t overflow;          // traversal stack overflows
@@ -206,8 +207,9 @@ size_t trace_ws_layout(int64_t N, int64_t T, int32_t n_obj, int64_t K, char* bas
 // job index in their ray field.  dev_jobs holds trace_batch_jobs_bytes(J) bytes.
 size_t trace_batch_jobs_bytes(int32_t J);
 int64_t trace_batch_rays(int32_t J, const et_job* jobs);
+// carry: a later job wave of one batch (segment, line-of-sight and record totals carry over)
 void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_paths* paths, const TraceWS& w,
-                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s);
+                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s, bool carry = false);
 void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths, const TraceWS& ws, Ctl* ctl,
                bool counting, hipStream_t s);
 
@@ -288,7 +290,9 @@ struct BatchTune {
   int32_t synth_wgs = 2048;
   int32_t adjoint_wgs = 1024;
   int32_t trace_blocks = 2048;    // grid of the bounce kernels (grid-stride over the active rays)
+  int64_t wave_rays = 1ll << 23;  // rays of a job wave: jobs run in waves whose rays add up to this
 };
+constexpr int64_t MIN_WAVE_RAYS = 1024;
 // Largest values the autotuner tries; workspaces are sized for them.
 constexpr int32_t TUNE_MAX_WGS = 4096;
 constexpr int32_t TUNE_MAX_TRACE_BLOCKS = 4096;

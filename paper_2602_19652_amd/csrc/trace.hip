@@ -261,20 +261,26 @@ __global__ void k_put_trace_jobs(TraceJobPack pk, TraceJob* __restrict__ dst) {
 
 __device__ inline double dnorm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
 
-__global__ void k_trace_init(Ctl* ctl, int64_t N) {
+// carry: a later job wave of a batch; the totals of the statistics carry over
+__global__ void k_trace_init(Ctl* ctl, int64_t N, int carry) {
   ctl->n_active[0] = N;
   ctl->n_active[1] = 0;
+  if (carry) {
+    ctl->rec_prev += ctl->rec_base;
+  } else {
+    ctl->rec_prev = 0;
+    ctl->seg = 0;
+    ctl->shadow = 0;
+    ctl->overflow = 0;
+    for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
+  }
   ctl->rec_base = 0;
-  ctl->seg = 0;
-  ctl->shadow = 0;
-  ctl->overflow = 0;
   ctl->cmax_bits = 0;
   ctl->n_elig = 0;
   ctl->diff_kept = 0;
   ctl->n_groups = 0;
   ctl->n_draw = 0;
   for (int i = 0; i < 4; ++i) ctl->tot[i] = 0;
-  for (int i = 0; i < 6; ++i) ctl->cnt[i] = 0;
 }
 
 // The job of batch ray g (the last job with ray0 <= g; jobs without rays share ray0 with the next).
@@ -919,7 +925,7 @@ int64_t trace_batch_rays(int32_t J, const et_job* jobs) {
 }
 
 void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_paths* paths, const TraceWS& w,
-                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s) {
+                     Ctl* ctl, bool counting, int32_t blocks, hipStream_t s, bool carry) {
   TraceJob* dj = (TraceJob*)dev_jobs;
   TraceJobPack pk{};
   int64_t N = 0;
@@ -941,7 +947,7 @@ void trace_batch_run(int32_t J, const et_job* jobs, void* dev_jobs, const et_pat
   PoseArgs all{};
   all.N = N;
   const et_paths P = *paths;
-  k_trace_init<<<1, 1, 0, s>>>(ctl, N);
+  k_trace_init<<<1, 1, 0, s>>>(ctl, N, carry ? 1 : 0);
   ET_HIP(hipGetLastError());
   // bounce grid: the tuned block count, within what the workspace's global stacks serve
   const int64_t cap_blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, w.gstack_threads / BS));
@@ -973,7 +979,7 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
   const PoseArgs a = pose_args(sim);
   const et_paths P = *paths;
   const bool perrx = (sim->flags & ET_PER_RX_VISIBILITY) != 0;
-  k_trace_init<<<1, 1, 0, s>>>(ctl, a.N);
+  k_trace_init<<<1, 1, 0, s>>>(ctl, a.N, 0);
   ET_HIP(hipGetLastError());
   // every traversing grid below stays within the workspace's global stack columns
   auto stack_fits = [&](int64_t n) {

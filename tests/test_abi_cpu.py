@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(built):
 
 def test_abi_version_and_status_strings(built):
     built.et_abi_version.restype = ctypes.c_int
-    assert built.et_abi_version() == 3
+    assert built.et_abi_version() == 4
     built.et_status_string.restype = ctypes.c_char_p
     built.et_status_string.argtypes = [ctypes.c_int]
     assert built.et_status_string(0) == b"ok"

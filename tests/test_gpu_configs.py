@@ -108,6 +108,22 @@ def test_batch_fused_matches_plain_and_graph(et, ctx, batch_small):
     errs = [rel_l2(Hb[i], plain[i]) for i in range(len(b.jobs))]
     print(f"fused batch of {len(b.jobs)} jobs: segments {st.segments}, max rel L2 vs plain {max(errs):.3e}")
     assert max(errs) <= 1e-5
+    # in job waves of at most 4096 rays: the same segments and records in total, a smaller workspace
+    t0 = ctx.tuning()
+    ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 4096)
+    try:
+        bw = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+        Hw = bw.run().cpu().numpy()
+        stw = ctx.stats()
+        ew = [rel_l2(Hw[i], plain[i]) for i in range(len(b.jobs))]
+        print(f"in waves of <= 4096 rays: workspace {bw.ws.numel() / 1e6:.1f} MB against {batch.ws.numel() / 1e6:.1f} "
+              f"MB, segments {stw.segments}, records {stw.records} (one wave {st.records}), max rel L2 vs plain "
+              f"{max(ew):.3e}")
+        assert stw.segments == seg and stw.records == st.records
+        assert bw.ws.numel() < batch.ws.numel()
+        assert max(ew) <= 1e-5
+    finally:
+        ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 0)
     assert np.array_equal(batch.run().cpu().numpy(), Hb), "fused batch not deterministic"
     # graph capture on a side stream, replayed several times with eager work in between
     s = torch.cuda.Stream()
@@ -126,11 +142,24 @@ def _certified_records(rec):
     return {k: v[keep] for k, v in rec.items() if k not in ("certified", "nseg")}
 
 
-def test_batch_fused_matches_oracle_per_job(et, ctx, batch_small):
+@pytest.mark.parametrize("wave_rays", [0, 1024])
+def test_batch_fused_matches_oracle_per_job(et, ctx, batch_small, wave_rays):
     """Every job of a fused batch (6 poses in the room and the 4 uneven scenes, uneven ray
     counts) on its oracle-certified rays: the fused forward's spectra (eager, and graph replays
     with eager work between them) against the oracle's per job and per receiver, and the fused
-    adjoint's dL/dk and dL/dx_m per job against the oracle gradient for a seeded dL/dconj(H)."""
+    adjoint's dL/dk and dL/dx_m per job against the oracle gradient for a seeded dL/dconj(H).
+    Once as one job wave and once in waves of at most 1024 rays (four waves here), which reuse
+    one wave's workspace."""
+    import torch
+    t0 = ctx.tuning()
+    ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, wave_rays)
+    try:
+        _batch_vs_oracle(et, ctx, batch_small)
+    finally:
+        ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 0)
+
+
+def _batch_vs_oracle(et, ctx, batch_small):
     import torch
     b = batch_small
     scenes = [et.Scene(ctx, s) for s in b.scenes]
@@ -144,6 +173,8 @@ def test_batch_fused_matches_oracle_per_job(et, ctx, batch_small):
         psims.append(sim)
         sims.append(et.Sim(sim, flags=et.ET_SPECULAR, ray_dirs=dirs))
     batch = et.Batch(ctx, [(scenes[j.scene_index], sims[i]) for i, j in enumerate(b.jobs)])
+    print(f"batch of {len(b.jobs)} jobs, {sum(s.desc.N for s in sims)} rays, wave_rays {ctx.tuning().wave_rays}: "
+          f"workspace {batch.ws.numel() / 1e6:.1f} MB")
     J, M, F = len(b.jobs), sims[0].M, sims[0].F
     gen = np.random.default_rng(44)
     g = (gen.normal(size=(J, M, F)) + 1j * gen.normal(size=(J, M, F))).astype(np.complex64)
