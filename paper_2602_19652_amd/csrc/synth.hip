@@ -323,7 +323,6 @@ constexpr int K2 = 64;        // bins per inner run (k = 64 k1 + k2)
 constexpr int KT1 = 64;       // outer indices per workgroup
 constexpr int RB = 32;        // records per stage (contraction depth per stage)
 constexpr int RPW = RB / 4;   // records per wave and stage
-constexpr int XS = 80;        // LDS row stride (floats): 16-lane groups land on distinct banks
 constexpr int SMAX = 16;      // band segments (runs of equal material and directivity band) per 64-row tile
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -341,17 +340,23 @@ struct PairLean {
   float base, slope, gamma;
   float vx, vy, vz;
   int mat, kind;         // mat: row of the band tables (the material, or the record: rec_rows)
+  float lbm;             // bound on the log2 band factor (with directivity) over every band: the
+                         // generating factors carry it, so Xa stays below the record's bound and
+                         // the per-segment factors below 1
   // GRAD: receiver-gradient coefficients, d/dx_m of (ln A + j phi) = (c1 + c2 f + j c3 f) u - lobe
   float gux, guy, guz;   // u = (x_m - p) / l
   float gc1;             // -p / r - ln10 a0 / 20
   float glx, gly, glz;   // 2 (gamma / sin gamma) (d' - cos(gamma) u) / l (specular; 0 otherwise)
 };
 
+// GRAD: the adjoint's set-up (receiver-gradient coefficients; band factors without k).  dmax: the
+// receiver's largest log2 directivity gain (0 without directivity).
 template <bool GRAD = false>
 __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const int32_t* __restrict__ idx, int64_t e,
-                                 int64_t hi, int m, PairLean& q) {
+                                 int64_t hi, int m, PairLean& q, float dmax = 0.f) {
   q.a32 = q.bx32 = q.by32 = 0;
   q.base = -INFINITY;
+  q.lbm = 0.f;
   q.slope = q.gamma = q.vx = q.vy = q.vz = 0.f;
   q.mat = q.kind = 0;
   if (GRAD) q.gux = q.guy = q.guz = q.gc1 = q.glx = q.gly = q.glz = 0.f;
@@ -406,16 +411,39 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
       q.vx = -ux; q.vy = -uy; q.vz = -uz;
     }
   }
+  float bm = -INFINITY;
+  for (int b = 0; b < a.Bk; ++b) bm = fmaxf(bm, band_log2_v<GRAD>(a, q.kind, q.mat, q.gamma, b));
+  q.lbm = bm + dmax;
+  if (q.lbm == -INFINITY) q.base = -INFINITY;   // every band factor is zero: nothing to add
 }
 
-// The contraction runs as Gauss's three real products: with X = Xr + j Xi, Y = Yr + j Yi,
-//   A0 = Xr + Xi, A1 = Xr, A2 = Xi;  B0 = Yr, B1 = Yi - Yr, B2 = Yr + Yi,
-//   Re H = A0.B0 - A2.B2,  Im H = A0.B0 + A1.B1.
-// The LDS holds Xr, Xi, Yr, Yi; the sums are formed when the operands are loaded.
-struct GaussBuf {
-  float X[2][RB][XS];         // [re/im][record][k1]
-  float Y[2][RB][XS];         // [re/im][record][k2]
+// The forward contraction runs on the f16 matrix cores (v_mfma_f32_16x16x32_f16: 32 records per
+// instruction, FP32 accumulation).  Each FP32 operand v is split into two halves, hi = f16(v) and
+// lo = f16(v - hi), about 22 significant bits together; a real product takes three half
+// products, hi hi + hi lo + lo hi (lo lo lies below 2^-22 of it), and the complex product the four
+// real ones re re, im im, re im, im re.  The LDS holds the halves k-major: row k (an outer index
+// of X, an inner index of Y) holds the stage's 32 records in 4 chunks of 8, the chunk a lane
+// hands to an instruction (rows 80 bytes apart, so 16 lanes reading 16 bytes land on distinct
+// banks).  f16 has a narrow exponent range: X is scaled by 2^(XTOP - E) with E a workgroup-wide
+// bound on log2 |X| over each group of 256 records, taken before the group is generated; when a
+// group's bound exceeds E the accumulators are rescaled by a power of two (exact).  A record far
+// below the bound loses relative precision in proportion to its negligible share of the sum.
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+constexpr int HROW = 5;          // halfx8 per LDS row: 4 chunks of 8 records and a pad
+constexpr float XTOP = 12.f;     // log2 of the largest scaled |X| (|Y| <= 1 for non-negative absorption)
+struct H16Buf {
+  halfx8 A[4][KT1][HROW];        // X halves: [re hi, re lo, im hi, im lo][k1][record chunk]
+  halfx8 B[4][K2][HROW];         // Y halves: [re hi, re lo, im hi, im lo][k2][record chunk]
 };
+
+__device__ inline void split8(const float (&v)[8], halfx8& h, halfx8& l) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const _Float16 x = (_Float16)v[i];
+    h[i] = x;
+    l[i] = (_Float16)(v[i] - (float)x);
+  }
+}
 
 // Two-level generation: X[8a+b] = Xa[a] Xb[b] bf[seg(8a+b)] and Y[8a+b] = Ya[a] Yb[b]:
 // 32 exp2/sin/cos factors per record instead of 128 values, plus one real band factor
@@ -463,22 +491,22 @@ __device__ inline float2 cexp2(float lg, float rev) {
 }
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// One wave generates the X and Y rows of RPW records (sub-stage t of its 64 set-up records).
-// nseg band segments cover the tile; this lane's row lies in segment myseg.
-// X lands at xr/xi[record * xs + k1], Y at yr/yi[record * ys + k2].
+// One wave computes the generating factors of RPW records (sub-stage t of its 64 set-up
+// records): Xa, Xb, Ya, Yb (8 each) and the band factor of every (record, band segment) of the
+// tile, into its WaveScratch.  esh (log2) scales every X of the sub-stage.
 // KFREE: the specular band factor leaves out k (see band_log2_v).
 template <bool KFREE = false>
-__device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi, int xs,
-                                float* yr, float* yi, int ys, WaveScratch& W) {
+__device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
+                                   int nseg, const SegTable& st, float esh, WaveScratch& W) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
   const uint32_t a_r = (uint32_t)__shfl((int)q.a32, src), bx_r = (uint32_t)__shfl((int)q.bx32, src),
                  by_r = (uint32_t)__shfl((int)q.by32, src);
+  const float lbm_r = __shfl(q.lbm, src);
   const bool ok = base_r != -INFINITY;
   const uint32_t k1a = (uint32_t)(k1_0 + 8 * j);   // first outer index of group j
-  const float lg = base_r + (float)(k1a * K2) * slope_r;
+  const float lg = base_r + (float)(k1a * K2) * slope_r + esh + lbm_r;
   const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
   const float2 z0 = make_float2(0.f, 0.f);
   W.xa[r][j] = ok && 8 * j < nk1 ? cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S) : z0;
@@ -491,7 +519,7 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
     const int i = i0 + lane;
     const int rr = min(i / nseg, RPW - 1), sg = i - (i / nseg) * nseg;
     const int sr = t * RPW + rr;
-    const float g_r = __shfl(q.gamma, sr), b_r = __shfl(q.base, sr);
+    const float g_r = __shfl(q.gamma, sr), b_r = __shfl(q.base, sr), lm_r = __shfl(q.lbm, sr);
     const int m_r = __shfl(q.mat, sr), k_r = __shfl(q.kind, sr);
     const float vx = __shfl(q.vx, sr), vy = __shfl(q.vy, sr), vz = __shfl(q.vz, sr);
     if (i < RPW * nseg) {
@@ -499,7 +527,7 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
       if (b_r != -INFINITY) {
         float lb = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[sg]);
         if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
-        f = exp2f(lb);
+        f = exp2f(lb - lm_r);   // <= 1: the record's bound lbm rides on Xa
       }
       W.bf[rr][sg] = f;
     }
@@ -507,16 +535,32 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
   // the factors are read back by other lanes of this wave only
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// X and Y values of record rr for this lane's outer and inner index (lane = 8 a + b):
+// X[lane] = Xa[a] Xb[b] bf[segment of the lane's row], Y[lane] = Ya[a] Yb[b].
+__device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myseg, bool xon, float2& x, float2& y) {
   const int ka = lane >> 3, kb = lane & 7;
+  const float f = W.bf[rr][myseg];
+  x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
+  y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
+  x.x *= f;
+  x.y *= f;
+  if (!xon) x = make_float2(0.f, 0.f);
+}
+
+// FP32 X and Y rows of the sub-stage's records (the adjoint's operands): X at
+// xr/xi[record * xs + k1], Y at yr/yi[record * ys + k2].
+template <bool KFREE = false>
+__device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
+                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi, int xs,
+                                float* yr, float* yi, int ys, WaveScratch& W) {
+  gen_factors<KFREE>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, W);
   const bool xon = lane < nk1;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
-    const float f = W.bf[rr][myseg];
-    float2 x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
-    const float2 y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
-    x.x *= f;
-    x.y *= f;
-    if (!xon) x = z0;
+    float2 x, y;
+    xy_value(W, rr, lane, myseg, xon, x, y);
     xr[(row0 + rr) * xs + lane] = x.x;
     xi[(row0 + rr) * xs + lane] = x.y;
     yr[(row0 + rr) * ys + lane] = y.x;
@@ -526,59 +570,125 @@ __device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, in
   __builtin_amdgcn_wave_barrier();
 }
 
-// NK contraction steps of 4 records from record kk0: the (k1, k2) block of rows xrow0 + [0, 32)
-// and columns 32 h2 + [0, 32), Gauss forms built as the operands are loaded.
-template <int NK>
-__device__ inline void contract(const GaussBuf& buf, int kk0, int xrow0, int h2, int lane, floatx4 (&acc)[3][2][2]) {
-  const int cc = lane & 15;
-  // operands of step kq + 1 are read from LDS before the matrix products of step kq issue,
-  // so their latency hides behind those products
-  float nxr[2], nxi[2], nyr[2], nyi[2];
-  auto load = [&](int kq) {
-    const int rr = kk0 + 4 * kq + (lane >> 4);
+// The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
+// index into B, chunk wv (the wave's 8 records of the stage).
+__device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, bool xon, H16Buf& buf) {
+  float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      nxr[i] = buf.X[0][rr][xrow0 + i * 16 + cc];
-      nxi[i] = buf.X[1][rr][xrow0 + i * 16 + cc];
-      nyr[i] = buf.Y[0][rr][h2 * 32 + i * 16 + cc];
-      nyi[i] = buf.Y[1][rr][h2 * 32 + i * 16 + cc];
+  for (int rr = 0; rr < RPW; ++rr) {
+    float2 x, y;
+    xy_value(W, rr, lane, myseg, xon, x, y);
+    xr[rr] = x.x; xi[rr] = x.y; yr[rr] = y.x; yi[rr] = y.y;
+  }
+  halfx8 h, l;
+  split8(xr, h, l);
+  buf.A[0][lane][wv] = h;
+  buf.A[1][lane][wv] = l;
+  split8(xi, h, l);
+  buf.A[2][lane][wv] = h;
+  buf.A[3][lane][wv] = l;
+  split8(yr, h, l);
+  buf.B[0][lane][wv] = h;
+  buf.B[1][lane][wv] = l;
+  split8(yi, h, l);
+  buf.B[2][lane][wv] = h;
+  buf.B[3][lane][wv] = l;
+}
+
+// Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
+// blocks; with at most 32 rows (SPLIT), row block wv % 2 against the column blocks of half wv / 2.
+template <bool SPLIT>
+__device__ inline void wave_blocks(int wv, int& rb0, int& cb0) {
+  rb0 = SPLIT ? (wv & 1) : 2 * (wv >> 1);
+  cb0 = SPLIT ? 2 * (wv >> 1) : 2 * (wv & 1);
+}
+
+// One stage (32 records) into the wave's blocks: acc[0] += Xr Yr, acc[1] += Xi Yi,
+// acc[2] += Xr Yi + Xi Yr, each real product as three half products.
+template <bool SPLIT>
+__device__ inline void contract_h16(const H16Buf& buf, int wv, int lane, floatx4 (&acc)[3][2][2]) {
+  constexpr int NRB = SPLIT ? 1 : 2;
+  int rb0, cb0;
+  wave_blocks<SPLIT>(wv, rb0, cb0);
+  const int r16 = lane & 15, ch = lane >> 4;
+  halfx8 b[2][4];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) b[jj][f] = buf.B[f][16 * (cb0 + jj) + r16][ch];
+#pragma unroll
+  for (int i = 0; i < NRB; ++i) {
+    halfx8 av[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) av[f] = buf.A[f][16 * (rb0 + i) + r16][ch];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      floatx4 rr = acc[0][i][jj], ii = acc[1][i][jj], im = acc[2][i][jj];
+      rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], b[jj][0], rr, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], b[jj][1], rr, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], b[jj][0], rr, 0, 0, 0);
+      ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], b[jj][2], ii, 0, 0, 0);
+      ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], b[jj][3], ii, 0, 0, 0);
+      ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[3], b[jj][2], ii, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], b[jj][2], im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[0], b[jj][3], im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[1], b[jj][2], im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], b[jj][0], im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[2], b[jj][1], im, 0, 0, 0);
+      im = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[3], b[jj][0], im, 0, 0, 0);
+      acc[0][i][jj] = rr;
+      acc[1][i][jj] = ii;
+      acc[2][i][jj] = im;
     }
-  };
-  load(0);
-#pragma unroll
-  for (int kq = 0; kq < NK; ++kq) {
-    float av[3][2], bv[3][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float xr = nxr[i], xi = nxi[i], yr = nyr[i], yi = nyi[i];
-      av[0][i] = xr + xi; av[1][i] = xr; av[2][i] = xi;
-      bv[0][i] = yr; bv[1][i] = yi - yr; bv[2][i] = yr + yi;
-    }
-    if (kq + 1 < NK) load(kq + 1);
-#pragma unroll
-    for (int tt = 0; tt < 3; ++tt)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
-          acc[tt][i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tt][i], bv[tt][jj], acc[tt][i][jj], 0, 0, 0);
   }
 }
 
-// Workgroup = (record chunk p, receiver m, 64 outer indices).  Every 8 stages each wave sets
-// up 64 records (one per lane); every stage each wave generates 8 of them, then each wave
-// contracts all 32 records of the stage into its 32 x 32 block of (k1, k2) on the matrix
-// cores.  SPLIT (a single tile of at most 32 outer indices, e.g. 2048 bins, so one row
-// block): the wave pairs split each stage's records instead and add their accumulators at
-// the end.
+__device__ inline float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Upper bound on log2 |X[k1] Y[k2]| over the tile for the record set up in q (-inf for none):
+// the amplitude at the tile's first or last row, the record's band bound lbm (largest band
+// factor with its lobe, plus the receiver's largest log2 directivity gain), and what |Y| can
+// exceed 1 by.
+__device__ inline float record_bound(const PairLean& q, int k1_0, int nk1) {
+  if (q.base == -INFINITY) return -INFINITY;
+  const float s64 = (float)K2 * q.slope;
+  return q.base + fmaxf((float)k1_0 * s64, (float)(k1_0 + nk1 - 1) * s64) + fmaxf(0.f, (float)(K2 - 1) * q.slope) +
+         q.lbm;
+}
+
+// Largest log2 directivity gain of receiver m over every band and cell (the bilinear gain never
+// exceeds it); 0 without directivity.  Every thread of the workgroup calls it.
+__device__ inline float dir_log2_max(const SynthArgs& a, int m, int tid, float* red) {
+  if (!a.Bd) return 0.f;
+  const float* tab = a.dir + (size_t)m * a.Bd * a.El * a.Az;
+  const int n = a.Bd * a.El * a.Az;
+  float v = 0.f;
+  for (int i = tid; i < n; i += 256) v = fmaxf(v, tab[i]);
+  v = wave_max(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  v = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  return log2f(v);
+}
+
+// Workgroup = (record chunk p, receiver m, 64 outer indices).  Every 8 stages each wave sets up
+// 64 records (one per lane) and the workgroup bounds their |X|; every stage each wave generates
+// 8 of them as f16 halves into LDS, then each wave contracts all 32 records of the stage into
+// its blocks of (k1, k2) on the matrix cores.
 template <bool BATCH, bool SPLIT>
 __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
                                                     et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
                                                     float* __restrict__ part) {
   SYNTH_RESOLVE();
-  __shared__ __align__(16) GaussBuf buf;
+  __shared__ __align__(16) H16Buf buf;
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
+  __shared__ float red[4];
   const int p = bp, m = bm, k1t = bt;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K1 = a.F / K2;
@@ -586,9 +696,8 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArg
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
+  const float dmax = dir_log2_max(a, m, tid, red);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
-  const int h1 = wv >> 1, h2 = wv & 1;                        // this wave's 32 x 32 block of (k1, k2)
-  const int xrow0 = SPLIT ? 0 : h1 * 32;                      // SPLIT: one row block, records split
   floatx4 acc[3][2][2];
 #pragma unroll
   for (int t = 0; t < 3; ++t)
@@ -596,56 +705,52 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArg
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) acc[t][i][jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float E = -INFINITY;   // current exponent bound (uniform over the workgroup)
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
-    // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
-    if (t == 0) pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &buf.X[0][0][0], &buf.X[1][0][0], XS,
-             &buf.Y[0][0][0], &buf.Y[1][0][0], XS, wscr[wv]);
-    __syncthreads();
-    if (SPLIT) contract<RB / 8>(buf, h1 * (RB / 2), 0, h2, lane, acc);
-    else contract<RB / 4>(buf, 0, xrow0, h2, lane, acc);
-    __syncthreads();
-  }
-  if (SPLIT) {
-    // the second wave of each pair hands its accumulators over through the (now idle) buffer
-    static_assert(sizeof(GaussBuf) >= sizeof(float) * 2 * 48 * 64, "hand-over space");
-    float* xs = reinterpret_cast<float*>(&buf);
-    if (h1 == 1) {
+    if (t == 0) {
+      // wave w of stage group g owns records [lo + 256 g + 64 w, +64); sub-stage t takes 8 of them
+      pair_lean(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q, dmax);
+      const float ub = wave_max(record_bound(q, k1_0, nk1));
+      if (lane == 0) red[wv] = ub;
+      __syncthreads();
+      const float Eg = ceilf(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+      if (Eg > E) {
+        if (E != -INFINITY) {
+          const float r = exp2f(E - Eg);
 #pragma unroll
-      for (int t = 0; t < 3; ++t)
+          for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xs[((((h2 * 3 + t) * 2 + i) * 2 + jj) * 4 + v) * 64 + lane] = acc[t][i][jj][v];
+              for (int jj = 0; jj < 2; ++jj) acc[tt][i][jj] *= r;
+        }
+        E = Eg;
+      }
     }
+    gen_factors(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv]);
+    write_h16(wscr[wv], lane, wv, myseg, lane < nk1, buf);
     __syncthreads();
-    if (h1 == 1) return;
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[t][i][jj][v] += xs[((((h2 * 3 + t) * 2 + i) * 2 + jj) * 4 + v) * 64 + lane];
+    contract_h16<SPLIT>(buf, wv, lane, acc);
+    __syncthreads();
   }
-  // accumulator (i, jj, v) of lane l holds row k1 = xrow0 + 16 i + 4 (l / 16) + v, column k2 = 16 jj + l % 16
+  // accumulator (i, jj, v) of lane l: row k1 = 16 (rb0 + i) + 4 (l / 16) + v, column k2 = 16 (cb0 + jj) + l % 16
+  const float us = E != -INFINITY ? exp2f(E - XTOP) : 0.f;
+  int rb0, cb0;
+  wave_blocks<SPLIT>(wv, rb0, cb0);
   float* out = part + (((size_t)p * a.M + m) * a.F) * 2;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < (SPLIT ? 1 : 2); ++i)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int k1 = xrow0 + i * 16 + (lane >> 4) * 4 + v, k2 = h2 * 32 + jj * 16 + (lane & 15);
+        const int k1 = 16 * (rb0 + i) + (lane >> 4) * 4 + v, k2 = 16 * (cb0 + jj) + (lane & 15);
         if (k1 < nk1) {
           const size_t o = (size_t)((k1_0 + k1) * K2 + k2) * 2;
-          out[o] = acc[0][i][jj][v] - acc[2][i][jj][v];
-          out[o + 1] = acc[0][i][jj][v] + acc[1][i][jj][v];
+          out[o] = (acc[0][i][jj][v] - acc[1][i][jj][v]) * us;
+          out[o + 1] = acc[2][i][jj][v] * us;
         }
       }
 }
