@@ -549,27 +549,6 @@ __device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myse
   if (!xon) x = make_float2(0.f, 0.f);
 }
 
-// FP32 X and Y rows of the sub-stage's records (the adjoint's operands): X at
-// xr/xi[record * xs + k1], Y at yr/yi[record * ys + k2].
-template <bool KFREE = false>
-__device__ inline void generate(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                int row0, int nseg, int myseg, const SegTable& st, float* xr, float* xi, int xs,
-                                float* yr, float* yi, int ys, WaveScratch& W) {
-  gen_factors<KFREE>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, W);
-  const bool xon = lane < nk1;
-#pragma unroll
-  for (int rr = 0; rr < RPW; ++rr) {
-    float2 x, y;
-    xy_value(W, rr, lane, myseg, xon, x, y);
-    xr[(row0 + rr) * xs + lane] = x.x;
-    xi[(row0 + rr) * xs + lane] = x.y;
-    yr[(row0 + rr) * ys + lane] = y.x;
-    yi[(row0 + rr) * ys + lane] = y.y;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
 // index into B, chunk wv (the wave's 8 records of the stage).
 __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, bool xon, H16Buf& buf) {
@@ -594,6 +573,9 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
   buf.B[2][lane][wv] = h;
   buf.B[3][lane][wv] = l;
 }
+
+struct BwdBuf;
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, bool xon, BwdBuf& bb);
 
 // Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
 // blocks; with at most 32 rows (SPLIT), row block wv % 2 against the column blocks of half wv / 2.
@@ -1039,7 +1021,9 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 //   S_b = sum_{k1 in b} X[k1] Z[k1],          Z[k1]  = sum_k2 G[k1, k2] Y[k2],
 //   S1  = sum_k1 X[k1] (f_k1 Z[k1] + df Z'[k1]),  Z'[k1] = sum_k2 G[k1, k2] k2 Y[k2],
 // f_k1 the frequency of bin 64 k1.  Z and Z' are complex matrix products contracting over
-// k2 (Gauss's three real products on the matrix cores, G in registers).  The per-row
+// k2 on the f16 matrix cores with split operands (as in the forward kernel): G = conj(g) and
+// k2 G sit in registers as halves, each scaled into the f16 range by a power of two per wave,
+// and Y is written as halves, record-major (8 inner indices per lane, 16-byte reads).  The per-row
 // products go to LDS; per record, band sums and the weighted sum run in FP64 in a fixed
 // order, and the FP64 chain rule of the direct adjoint turns them into dL/dk and dL/dx_m.
 // LDS record stride of the adjoint's X, Y and R0: with 68 = 4 (mod 64) the MFMA operand reads
@@ -1049,9 +1033,10 @@ constexpr int BS68 = 68;
 
 // X carries the band factor without k for specular records: Re(X Z) summed over a band's rows
 // is then dH/dk of that band (also where k = 0), and k enters the other sums per row.
+constexpr int YROW = 9;     // halfx8 per record row of Y halves: 64 inner indices and a pad (144-byte rows)
 struct __align__(16) BwdBuf {
   float X[2][RB][BS68];      // [re/im][record][k1]
-  float Y[2][RB][BS68];      // [re/im][record][k2]
+  halfx8 Y[4][RB][YROW];     // Y halves [re hi, re lo, im hi, im lo][record][chunk of 8 inner indices]
   float R0[RB][BS68];        // Re(X Z) per (record, row)
   float2 R1[RB][17];         // sum over 4 rows of k X (f Z + df Z') per (record, row group)
   double kv[RB][17];         // dL/dk contribution per (record, band)
@@ -1060,6 +1045,33 @@ struct __align__(16) BwdBuf {
   float kf[256 + 16];        // per (material, band): k; then a row of ones (records of other kinds)
   int32_t recb[RB];          // per record of the stage: its row of kf (mat Bk, or the ones row)
 };
+
+// The adjoint's operands of the sub-stage's records: X in FP32 at [record][k1] (lane = k1), and Y
+// as f16 halves record-major, lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7
+// of record r: Y[8 c + i] = Ya[c] Yb[i].
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, bool xon, BwdBuf& bb) {
+  const int row0 = wv * RPW;
+#pragma unroll
+  for (int rr = 0; rr < RPW; ++rr) {
+    float2 x, y;
+    xy_value(W, rr, lane, myseg, xon, x, y);
+    bb.X[0][row0 + rr][lane] = x.x;
+    bb.X[1][row0 + rr][lane] = x.y;
+  }
+  const int r = lane >> 3, c = lane & 7;
+  const float2 ya = W.ya[r][c];
+  float yr[8], yi[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float2 y = cmul(ya, W.yb[r][i]);
+    yr[i] = y.x;
+    yi[i] = y.y;
+  }
+  split8(yr, bb.Y[0][row0 + r][c], bb.Y[1][row0 + r][c]);
+  split8(yi, bb.Y[2][row0 + r][c], bb.Y[3][row0 + r][c]);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 template <bool BATCH, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
@@ -1084,18 +1096,54 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   constexpr int NB = SPLIT ? 1 : 2;              // record blocks of 16 per wave and stage
   const int rbw = SPLIT ? (wv & 1) : wv;
   const int nb0 = SPLIT ? (wv >> 1) : 0;
-  // A operands: rows k1 = 16 rbw + lane % 16 of G, columns k2 = 4 ks + lane / 16, as Gauss forms
-  float ga[3][16];
-  const int r1g = rbw * 16 + (lane & 15);
+  // A operands: rows k1 = 16 rbw + lane % 16 of G = conj(g) and of k2 G, inner indices
+  // k2 = 32 h + 8 (lane / 16) + i (h < 2, i < 8), as f16 halves [re hi, re lo, im hi, im lo],
+  // scaled by 2^eg and 2^eg2 (per wave) so that the largest magnitude is near 2^12
+  halfx8 ga[2][4], gw[2][4];
+  float usz, usw;   // 2^-eg, 2^-eg2: undo the scales on Z and Z'
+  {
+    const int r1g = rbw * 16 + (lane & 15);
+    float gr[2][8], gi[2][8];
+    float mz = 0.f, mw = 0.f;
 #pragma unroll
-  for (int ks = 0; ks < 16; ++ks) {
-    float gr = 0.f, gi = 0.f;
-    if (r1g < nk1) {
-      const int k = (k1_0 + r1g) * K2 + 4 * ks + (lane >> 4);
-      gr = g[((size_t)m * a.F + k) * 2];
-      gi = -g[((size_t)m * a.F + k) * 2 + 1];
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k2 = 32 * h + 8 * (lane >> 4) + i;
+        float vr = 0.f, vi = 0.f;
+        if (r1g < nk1) {
+          const int k = (k1_0 + r1g) * K2 + k2;
+          vr = g[((size_t)m * a.F + k) * 2];
+          vi = -g[((size_t)m * a.F + k) * 2 + 1];
+        }
+        gr[h][i] = vr;
+        gi[h][i] = vi;
+        const float mg = fmaxf(fabsf(vr), fabsf(vi));
+        mz = fmaxf(mz, mg);
+        mw = fmaxf(mw, mg * (float)k2);
+      }
+    mz = wave_max(mz);
+    mw = wave_max(mw);
+    const float ez = mz > 0.f ? 12.f - ceilf(log2f(mz)) : 0.f, ew = mw > 0.f ? 12.f - ceilf(log2f(mw)) : 0.f;
+    const float sz = exp2f(ez), sw = exp2f(ew);
+    usz = exp2f(-ez);
+    usw = exp2f(-ew);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float zr[8], zi[8], wr[8], wi[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float k2 = (float)(32 * h + 8 * (lane >> 4) + i);
+        zr[i] = gr[h][i] * sz;
+        zi[i] = gi[h][i] * sz;
+        wr[i] = gr[h][i] * k2 * sw;
+        wi[i] = gi[h][i] * k2 * sw;
+      }
+      split8(zr, ga[h][0], ga[h][1]);
+      split8(zi, ga[h][2], ga[h][3]);
+      split8(wr, gw[h][0], gw[h][1]);
+      split8(wi, gw[h][2], gw[h][3]);
     }
-    ga[0][ks] = gr + gi; ga[1][ks] = gr; ga[2][ks] = gi;
   }
   const float frow0 = (float)(a.f_lo + (double)(k1_0 * K2) * a.df), df64 = (float)(K2 * a.df), dff = (float)a.df;
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;
@@ -1125,8 +1173,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    generate<true>(a, q, t, m, k1_0, nk1, lane, wv * RPW, nseg, myseg, st, &bb.X[0][0][0], &bb.X[1][0][0], BS68,
-                   &bb.Y[0][0][0], &bb.Y[1][0][0], BS68, wscr[wv]);
+    gen_factors<true>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv]);
+    write_bwd(wscr[wv], lane, wv, myseg, lane < nk1, bb);
     {
       // each generated record's row of k factors
       const int src = t * RPW + (lane & 7);
@@ -1134,26 +1182,40 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       if (lane < RPW) bb.recb[wv * RPW + lane] = k_r == 0 ? m_r * a.Bk : QB;
     }
     __syncthreads();
+    // acc[0..2]: Z as Gr Yr, Gi Yi, Gr Yi + Gi Yr; acc[3..5]: Z' likewise (k2 G)
     floatx4 acc[6][NB];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 16; ++ks) {
-      const int kk = 4 * ks + (lane >> 4);
-      const float w2 = (float)kk;
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int nn = (nb0 + j) * 16 + (lane & 15);
-        const float yr = bb.Y[0][nn][kk], yi = bb.Y[1][nn][kk];
-        const float b0 = yr, b1 = yi - yr, b2 = yr + yi;
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], b0, acc[0][j], 0, 0, 0);
-        acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], b1, acc[1][j], 0, 0, 0);
-        acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], b2, acc[2][j], 0, 0, 0);
-        acc[3][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[0][ks], w2 * b0, acc[3][j], 0, 0, 0);
-        acc[4][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[1][ks], w2 * b1, acc[4][j], 0, 0, 0);
-        acc[5][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[2][ks], w2 * b2, acc[5][j], 0, 0, 0);
+        halfx8 y[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) y[f] = bb.Y[f][nn][4 * h + (lane >> 4)];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const halfx8* A = u ? gw[h] : ga[h];
+          floatx4 rr = acc[3 * u][j], ii = acc[3 * u + 1][j], im = acc[3 * u + 2][j];
+          rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0], y[0], rr, 0, 0, 0);
+          rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0], y[1], rr, 0, 0, 0);
+          rr = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1], y[0], rr, 0, 0, 0);
+          ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[2], y[2], ii, 0, 0, 0);
+          ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[2], y[3], ii, 0, 0, 0);
+          ii = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[3], y[2], ii, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0], y[2], im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0], y[3], im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1], y[2], im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[2], y[0], im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[2], y[1], im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[3], y[0], im, 0, 0, 0);
+          acc[3 * u][j] = rr;
+          acc[3 * u + 1][j] = ii;
+          acc[3 * u + 2][j] = im;
+        }
       }
     }
     // accumulator (j, v) of lane l: row 16 rbw + 4 (l / 16) + v, record 16 (nb0 + j) + l % 16
@@ -1170,8 +1232,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       float s1r = 0.f, s1i = 0.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float zr = acc[0][j][v] - acc[2][j][v], zi = acc[0][j][v] + acc[1][j][v];
-        const float wr = acc[3][j][v] - acc[5][j][v], wi = acc[3][j][v] + acc[4][j][v];
+        const float zr = (acc[0][j][v] - acc[1][j][v]) * usz, zi = acc[2][j][v] * usz;
+        const float wr = (acc[3][j][v] - acc[4][j][v]) * usw, wi = acc[5][j][v] * usw;
         const float xr = xrv[v], xi = xiv[v];
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
         const float fr = frow0 + (float)(r10 + v) * df64;
