@@ -1031,15 +1031,18 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 // contiguous, and 16-byte accesses of four consecutive rows are conflict-free per quarter wave.
 constexpr int BS68 = 68;
 
+// Group-major sums (stride 36): the eight threads of each of a wave's eight records reading
+// groups 2 j + i fall on 64 distinct banks.
 // X carries the band factor without k for specular records: Re(X Z) summed over a band's rows
 // is then dH/dk of that band (also where k = 0), and k enters the other sums per row.
 constexpr int YROW = 9;     // halfx8 per record row of Y halves: 64 inner indices and a pad (144-byte rows)
 struct __align__(16) BwdBuf {
   float X[2][RB][BS68];      // [re/im][record][k1]
   halfx8 Y[4][RB][YROW];     // Y halves [re hi, re lo, im hi, im lo][record][chunk of 8 inner indices]
-  float R0[RB][BS68];        // Re(X Z) per (record, row)
-  float2 R1[RB][17];         // sum over 4 rows of k X (f Z + df Z') per (record, row group)
-  double kv[RB][17];         // dL/dk contribution per (record, band)
+  float R0[RB][BS68];        // Re(X Z) per (record, row) (band edges off the 4-row groups)
+  float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (G4)
+  float2 R1[16][36];         // sum over 4 rows of k X (f Z + df Z') per (row group, record)
+  double kv[2][RB][17];      // dL/dk contribution per (record, band), stage parity
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
   double lobe_w[256];        // per (material, band): 1 / (2 beta^2)
   float kf[256 + 16];        // per (material, band): k; then a row of ones (records of other kinds)
@@ -1073,7 +1076,9 @@ __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int mys
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool BATCH, bool SPLIT>
+// G4: every band edge of the grid falls on a group of 4 rows (a multiple of 256 bins), so each
+// lane's four rows of the matrix-product output belong to one band and are summed in registers.
+template <bool BATCH, bool SPLIT, bool G4>
 __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                         ChunkTab ct, et_paths P, const int32_t* __restrict__ idx,
                                                         const Ctl* ctl, const float* __restrict__ g,
@@ -1152,7 +1157,6 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const int QB = a.Q * a.Bk;
   double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
-  for (int i = tid; i < a.Q; i += 256) bb.kmask[0][i] = bb.kmask[1][i] = 0u;   // first used after two barriers
   for (int i = tid; i < QB; i += 256) {
     const double bt = (double)a.beta[i];
     bb.lobe_w[i] = 1.0 / (2.0 * bt * bt);
@@ -1237,15 +1241,40 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         const float xr = xrv[v], xi = xiv[v];
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
         const float fr = frow0 + (float)(r10 + v) * df64;
-        const float kv = kfr[rband[v]];
         crv[v] = cr;
-        s1r += kv * (fr * cr + dff * (xr * wr - xi * wi));
-        s1i += kv * (fr * ci + dff * (xr * wi + xi * wr));
+        if (G4) {   // one band over the four rows: k applies to their sum
+          s1r += fr * cr + dff * (xr * wr - xi * wi);
+          s1i += fr * ci + dff * (xr * wi + xi * wr);
+        } else {
+          const float kv = kfr[rband[v]];
+          s1r += kv * (fr * cr + dff * (xr * wr - xi * wi));
+          s1i += kv * (fr * ci + dff * (xr * wi + xi * wr));
+        }
       }
-      *reinterpret_cast<float4*>(&bb.R0[n][r10]) = make_float4(crv[0], crv[1], crv[2], crv[3]);
-      bb.R1[n][rbw * 4 + (lane >> 4)] = make_float2(s1r, s1i);
+      const int grp = rbw * 4 + (lane >> 4);
+      if (G4) {
+        const float kv = kfr[rband[0]];
+        bb.Rg[grp][n] = (crv[0] + crv[1]) + (crv[2] + crv[3]);
+        bb.R1[grp][n] = make_float2(kv * s1r, kv * s1i);
+      } else {
+        *reinterpret_cast<float4*>(&bb.R0[n][r10]) = make_float4(crv[0], crv[1], crv[2], crv[3]);
+        bb.R1[grp][n] = make_float2(s1r, s1i);
+      }
     }
+    // this stage's masks were last read after the previous stage's second barrier
+    for (int i = tid; i < a.Q; i += 256) bb.kmask[s & 1][i] = 0u;
     __syncthreads();
+    if (s > 0 && tid < QB) {
+      // dL/dk of the previous stage: this (material, band)'s records, in increasing order
+      const int qq = tid / a.Bk, b = tid - qq * a.Bk;
+      const int pp = (int)((s - 1) & 1);
+      uint32_t mk = bb.kmask[pp][qq];
+      while (mk) {
+        const int n = __ffs(mk) - 1;
+        kacc += bb.kv[pp][n][b];
+        mk &= mk - 1u;
+      }
+    }
     {
       // eight threads per record: row sums in FP64, bands j and j + 8.  Record n of this stage
       // was set up by lane 8 t + n % 8 of this same wave: its data arrive by shuffle.
@@ -1256,49 +1285,55 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       const float gux = __shfl(q.gux, src), guy = __shfl(q.guy, src), guz = __shfl(q.guz, src);
       const float gc1 = __shfl(q.gc1, src);
       const float glx = __shfl(q.glx, src), gly = __shfl(q.gly, src), glz = __shfl(q.glz, src);
-      double s1r = 0.0, s1i = 0.0;
+      // partial sums of this thread (row groups 2 j, 2 j + 1; bands j, j + 8) in FP32, combined
+      // over the record's eight threads in a fixed order
+      float s1r = 0.f, s1i = 0.f;
       const int ngroups = SPLIT ? 8 : 16;   // row groups of 4 written this stage
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (j + 8 * h >= ngroups) continue;
-        const float2 c = bb.R1[n][j + 8 * h];
-        s1r += (double)c.x;
-        s1i += (double)c.y;
+      for (int i = 0; i < 2; ++i) {
+        if (2 * j + i >= ngroups) continue;
+        const float2 c = bb.R1[2 * j + i][n];
+        s1r += c.x;
+        s1i += c.y;
       }
-      double s0 = 0.0, wl = 0.0;
+      float s0 = 0.f, wl = 0.f;
+      const int pp = (int)(s & 1);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int b = j + 8 * h;
-        double sb = 0.0;
+        float sb = 0.f;
         if (b < a.Bk) {
           const int sg = st.bseg[b];
           if (sg >= 0) {
-            // the band's rows in four interleaved FP32 partial sums (independent LDS reads),
-            // combined in a fixed order
-            const int e = st.s1[sg];
-            int r1 = st.s0[sg];
-            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-            for (; r1 + 4 <= e; r1 += 4) {
-              p0 += bb.R0[n][r1];
-              p1 += bb.R0[n][r1 + 1];
-              p2 += bb.R0[n][r1 + 2];
-              p3 += bb.R0[n][r1 + 3];
+            if (G4) {
+              for (int gg = st.s0[sg] >> 2; gg < st.s1[sg] >> 2; ++gg) sb += bb.Rg[gg][n];
+            } else {
+              // the band's rows in four interleaved partial sums (independent LDS reads)
+              const int e = st.s1[sg];
+              int r1 = st.s0[sg];
+              float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+              for (; r1 + 4 <= e; r1 += 4) {
+                p0 += bb.R0[n][r1];
+                p1 += bb.R0[n][r1 + 1];
+                p2 += bb.R0[n][r1 + 2];
+                p3 += bb.R0[n][r1 + 3];
+              }
+              for (; r1 < e; ++r1) p0 += bb.R0[n][r1];
+              sb = (p0 + p1) + (p2 + p3);
             }
-            for (; r1 < e; ++r1) p0 += bb.R0[n][r1];
-            sb = (double)((p0 + p1) + (p2 + p3));
           }
         }
         // sb leaves out k for specular records: k sb is the band's share of H's sums, 2 sb its dL/dk
         double kvv = 0.0;
         if (b < a.Bk) {
-          const double kb = kind == 0 ? (double)bb.kf[mat * a.Bk + b] : 1.0;
+          const float kb = kind == 0 ? bb.kf[mat * a.Bk + b] : 1.f;
           s0 += kb * sb;
           if (valid && kind == 0) {
-            wl += kb * sb * bb.lobe_w[mat * a.Bk + b];
-            kvv = 2.0 * sb;
+            wl += kb * sb * (float)bb.lobe_w[mat * a.Bk + b];
+            kvv = 2.0 * (double)sb;
           }
         }
-        bb.kv[n][b] = kvv;
+        bb.kv[pp][n][b] = kvv;
       }
 #pragma unroll
       for (int o = 1; o < 8; o <<= 1) {
@@ -1307,29 +1342,28 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         s0 += __shfl_xor(s0, o);
         wl += __shfl_xor(wl, o);
       }
-      // record n joins its material's mask of this stage (an OR: the result is order-free);
-      // the other parity's masks (read by the previous stage) are cleared for the next one
-      if (j == 0 && valid && kind == 0) atomicOr(&bb.kmask[s & 1][mat], 1u << n);
-      for (int i = tid; i < a.Q; i += 256) bb.kmask[(s + 1) & 1][i] = 0u;
+      // record n joins its material's mask of this stage (an OR: the result is order-free)
+      if (j == 0 && valid && kind == 0) atomicOr(&bb.kmask[pp][mat], 1u << n);
       if (j == 0 && valid) {
         // d(ln A + j phi)/dx_m = [(-p/r - ln10 (a0 + a1 f)/20) + j sigma 2 pi f / c] u - d(gamma^2)/dx / (2 beta^2)
-        const double cu = (double)gc1 * s0 + c2 * s1r + c3 * s1i;
-        const double g0 = 2.0 * cu * (double)gux + wl * (double)glx;
-        const double g1 = 2.0 * cu * (double)guy + wl * (double)gly;
-        const double g2 = 2.0 * cu * (double)guz + wl * (double)glz;
+        const double cu = (double)gc1 * (double)s0 + c2 * (double)s1r + c3 * (double)s1i;
+        const double g0 = 2.0 * cu * (double)gux + (double)wl * (double)glx;
+        const double g1 = 2.0 * cu * (double)guy + (double)wl * (double)gly;
+        const double g2 = 2.0 * cu * (double)guz + (double)wl * (double)glz;
         gx0 += g0; gx1 += g1; gx2 += g2;
       }
     }
-    __syncthreads();
-    if (tid < QB) {
-      // this material's records of the stage, in increasing order
-      const int qq = tid / a.Bk, b = tid - qq * a.Bk;
-      uint32_t mk = bb.kmask[s & 1][qq];
-      while (mk) {
-        const int n = __ffs(mk) - 1;
-        kacc += bb.kv[n][b];
-        mk &= mk - 1u;
-      }
+  }
+  __syncthreads();
+  if (nst > 0 && tid < QB) {
+    // dL/dk of the last stage
+    const int qq = tid / a.Bk, b = tid - qq * a.Bk;
+    const int pp = (int)((nst - 1) & 1);
+    uint32_t mk = bb.kmask[pp][qq];
+    while (mk) {
+      const int n = __ffs(mk) - 1;
+      kacc += bb.kv[pp][n][b];
+      mk &= mk - 1u;
     }
   }
   const size_t slot = ((size_t)p * gridDim.z + k1t) * a.M + m;
@@ -1689,6 +1723,25 @@ int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, 
 
 bool synth_bwd_factorised_ok(const et_sim_desc* sim) { return !sim->directivity && synth_factorised_ok(sim); }
 
+// Every material band edge on a multiple of four outer indices (256 bins): the adjoint sums a
+// lane's four output rows before the band sums.
+bool bands_on_row_groups(const et_sim_desc* sim) {
+  const int64_t F = sim->F, Bk = sim->Bk;
+  for (int64_t k1 = 1; k1 < F / K2; ++k1)
+    if (k1 % 4 && (k1 * K2) * Bk / F != ((k1 - 1) * K2) * Bk / F) return false;
+  return true;
+}
+
+template <bool BATCH>
+void launch_bwd_mfma(bool split, bool g4, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
+                     const ChunkTab& ct, const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g,
+                     double* gpx, double* gpk) {
+  if (split && g4) k_synth_bwd_mfma<BATCH, true, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else if (split) k_synth_bwd_mfma<BATCH, true, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else if (g4) k_synth_bwd_mfma<BATCH, false, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else k_synth_bwd_mfma<BATCH, false, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+}
+
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
   cap = std::max<int64_t>(cap, 1);
   const bool mf = synth_bwd_factorised_ok(sim);
@@ -1727,12 +1780,8 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);
-    if (sim->F / K2 <= 32)
-      k_synth_bwd_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra,
-                                                         ws.gpart_x, ws.gpart_k);
-    else
-      k_synth_bwd_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, grad_spectra,
-                                                          ws.gpart_x, ws.gpart_k);
+    launch_bwd_mfma<false>(sim->F / K2 <= 32, bands_on_row_groups(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx,
+                           ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
   } else {
     dim3 grid(ws.gchunks, sim->M);
     const size_t shm = sizeof(float2) * (size_t)sim->F;
@@ -1774,6 +1823,8 @@ size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const B
   w.cap = cap;
   w.mf = synth_batch_factorised(J, jobs, false);
   w.mf_bwd = adjoint && synth_batch_factorised(J, jobs, true);
+  w.g4 = true;
+  for (int32_t i = 0; i < J; ++i) w.g4 = w.g4 && bands_on_row_groups(jobs[i].sim);
   w.target = chunk_target(s0, w.mf, tune.synth_wgs);
   w.target_bwd = chunk_target(s0, w.mf_bwd, tune.adjoint_wgs);
   // grid size: the chunk count is at most target + J (sum_j ceil(n_j / per)); buffers are
@@ -1868,10 +1919,7 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[2], s));
     if (w.mf_bwd) {
       dim3 grid(w.chunks_bwd, s0->M, w.T1);
-      if (s0->F / K2 <= 32)
-        k_synth_bwd_mfma<true, true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
-      else
-        k_synth_bwd_mfma<true, false><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
+      launch_bwd_mfma<true>(s0->F / K2 <= 32, w.g4, grid, s, a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
     } else {
       dim3 grid(w.chunks_bwd, s0->M);
       k_synth_bwd<true><<<grid, GB, sizeof(float2) * (size_t)s0->F, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,

@@ -329,6 +329,8 @@ ADJOINT_CASES = {
     # name: (bins, material bands, forced direct, diffraction records added, kernel expected)
     "factorised_F512": (512, 8, False, False, 1),
     "factorised_F8192_two_tiles": (8192, 16, False, False, 1),
+    "factorised_F1024_bands_on_256_bins": (1024, 4, False, False, 1),   # 16 outer indices, band edges on 4 of them
+    "factorised_F3072_bands_off_256_bins": (3072, 16, False, False, 1),  # 48 outer indices, 3 per band
     "factorised_F512_diffraction": (512, 8, False, True, 1),
     "direct_F512": (512, 8, True, False, 2),
     "direct_F500": (500, 4, False, False, 2),      # bins not a multiple of 64
