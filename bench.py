@@ -32,9 +32,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays·bounces/s + G(hit·mic·bin)/s synthesis; batched fwd+adjoint vs plain"
 PEAK_HBM_GBS = 8000.0
-PEAK_MFMA_F32_TFLOPS = 157.3
+PEAK_MFMA_F16_TFLOPS = 2500.0    # dense fp16 matrix cores: the synthesis products' operand type
+PEAK_MFMA_F32_TFLOPS = 157.3     # dense fp32 matrix cores: the ceiling of an fp32-operand contraction
 SYNTH_FLOP_PER_TERM = 8          # one complex multiply-accumulate (4 mul + 4 add)
 ADJ_FLOP_PER_TERM = 16           # two: the band sum conj(g) T and the frequency-weighted sum
+# executed on the matrix cores: every fp32 factor is split into two f16 halves and each real
+# product taken as three half products (hi hi, hi lo, lo hi); a complex multiply-accumulate
+# is four real products, so 12 half products of 2 flop each per term (twice that in the adjoint)
+SYNTH_EXEC_FLOP_PER_TERM = 24
+ADJ_EXEC_FLOP_PER_TERM = 48
+FLOP_PER_MFMA_F16 = 2 * 16 * 16 * 32   # v_mfma_f32_16x16x32_f16
 NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 128
 
 
@@ -47,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=32768, help="rays of the oracle's bounded sample (about 10 s of host work)")
     ap.add_argument("--profile-only", action="store_true", help="a few steps, no baselines (for rocprofv3)")
+    ap.add_argument("--profile-workload", choices=("room", "foliage"), default="room",
+                    help="the step --profile-only runs: the room (with one adjoint call) or the foliage scene")
     ap.add_argument("--no-extra-legs", action="store_true",
                     help="skip the dynamic-scene and other-workload legs (a kernel trace then holds only the "
                          "room step's synthesis launches)")
@@ -60,29 +69,60 @@ def source_hash(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch measured by rocprofv3 counters, if taken on the current source."""
+def counter_for(kernel: str, key: str = "bytes_per_launch"):
+    """A per-launch figure from rocprofv3 counters (HBM bytes, matrix-core instructions), if
+    taken on the current source of the kernel; None otherwise."""
     f = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(f):
         return None
     d = json.load(open(f))
     e = d.get(kernel)
-    if not e:
+    if not e or key not in e:
         return None
     src = os.path.join(ROOT, "paper_2602_19652_amd", "csrc", e["source"])
     if source_hash(src) != e["source_sha"]:
         return None
-    return e["bytes_per_launch"]
+    return e[key]
 
 
-def cpu_baseline(scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_total: int):
-    """The oracle (FP64 brute force) on a bounded sample of the same workload, scaled to the
-    whole job: time per segment (trace, with the per-hit line-of-sight rays) and per term
-    (synthesis) measured on the sample, then the job's segment and term counts."""
-    import oracle as O
-    g = np.random.Generator(np.random.PCG64(4242))
+def traffic_for(kernel: str):
+    return counter_for(kernel, "bytes_per_launch")
+
+
+def mfma_roofline(kname: str, terms: int, ms: float, flop_per_term: int, exec_flop_per_term: int) -> dict:
+    """Roofline of a synthesis kernel on the fp16 matrix cores: algorithmic flop (the complex
+    multiply-accumulates of the plain sum) and executed flop (from the matrix-core instruction
+    counter when it was taken on this source, else from the kernel's structure)."""
+    alg = terms * flop_per_term
+    achieved = alg / (ms * 1e-3) / 1e12
+    n_mfma = counter_for(kname, "mfma_insts_per_launch")
+    exec_flop = n_mfma * FLOP_PER_MFMA_F16 if n_mfma else terms * exec_flop_per_term
+    exec_tf = exec_flop / (ms * 1e-3) / 1e12
+    return {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_F16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_MFMA_F16_TFLOPS, "traffic": traffic_for(kname), "kernel_ms": ms,
+            "algorithmic_flop_per_launch": alg,
+            "per_unit": f"{flop_per_term} flop per (visible record, receiver, bin)",
+            "executed": {"flop_per_launch": exec_flop, "achieved": exec_tf, "frac": exec_tf / PEAK_MFMA_F16_TFLOPS,
+                         "source": "SQ_INSTS_MFMA x 16384" if n_mfma else
+                         f"{exec_flop_per_term} flop per term (three f16 half products per real product)"},
+            "algorithmic_over_f32_mfma_peak": achieved / PEAK_MFMA_F32_TFLOPS}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_sample(O, scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_total: int, seed: int):
+    g = np.random.Generator(np.random.PCG64(seed))
     sub = np.sort(g.choice(len(sim["ray_dirs"]), n_rays, replace=False))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     rec = O.trace(scene, sim, dirs=sim["ray_dirs"][sub], certify=False)
     t1 = time.perf_counter()
@@ -94,11 +134,30 @@ def cpu_baseline(scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_
     t_seg = (t1 - t0) / max(seg, 1)
     t_term = (t2 - t1) / max(terms, 1)
     job_s = seg_total * t_seg + terms_total * t_term
-    return {"value": seg_total / job_s / 1e6, "unit": "Mrays·bounces/s", "cores": threads, "kind": "oracle",
+    return {"value": seg_total / job_s / 1e6,
             "sample": f"{n_rays} seeded rays traced by brute force ({seg} segments, {t1 - t0:.1f} s) and their "
                       f"{len(rec['rtot'])} records synthesised on every 16th bin ({terms:.3g} terms, {t2 - t1:.1f} s); "
                       f"whole-job time extrapolated linearly in segments and terms",
             "sec_per_segment": t_seg, "sec_per_term": t_term}
+
+
+def cpu_baseline(scene, sim, n_rays: int, M: int, F: int, seg_total: int, terms_total: int):
+    """The oracle (FP64 brute force, OpenMP over rays and receivers) on a bounded sample of
+    the same workload, scaled to the whole job: time per segment (trace, with the per-hit
+    line-of-sight rays) and per term (synthesis) measured on the sample, then the job's
+    segment and term counts.  Once with every host thread the process may use, once on one
+    thread over an eighth of the sample."""
+    import oracle as O
+    L = O.lib()
+    model, avail = host_cpu()
+    L.omp_set_num_threads(avail)
+    threads = int(L.omp_get_max_threads())
+    full = _oracle_sample(O, scene, sim, n_rays, M, F, seg_total, terms_total, 4242)
+    L.omp_set_num_threads(1)
+    one = _oracle_sample(O, scene, sim, max(n_rays // 8, 256), M, F, seg_total, terms_total, 4243)
+    L.omp_set_num_threads(avail)
+    one["cores"] = 1
+    return dict(full, unit="Mrays·bounces/s", cores=threads, kind="oracle", host_cpu=model, one_core=one)
 
 
 def main():
@@ -113,7 +172,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs the GPU"
     torch.cuda.set_device(0)
-    scene, sim = W.room_scene(n_rays=args.rays)
+    if args.profile_only and args.profile_workload == "foliage":
+        scene, sim = W.foliage_scene()
+        sim["area_ref"] = W.median_triangle_area(scene)
+    else:
+        scene, sim = W.room_scene(n_rays=args.rays)
     ctx = et.Context(0)
     sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
     info = sc.info()
@@ -141,11 +204,12 @@ def main():
     n_vis = int((P.flags[:n_rec] & 1).sum().item())      # blocked records contribute nothing
     terms = n_vis * s.M * s.F
     if args.profile_only:
-        # one adjoint call over the step's paths, for the counter runs
-        gen = torch.Generator(device="cuda").manual_seed(2024)
-        et.synthesize_backward(ctx, s, P, torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda", generator=gen),
-                               ws=ws)
-        torch.cuda.synchronize()
+        if args.profile_workload == "room":
+            # one adjoint call over the step's paths, for the counter runs
+            gen = torch.Generator(device="cuda").manual_seed(2024)
+            et.synthesize_backward(ctx, s, P, torch.randn(s.M, s.F, dtype=torch.complex64, device="cuda",
+                                                          generator=gen), ws=ws)
+            torch.cuda.synchronize()
         # calibration for hardware byte counters: one plain device copy of a known size
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
@@ -260,29 +324,26 @@ def main():
     dynamic = None if args.no_extra_legs else dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
     other_configs = None if args.no_extra_legs else configs_leg(ctx, et, W, reps)
 
-    synth_flops = terms * SYNTH_FLOP_PER_TERM
-    synth_tflops = synth_flops / (ms_synth_kernel * 1e-3) / 1e12
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
     trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
-    if ms_synth >= ms_trace:
-        # kernel instantiation names as the profiler reports them
-        kname = (f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}>" if kern == 1
-                 else "k_synth_direct<false>")
-        roof = {"kernel": kname, "bound": "mfma",
-                "achieved": synth_tflops, "peak": PEAK_MFMA_F32_TFLOPS, "unit": "TFLOP/s",
-                "frac": synth_tflops / PEAK_MFMA_F32_TFLOPS, "traffic": traffic_for(kname),
-                "kernel_ms": ms_synth_kernel, "algorithmic_flop_per_launch": synth_flops,
-                "per_unit": f"{SYNTH_FLOP_PER_TERM} flop per (visible record, receiver, bin)"}
+    # kernel instantiation names as the profiler reports them
+    split = "true" if s.F // 64 <= 32 else "false"
+    adj_name = (f"k_synth_bwd_mfma<false, {split}, {'true' if bands_on_row_groups(s.F, s.desc.Bk) else 'false'}>"
+                if adj_kern == 1 else "k_synth_bwd<false>")
+    if ms_synth >= ms_trace and kern == 1:
+        roof = mfma_roofline(f"k_synth_mfma<false, {split}>", terms, ms_synth_kernel, SYNTH_FLOP_PER_TERM,
+                             SYNTH_EXEC_FLOP_PER_TERM)
     else:
-        roof = {"kernel": "k_bounce<false, false, false>", "bound": "hbm", "achieved": trace_gbs, "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false, false>")}
+        roof = trace_roofline(trav_bytes, ms_trace)
+    adj_roof = (mfma_roofline(adj_name, terms, ms_adj_kernel, ADJ_FLOP_PER_TERM, ADJ_EXEC_FLOP_PER_TERM)
+                if adj_kern == 1 else None)
     line = {
         "metric": METRIC,
         "value": seg / (ms_step * 1e-3) / 1e6,
         "unit": "Mrays·bounces/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "dtype": "f32+f64+f16x3", "data": "synthetic",
         "config": {"workload": "room scene: 10x8x3 m room + 100 boxes + 100 cylinders (193,212 tris), 2^20 rays, "
                                "<=4 reflection points, 32 mics, 4096 bins 20-100 kHz, 65,536 diffraction samples",
                    "rays": s.desc.N, "triangles": info.T, "receivers": s.M, "bins": s.F, "max_bounces": s.desc.max_bounces,
@@ -301,10 +362,7 @@ def main():
         "adjoint": {"workload": "fixed paths of the step, 32 receivers x 4096 bins, seeded dL/dconj(H)",
                     "ms": ms_adj, "kernel_ms": ms_adj_kernel, "kernel": adj_kern,
                     "g_terms_per_s": terms / (ms_adj * 1e-3) / 1e9,
-                    "kernel_tflops_algorithmic": adj_tflops, "frac_of_mfma_peak": adj_tflops / PEAK_MFMA_F32_TFLOPS,
-                    "per_unit": f"{ADJ_FLOP_PER_TERM} flop per (visible record, receiver, bin)",
-                    "traffic": traffic_for(f"k_synth_bwd_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}>"
-                                           if adj_kern == 1 else "k_synth_bwd<false>")},
+                    "kernel_tflops_algorithmic": adj_tflops, "roofline": adj_roof},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "dynamic_scene": dynamic,
         "other_configs": other_configs,
@@ -323,6 +381,23 @@ def main():
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(ctx, args)
     print(json.dumps(line))
+
+
+def bands_on_row_groups(F: int, Bk: int) -> bool:
+    """Every material band edge on a multiple of 256 bins (the adjoint's grouped-row variant)."""
+    K1 = F // 64
+    return all(k1 % 4 == 0 or (k1 * 64 * Bk) // F == ((k1 - 1) * 64 * Bk) // F for k1 in range(1, K1))
+
+
+def trace_roofline(trav_bytes: int, ms_trace: float) -> dict:
+    """The traversal against HBM: node, triangle and ray bytes the traversal algorithm touches
+    (counting pass) over the trace time of the step."""
+    gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
+    kname = "k_bounce<false, false, false>"
+    return {"kernel": kname, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_for(kname), "algorithmic_bytes": trav_bytes,
+            "per_unit": f"{NODE_BYTES} B per node visit, {TRI_BYTES} B per triangle test, {RAY_IO_BYTES} B per ray "
+                        f"(closest-hit and line-of-sight traversals)"}
 
 
 def configs_leg(ctx, et, W, reps):
@@ -349,10 +424,30 @@ def configs_leg(ctx, et, W, reps):
         ms = e0.elapsed_time(e1) / reps
         st = ctx.stats()
         n_vis = int((P_c.flags[:st.records] & 1).sum().item())
+        terms_c = n_vis * s_c.M * s_c.F
+        # traversal work of the same trace (separate counting pass, outside the timed region)
+        ctx.set_counting(True)
+        et.trace(ctx, sc_c, s_c, paths=P_c, ws=ws_c)
+        cnt = ctx.counters()
+        ctx.set_counting(False)
+        trav = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
+                + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
+        split = "true" if s_c.F // 64 <= 32 else "false"
+        if st.ms_synth_kernel > st.ms_trace and st.synth_kernel == 1:
+            roof = mfma_roofline(f"k_synth_mfma<false, {split}>", terms_c, st.ms_synth_kernel, SYNTH_FLOP_PER_TERM,
+                                 SYNTH_EXEC_FLOP_PER_TERM)
+        else:
+            roof = trace_roofline(trav, st.ms_trace)
+            if name != "tiny":
+                roof["traffic"] = counter_for(f"{roof['kernel']} [{name}]")
         res[name] = {"triangles": len(scene_c["tris"]), "rays": s_c.desc.N, "receivers": s_c.M, "bins": s_c.F,
                      "ms_per_step": ms, "mrays_bounces_per_s": st.segments / (ms * 1e-3) / 1e6,
                      "trace_ms": st.ms_trace, "synth_kernel_ms": st.ms_synth_kernel, "synth_kernel": st.synth_kernel,
-                     "g_terms_per_s": n_vis * s_c.M * s_c.F / (ms * 1e-3) / 1e9, "build_ms": sc_c.info().build_ms}
+                     "g_terms_per_s": terms_c / (ms * 1e-3) / 1e9, "build_ms": sc_c.info().build_ms,
+                     "traversal": {"nodes_per_segment": cnt.nodes_closest / max(cnt.rays_closest, 1),
+                                   "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
+                                   "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1)},
+                     "roofline": roof}
         del P_c, ws_c, sc_c
         torch.cuda.empty_cache()
     return res

@@ -431,18 +431,32 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 constexpr int HROW = 5;          // halfx8 per LDS row: 4 chunks of 8 records and a pad
 constexpr float XTOP = 12.f;     // log2 of the largest scaled |X| (|Y| <= 1 for non-negative absorption)
+template <bool SPLIT>
 struct H16Buf {
-  halfx8 A[4][KT1][HROW];        // X halves: [re hi, re lo, im hi, im lo][k1][record chunk]
+  static constexpr int NA = SPLIT ? KT1 / 2 : KT1;   // rows of X (a tile of at most 32 with SPLIT)
+  halfx8 A[4][NA][HROW];         // X halves: [re hi, re lo, im hi, im lo][k1][record chunk]
   halfx8 B[4][K2][HROW];         // Y halves: [re hi, re lo, im hi, im lo][k2][record chunk]
 };
 
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// hi = f16(v) two at a time (round to nearest even); lo = f16(v - hi), the difference taken
+// exactly by a mixed-precision fma from the f16 hi and the f32 v, written into the low, then
+// the high half of one register (the fma leaves the other half as it is).
 __device__ inline void split8(const float (&v)[8], halfx8& h, halfx8& l) {
+  union { halfx8 h8; uint32_t u[4]; } H, L;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const _Float16 x = (_Float16)v[i];
-    h[i] = x;
-    l[i] = (_Float16)(v[i] - (float)x);
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t xu = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[2 * i], v[2 * i + 1]}, half2v));
+    uint32_t lo;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(xu), "v"(v[2 * i]));
+    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(lo) : "v"(xu), "v"(v[2 * i + 1]));
+    H.u[i] = xu;
+    L.u[i] = lo;
   }
+  h = H.h8;
+  l = L.h8;
 }
 
 // Two-level generation: X[8a+b] = Xa[a] Xb[b] bf[seg(8a+b)] and Y[8a+b] = Ya[a] Yb[b]:
@@ -450,7 +464,7 @@ __device__ inline void split8(const float (&v)[8], halfx8& h, halfx8& l) {
 // bf = 2^(band + directivity log2) per segment of outer indices with equal bands.
 struct WaveScratch {
   float2 xa[RPW][8], xb[RPW][8], ya[RPW][8], yb[RPW][8];
-  float bf[RPW][SMAX];
+  float bf[RPW][SMAX + 1];   // [nseg]: zero, for rows past the tile
 };
 
 // Band segments of a tile of outer indices: segment s covers the rows whose material band
@@ -462,7 +476,8 @@ struct SegTable {
 };
 
 // Band segments of the tile [k1_0, k1_0 + nk1) (the host guarantees bands constant per row
-// and at most SMAX segments).  Every thread learns nseg and the segment of its lane's row.
+// and at most SMAX segments).  Every thread learns nseg and the segment of its lane's row
+// (nseg for a row past the tile).
 __device__ inline void seg_init(const SynthArgs& a, int k1_0, int nk1, int tid, SegTable& st, int& nseg, int& myseg) {
   const int lane = tid & 63, wv = tid >> 6;
   const int kr = (k1_0 + min(lane, nk1 - 1)) * K2;
@@ -471,7 +486,8 @@ __device__ inline void seg_init(const SynthArgs& a, int k1_0, int nk1, int tid, 
   const bool starts = lane < nk1 && (lane == 0 || bb != bb_prev || bd != bd_prev);
   const uint64_t sm = __ballot(starts);
   nseg = __popcll(sm);
-  myseg = __popcll(sm & (~0ull >> (63 - lane))) - 1;
+  // rows past the tile take the extra segment nseg, whose band factor is zero
+  myseg = lane < nk1 ? __popcll(sm & (~0ull >> (63 - lane))) - 1 : nseg;
   if (tid < 16) st.bseg[tid] = -1;
   __syncthreads();
   if (wv == 0 && starts && myseg < SMAX) {
@@ -513,25 +529,39 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
   W.xb[r][j] = ok ? cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S) : z0;
   W.ya[r][j] = ok ? cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S) : z0;
   W.yb[r][j] = ok ? cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S) : z0;
-  // band factors of (record, segment); the trip count is uniform, so every lane takes part
-  // in the shuffles
-  for (int i0 = 0; i0 < RPW * nseg; i0 += 64) {
-    const int i = i0 + lane;
-    const int rr = min(i / nseg, RPW - 1), sg = i - (i / nseg) * nseg;
-    const int sr = t * RPW + rr;
-    const float g_r = __shfl(q.gamma, sr), b_r = __shfl(q.base, sr), lm_r = __shfl(q.lbm, sr);
-    const int m_r = __shfl(q.mat, sr), k_r = __shfl(q.kind, sr);
-    const float vx = __shfl(q.vx, sr), vy = __shfl(q.vy, sr), vz = __shfl(q.vz, sr);
-    if (i < RPW * nseg) {
+  // band factors of every (record, segment), and zero for the segment past the tile
+  if (!KFREE) {
+    // lane (r, j) takes segments j, j + 8, ... of record r
+    const float g_r = __shfl(q.gamma, src);
+    const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
+    float vx = 0.f, vy = 0.f, vz = 0.f;
+    if (a.Bd) {
+      vx = __shfl(q.vx, src);
+      vy = __shfl(q.vy, src);
+      vz = __shfl(q.vz, src);
+    }
+    for (int sg = j; sg < nseg; sg += 8) {
       float f = 0.f;
-      if (b_r != -INFINITY) {
-        float lb = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[sg]);
+      if (ok) {
+        float lb = band_log2_v(a, k_r, m_r, g_r, st.sb[sg]);
         if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
-        f = exp2f(lb - lm_r);   // <= 1: the record's bound lbm rides on Xa
+        f = exp2f(lb - lbm_r);   // <= 1: the record's bound lbm rides on Xa
       }
-      W.bf[rr][sg] = f;
+      W.bf[r][sg] = f;
+    }
+  } else {
+    // the adjoint (no directivity): the pairs enumerated over the wave, each lane fetching its
+    // record's data (fewer registers live across the loop: measured faster in that kernel)
+    for (int i0 = 0; i0 < RPW * nseg; i0 += 64) {
+      const int i = i0 + lane;
+      const int rr = min(i / nseg, RPW - 1), sg = i - (i / nseg) * nseg;
+      const int sr = t * RPW + rr;
+      const float g2 = __shfl(q.gamma, sr), b2 = __shfl(q.base, sr), lm2 = __shfl(q.lbm, sr);
+      const int m2 = __shfl(q.mat, sr), k2 = __shfl(q.kind, sr);
+      if (i < RPW * nseg) W.bf[rr][sg] = b2 != -INFINITY ? exp2f(band_log2_v<true>(a, k2, m2, g2, st.sb[sg]) - lm2) : 0.f;
     }
   }
+  if (j == 7) W.bf[r][nseg] = 0.f;
   // the factors are read back by other lanes of this wave only
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -539,33 +569,35 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
 
 // X and Y values of record rr for this lane's outer and inner index (lane = 8 a + b):
 // X[lane] = Xa[a] Xb[b] bf[segment of the lane's row], Y[lane] = Ya[a] Yb[b].
-__device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myseg, bool xon, float2& x, float2& y) {
+__device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myseg, float2& x, float2& y) {
   const int ka = lane >> 3, kb = lane & 7;
   const float f = W.bf[rr][myseg];
   x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
   y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
   x.x *= f;
   x.y *= f;
-  if (!xon) x = make_float2(0.f, 0.f);
 }
 
 // The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
 // index into B, chunk wv (the wave's 8 records of the stage).
-__device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, bool xon, H16Buf& buf) {
+template <bool SPLIT>
+__device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, H16Buf<SPLIT>& buf) {
   float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value(W, rr, lane, myseg, xon, x, y);
+    xy_value(W, rr, lane, myseg, x, y);
     xr[rr] = x.x; xi[rr] = x.y; yr[rr] = y.x; yi[rr] = y.y;
   }
   halfx8 h, l;
-  split8(xr, h, l);
-  buf.A[0][lane][wv] = h;
-  buf.A[1][lane][wv] = l;
-  split8(xi, h, l);
-  buf.A[2][lane][wv] = h;
-  buf.A[3][lane][wv] = l;
+  if (lane < H16Buf<SPLIT>::NA) {
+    split8(xr, h, l);
+    buf.A[0][lane][wv] = h;
+    buf.A[1][lane][wv] = l;
+    split8(xi, h, l);
+    buf.A[2][lane][wv] = h;
+    buf.A[3][lane][wv] = l;
+  }
   split8(yr, h, l);
   buf.B[0][lane][wv] = h;
   buf.B[1][lane][wv] = l;
@@ -575,7 +607,7 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
 }
 
 struct BwdBuf;
-__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, bool xon, BwdBuf& bb);
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb);
 
 // Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
 // blocks; with at most 32 rows (SPLIT), row block wv % 2 against the column blocks of half wv / 2.
@@ -588,7 +620,7 @@ __device__ inline void wave_blocks(int wv, int& rb0, int& cb0) {
 // One stage (32 records) into the wave's blocks: acc[0] += Xr Yr, acc[1] += Xi Yi,
 // acc[2] += Xr Yi + Xi Yr, each real product as three half products.
 template <bool SPLIT>
-__device__ inline void contract_h16(const H16Buf& buf, int wv, int lane, floatx4 (&acc)[3][2][2]) {
+__device__ inline void contract_h16(const H16Buf<SPLIT>& buf, int wv, int lane, floatx4 (&acc)[3][2][2]) {
   constexpr int NRB = SPLIT ? 1 : 2;
   int rb0, cb0;
   wave_blocks<SPLIT>(wv, rb0, cb0);
@@ -663,11 +695,11 @@ __device__ inline float dir_log2_max(const SynthArgs& a, int m, int tid, float* 
 // 8 of them as f16 halves into LDS, then each wave contracts all 32 records of the stage into
 // its blocks of (k1, k2) on the matrix cores.
 template <bool BATCH, bool SPLIT>
-__global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
+__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
                                                     et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
                                                     float* __restrict__ part) {
   SYNTH_RESOLVE();
-  __shared__ __align__(16) H16Buf buf;
+  __shared__ __align__(16) H16Buf<SPLIT> buf;
   __shared__ WaveScratch wscr[4];
   __shared__ SegTable st;
   __shared__ float red[4];
@@ -712,7 +744,7 @@ __global__ __launch_bounds__(256) void k_synth_mfma(SynthArgs a0, const SynthArg
       }
     }
     gen_factors(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv]);
-    write_h16(wscr[wv], lane, wv, myseg, lane < nk1, buf);
+    write_h16(wscr[wv], lane, wv, myseg, buf);
     __syncthreads();
     contract_h16<SPLIT>(buf, wv, lane, acc);
     __syncthreads();
@@ -1044,7 +1076,7 @@ struct __align__(16) BwdBuf {
   float2 R1[16][36];         // sum over 4 rows of k X (f Z + df Z') per (row group, record)
   double kv[2][RB][17];      // dL/dk contribution per (record, band), stage parity
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
-  double lobe_w[256];        // per (material, band): 1 / (2 beta^2)
+  float lobe_w[256];         // per (material, band): 1 / (2 beta^2)
   float kf[256 + 16];        // per (material, band): k; then a row of ones (records of other kinds)
   int32_t recb[RB];          // per record of the stage: its row of kf (mat Bk, or the ones row)
 };
@@ -1052,12 +1084,12 @@ struct __align__(16) BwdBuf {
 // The adjoint's operands of the sub-stage's records: X in FP32 at [record][k1] (lane = k1), and Y
 // as f16 halves record-major, lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7
 // of record r: Y[8 c + i] = Ya[c] Yb[i].
-__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, bool xon, BwdBuf& bb) {
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb) {
   const int row0 = wv * RPW;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value(W, rr, lane, myseg, xon, x, y);
+    xy_value(W, rr, lane, myseg, x, y);
     bb.X[0][row0 + rr][lane] = x.x;
     bb.X[1][row0 + rr][lane] = x.y;
   }
@@ -1159,7 +1191,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
   for (int i = tid; i < QB; i += 256) {
     const double bt = (double)a.beta[i];
-    bb.lobe_w[i] = 1.0 / (2.0 * bt * bt);
+    bb.lobe_w[i] = (float)(1.0 / (2.0 * bt * bt));
     bb.kf[i] = a.refl_k[i];
   }
   if (tid < a.Bk) bb.kf[QB + tid] = 1.f;
@@ -1178,7 +1210,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
     gen_factors<true>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv]);
-    write_bwd(wscr[wv], lane, wv, myseg, lane < nk1, bb);
+    write_bwd(wscr[wv], lane, wv, myseg, bb);
     {
       // each generated record's row of k factors
       const int src = t * RPW + (lane & 7);
@@ -1329,7 +1361,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
           const float kb = kind == 0 ? bb.kf[mat * a.Bk + b] : 1.f;
           s0 += kb * sb;
           if (valid && kind == 0) {
-            wl += kb * sb * (float)bb.lobe_w[mat * a.Bk + b];
+            wl += kb * sb * bb.lobe_w[mat * a.Bk + b];
             kvv = 2.0 * (double)sb;
           }
         }
