@@ -328,10 +328,10 @@ def main():
     trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
     # kernel instantiation names as the profiler reports them
     split = "true" if s.F // 64 <= 32 else "false"
-    adj_name = (f"k_synth_bwd_mfma<false, {split}, {'true' if bands_on_row_groups(s.F, s.desc.Bk) else 'false'}>"
-                if adj_kern == 1 else "k_synth_bwd<false>")
+    adj_name = (f"k_synth_bwd_mfma<false, {split}, {adjoint_grouping(s.F, s.desc.Bk)}>" if adj_kern == 1
+                else "k_synth_bwd<false>")
     if ms_synth >= ms_trace and kern == 1:
-        roof = mfma_roofline(f"k_synth_mfma<false, {split}>", terms, ms_synth_kernel, SYNTH_FLOP_PER_TERM,
+        roof = mfma_roofline(fwd_kernel_name(s), terms, ms_synth_kernel, SYNTH_FLOP_PER_TERM,
                              SYNTH_EXEC_FLOP_PER_TERM)
     else:
         roof = trace_roofline(trav_bytes, ms_trace)
@@ -383,10 +383,25 @@ def main():
     print(json.dumps(line))
 
 
-def bands_on_row_groups(F: int, Bk: int) -> bool:
-    """Every material band edge on a multiple of 256 bins (the adjoint's grouped-row variant)."""
+def bands_on_groups(F: int, bands, g: int, whole: bool) -> bool:
+    """Every band edge (of each band count in `bands`) on a multiple of 64 g bins, and with
+    `whole` the bins a multiple of 64 g: the grouped-row instantiations of the synthesis kernels."""
     K1 = F // 64
-    return all(k1 % 4 == 0 or (k1 * 64 * Bk) // F == ((k1 - 1) * 64 * Bk) // F for k1 in range(1, K1))
+    if whole and K1 % g:
+        return False
+    return all(k1 % g == 0 or (k1 * 64 * B) // F == ((k1 - 1) * 64 * B) // F
+               for B in bands if B for k1 in range(1, K1))
+
+
+def adjoint_grouping(F: int, Bk: int) -> int:
+    return 8 if bands_on_groups(F, [Bk], 8, True) else 4 if bands_on_groups(F, [Bk], 4, False) else 1
+
+
+def fwd_kernel_name(s) -> str:
+    """The forward matrix-core kernel's instantiation, as the profiler names it."""
+    Bd = s.desc.Bd if s.desc.directivity else 0
+    g8 = bands_on_groups(s.F, [s.desc.Bk, Bd], 8, True)
+    return f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}, {'true' if g8 else 'false'}>"
 
 
 def trace_roofline(trav_bytes: int, ms_trace: float) -> dict:
@@ -434,7 +449,7 @@ def configs_leg(ctx, et, W, reps):
                 + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
         split = "true" if s_c.F // 64 <= 32 else "false"
         if st.ms_synth_kernel > st.ms_trace and st.synth_kernel == 1:
-            roof = mfma_roofline(f"k_synth_mfma<false, {split}>", terms_c, st.ms_synth_kernel, SYNTH_FLOP_PER_TERM,
+            roof = mfma_roofline(fwd_kernel_name(s_c), terms_c, st.ms_synth_kernel, SYNTH_FLOP_PER_TERM,
                                  SYNTH_EXEC_FLOP_PER_TERM)
         else:
             roof = trace_roofline(trav, st.ms_trace)

@@ -304,6 +304,7 @@ struct SynthBatchWS {
   int64_t cap;
   bool mf, mf_bwd;
   bool g4;   // adjoint: every band edge on a multiple of 256 bins in every job
+  bool g8;   // forward: every band edge on a multiple of 512 bins, and the bins, in every job
   int32_t target, target_bwd;   // chunk count the batch aims at
   int32_t chunks, chunks_bwd;   // grid size: target + J bounds the chunk count
   int32_t T1;                   // adjoint tiles of outer indices

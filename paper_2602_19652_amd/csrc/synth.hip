@@ -414,7 +414,10 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
   float bm = -INFINITY;
   for (int b = 0; b < a.Bk; ++b) bm = fmaxf(bm, band_log2_v<GRAD>(a, q.kind, q.mat, q.gamma, b));
   q.lbm = bm + dmax;
-  if (q.lbm == -INFINITY) q.base = -INFINITY;   // every band factor is zero: nothing to add
+  if (q.lbm == -INFINITY) {   // every band factor is zero: nothing to add (lbm stays finite)
+    q.base = -INFINITY;
+    q.lbm = 0.f;
+  }
 }
 
 // The forward contraction runs on the f16 matrix cores (v_mfma_f32_16x16x32_f16: 32 records per
@@ -501,8 +504,10 @@ __device__ inline void seg_init(const SynthArgs& a, int k1_0, int nk1, int tid, 
   __syncthreads();
 }
 
+// 2^lg e^(2 pi j rev) from the hardware exp2, sin and cos (a result below 2^-126 flushes to zero:
+// such a value is below 2^-138 of the tile's largest term)
 __device__ inline float2 cexp2(float lg, float rev) {
-  const float amp = exp2f(lg);
+  const float amp = __builtin_amdgcn_exp2f(lg);
   return make_float2(amp * __builtin_amdgcn_cosf(rev), amp * __builtin_amdgcn_sinf(rev));
 }
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -511,9 +516,11 @@ __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x
 // records): Xa, Xb, Ya, Yb (8 each) and the band factor of every (record, band segment) of the
 // tile, into its WaveScratch.  esh (log2) scales every X of the sub-stage.
 // KFREE: the specular band factor leaves out k (see band_log2_v).
-template <bool KFREE = false>
+// G8: every band segment is a union of whole groups of 8 rows (seg8: the segment of this lane's
+// group j, rows 8 j .. 8 j + 7): the band factor is folded into Xa and no table is written.
+template <bool KFREE = false, bool G8 = false>
 __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                   int nseg, const SegTable& st, float esh, WaveScratch& W) {
+                                   int nseg, const SegTable& st, float esh, WaveScratch& W, int seg8 = 0) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
@@ -522,15 +529,28 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
   const float lbm_r = __shfl(q.lbm, src);
   const bool ok = base_r != -INFINITY;
   const uint32_t k1a = (uint32_t)(k1_0 + 8 * j);   // first outer index of group j
-  const float lg = base_r + (float)(k1a * K2) * slope_r + esh + lbm_r;
+  // Xa is zero for a record that adds nothing (and past the tile); then X is zero whatever the
+  // other factors (finite for every record: a skipped record has slope 0 and phase steps 0)
+  float lband = lbm_r;   // the band factor's log2 on Xa: the bound, or with G8 the group's own
+  if (G8) {
+    const float g_r = __shfl(q.gamma, src);
+    const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
+    lband = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[seg8]);
+    if (a.Bd) {
+      const float vx = __shfl(q.vx, src), vy = __shfl(q.vy, src), vz = __shfl(q.vz, src);
+      lband += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[seg8]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
+    }
+  }
+  const float lg = ok && 8 * j < nk1 ? base_r + (float)(k1a * K2) * slope_r + esh + lband : -INFINITY;
   const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
-  const float2 z0 = make_float2(0.f, 0.f);
-  W.xa[r][j] = ok && 8 * j < nk1 ? cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S) : z0;
-  W.xb[r][j] = ok ? cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S) : z0;
-  W.ya[r][j] = ok ? cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S) : z0;
-  W.yb[r][j] = ok ? cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S) : z0;
+  W.xa[r][j] = cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S);
+  W.xb[r][j] = cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S);
+  W.ya[r][j] = cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S);
+  W.yb[r][j] = cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S);
   // band factors of every (record, segment), and zero for the segment past the tile
-  if (!KFREE) {
+  if (G8) {
+    // (folded into Xa)
+  } else if (!KFREE) {
     // lane (r, j) takes segments j, j + 8, ... of record r
     const float g_r = __shfl(q.gamma, src);
     const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
@@ -541,13 +561,10 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
       vz = __shfl(q.vz, src);
     }
     for (int sg = j; sg < nseg; sg += 8) {
-      float f = 0.f;
-      if (ok) {
-        float lb = band_log2_v(a, k_r, m_r, g_r, st.sb[sg]);
-        if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
-        f = exp2f(lb - lbm_r);   // <= 1: the record's bound lbm rides on Xa
-      }
-      W.bf[r][sg] = f;
+      // (finite for a skipped record too: its Xa is zero)
+      float lb = band_log2_v(a, k_r, m_r, g_r, st.sb[sg]);
+      if (a.Bd) lb += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[sg]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
+      W.bf[r][sg] = __builtin_amdgcn_exp2f(lb - lbm_r);   // <= 1: the record's bound lbm rides on Xa
     }
   } else {
     // the adjoint (no directivity): the pairs enumerated over the wave, each lane fetching its
@@ -561,7 +578,7 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
       if (i < RPW * nseg) W.bf[rr][sg] = b2 != -INFINITY ? exp2f(band_log2_v<true>(a, k2, m2, g2, st.sb[sg]) - lm2) : 0.f;
     }
   }
-  if (j == 7) W.bf[r][nseg] = 0.f;
+  if (!G8 && j == 7) W.bf[r][nseg] = 0.f;
   // the factors are read back by other lanes of this wave only
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -569,24 +586,28 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
 
 // X and Y values of record rr for this lane's outer and inner index (lane = 8 a + b):
 // X[lane] = Xa[a] Xb[b] bf[segment of the lane's row], Y[lane] = Ya[a] Yb[b].
+// G8: the band factor is already on Xa.
+template <bool G8 = false>
 __device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myseg, float2& x, float2& y) {
   const int ka = lane >> 3, kb = lane & 7;
-  const float f = W.bf[rr][myseg];
   x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
   y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
-  x.x *= f;
-  x.y *= f;
+  if (!G8) {
+    const float f = W.bf[rr][myseg];
+    x.x *= f;
+    x.y *= f;
+  }
 }
 
 // The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
 // index into B, chunk wv (the wave's 8 records of the stage).
-template <bool SPLIT>
+template <bool SPLIT, bool G8>
 __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, H16Buf<SPLIT>& buf) {
   float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value(W, rr, lane, myseg, x, y);
+    xy_value<G8>(W, rr, lane, myseg, x, y);
     xr[rr] = x.x; xi[rr] = x.y; yr[rr] = y.x; yi[rr] = y.y;
   }
   halfx8 h, l;
@@ -607,6 +628,7 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
 }
 
 struct BwdBuf;
+template <bool G8>
 __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb);
 
 // Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
@@ -694,10 +716,13 @@ __device__ inline float dir_log2_max(const SynthArgs& a, int m, int tid, float* 
 // 64 records (one per lane) and the workgroup bounds their |X|; every stage each wave generates
 // 8 of them as f16 halves into LDS, then each wave contracts all 32 records of the stage into
 // its blocks of (k1, k2) on the matrix cores.
-template <bool BATCH, bool SPLIT>
-__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs, ChunkTab ct,
-                                                    et_paths P, const int32_t* __restrict__ idx, const Ctl* ctl,
-                                                    float* __restrict__ part) {
+// G8: every band segment is a union of whole groups of 8 rows and the grid holds whole groups
+// (bins a multiple of 512): the band factor rides on Xa.
+template <bool BATCH, bool SPLIT, bool G8>
+__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
+                                                                   ChunkTab ct, et_paths P,
+                                                                   const int32_t* __restrict__ idx, const Ctl* ctl,
+                                                                   float* __restrict__ part) {
   SYNTH_RESOLVE();
   __shared__ __align__(16) H16Buf<SPLIT> buf;
   __shared__ WaveScratch wscr[4];
@@ -710,6 +735,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
+  const int seg8 = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1);   // segment of row group lane % 8
   const float dmax = dir_log2_max(a, m, tid, red);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
   floatx4 acc[3][2][2];
@@ -743,8 +769,8 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
         E = Eg;
       }
     }
-    gen_factors(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv]);
-    write_h16(wscr[wv], lane, wv, myseg, buf);
+    gen_factors<false, G8>(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv], seg8);
+    write_h16<SPLIT, G8>(wscr[wv], lane, wv, myseg, buf);
     __syncthreads();
     contract_h16<SPLIT>(buf, wv, lane, acc);
     __syncthreads();
@@ -1084,12 +1110,13 @@ struct __align__(16) BwdBuf {
 // The adjoint's operands of the sub-stage's records: X in FP32 at [record][k1] (lane = k1), and Y
 // as f16 halves record-major, lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7
 // of record r: Y[8 c + i] = Ya[c] Yb[i].
+template <bool G8>
 __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb) {
   const int row0 = wv * RPW;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value(W, rr, lane, myseg, x, y);
+    xy_value<G8>(W, rr, lane, myseg, x, y);
     bb.X[0][row0 + rr][lane] = x.x;
     bb.X[1][row0 + rr][lane] = x.y;
   }
@@ -1108,13 +1135,16 @@ __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int mys
   __builtin_amdgcn_wave_barrier();
 }
 
-// G4: every band edge of the grid falls on a group of 4 rows (a multiple of 256 bins), so each
-// lane's four rows of the matrix-product output belong to one band and are summed in registers.
-template <bool BATCH, bool SPLIT, bool G4>
+// GRP 4: every band edge of the grid falls on a group of 4 rows (a multiple of 256 bins), so
+// each lane's four rows of the matrix-product output belong to one band and are summed in
+// registers.  GRP 8: moreover every edge falls on a group of 8 rows and the grid holds whole
+// groups (bins a multiple of 512): the band factor rides on Xa, as in the forward kernel.
+template <bool BATCH, bool SPLIT, int GRP>
 __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                         ChunkTab ct, et_paths P, const int32_t* __restrict__ idx,
                                                         const Ctl* ctl, const float* __restrict__ g,
                                                         double* __restrict__ gpx, double* __restrict__ gpk) {
+  constexpr bool G4 = GRP >= 4, G8 = GRP == 8;
   SYNTH_RESOLVE();
   if (BATCH) g += (size_t)jb * a.M * a.F * 2;
   __shared__ __align__(16) BwdBuf bb;
@@ -1128,6 +1158,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
+  const int seg8 = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1);   // segment of row group lane % 8 (G8)
   // wave -> block of 16 rows; SPLIT (a tile of at most 32 rows, two blocks) gives each wave
   // pair one block and each wave of a pair one of the stage's two record blocks
   constexpr int NB = SPLIT ? 1 : 2;              // record blocks of 16 per wave and stage
@@ -1209,8 +1240,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    gen_factors<true>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv]);
-    write_bwd(wscr[wv], lane, wv, myseg, bb);
+    gen_factors<true, G8>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv], seg8);
+    write_bwd<G8>(wscr[wv], lane, wv, myseg, bb);
     {
       // each generated record's row of k factors
       const int src = t * RPW + (lane & 7);
@@ -1642,6 +1673,29 @@ __global__ void k_bwd_reduce_batch(const double* __restrict__ gpx, const double*
 
 }  // namespace
 
+// Every material (and directivity) band edge on a multiple of g outer indices (64 g bins) and
+// the bins a multiple of 64 g.
+bool bands_on_groups(const et_sim_desc* sim, int64_t g) {
+  const int64_t F = sim->F, Bk = sim->Bk, Bd = sim->directivity ? sim->Bd : 0, K1 = F / K2;
+  if (K1 % g) return false;
+  for (int64_t k1 = 1; k1 < K1; ++k1) {
+    if (k1 % g == 0) continue;
+    const int64_t k = k1 * K2, kp = k - K2;
+    if (k * Bk / F != kp * Bk / F) return false;
+    if (Bd && k * Bd / F != kp * Bd / F) return false;
+  }
+  return true;
+}
+
+template <bool BATCH>
+void launch_fwd_mfma(bool split, bool g8, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
+                     const ChunkTab& ct, const et_paths& P, const int32_t* idx, const Ctl* ctl, float* part) {
+  if (split && g8) k_synth_mfma<BATCH, true, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  else if (split) k_synth_mfma<BATCH, true, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  else if (g8) k_synth_mfma<BATCH, false, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  else k_synth_mfma<BATCH, false, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+}
+
 bool synth_factorised_ok(const et_sim_desc* sim) {
   // needs k = 64 k1 + k2, material / directivity bands constant over each run of 64 bins
   // (the band factor is per outer index), and at most SMAX band segments per tile of KT1
@@ -1699,8 +1753,8 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(ws.P, sim->M, (K1 + KT1 - 1) / KT1);
-    if (K1 <= 32) k_synth_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
-    else k_synth_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
+    launch_fwd_mfma<false>(K1 <= 32, bands_on_groups(sim, 8), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
+                           ws.partial);
   } else {
     dim3 grid(ws.P, sim->M, (sim->F + DTILE - 1) / DTILE);
     k_synth_direct<false><<<grid, DB, 0, s>>>(a, nullptr, ChunkTab{}, P, ws.vidx, ctl, ws.partial);
@@ -1740,8 +1794,8 @@ int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, 
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(w.P, sim->M, (K1 + KT1 - 1) / KT1);
-    if (K1 <= 32) k_synth_mfma<false, true><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
-    else k_synth_mfma<false, false><<<grid, 256, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
+    launch_fwd_mfma<false>(K1 <= 32, bands_on_groups(sim, 8), grid, s, a, nullptr, ChunkTab{}, Pth, nullptr, ctl,
+                           w.partial);
   } else {
     dim3 grid(w.P, sim->M, (sim->F + DTILE - 1) / DTILE);
     k_synth_direct<false><<<grid, DB, 0, s>>>(a, nullptr, ChunkTab{}, Pth, nullptr, ctl, w.partial);
@@ -1764,14 +1818,27 @@ bool bands_on_row_groups(const et_sim_desc* sim) {
   return true;
 }
 
+template <bool BATCH, bool SPLIT>
+void launch_bwd_grp(int grp, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs, const ChunkTab& ct,
+                    const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g, double* gpx,
+                    double* gpk) {
+  if (grp == 8) k_synth_bwd_mfma<BATCH, SPLIT, 8><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else if (grp == 4) k_synth_bwd_mfma<BATCH, SPLIT, 4><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else k_synth_bwd_mfma<BATCH, SPLIT, 1><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+}
+
 template <bool BATCH>
-void launch_bwd_mfma(bool split, bool g4, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
+void launch_bwd_mfma(bool split, int grp, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
                      const ChunkTab& ct, const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g,
                      double* gpx, double* gpk) {
-  if (split && g4) k_synth_bwd_mfma<BATCH, true, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else if (split) k_synth_bwd_mfma<BATCH, true, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else if (g4) k_synth_bwd_mfma<BATCH, false, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else k_synth_bwd_mfma<BATCH, false, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  if (split) launch_bwd_grp<BATCH, true>(grp, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else launch_bwd_grp<BATCH, false>(grp, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+}
+
+// Row grouping of the adjoint for a job: 8 (band edges on 512 bins, whole groups), 4 (on 256
+// bins) or 1.
+int bwd_grouping(const et_sim_desc* sim) {
+  return bands_on_groups(sim, 8) ? 8 : bands_on_row_groups(sim) ? 4 : 1;
 }
 
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
@@ -1812,8 +1879,8 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);
-    launch_bwd_mfma<false>(sim->F / K2 <= 32, bands_on_row_groups(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx,
-                           ctl, grad_spectra, ws.gpart_x, ws.gpart_k);
+    launch_bwd_mfma<false>(sim->F / K2 <= 32, bwd_grouping(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
+                           grad_spectra, ws.gpart_x, ws.gpart_k);
   } else {
     dim3 grid(ws.gchunks, sim->M);
     const size_t shm = sizeof(float2) * (size_t)sim->F;
@@ -1855,8 +1922,11 @@ size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const B
   w.cap = cap;
   w.mf = synth_batch_factorised(J, jobs, false);
   w.mf_bwd = adjoint && synth_batch_factorised(J, jobs, true);
-  w.g4 = true;
-  for (int32_t i = 0; i < J; ++i) w.g4 = w.g4 && bands_on_row_groups(jobs[i].sim);
+  w.g4 = w.g8 = true;
+  for (int32_t i = 0; i < J; ++i) {
+    w.g4 = w.g4 && bands_on_row_groups(jobs[i].sim);
+    w.g8 = w.g8 && bands_on_groups(jobs[i].sim, 8);
+  }
   w.target = chunk_target(s0, w.mf, tune.synth_wgs);
   w.target_bwd = chunk_target(s0, w.mf_bwd, tune.adjoint_wgs);
   // grid size: the chunk count is at most target + J (sum_j ceil(n_j / per)); buffers are
@@ -1934,8 +2004,7 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[0], s));
     if (w.mf) {
       dim3 grid(w.chunks, s0->M, (s0->F / K2 + KT1 - 1) / KT1);
-      if (s0->F / K2 <= 32) k_synth_mfma<true, true><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
-      else k_synth_mfma<true, false><<<grid, 256, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
+      launch_fwd_mfma<true>(s0->F / K2 <= 32, w.g8, grid, s, a0, dj, ct, P, w.vidx, ctl, w.partial);
     } else {
       dim3 grid(w.chunks, s0->M, (s0->F + DTILE - 1) / DTILE);
       k_synth_direct<true><<<grid, DB, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
@@ -1951,7 +2020,8 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[2], s));
     if (w.mf_bwd) {
       dim3 grid(w.chunks_bwd, s0->M, w.T1);
-      launch_bwd_mfma<true>(s0->F / K2 <= 32, w.g4, grid, s, a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x, w.gpart_k);
+      launch_bwd_mfma<true>(s0->F / K2 <= 32, w.g8 ? 8 : w.g4 ? 4 : 1, grid, s, a0, dj, ct, P, w.vidx, ctl, grad,
+                            w.gpart_x, w.gpart_k);
     } else {
       dim3 grid(w.chunks_bwd, s0->M);
       k_synth_bwd<true><<<grid, GB, sizeof(float2) * (size_t)s0->F, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,
