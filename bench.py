@@ -43,13 +43,20 @@ SYNTH_EXEC_FLOP_PER_TERM = 24
 ADJ_EXEC_FLOP_PER_TERM = 48
 FLOP_PER_MFMA_F16 = 2 * 16 * 16 * 32   # v_mfma_f32_16x16x32_f16
 NODE_BYTES, TRI_BYTES, RAY_IO_BYTES = 64, 48, 128
+# traversal arithmetic per unit, one VALU lane operation each (an FMA counts once): a node visit
+# is the slab test of both child boxes (per box 6 FMA, 6 min/max per axis, 4 for the entry and
+# exit reductions, the widening multiply, 1 min and 1 compare); a triangle test is the watertight
+# test (9 translations, 6 shears, 6 for the edge functions, 6 sign tests, 2 for the determinant,
+# 3 scalings, 3 for T, 1 division); a ray its set-up (reciprocals, axis choice, shear constants)
+NODE_OPS, TRI_OPS, RAY_OPS = 38, 36, 25
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane operations per second: 256 CUs x 4 SIMDs x 16 lanes
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rays", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=32768, help="rays of the oracle's bounded sample (about 10 s of host work)")
@@ -313,19 +320,29 @@ def main():
         ms_adj_kernel += sta.ms_adjoint_kernel / reps
     adj_kern = sta.adjoint_kernel
 
+    # achievable HBM bandwidth: a plain 1 GiB device copy (bytes read + written over its time)
+    src_b = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+    dst_b = torch.empty_like(src_b)
+    dst_b.copy_(src_b)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        dst_b.copy_(src_b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src_b.numel() / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del src_b, dst_b
+
     # traversal work counters (separate counting pass, outside the timed region)
     ctx.set_counting(True)
     et.trace(ctx, sc, s, paths=P, ws=ws)
     cnt = ctx.counters()
     ctx.set_counting(False)
-    trav_bytes = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
-                  + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
 
     dynamic = None if args.no_extra_legs else dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
     other_configs = None if args.no_extra_legs else configs_leg(ctx, et, W, reps)
 
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
-    trace_gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
     # kernel instantiation names as the profiler reports them
     split = "true" if s.F // 64 <= 32 else "false"
     adj_name = (f"k_synth_bwd_mfma<false, {split}, {adjoint_grouping(s.F, s.desc.Bk)}>" if adj_kern == 1
@@ -334,7 +351,7 @@ def main():
         roof = mfma_roofline(fwd_kernel_name(s), terms, ms_synth_kernel, SYNTH_FLOP_PER_TERM,
                              SYNTH_EXEC_FLOP_PER_TERM)
     else:
-        roof = trace_roofline(trav_bytes, ms_trace)
+        roof = trace_roofline(cnt, ms_trace)
     adj_roof = (mfma_roofline(adj_name, terms, ms_adj_kernel, ADJ_FLOP_PER_TERM, ADJ_EXEC_FLOP_PER_TERM)
                 if adj_kern == 1 else None)
     line = {
@@ -369,8 +386,7 @@ def main():
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
                       "nodes_per_shadow_ray": cnt.nodes_any / max(cnt.rays_any, 1),
-                      "algorithmic_bytes": trav_bytes, "effective_GBs": trace_gbs,
-                      "frac_of_hbm_peak": trace_gbs / PEAK_HBM_GBS, "traffic": traffic_for("k_bounce<false, false, false>")},
+                      "roofline": trace_roofline(cnt, ms_trace), "achievable_hbm_GBs": copy_gbs},
         "roofline": roof,
         "cpu_baseline": None,
     }
@@ -404,15 +420,25 @@ def fwd_kernel_name(s) -> str:
     return f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}, {'true' if g8 else 'false'}>"
 
 
-def trace_roofline(trav_bytes: int, ms_trace: float) -> dict:
-    """The traversal against HBM: node, triangle and ray bytes the traversal algorithm touches
-    (counting pass) over the trace time of the step."""
+def trace_roofline(cnt, ms_trace: float, traffic_key: str = "k_bounce<false, false, false>") -> dict:
+    """The traversal against HBM bandwidth: the node, triangle and ray bytes its visits touch
+    (counting pass) over the trace time of the step.  Caches serve most of them, so they can
+    exceed what HBM delivers; the measured HBM bytes of the bounce kernel are `traffic`.  The
+    arithmetic of the same visits against the vector-ALU lane rate is reported beside it."""
+    nodes, tris = cnt.nodes_closest + cnt.nodes_any, cnt.tris_closest + cnt.tris_any
+    rays = cnt.rays_closest + cnt.rays_any
+    trav_bytes = nodes * NODE_BYTES + tris * TRI_BYTES + rays * RAY_IO_BYTES
     gbs = trav_bytes / (ms_trace * 1e-3) / 1e9
-    kname = "k_bounce<false, false, false>"
-    return {"kernel": kname, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_for(kname), "algorithmic_bytes": trav_bytes,
+    ops = nodes * NODE_OPS + tris * TRI_OPS + rays * RAY_OPS
+    tops = ops / (ms_trace * 1e-3) / 1e12
+    return {"kernel": "k_bounce<false, false, false>", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS, "traffic": counter_for(traffic_key),
+            "algorithmic_bytes": trav_bytes,
             "per_unit": f"{NODE_BYTES} B per node visit, {TRI_BYTES} B per triangle test, {RAY_IO_BYTES} B per ray "
-                        f"(closest-hit and line-of-sight traversals)"}
+                        f"(closest-hit and line-of-sight traversals)",
+            "alu": {"achieved": tops, "peak": PEAK_VALU_TOPS, "unit": "Top/s", "frac": tops / PEAK_VALU_TOPS,
+                    "algorithmic_ops": ops,
+                    "per_unit": f"{NODE_OPS} ops per node visit, {TRI_OPS} per triangle test, {RAY_OPS} per ray"}}
 
 
 def configs_leg(ctx, et, W, reps):
@@ -445,16 +471,11 @@ def configs_leg(ctx, et, W, reps):
         et.trace(ctx, sc_c, s_c, paths=P_c, ws=ws_c)
         cnt = ctx.counters()
         ctx.set_counting(False)
-        trav = ((cnt.nodes_closest + cnt.nodes_any) * NODE_BYTES + (cnt.tris_closest + cnt.tris_any) * TRI_BYTES
-                + (cnt.rays_closest + cnt.rays_any) * RAY_IO_BYTES)
-        split = "true" if s_c.F // 64 <= 32 else "false"
         if st.ms_synth_kernel > st.ms_trace and st.synth_kernel == 1:
             roof = mfma_roofline(fwd_kernel_name(s_c), terms_c, st.ms_synth_kernel, SYNTH_FLOP_PER_TERM,
                                  SYNTH_EXEC_FLOP_PER_TERM)
         else:
-            roof = trace_roofline(trav, st.ms_trace)
-            if name != "tiny":
-                roof["traffic"] = counter_for(f"{roof['kernel']} [{name}]")
+            roof = trace_roofline(cnt, st.ms_trace, f"k_bounce<false, false, false> [{name}]")
         res[name] = {"triangles": len(scene_c["tris"]), "rays": s_c.desc.N, "receivers": s_c.M, "bins": s_c.F,
                      "ms_per_step": ms, "mrays_bounces_per_s": st.segments / (ms * 1e-3) / 1e6,
                      "trace_ms": st.ms_trace, "synth_kernel_ms": st.ms_synth_kernel, "synth_kernel": st.synth_kernel,

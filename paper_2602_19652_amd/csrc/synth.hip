@@ -24,10 +24,13 @@
 //      Y = exp2(k2 slope) e^{j 2 pi k2 cb},
 //    whenever the material/directivity bands are constant over each run of 64 bins, so
 //    H_m[k1, k2] = sum_n X[n,k1] Y[n,k2] is a complex matrix product contracting over the
-//    records.  It runs on the FP32 matrix cores (v_mfma_f32_16x16x4f32) as Gauss's three
-//    real products; X and Y themselves come from 32 exp2/sin/cos factors per (record,
-//    receiver) (a second 8 x 8 split) plus one exp2 per band segment, so only about 40
-//    transcendental triples remain of the 4096 per (record, receiver) of a 4096-bin grid.
+//    records.  It runs on the f16 matrix cores (v_mfma_f32_16x16x32_f16) with every FP32
+//    operand split into two f16 halves and three half products per real product (FP32
+//    accumulation); X and Y themselves come from 32 exp2/sin/cos factors per (record,
+//    receiver) (a second 8 x 8 split) plus the band factors (one exp2 per band segment, or
+//    folded into the first factor when the band edges fall on groups of 8 outer indices),
+//    so only about 40 transcendental triples remain of the 4096 per (record, receiver) of a
+//    4096-bin grid.
 //  * direct: one sin/cos/exp2 per (record, receiver, bin), any band layout.
 // Both write per-chunk partial spectra that a final kernel sums in a fixed order
 // (bit-reproducible results).
