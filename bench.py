@@ -344,9 +344,7 @@ def main():
 
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
     # kernel instantiation names as the profiler reports them
-    split = "true" if s.F // 64 <= 32 else "false"
-    adj_name = (f"k_synth_bwd_mfma<false, {split}, {adjoint_grouping(s.F, s.desc.Bk)}>" if adj_kern == 1
-                else "k_synth_bwd<false>")
+    adj_name = adj_kernel_name(s) if adj_kern == 1 else "k_synth_bwd<false>"
     if ms_synth >= ms_trace and kern == 1:
         roof = mfma_roofline(fwd_kernel_name(s), terms, ms_synth_kernel, SYNTH_FLOP_PER_TERM,
                              SYNTH_EXEC_FLOP_PER_TERM)
@@ -409,15 +407,19 @@ def bands_on_groups(F: int, bands, g: int, whole: bool) -> bool:
                for B in bands if B for k1 in range(1, K1))
 
 
-def adjoint_grouping(F: int, Bk: int) -> int:
-    return 8 if bands_on_groups(F, [Bk], 8, True) else 4 if bands_on_groups(F, [Bk], 4, False) else 1
+def fold_mode(F: int, bands) -> int:
+    """How the synthesis kernels fold the band factor: 8 (band edges on 512 bins), 4 (256), 0."""
+    return 8 if bands_on_groups(F, bands, 8, True) else 4 if bands_on_groups(F, bands, 4, True) else 0
 
 
 def fwd_kernel_name(s) -> str:
     """The forward matrix-core kernel's instantiation, as the profiler names it."""
     Bd = s.desc.Bd if s.desc.directivity else 0
-    g8 = bands_on_groups(s.F, [s.desc.Bk, Bd], 8, True)
-    return f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}, {'true' if g8 else 'false'}>"
+    return f"k_synth_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}, {fold_mode(s.F, [s.desc.Bk, Bd])}>"
+
+
+def adj_kernel_name(s) -> str:
+    return f"k_synth_bwd_mfma<false, {'true' if s.F // 64 <= 32 else 'false'}, {fold_mode(s.F, [s.desc.Bk])}>"
 
 
 def trace_roofline(cnt, ms_trace: float, traffic_key: str = "k_bounce<false, false, false>") -> dict:

@@ -303,8 +303,7 @@ struct SynthBatchWS {
   int32_t J;
   int64_t cap;
   bool mf, mf_bwd;
-  bool g4;   // adjoint: every band edge on a multiple of 256 bins in every job
-  bool g8;   // forward: every band edge on a multiple of 512 bins, and the bins, in every job
+  int fold;    // 8 / 4: every band edge on a multiple of 512 / 256 bins, and the bins, in every job; else 0
   int32_t target, target_bwd;   // chunk count the batch aims at
   int32_t chunks, chunks_bwd;   // grid size: target + J bounds the chunk count
   int32_t T1;                   // adjoint tiles of outer indices

@@ -470,7 +470,10 @@ __device__ inline void split8(const float (&v)[8], halfx8& h, halfx8& l) {
 // bf = 2^(band + directivity log2) per segment of outer indices with equal bands.
 struct WaveScratch {
   float2 xa[RPW][8], xb[RPW][8], ya[RPW][8], yb[RPW][8];
-  float bf[RPW][SMAX + 1];   // [nseg]: zero, for rows past the tile
+  union {
+    float bf[RPW][SMAX + 1];   // [nseg]: zero, for rows past the tile
+    float2 xh[RPW][8];         // FOLD: Xa of rows 8 a + 4 .. 8 a + 7 (their half group's band)
+  };
 };
 
 // Band segments of a tile of outer indices: segment s covers the rows whose material band
@@ -519,11 +522,14 @@ __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x
 // records): Xa, Xb, Ya, Yb (8 each) and the band factor of every (record, band segment) of the
 // tile, into its WaveScratch.  esh (log2) scales every X of the sub-stage.
 // KFREE: the specular band factor leaves out k (see band_log2_v).
-// G8: every band segment is a union of whole groups of 8 rows (seg8: the segment of this lane's
-// group j, rows 8 j .. 8 j + 7): the band factor is folded into Xa and no table is written.
-template <bool KFREE = false, bool G8 = false>
+// FOLD 4: every band segment is a union of whole half groups of 4 rows (segl, segh: the segments
+// of rows 8 j and 8 j + 4 of this lane's group j): the band factor is folded into Xa, one copy
+// per half group (Xa for rows 8 j .. 8 j + 3, Xh for 8 j + 4 .. 8 j + 7), and no table is written.
+// FOLD 8: whole groups of 8 rows, one copy (Xa).
+template <bool KFREE = false, int FOLD = 0>
 __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t, int m, int k1_0, int nk1, int lane,
-                                   int nseg, const SegTable& st, float esh, WaveScratch& W, int seg8 = 0) {
+                                   int nseg, const SegTable& st, float esh, WaveScratch& W, int segl = 0,
+                                   int segh = 0) {
   const int r = lane >> 3, j = lane & 7;
   const int src = t * RPW + r;                 // lane that set up record r of this sub-stage
   const float base_r = __shfl(q.base, src), slope_r = __shfl(q.slope, src);
@@ -534,25 +540,39 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
   const uint32_t k1a = (uint32_t)(k1_0 + 8 * j);   // first outer index of group j
   // Xa is zero for a record that adds nothing (and past the tile); then X is zero whatever the
   // other factors (finite for every record: a skipped record has slope 0 and phase steps 0)
-  float lband = lbm_r;   // the band factor's log2 on Xa: the bound, or with G8 the group's own
-  if (G8) {
+  const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
+  const float lg0 = base_r + (float)(k1a * K2) * slope_r + esh;
+  if (FOLD) {
+    // the band factors of the two half groups (no record's bound needed: each is its own)
     const float g_r = __shfl(q.gamma, src);
     const int m_r = __shfl(q.mat, src), k_r = __shfl(q.kind, src);
-    lband = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[seg8]);
+    float ll = band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[segl]);
+    float lh = FOLD == 4 ? band_log2_v<KFREE>(a, k_r, m_r, g_r, st.sb[segh]) : 0.f;
     if (a.Bd) {
       const float vx = __shfl(q.vx, src), vy = __shfl(q.vy, src), vz = __shfl(q.vz, src);
-      lband += log2f(dir_gain(a.dir + ((size_t)m * a.Bd + st.sd[seg8]) * a.El * a.Az, a.El, a.Az, vx, vy, vz));
+      const float* tab = a.dir + (size_t)m * a.Bd * a.El * a.Az;
+      ll += log2f(dir_gain(tab + (size_t)st.sd[segl] * a.El * a.Az, a.El, a.Az, vx, vy, vz));
+      if (FOLD == 4) lh += log2f(dir_gain(tab + (size_t)st.sd[segh] * a.El * a.Az, a.El, a.Az, vx, vy, vz));
     }
+    const float rev = (float)(int32_t)(a_r + k1a * bx_r) * S;
+    const float c = __builtin_amdgcn_cosf(rev), sn = __builtin_amdgcn_sinf(rev);
+    const float al = ok && 8 * j < nk1 ? __builtin_amdgcn_exp2f(lg0 + ll) : 0.f;
+    W.xa[r][j] = make_float2(al * c, al * sn);
+    if (FOLD == 4) {
+      const float ah = ok && 8 * j + 4 < nk1 ? __builtin_amdgcn_exp2f(lg0 + lh) : 0.f;
+      W.xh[r][j] = make_float2(ah * c, ah * sn);
+    }
+  } else {
+    // the record's band bound lbm rides on Xa; the band factors (<= 1) go to the table below
+    const float lg = ok && 8 * j < nk1 ? lg0 + lbm_r : -INFINITY;
+    W.xa[r][j] = cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S);
   }
-  const float lg = ok && 8 * j < nk1 ? base_r + (float)(k1a * K2) * slope_r + esh + lband : -INFINITY;
-  const float S = 2.3283064365386963e-10f;   // 2^-32: Q0.32 cycles to revolutions
-  W.xa[r][j] = cexp2(lg, (float)(int32_t)(a_r + k1a * bx_r) * S);
   W.xb[r][j] = cexp2((float)(j * K2) * slope_r, (float)(int32_t)((uint32_t)j * bx_r) * S);
   W.ya[r][j] = cexp2((float)(8 * j) * slope_r, (float)(int32_t)((uint32_t)(8 * j) * by_r) * S);
   W.yb[r][j] = cexp2((float)j * slope_r, (float)(int32_t)((uint32_t)j * by_r) * S);
   // band factors of every (record, segment), and zero for the segment past the tile
-  if (G8) {
-    // (folded into Xa)
+  if (FOLD) {
+    // (folded into Xa and Xh)
   } else if (!KFREE) {
     // lane (r, j) takes segments j, j + 8, ... of record r
     const float g_r = __shfl(q.gamma, src);
@@ -581,7 +601,7 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
       if (i < RPW * nseg) W.bf[rr][sg] = b2 != -INFINITY ? exp2f(band_log2_v<true>(a, k2, m2, g2, st.sb[sg]) - lm2) : 0.f;
     }
   }
-  if (!G8 && j == 7) W.bf[r][nseg] = 0.f;
+  if (!FOLD && j == 7) W.bf[r][nseg] = 0.f;
   // the factors are read back by other lanes of this wave only
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -589,13 +609,17 @@ __device__ inline void gen_factors(const SynthArgs& a, const PairLean& q, int t,
 
 // X and Y values of record rr for this lane's outer and inner index (lane = 8 a + b):
 // X[lane] = Xa[a] Xb[b] bf[segment of the lane's row], Y[lane] = Ya[a] Yb[b].
-// G8: the band factor is already on Xa.
-template <bool G8 = false>
+// FOLD 4: the band factor is already on Xa (b < 4) or Xh (b >= 4); FOLD 8: on Xa.
+template <int FOLD = 0>
 __device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myseg, float2& x, float2& y) {
   const int ka = lane >> 3, kb = lane & 7;
-  x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
   y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
-  if (!G8) {
+  if (FOLD == 8) {
+    x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
+  } else if (FOLD == 4) {
+    x = cmul(kb < 4 ? W.xa[rr][ka] : W.xh[rr][ka], W.xb[rr][kb]);
+  } else {
+    x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
     const float f = W.bf[rr][myseg];
     x.x *= f;
     x.y *= f;
@@ -604,13 +628,13 @@ __device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myse
 
 // The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
 // index into B, chunk wv (the wave's 8 records of the stage).
-template <bool SPLIT, bool G8>
+template <bool SPLIT, int FOLD>
 __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, H16Buf<SPLIT>& buf) {
   float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value<G8>(W, rr, lane, myseg, x, y);
+    xy_value<FOLD>(W, rr, lane, myseg, x, y);
     xr[rr] = x.x; xi[rr] = x.y; yr[rr] = y.x; yi[rr] = y.y;
   }
   halfx8 h, l;
@@ -631,7 +655,7 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
 }
 
 struct BwdBuf;
-template <bool G8>
+template <int FOLD>
 __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb);
 
 // Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
@@ -719,9 +743,9 @@ __device__ inline float dir_log2_max(const SynthArgs& a, int m, int tid, float* 
 // 64 records (one per lane) and the workgroup bounds their |X|; every stage each wave generates
 // 8 of them as f16 halves into LDS, then each wave contracts all 32 records of the stage into
 // its blocks of (k1, k2) on the matrix cores.
-// G8: every band segment is a union of whole groups of 8 rows and the grid holds whole groups
-// (bins a multiple of 512): the band factor rides on Xa.
-template <bool BATCH, bool SPLIT, bool G8>
+// FOLD 4 (8): every band edge falls on a multiple of 4 (8) rows and the grid holds whole groups of
+// that many rows (bins a multiple of 256, 512): the band factor rides on Xa.
+template <bool BATCH, bool SPLIT, int FOLD>
 __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                                    ChunkTab ct, et_paths P,
                                                                    const int32_t* __restrict__ idx, const Ctl* ctl,
@@ -738,7 +762,8 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
-  const int seg8 = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1);   // segment of row group lane % 8
+  // segments of the two half groups of row group lane % 8 (FOLD)
+  const int segl = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1), segh = min(__shfl(myseg, 8 * (lane & 7) + 4), nseg - 1);
   const float dmax = dir_log2_max(a, m, tid, red);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
   floatx4 acc[3][2][2];
@@ -772,8 +797,9 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
         E = Eg;
       }
     }
-    gen_factors<false, G8>(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv], seg8);
-    write_h16<SPLIT, G8>(wscr[wv], lane, wv, myseg, buf);
+    gen_factors<false, FOLD>(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv], segl,
+                             segh);
+    write_h16<SPLIT, FOLD>(wscr[wv], lane, wv, myseg, buf);
     __syncthreads();
     contract_h16<SPLIT>(buf, wv, lane, acc);
     __syncthreads();
@@ -1101,7 +1127,7 @@ struct __align__(16) BwdBuf {
   float X[2][RB][BS68];      // [re/im][record][k1]
   halfx8 Y[4][RB][YROW];     // Y halves [re hi, re lo, im hi, im lo][record][chunk of 8 inner indices]
   float R0[RB][BS68];        // Re(X Z) per (record, row) (band edges off the 4-row groups)
-  float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (G4)
+  float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (FOLD)
   float2 R1[16][36];         // sum over 4 rows of k X (f Z + df Z') per (row group, record)
   double kv[2][RB][17];      // dL/dk contribution per (record, band), stage parity
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
@@ -1113,13 +1139,13 @@ struct __align__(16) BwdBuf {
 // The adjoint's operands of the sub-stage's records: X in FP32 at [record][k1] (lane = k1), and Y
 // as f16 halves record-major, lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7
 // of record r: Y[8 c + i] = Ya[c] Yb[i].
-template <bool G8>
+template <int FOLD>
 __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb) {
   const int row0 = wv * RPW;
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
     float2 x, y;
-    xy_value<G8>(W, rr, lane, myseg, x, y);
+    xy_value<FOLD>(W, rr, lane, myseg, x, y);
     bb.X[0][row0 + rr][lane] = x.x;
     bb.X[1][row0 + rr][lane] = x.y;
   }
@@ -1138,16 +1164,15 @@ __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int mys
   __builtin_amdgcn_wave_barrier();
 }
 
-// GRP 4: every band edge of the grid falls on a group of 4 rows (a multiple of 256 bins), so
-// each lane's four rows of the matrix-product output belong to one band and are summed in
-// registers.  GRP 8: moreover every edge falls on a group of 8 rows and the grid holds whole
-// groups (bins a multiple of 512): the band factor rides on Xa, as in the forward kernel.
-template <bool BATCH, bool SPLIT, int GRP>
+// FOLD 4 (8): every band edge of the grid falls on a group of 4 (8) rows (a multiple of 256, 512
+// bins) and the grid holds whole groups: each lane's four rows of the matrix-product output belong
+// to one band and are summed in registers, and the band factor rides on Xa as in the forward
+// kernel.
+template <bool BATCH, bool SPLIT, int FOLD>
 __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                         ChunkTab ct, et_paths P, const int32_t* __restrict__ idx,
                                                         const Ctl* ctl, const float* __restrict__ g,
                                                         double* __restrict__ gpx, double* __restrict__ gpk) {
-  constexpr bool G4 = GRP >= 4, G8 = GRP == 8;
   SYNTH_RESOLVE();
   if (BATCH) g += (size_t)jb * a.M * a.F * 2;
   __shared__ __align__(16) BwdBuf bb;
@@ -1161,7 +1186,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const int nk1 = min(KT1, K1 - k1_0);
   int nseg, myseg;
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
-  const int seg8 = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1);   // segment of row group lane % 8 (G8)
+  // segments of the two half groups of row group lane % 8 (FOLD)
+  const int segl = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1), segh = min(__shfl(myseg, 8 * (lane & 7) + 4), nseg - 1);
   // wave -> block of 16 rows; SPLIT (a tile of at most 32 rows, two blocks) gives each wave
   // pair one block and each wave of a pair one of the stage's two record blocks
   constexpr int NB = SPLIT ? 1 : 2;              // record blocks of 16 per wave and stage
@@ -1243,8 +1269,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
-    gen_factors<true, G8>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv], seg8);
-    write_bwd<G8>(wscr[wv], lane, wv, myseg, bb);
+    gen_factors<true, FOLD>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv], segl, segh);
+    write_bwd<FOLD>(wscr[wv], lane, wv, myseg, bb);
     {
       // each generated record's row of k factors
       const int src = t * RPW + (lane & 7);
@@ -1308,7 +1334,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
         const float fr = frow0 + (float)(r10 + v) * df64;
         crv[v] = cr;
-        if (G4) {   // one band over the four rows: k applies to their sum
+        if (FOLD) {   // one band over the four rows: k applies to their sum
           s1r += fr * cr + dff * (xr * wr - xi * wi);
           s1i += fr * ci + dff * (xr * wi + xi * wr);
         } else {
@@ -1318,7 +1344,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         }
       }
       const int grp = rbw * 4 + (lane >> 4);
-      if (G4) {
+      if (FOLD) {
         const float kv = kfr[rband[0]];
         bb.Rg[grp][n] = (crv[0] + crv[1]) + (crv[2] + crv[3]);
         bb.R1[grp][n] = make_float2(kv * s1r, kv * s1i);
@@ -1371,7 +1397,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         if (b < a.Bk) {
           const int sg = st.bseg[b];
           if (sg >= 0) {
-            if (G4) {
+            if (FOLD) {
               for (int gg = st.s0[sg] >> 2; gg < st.s1[sg] >> 2; ++gg) sb += bb.Rg[gg][n];
             } else {
               // the band's rows in four interleaved partial sums (independent LDS reads)
@@ -1690,13 +1716,24 @@ bool bands_on_groups(const et_sim_desc* sim, int64_t g) {
   return true;
 }
 
+// How the band factor rides on the generating factors (forward and adjoint): 8 when every band
+// edge falls on a multiple of 512 bins and the bins are a multiple of 512, 4 for 256, 0 (a table
+// of band factors) otherwise.
+int bands_fold(const et_sim_desc* sim) { return bands_on_groups(sim, 8) ? 8 : bands_on_groups(sim, 4) ? 4 : 0; }
+
+template <bool BATCH, bool SPLIT>
+void launch_fwd_fold(int fold, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs, const ChunkTab& ct,
+                     const et_paths& P, const int32_t* idx, const Ctl* ctl, float* part) {
+  if (fold == 8) k_synth_mfma<BATCH, SPLIT, 8><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  else if (fold == 4) k_synth_mfma<BATCH, SPLIT, 4><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  else k_synth_mfma<BATCH, SPLIT, 0><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+}
+
 template <bool BATCH>
-void launch_fwd_mfma(bool split, bool g8, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
+void launch_fwd_mfma(bool split, int fold, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
                      const ChunkTab& ct, const et_paths& P, const int32_t* idx, const Ctl* ctl, float* part) {
-  if (split && g8) k_synth_mfma<BATCH, true, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
-  else if (split) k_synth_mfma<BATCH, true, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
-  else if (g8) k_synth_mfma<BATCH, false, true><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
-  else k_synth_mfma<BATCH, false, false><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, part);
+  if (split) launch_fwd_fold<BATCH, true>(fold, grid, s, a, jobs, ct, P, idx, ctl, part);
+  else launch_fwd_fold<BATCH, false>(fold, grid, s, a, jobs, ct, P, idx, ctl, part);
 }
 
 bool synth_factorised_ok(const et_sim_desc* sim) {
@@ -1756,7 +1793,7 @@ int synth_run(const et_sim_desc* sim, const et_paths* paths, const SynthWS& ws, 
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(ws.P, sim->M, (K1 + KT1 - 1) / KT1);
-    launch_fwd_mfma<false>(K1 <= 32, bands_on_groups(sim, 8), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
+    launch_fwd_mfma<false>(K1 <= 32, bands_fold(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
                            ws.partial);
   } else {
     dim3 grid(ws.P, sim->M, (sim->F + DTILE - 1) / DTILE);
@@ -1797,7 +1834,7 @@ int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, 
   if (mf) {
     const int K1 = sim->F / K2;
     dim3 grid(w.P, sim->M, (K1 + KT1 - 1) / KT1);
-    launch_fwd_mfma<false>(K1 <= 32, bands_on_groups(sim, 8), grid, s, a, nullptr, ChunkTab{}, Pth, nullptr, ctl,
+    launch_fwd_mfma<false>(K1 <= 32, bands_fold(sim), grid, s, a, nullptr, ChunkTab{}, Pth, nullptr, ctl,
                            w.partial);
   } else {
     dim3 grid(w.P, sim->M, (sim->F + DTILE - 1) / DTILE);
@@ -1812,36 +1849,21 @@ int synth_run_noalloc(const et_sim_desc* sim, const et_paths* paths, void* buf, 
 
 bool synth_bwd_factorised_ok(const et_sim_desc* sim) { return !sim->directivity && synth_factorised_ok(sim); }
 
-// Every material band edge on a multiple of four outer indices (256 bins): the adjoint sums a
-// lane's four output rows before the band sums.
-bool bands_on_row_groups(const et_sim_desc* sim) {
-  const int64_t F = sim->F, Bk = sim->Bk;
-  for (int64_t k1 = 1; k1 < F / K2; ++k1)
-    if (k1 % 4 && (k1 * K2) * Bk / F != ((k1 - 1) * K2) * Bk / F) return false;
-  return true;
-}
-
 template <bool BATCH, bool SPLIT>
-void launch_bwd_grp(int grp, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs, const ChunkTab& ct,
-                    const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g, double* gpx,
-                    double* gpk) {
-  if (grp == 8) k_synth_bwd_mfma<BATCH, SPLIT, 8><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else if (grp == 4) k_synth_bwd_mfma<BATCH, SPLIT, 4><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else k_synth_bwd_mfma<BATCH, SPLIT, 1><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+void launch_bwd_fold(int fold, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs, const ChunkTab& ct,
+                     const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g, double* gpx,
+                     double* gpk) {
+  if (fold == 8) k_synth_bwd_mfma<BATCH, SPLIT, 8><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else if (fold == 4) k_synth_bwd_mfma<BATCH, SPLIT, 4><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else k_synth_bwd_mfma<BATCH, SPLIT, 0><<<grid, 256, 0, s>>>(a, jobs, ct, P, idx, ctl, g, gpx, gpk);
 }
 
 template <bool BATCH>
-void launch_bwd_mfma(bool split, int grp, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
+void launch_bwd_mfma(bool split, int fold, dim3 grid, hipStream_t s, const SynthArgs& a, const SynthArgs* jobs,
                      const ChunkTab& ct, const et_paths& P, const int32_t* idx, const Ctl* ctl, const float* g,
                      double* gpx, double* gpk) {
-  if (split) launch_bwd_grp<BATCH, true>(grp, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-  else launch_bwd_grp<BATCH, false>(grp, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
-}
-
-// Row grouping of the adjoint for a job: 8 (band edges on 512 bins, whole groups), 4 (on 256
-// bins) or 1.
-int bwd_grouping(const et_sim_desc* sim) {
-  return bands_on_groups(sim, 8) ? 8 : bands_on_row_groups(sim) ? 4 : 1;
+  if (split) launch_bwd_fold<BATCH, true>(fold, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
+  else launch_bwd_fold<BATCH, false>(fold, grid, s, a, jobs, ct, P, idx, ctl, g, gpx, gpk);
 }
 
 size_t synth_bwd_ws_layout(const et_sim_desc* sim, int64_t cap, char* base, SynthWS* ws) {
@@ -1882,7 +1904,7 @@ int synth_bwd_run(const et_sim_desc* sim, const et_paths* paths, const float* gr
   if (kb) ET_HIP(hipEventRecord(kb, s));
   if (mf) {
     dim3 grid(ws.gchunks, sim->M, ws.gtiles);
-    launch_bwd_mfma<false>(sim->F / K2 <= 32, bwd_grouping(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
+    launch_bwd_mfma<false>(sim->F / K2 <= 32, bands_fold(sim), grid, s, a, nullptr, ChunkTab{}, P, ws.vidx, ctl,
                            grad_spectra, ws.gpart_x, ws.gpart_k);
   } else {
     dim3 grid(ws.gchunks, sim->M);
@@ -1925,11 +1947,8 @@ size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const B
   w.cap = cap;
   w.mf = synth_batch_factorised(J, jobs, false);
   w.mf_bwd = adjoint && synth_batch_factorised(J, jobs, true);
-  w.g4 = w.g8 = true;
-  for (int32_t i = 0; i < J; ++i) {
-    w.g4 = w.g4 && bands_on_row_groups(jobs[i].sim);
-    w.g8 = w.g8 && bands_on_groups(jobs[i].sim, 8);
-  }
+  w.fold = 8;   // the coarsest folding every job allows
+  for (int32_t i = 0; i < J; ++i) w.fold = std::min(w.fold, bands_fold(jobs[i].sim));
   w.target = chunk_target(s0, w.mf, tune.synth_wgs);
   w.target_bwd = chunk_target(s0, w.mf_bwd, tune.adjoint_wgs);
   // grid size: the chunk count is at most target + J (sum_j ceil(n_j / per)); buffers are
@@ -2007,7 +2026,7 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[0], s));
     if (w.mf) {
       dim3 grid(w.chunks, s0->M, (s0->F / K2 + KT1 - 1) / KT1);
-      launch_fwd_mfma<true>(s0->F / K2 <= 32, w.g8, grid, s, a0, dj, ct, P, w.vidx, ctl, w.partial);
+      launch_fwd_mfma<true>(s0->F / K2 <= 32, w.fold, grid, s, a0, dj, ct, P, w.vidx, ctl, w.partial);
     } else {
       dim3 grid(w.chunks, s0->M, (s0->F + DTILE - 1) / DTILE);
       k_synth_direct<true><<<grid, DB, 0, s>>>(a0, dj, ct, P, w.vidx, ctl, w.partial);
@@ -2023,8 +2042,8 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
     if (ev) ET_HIP(hipEventRecord(ev[2], s));
     if (w.mf_bwd) {
       dim3 grid(w.chunks_bwd, s0->M, w.T1);
-      launch_bwd_mfma<true>(s0->F / K2 <= 32, w.g8 ? 8 : w.g4 ? 4 : 1, grid, s, a0, dj, ct, P, w.vidx, ctl, grad,
-                            w.gpart_x, w.gpart_k);
+      launch_bwd_mfma<true>(s0->F / K2 <= 32, w.fold, grid, s, a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,
+                            w.gpart_k);
     } else {
       dim3 grid(w.chunks_bwd, s0->M);
       k_synth_bwd<true><<<grid, GB, sizeof(float2) * (size_t)s0->F, s>>>(a0, dj, ct, P, w.vidx, ctl, grad, w.gpart_x,
