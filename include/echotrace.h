@@ -362,9 +362,9 @@ int et_eq_directions(et_ctx* ctx, int64_t N, double cone_half_angle, void* ws, s
  * adjoint kernels aim at, and the grid of the bounce kernels (grid-stride over the active
  * rays).  Workspaces from et_batch_workspace_size serve every allowed value. */
 typedef struct {
-  int32_t synth_wgs;      /* 64 .. 4096 */
-  int32_t adjoint_wgs;    /* 64 .. 4096 */
-  int32_t trace_blocks;   /* 64 .. 4096 */
+  int32_t synth_wgs;      /* 64 .. 16384 (default 4096) */
+  int32_t adjoint_wgs;    /* 64 .. 16384 (default 4096) */
+  int32_t trace_blocks;   /* 64 .. 8192 (default 4096) */
   int32_t wave_rays;      /* rays per job wave of a fused batch: >= 1024, or 0 for the default 2^23.
                              Jobs run in waves of consecutive jobs whose rays add up to at most this
                              (a larger job forms its own wave); the workspace holds one wave's rays
@@ -376,8 +376,8 @@ int et_get_tuning(et_ctx* ctx, et_tuning* out);
 int et_set_tuning(et_ctx* ctx, const et_tuning* t);   /* ET_E_INVALID outside the ranges */
 
 /* Autotuner: runs the fused batch (as et_simulate_batch, with the adjoint when grad_spectra
- * is given) once per candidate shape (synthesis and adjoint workgroups 512, 1024, 2048,
- * 4096; bounce grids 1024, 1280, 2048, 4096 blocks), times the trace phase, the synthesis
+ * is given) once per candidate shape (synthesis and adjoint workgroups 1024, 2048, 4096, 8192,
+ * 16384; bounce grids 1024, 2048, 4096, 6144, 8192 blocks), times the trace phase, the synthesis
  * kernel and the adjoint kernel with events, keeps for each knob its fastest candidate in
  * the context (the phases do not interact) and returns the choice with its times.  The
  * outputs hold the results of the last run.  ET_E_UNSUPPORTED for batches that do not run

@@ -942,8 +942,8 @@ int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
       validate_sim(jobs[j].sim, true);
     }
     ET_CHECK(batch_fused(J, jobs), ET_E_UNSUPPORTED, "autotuning applies to fused (specular-only) batches");
-    const int32_t cw[4] = {512, 1024, 2048, 4096};
-    const int32_t cb[4] = {1024, 1280, 2048, 4096};
+    const int32_t cw[5] = {1024, 2048, 4096, 8192, 16384};
+    const int32_t cb[5] = {1024, 2048, 4096, 6144, 8192};
     auto run = [&](double* t) {
       batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx, true);
       ET_HIP(hipStreamSynchronize(ctx->stream));
@@ -952,7 +952,7 @@ int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
     double t[3], best[3] = {INFINITY, INFINITY, INFINITY};
     BatchTune pick = ctx->tune;
     run(t);   // warm-up
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
       ctx->tune.synth_wgs = ctx->tune.adjoint_wgs = cw[i];
       ctx->tune.trace_blocks = cb[i];
       run(t);

@@ -287,15 +287,15 @@ void signal_run(int64_t M, int64_t n_t, const float* h, int64_t L, const float* 
 // Launch shapes of the fused batch (the autotuner's knobs): workgroups of the main synthesis
 // and adjoint kernels the record chunks aim at.
 struct BatchTune {
-  int32_t synth_wgs = 2048;
-  int32_t adjoint_wgs = 1024;
-  int32_t trace_blocks = 2048;    // grid of the bounce kernels (grid-stride over the active rays)
+  int32_t synth_wgs = 4096;       // (the autotuner's choice for the 320-job batch of 2048-bin jobs)
+  int32_t adjoint_wgs = 4096;
+  int32_t trace_blocks = 4096;    // grid of the bounce kernels (grid-stride over the active rays)
   int64_t wave_rays = 1ll << 23;  // rays of a job wave: jobs run in waves whose rays add up to this
 };
 constexpr int64_t MIN_WAVE_RAYS = 1024;
 // Largest values the autotuner tries; workspaces are sized for them.
-constexpr int32_t TUNE_MAX_WGS = 4096;
-constexpr int32_t TUNE_MAX_TRACE_BLOCKS = 4096;
+constexpr int32_t TUNE_MAX_WGS = 16384;
+constexpr int32_t TUNE_MAX_TRACE_BLOCKS = 8192;
 
 // Fused batch synthesis: the visible records of all jobs, sorted by job, in chunks that never
 // mix jobs; one launch of the synthesis (and adjoint) kernel for the whole batch.

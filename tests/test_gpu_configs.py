@@ -273,8 +273,8 @@ def test_batch_autotune(et, ctx, batch_small):
         t = batch.autotune(grad_spectra=grad)
         print(f"autotune: synth {t.synth_wgs} wgs ({t.ms_synth:.3f} ms), adjoint {t.adjoint_wgs} wgs "
               f"({t.ms_adjoint:.3f} ms), bounce grid {t.trace_blocks} ({t.ms_trace:.3f} ms)")
-        assert t.synth_wgs in (512, 1024, 2048, 4096) and t.adjoint_wgs in (512, 1024, 2048, 4096)
-        assert t.trace_blocks in (1024, 1280, 2048, 4096)
+        assert t.synth_wgs in (1024, 2048, 4096, 8192, 16384) and t.adjoint_wgs in (1024, 2048, 4096, 8192, 16384)
+        assert t.trace_blocks in (1024, 2048, 4096, 6144, 8192)
         assert t.ms_trace > 0 and t.ms_synth > 0 and t.ms_adjoint > 0
         cur = ctx.tuning()
         assert (cur.synth_wgs, cur.adjoint_wgs, cur.trace_blocks) == (t.synth_wgs, t.adjoint_wgs, t.trace_blocks)
