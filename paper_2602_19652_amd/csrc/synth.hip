@@ -1105,14 +1105,15 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 // Factorised adjoint.  For record n and receiver m the adjoint needs, per material band b,
 //   S_b = sum_{k in b} conj(g_k) T_k   and   S1 = sum_k f_k conj(g_k) T_k,
 // with T_k = X[k1] Y[k2] as in the forward kernel and G = conj(g) as a [k1][k2] matrix:
-//   S_b = sum_{k1 in b} X[k1] Z[k1],          Z[k1]  = sum_k2 G[k1, k2] Y[k2],
-//   S1  = sum_k1 X[k1] (f_k1 Z[k1] + df Z'[k1]),  Z'[k1] = sum_k2 G[k1, k2] k2 Y[k2],
-// f_k1 the frequency of bin 64 k1.  Z and Z' are complex matrix products contracting over
-// k2 on the f16 matrix cores with split operands (as in the forward kernel): G = conj(g) and
-// k2 G sit in registers as halves, each scaled into the f16 range by a power of two per wave,
-// and Y is written as halves, record-major (8 inner indices per lane, 16-byte reads).  The per-row
-// products go to LDS; per record, band sums and the weighted sum run in FP64 in a fixed
-// order, and the FP64 chain rule of the direct adjoint turns them into dL/dk and dL/dx_m.
+//   S_b = sum_{k1 in b} X[k1] Z[k1],   Z[k1]  = sum_k2 G[k1, k2] Y[k2],
+//   S1  = sum_k1 X[k1] Z'[k1],         Z'[k1] = sum_k2 f_k G[k1, k2] Y[k2],
+// f_k the frequency of bin k = 64 k1 + k2.  Z and Z' are complex matrix products contracting
+// over k2 on the f16 matrix cores with split operands (as in the forward kernel): G = conj(g)
+// and f_k G sit in registers as halves, each scaled into the f16 range by a power of two per
+// wave, and Y is written as halves, record-major (8 inner indices per lane, 16-byte reads).
+// The per-row products go to LDS; per record, band sums and the weighted sum run in FP32 in a
+// fixed order, and the chain rule of the direct adjoint turns them into dL/dk and dL/dx_m
+// (accumulated over records in FP64).
 // LDS record stride of the adjoint's X, Y and R0: with 68 = 4 (mod 64) the MFMA operand reads
 // Y[16 nb + lane % 16][4 ks + lane / 16] hit 64 distinct banks, generation writes stay
 // contiguous, and 16-byte accesses of four consecutive rows are conflict-free per quarter wave.
@@ -1128,7 +1129,7 @@ struct __align__(16) BwdBuf {
   halfx8 Y[4][RB][YROW];     // Y halves [re hi, re lo, im hi, im lo][record][chunk of 8 inner indices]
   float R0[RB][BS68];        // Re(X Z) per (record, row) (band edges off the 4-row groups)
   float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (FOLD)
-  float2 R1[16][36];         // sum over 4 rows of k X (f Z + df Z') per (row group, record)
+  float2 R1[16][36];         // sum over 4 rows of k X Z' per (row group, record)
   double kv[2][RB][17];      // dL/dk contribution per (record, band), stage parity
   uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
   float lobe_w[256];         // per (material, band): 1 / (2 beta^2)
@@ -1193,31 +1194,33 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   constexpr int NB = SPLIT ? 1 : 2;              // record blocks of 16 per wave and stage
   const int rbw = SPLIT ? (wv & 1) : wv;
   const int nb0 = SPLIT ? (wv >> 1) : 0;
-  // A operands: rows k1 = 16 rbw + lane % 16 of G = conj(g) and of k2 G, inner indices
-  // k2 = 32 h + 8 (lane / 16) + i (h < 2, i < 8), as f16 halves [re hi, re lo, im hi, im lo],
-  // scaled by 2^eg and 2^eg2 (per wave) so that the largest magnitude is near 2^12
+  // A operands: rows k1 = 16 rbw + lane % 16 of G = conj(g) and of f_k G (f_k the bin's
+  // frequency), inner indices k2 = 32 h + 8 (lane / 16) + i (h < 2, i < 8), as f16 halves
+  // [re hi, re lo, im hi, im lo], scaled by 2^eg and 2^eg2 (per wave) so that the largest
+  // magnitude is near 2^12
   halfx8 ga[2][4], gw[2][4];
   float usz, usw;   // 2^-eg, 2^-eg2: undo the scales on Z and Z'
   {
     const int r1g = rbw * 16 + (lane & 15);
-    float gr[2][8], gi[2][8];
+    float gr[2][8], gi[2][8], fk[2][8];
     float mz = 0.f, mw = 0.f;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k2 = 32 * h + 8 * (lane >> 4) + i;
+        const int k = (k1_0 + r1g) * K2 + k2;
         float vr = 0.f, vi = 0.f;
         if (r1g < nk1) {
-          const int k = (k1_0 + r1g) * K2 + k2;
           vr = g[((size_t)m * a.F + k) * 2];
           vi = -g[((size_t)m * a.F + k) * 2 + 1];
         }
         gr[h][i] = vr;
         gi[h][i] = vi;
+        fk[h][i] = (float)(a.f_lo + (double)k * a.df);
         const float mg = fmaxf(fabsf(vr), fabsf(vi));
         mz = fmaxf(mz, mg);
-        mw = fmaxf(mw, mg * (float)k2);
+        mw = fmaxf(mw, mg * fabsf(fk[h][i]));
       }
     mz = wave_max(mz);
     mw = wave_max(mw);
@@ -1230,11 +1233,10 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       float zr[8], zi[8], wr[8], wi[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const float k2 = (float)(32 * h + 8 * (lane >> 4) + i);
         zr[i] = gr[h][i] * sz;
         zi[i] = gi[h][i] * sz;
-        wr[i] = gr[h][i] * k2 * sw;
-        wi[i] = gi[h][i] * k2 * sw;
+        wr[i] = gr[h][i] * fk[h][i] * sw;
+        wi[i] = gi[h][i] * fk[h][i] * sw;
       }
       split8(zr, ga[h][0], ga[h][1]);
       split8(zi, ga[h][2], ga[h][3]);
@@ -1242,7 +1244,6 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       split8(wi, gw[h][2], gw[h][3]);
     }
   }
-  const float frow0 = (float)(a.f_lo + (double)(k1_0 * K2) * a.df), df64 = (float)(K2 * a.df), dff = (float)a.df;
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;
   const double ln10 = 2.30258509299404568402;
   const double c2 = -ln10 * a.A1 / 20.0, c3 = -(double)a.sigma * 2.0 * M_PI / a.c;
@@ -1278,7 +1279,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       if (lane < RPW) bb.recb[wv * RPW + lane] = k_r == 0 ? m_r * a.Bk : QB;
     }
     __syncthreads();
-    // acc[0..2]: Z as Gr Yr, Gi Yi, Gr Yi + Gi Yr; acc[3..5]: Z' likewise (k2 G)
+    // acc[0..2]: Z as Gr Yr, Gi Yi, Gr Yi + Gi Yr; acc[3..5]: Z' likewise (f_k G)
     floatx4 acc[6][NB];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
@@ -1326,31 +1327,33 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       const float* kfr = bb.kf + bb.recb[n];
       float crv[4];
       float s1r = 0.f, s1i = 0.f;
+      // Re(X Z) per row (the band sums) and X Z' (the frequency-weighted sum), both before the
+      // scales 2^-eg, 2^-eg2, which are applied once per lane below
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float zr = (acc[0][j][v] - acc[1][j][v]) * usz, zi = acc[2][j][v] * usz;
-        const float wr = (acc[3][j][v] - acc[4][j][v]) * usw, wi = acc[5][j][v] * usw;
+        const float zr = acc[0][j][v] - acc[1][j][v], zi = acc[2][j][v];
+        const float wr = acc[3][j][v] - acc[4][j][v], wi = acc[5][j][v];
         const float xr = xrv[v], xi = xiv[v];
-        const float cr = xr * zr - xi * zi, ci = xr * zi + xi * zr;
-        const float fr = frow0 + (float)(r10 + v) * df64;
-        crv[v] = cr;
+        crv[v] = xr * zr - xi * zi;
+        const float tr = xr * wr - xi * wi, ti = xr * wi + xi * wr;
         if (FOLD) {   // one band over the four rows: k applies to their sum
-          s1r += fr * cr + dff * (xr * wr - xi * wi);
-          s1i += fr * ci + dff * (xr * wi + xi * wr);
+          s1r += tr;
+          s1i += ti;
         } else {
           const float kv = kfr[rband[v]];
-          s1r += kv * (fr * cr + dff * (xr * wr - xi * wi));
-          s1i += kv * (fr * ci + dff * (xr * wi + xi * wr));
+          s1r += kv * tr;
+          s1i += kv * ti;
         }
       }
       const int grp = rbw * 4 + (lane >> 4);
       if (FOLD) {
-        const float kv = kfr[rband[0]];
-        bb.Rg[grp][n] = (crv[0] + crv[1]) + (crv[2] + crv[3]);
+        const float kv = kfr[rband[0]] * usw;
+        bb.Rg[grp][n] = ((crv[0] + crv[1]) + (crv[2] + crv[3])) * usz;
         bb.R1[grp][n] = make_float2(kv * s1r, kv * s1i);
       } else {
-        *reinterpret_cast<float4*>(&bb.R0[n][r10]) = make_float4(crv[0], crv[1], crv[2], crv[3]);
-        bb.R1[grp][n] = make_float2(s1r, s1i);
+        *reinterpret_cast<float4*>(&bb.R0[n][r10]) =
+            make_float4(crv[0] * usz, crv[1] * usz, crv[2] * usz, crv[3] * usz);
+        bb.R1[grp][n] = make_float2(s1r * usw, s1i * usw);
       }
     }
     // this stage's masks were last read after the previous stage's second barrier
