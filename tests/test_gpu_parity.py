@@ -136,6 +136,37 @@ SYNTH_LAYOUTS = {
 }
 
 
+# name: (bins, material bands, directivity bands or 0): the factorised kernel's ways of carrying
+# the band factor on tiles of more than 32 rows: edges on 512 bins (folded per group of 8 rows),
+# on 256 bins (folded per half group of 4 rows), and off both (a table of band factors; 3072
+# bins, 192-bin bands)
+FOLD_LAYOUTS = {
+    "F4096_bands8_fold8": (4096, 8, 0),
+    "F4096_bands16_fold4": (4096, 16, 0),
+    "F4096_bands16_dir8_fold4": (4096, 16, 8),
+    "F3072_bands16_table": (3072, 16, 0),
+}
+
+
+@pytest.mark.parametrize("layout", list(FOLD_LAYOUTS))
+def test_synthesis_band_folding(et, ctx, tiny, layout):
+    """The factorised kernel on a tile of 48 or 64 rows under each band-factor layout, every
+    bin, against the oracle's spectra of 2048 of the tiny scene's records."""
+    scene, sim, ref = tiny
+    F, Bk, Bd = FOLD_LAYOUTS[layout]
+    g = W.rng(13)
+    sim = dict(sim, F=F, refl_k=g.uniform(0.3, 0.99, (1, Bk)).astype(np.float32),
+               lobe_beta=g.uniform(0.05, 0.3, (1, Bk)).astype(np.float32),
+               diff_coef=np.full((1, Bk), 0.1, np.float32))
+    if Bd:
+        sim["directivity"] = g.uniform(0.2, 1.0, (len(sim["rx_pos"]), Bd, 8, 16)).astype(np.float32)
+    sub = {k: (v[:2048] if isinstance(v, np.ndarray) and len(v) == len(ref["rtot"]) else v) for k, v in ref.items()}
+    H = et.synthesize(ctx, et.Sim(sim, flags=et.ET_SPECULAR), et.Paths.from_records(sub)).cpu().numpy()
+    st = ctx.stats()
+    check_spectra(H, O.synth(sub, sim), f"band folding {layout} (kernel {st.synth_kernel}, {len(sub['rtot'])} records)")
+    assert st.synth_kernel == 1
+
+
 @pytest.mark.parametrize("layout", list(SYNTH_LAYOUTS))
 def test_synthesis_isolation_tiny(et, ctx, tiny, layout):
     """GPU synthesis of the oracle's own records vs the oracle's spectra, over band layouts
@@ -331,6 +362,7 @@ ADJOINT_CASES = {
     "factorised_F8192_two_tiles": (8192, 16, False, False, 1),
     "factorised_F1024_bands_on_256_bins": (1024, 4, False, False, 1),   # 16 outer indices, band edges on 4 of them
     "factorised_F3072_bands_off_256_bins": (3072, 16, False, False, 1),  # 48 outer indices, 3 per band
+    "factorised_F4096_bands_on_256_bins": (4096, 16, False, False, 1),   # a full 64-row tile, 4 per band
     "factorised_F512_diffraction": (512, 8, False, True, 1),
     "direct_F512": (512, 8, True, False, 2),
     "direct_F500": (500, 4, False, False, 2),      # bins not a multiple of 64
