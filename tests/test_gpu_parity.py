@@ -525,10 +525,12 @@ def test_passive_adjoint_matches_oracle(et, ctx, tiny):
 
 # ----------------------------------------------------------------------------- time domain
 
-@pytest.mark.parametrize("sigma,n_t", [(1, 4096), (-1, 4096), (1, 1024)])
+@pytest.mark.parametrize("sigma,n_t", [(1, 4096), (-1, 4096), (1, 1024), (1, 65536), (-1, 32768)])
 def test_impulse_response_matches_oracle(et, ctx, tiny, sigma, n_t):
     """h = F^-1[H] of the tiny scene's spectra (1024 bins 20-100 kHz; n_t = 4096 samples at
-    320 kHz, and the minimum n_t = F) against the oracle's definition."""
+    320 kHz, the minimum n_t = F, and rows too long for one workgroup's LDS: radix-4 passes
+    over global memory, with a radix-2 pass first for an odd power of two) against the
+    oracle's definition."""
     import torch
     scene, sim, ref = tiny
     sim = dict(sim, phase_sign=sigma)
