@@ -137,20 +137,21 @@ SYNTH_LAYOUTS = {
 
 
 # name: (bins, material bands, directivity bands or 0): the factorised kernel's ways of carrying
-# the band factor on tiles of more than 32 rows: edges on 512 bins (folded per group of 8 rows),
-# on 256 bins (folded per half group of 4 rows), and off both (a table of band factors; 3072
-# bins, 192-bin bands)
+# the band factor: edges on 512 bins (folded per group of 8 rows), on 256 bins (folded per half
+# group of 4 rows, also with a last group that holds 4 rows), and off both (a table of band
+# factors; 3072 bins, 192-bin bands)
 FOLD_LAYOUTS = {
     "F4096_bands8_fold8": (4096, 8, 0),
     "F4096_bands16_fold4": (4096, 16, 0),
     "F4096_bands16_dir8_fold4": (4096, 16, 8),
     "F3072_bands16_table": (3072, 16, 0),
+    "F1280_bands5_fold4_partial_group": (1280, 5, 0),   # 20 rows: the last group of 8 holds 4
 }
 
 
 @pytest.mark.parametrize("layout", list(FOLD_LAYOUTS))
 def test_synthesis_band_folding(et, ctx, tiny, layout):
-    """The factorised kernel on a tile of 48 or 64 rows under each band-factor layout, every
+    """The factorised kernel under each band-factor layout (tiles of 20, 48 and 64 rows), every
     bin, against the oracle's spectra of 2048 of the tiny scene's records."""
     scene, sim, ref = tiny
     F, Bk, Bd = FOLD_LAYOUTS[layout]
@@ -363,6 +364,7 @@ ADJOINT_CASES = {
     "factorised_F1024_bands_on_256_bins": (1024, 4, False, False, 1),   # 16 outer indices, band edges on 4 of them
     "factorised_F3072_bands_off_256_bins": (3072, 16, False, False, 1),  # 48 outer indices, 3 per band
     "factorised_F4096_bands_on_256_bins": (4096, 16, False, False, 1),   # a full 64-row tile, 4 per band
+    "factorised_F1280_partial_group": (1280, 5, False, False, 1),        # 20 rows, 4 per band
     "factorised_F512_diffraction": (512, 8, False, True, 1),
     "direct_F512": (512, 8, True, False, 2),
     "direct_F500": (500, 4, False, False, 2),      # bins not a multiple of 64
