@@ -1130,8 +1130,9 @@ struct __align__(16) BwdBuf {
   float R0[RB][BS68];        // Re(X Z) per (record, row) (band edges off the 4-row groups)
   float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (FOLD)
   float2 R1[16][36];         // sum over 4 rows of k X Z' per (row group, record)
-  double kv[2][RB][17];      // dL/dk contribution per (record, band), stage parity
-  uint32_t kmask[2][256];    // per stage parity and material: bit n set if record n is specular of it
+  float kv[16][RB];          // 2 S_b of each specular record of the stage (0 for the others), [band][record]
+  int32_t kmat[RB];          // the material of each specular record of the stage, -1 for the others
+  double dk[4][256];         // per wave: dL/dk of (material, band) over its records so far
   float lobe_w[256];         // per (material, band): 1 / (2 beta^2)
   float kf[256 + 16];        // per (material, band): k; then a row of ones (records of other kinds)
   int32_t recb[RB];          // per record of the stage: its row of kf (mat Bk, or the ones row)
@@ -1163,6 +1164,67 @@ __device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int mys
   split8(yi, bb.Y[2][row0 + r][c], bb.Y[3][row0 + r][c]);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Sum of v over each group of 8 consecutive lanes, valid in the group's first lane, added as
+// ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)) by lane moves within rows of 16 (no LDS).
+template <int CTRL>
+__device__ inline float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float sum8_first(float v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]: lane ^ 1
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]: lane ^ 2
+  v += dpp_mov<0x104>(v);   // row_shl 4: lane + 4 within the row
+  return v;
+}
+
+// dL/dk over the wave's 8 records n of the stage (8 wv .. 8 wv + 7): (material q, band b) adds
+// 2 S_b of the specular records of material q.  As a matrix product, kv [band][record] times the
+// records' one-hot materials [record][material], on the FP32 matrix cores (the products are
+// exact: 0 or the value) in tiles of 16 materials; each lane adds its four sums to the wave's
+// FP64 totals in LDS (one lane per (material, band)).  With at most 16 materials the sums stay
+// in the FP32 accumulator dkc over a group of 8 stages (64 records) and go to the totals when
+// flush is set.  Every lane of the wave calls it.
+__device__ inline void dk_wave(BwdBuf& bb, int wv, int lane, int Q, int Bk, floatx4& dkc, bool flush) {
+  const int col = lane & 15;   // A: band row; B: material column within the tile
+  float av[2];
+  int mv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = 8 * wv + 4 * h + (lane >> 4);
+    av[h] = col < Bk ? bb.kv[col][n] : 0.f;
+    mv[h] = bb.kmat[n];
+  }
+  if (Q <= 16) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) dkc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h], mv[h] == col ? 1.f : 0.f, dkc, 0, 0, 0);
+    if (flush) {
+      if (col < Q) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int b = 4 * (lane >> 4) + v;
+          if (b < Bk) bb.dk[wv][col * Bk + b] += (double)dkc[v];
+        }
+      }
+      dkc = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    return;
+  }
+  for (int q0 = 0; q0 < Q; q0 += 16) {
+    floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h], mv[h] == q0 + col ? 1.f : 0.f, c, 0, 0, 0);
+    // c[v]: band 4 (lane / 16) + v, material q0 + lane % 16
+    const int qq = q0 + col;
+    if (qq < Q) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int b = 4 * (lane >> 4) + v;
+        if (b < Bk) bb.dk[wv][qq * Bk + b] += (double)c[v];
+      }
+    }
+  }
 }
 
 // FOLD 4 (8): every band edge of the grid falls on a group of 4 (8) rows (a multiple of 256, 512
@@ -1248,7 +1310,6 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   const double ln10 = 2.30258509299404568402;
   const double c2 = -ln10 * a.A1 / 20.0, c3 = -(double)a.sigma * 2.0 * M_PI / a.c;
   const int QB = a.Q * a.Bk;
-  double kacc = 0.0;                 // thread i < Q Bk: dL/dk[i] of this workgroup
   double gx0 = 0.0, gx1 = 0.0, gx2 = 0.0;
   for (int i = tid; i < QB; i += 256) {
     const double bt = (double)a.beta[i];
@@ -1256,6 +1317,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     bb.kf[i] = a.refl_k[i];
   }
   if (tid < a.Bk) bb.kf[QB + tid] = 1.f;
+  for (int i = lane; i < QB; i += 64) bb.dk[wv][i] = 0.0;   // (each wave's own totals)
   // material band of each of this lane's four epilogue rows (rows past the grid: the last band)
   int rband[4];
   {
@@ -1266,6 +1328,16 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       rband[v] = (int)((kr * a.Bk) / a.F);
     }
   }
+  // rows [br0[h], br1[h]) of the tile in band (tid % 8) + 8 h, the bands this thread sums in the
+  // per-record epilogue (empty for a band not in the tile)
+  int br0[2], br1[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int b = (tid & 7) + 8 * h, sg = b < a.Bk ? st.bseg[b] : -1;
+    br0[h] = sg >= 0 ? st.s0[sg] : 0;
+    br1[h] = sg >= 0 ? st.s1[sg] : 0;
+  }
+  floatx4 dkc = {0.f, 0.f, 0.f, 0.f};
   PairLean q;
   for (int64_t s = 0; s < nst; ++s) {
     const int t = (int)(s & 7);
@@ -1356,20 +1428,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         bb.R1[grp][n] = make_float2(s1r * usw, s1i * usw);
       }
     }
-    // this stage's masks were last read after the previous stage's second barrier
-    for (int i = tid; i < a.Q; i += 256) bb.kmask[s & 1][i] = 0u;
     __syncthreads();
-    if (s > 0 && tid < QB) {
-      // dL/dk of the previous stage: this (material, band)'s records, in increasing order
-      const int qq = tid / a.Bk, b = tid - qq * a.Bk;
-      const int pp = (int)((s - 1) & 1);
-      uint32_t mk = bb.kmask[pp][qq];
-      while (mk) {
-        const int n = __ffs(mk) - 1;
-        kacc += bb.kv[pp][n][b];
-        mk &= mk - 1u;
-      }
-    }
     {
       // eight threads per record: row sums in FP64, bands j and j + 8.  Record n of this stage
       // was set up by lane 8 t + n % 8 of this same wave: its data arrive by shuffle.
@@ -1392,53 +1451,43 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         s1i += c.y;
       }
       float s0 = 0.f, wl = 0.f;
-      const int pp = (int)(s & 1);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int b = j + 8 * h;
         float sb = 0.f;
-        if (b < a.Bk) {
-          const int sg = st.bseg[b];
-          if (sg >= 0) {
-            if (FOLD) {
-              for (int gg = st.s0[sg] >> 2; gg < st.s1[sg] >> 2; ++gg) sb += bb.Rg[gg][n];
-            } else {
-              // the band's rows in four interleaved partial sums (independent LDS reads)
-              const int e = st.s1[sg];
-              int r1 = st.s0[sg];
-              float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-              for (; r1 + 4 <= e; r1 += 4) {
-                p0 += bb.R0[n][r1];
-                p1 += bb.R0[n][r1 + 1];
-                p2 += bb.R0[n][r1 + 2];
-                p3 += bb.R0[n][r1 + 3];
-              }
-              for (; r1 < e; ++r1) p0 += bb.R0[n][r1];
-              sb = (p0 + p1) + (p2 + p3);
-            }
+        if (FOLD) {
+          for (int gg = br0[h] >> 2; gg < br1[h] >> 2; ++gg) sb += bb.Rg[gg][n];
+        } else {
+          // the band's rows in four interleaved partial sums (independent LDS reads)
+          const int e = br1[h];
+          int r1 = br0[h];
+          float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+          for (; r1 + 4 <= e; r1 += 4) {
+            p0 += bb.R0[n][r1];
+            p1 += bb.R0[n][r1 + 1];
+            p2 += bb.R0[n][r1 + 2];
+            p3 += bb.R0[n][r1 + 3];
           }
+          for (; r1 < e; ++r1) p0 += bb.R0[n][r1];
+          sb = (p0 + p1) + (p2 + p3);
         }
         // sb leaves out k for specular records: k sb is the band's share of H's sums, 2 sb its dL/dk
-        double kvv = 0.0;
+        float kvv = 0.f;
         if (b < a.Bk) {
           const float kb = kind == 0 ? bb.kf[mat * a.Bk + b] : 1.f;
           s0 += kb * sb;
           if (valid && kind == 0) {
             wl += kb * sb * bb.lobe_w[mat * a.Bk + b];
-            kvv = 2.0 * (double)sb;
+            kvv = 2.f * sb;
           }
         }
-        bb.kv[pp][n][b] = kvv;
+        if (b < a.Bk) bb.kv[b][n] = kvv;
       }
-#pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        s1r += __shfl_xor(s1r, o);
-        s1i += __shfl_xor(s1i, o);
-        s0 += __shfl_xor(s0, o);
-        wl += __shfl_xor(wl, o);
-      }
-      // record n joins its material's mask of this stage (an OR: the result is order-free)
-      if (j == 0 && valid && kind == 0) atomicOr(&bb.kmask[pp][mat], 1u << n);
+      s1r = sum8_first(s1r);
+      s1i = sum8_first(s1i);
+      s0 = sum8_first(s0);
+      wl = sum8_first(wl);
+      if (j == 0) bb.kmat[n] = valid && kind == 0 ? mat : -1;
       if (j == 0 && valid) {
         // d(ln A + j phi)/dx_m = [(-p/r - ln10 (a0 + a1 f)/20) + j sigma 2 pi f / c] u - d(gamma^2)/dx / (2 beta^2)
         const double cu = (double)gc1 * (double)s0 + c2 * (double)s1r + c3 * (double)s1i;
@@ -1448,19 +1497,12 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
         gx0 += g0; gx1 += g1; gx2 += g2;
       }
     }
+    // the wave's records of this stage into dL/dk (their kv and kmat were written by this wave)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    dk_wave(bb, wv, lane, a.Q, a.Bk, dkc, t == 7);   // (nst is a multiple of 8)
   }
   __syncthreads();
-  if (nst > 0 && tid < QB) {
-    // dL/dk of the last stage
-    const int qq = tid / a.Bk, b = tid - qq * a.Bk;
-    const int pp = (int)((nst - 1) & 1);
-    uint32_t mk = bb.kmask[pp][qq];
-    while (mk) {
-      const int n = __ffs(mk) - 1;
-      kacc += bb.kv[pp][n][b];
-      mk &= mk - 1u;
-    }
-  }
   const size_t slot = ((size_t)p * gridDim.z + k1t) * a.M + m;
   const double gv[3] = {gx0, gx1, gx2};
   for (int c = 0; c < 3; ++c) {
@@ -1473,7 +1515,8 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     if (tid == 0) gpx[slot * 3 + c] = red[0];
     __syncthreads();
   }
-  if (tid < QB) gpk[slot * QB + tid] = kacc;
+  // the four waves' totals of each (material, band), in wave order
+  if (tid < QB) gpk[slot * QB + tid] = ((bb.dk[0][tid] + bb.dk[1][tid]) + bb.dk[2][tid]) + bb.dk[3][tid];
 }
 
 // One workgroup per output value (QB band coefficients, then 3 M receiver coordinates): its

@@ -222,6 +222,42 @@ def test_adjoint_at_its_limits(et, ctx):
         assert err.value.status == -5
 
 
+@pytest.mark.parametrize("Q,Bk,F", [(64, 4, 4096), (40, 3, 4608), (256, 1, 2048), (17, 15, 1920), (51, 5, 960)])
+def test_adjoint_with_many_materials(et, ctx, Q, Bk, F):
+    """dL/dk with more than 16 materials (the factorised adjoint sums it per tile of 16
+    materials): Q Bk up to 256, bands of whole 64-bin rows with edges on the 4-row groups
+    (4096, 4608 bins) and off them (1920, 960), a last material tile partly filled, tiles of
+    at most 32 rows (2048, 1920, 960 bins) and a grid of two tiles (4608).  Against the
+    oracle gradient."""
+    import torch
+    base_scene, base_sim = W.tiny_scene(n_rays=2048)
+    scene, sim, g = _tiny_materials(base_scene, base_sim, Q, Bk, F, 2048, 53 + Q)
+    ref = O.trace(scene, sim, certify=False)
+    hidden = dict(sim, refl_k=g.uniform(0.3, 0.99, (Q, Bk)).astype(np.float32))
+    H_star = O.synth(ref, hidden)
+    H = O.synth(ref, sim)
+    gk_ref, gx_ref = O.grad(ref, sim, H - H_star)
+    P = et.Paths.from_records(ref)
+    gk, gx = et.synthesize_backward(ctx, et.Sim(sim), P, torch.as_tensor(H - H_star).to("cuda"))
+    st = ctx.stats()
+    gk = gk.cpu().numpy()
+    ek, ex = rel_l2(gk, gk_ref), rel_l2(gx.cpu().numpy(), gx_ref)
+    used = np.unique(ref["mat"][ref["kind"] == 0])
+    print(f"adjoint, Q={Q}, Bk={Bk}, F={F} (kernel {st.adjoint_kernel}, {len(ref['rtot'])} records, "
+          f"{len(used)} materials hit): dL/dk {ek:.3e}, dL/dx {ex:.3e}")
+    assert st.adjoint_kernel == 1
+    assert ek <= TOL and ex <= TOL
+    assert len(used) > 16
+    # per material: a material that no record reflects from has a zero gradient, the others
+    # agree to TOL of the largest entry
+    scale = np.abs(gk_ref).max()
+    for qq in range(Q):
+        if qq not in used:
+            assert np.all(gk[qq] == 0), qq
+        else:
+            assert np.abs(gk[qq] - gk_ref[qq]).max() <= TOL * scale, qq
+
+
 @pytest.mark.parametrize("F", [4096, 65536])
 def test_synthesis_with_64_bands(et, ctx, F):
     """The largest band tables: 64 material bands and a 64-band receiver directivity.  At
