@@ -655,8 +655,7 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
 }
 
 struct BwdBuf;
-template <int FOLD>
-__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb);
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, BwdBuf& bb);
 
 // Row and column blocks (16 x 16) of a wave: with 64 rows, the quadrant (wv / 2, wv % 2) as 2 x 2
 // blocks; with at most 32 rows (SPLIT), row block wv % 2 against the column blocks of half wv / 2.
@@ -1114,9 +1113,8 @@ __global__ __launch_bounds__(GB) void k_synth_bwd(SynthArgs a0, const SynthArgs*
 // The per-row products go to LDS; per record, band sums and the weighted sum run in FP32 in a
 // fixed order, and the chain rule of the direct adjoint turns them into dL/dk and dL/dx_m
 // (accumulated over records in FP64).
-// LDS record stride of the adjoint's X, Y and R0: with 68 = 4 (mod 64) the MFMA operand reads
-// Y[16 nb + lane % 16][4 ks + lane / 16] hit 64 distinct banks, generation writes stay
-// contiguous, and 16-byte accesses of four consecutive rows are conflict-free per quarter wave.
+// LDS record stride of the adjoint's per-row products R0: with 68 = 4 (mod 64) the 16-byte
+// writes of four consecutive rows are conflict-free per quarter wave.
 constexpr int BS68 = 68;
 
 // Group-major sums (stride 36): the eight threads of each of a wave's eight records reading
@@ -1125,7 +1123,6 @@ constexpr int BS68 = 68;
 // is then dH/dk of that band (also where k = 0), and k enters the other sums per row.
 constexpr int YROW = 9;     // halfx8 per record row of Y halves: 64 inner indices and a pad (144-byte rows)
 struct __align__(16) BwdBuf {
-  float X[2][RB][BS68];      // [re/im][record][k1]
   halfx8 Y[4][RB][YROW];     // Y halves [re hi, re lo, im hi, im lo][record][chunk of 8 inner indices]
   float R0[RB][BS68];        // Re(X Z) per (record, row) (band edges off the 4-row groups)
   float Rg[16][36];          // Re(X Z) summed over a group of 4 rows, per (group, record) (FOLD)
@@ -1138,19 +1135,11 @@ struct __align__(16) BwdBuf {
   int32_t recb[RB];          // per record of the stage: its row of kf (mat Bk, or the ones row)
 };
 
-// The adjoint's operands of the sub-stage's records: X in FP32 at [record][k1] (lane = k1), and Y
-// as f16 halves record-major, lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7
-// of record r: Y[8 c + i] = Ya[c] Yb[i].
-template <int FOLD>
-__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, int myseg, BwdBuf& bb) {
+// The adjoint's matrix-product operand of the sub-stage's records: Y as f16 halves record-major,
+// lane (r, c) = (lane / 8, lane % 8) forming inner indices 8 c .. 8 c + 7 of record r:
+// Y[8 c + i] = Ya[c] Yb[i].  (X is formed where it is used, from the factors.)
+__device__ inline void write_bwd(const WaveScratch& W, int lane, int wv, BwdBuf& bb) {
   const int row0 = wv * RPW;
-#pragma unroll
-  for (int rr = 0; rr < RPW; ++rr) {
-    float2 x, y;
-    xy_value<FOLD>(W, rr, lane, myseg, x, y);
-    bb.X[0][row0 + rr][lane] = x.x;
-    bb.X[1][row0 + rr][lane] = x.y;
-  }
   const int r = lane >> 3, c = lane & 7;
   const float2 ya = W.ya[r][c];
   float yr[8], yi[8];
@@ -1318,14 +1307,16 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
   }
   if (tid < a.Bk) bb.kf[QB + tid] = 1.f;
   for (int i = lane; i < QB; i += 64) bb.dk[wv][i] = 0.0;   // (each wave's own totals)
-  // material band of each of this lane's four epilogue rows (rows past the grid: the last band)
-  int rband[4];
+  // material band and band segment of each of this lane's four epilogue rows (rows past the grid:
+  // the last band, and the segment past the tile, whose band factor is zero)
+  int rband[4], rseg[4];
   {
     const int r10 = rbw * 16 + (lane >> 4) * 4;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t kr = (int64_t)min(k1_0 + r10 + v, K1 - 1) * K2;
       rband[v] = (int)((kr * a.Bk) / a.F);
+      rseg[v] = __shfl(myseg, r10 + v);
     }
   }
   // rows [br0[h], br1[h]) of the tile in band (tid % 8) + 8 h, the bands this thread sums in the
@@ -1343,7 +1334,7 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
     const int t = (int)(s & 7);
     if (t == 0) pair_lean<true>(a, P, idx, lo + (s >> 3) * (8 * RB) + wv * 64 + lane, hi, m, q);
     gen_factors<true, FOLD>(a, q, t, m, k1_0, nk1, lane, nseg, st, 0.f, wscr[wv], segl, segh);
-    write_bwd<FOLD>(wscr[wv], lane, wv, myseg, bb);
+    write_bwd(wscr[wv], lane, wv, bb);
     {
       // each generated record's row of k factors
       const int src = t * RPW + (lane & 7);
@@ -1393,9 +1384,30 @@ __global__ __launch_bounds__(256, 2) void k_synth_bwd_mfma(SynthArgs a0, const S
       const int nb = nb0 + j;
       const int n = nb * 16 + (lane & 15);
       const int r10 = rbw * 16 + (lane >> 4) * 4;   // this lane's four rows r10 .. r10 + 3
-      const float4 x4r = *reinterpret_cast<const float4*>(&bb.X[0][n][r10]);
-      const float4 x4i = *reinterpret_cast<const float4*>(&bb.X[1][n][r10]);
-      const float xrv[4] = {x4r.x, x4r.y, x4r.z, x4r.w}, xiv[4] = {x4i.x, x4i.y, x4i.z, x4i.w};
+      // X of record n at these rows from its factors (wave n / 8 generated it): Xa (or Xh, the
+      // upper half group with FOLD 4) of group r10 / 8 times Xb of r10 % 8 .. + 3, times the
+      // row's band factor without FOLD
+      float xrv[4], xiv[4];
+      {
+        const WaveScratch& W = wscr[n >> 3];
+        const int rr = n & 7, ga = r10 >> 3, gb = r10 & 7;
+        const float2 xa = FOLD == 4 && gb >= 4 ? W.xh[rr][ga] : W.xa[rr][ga];
+        const float4 b01 = *reinterpret_cast<const float4*>(&W.xb[rr][gb]);
+        const float4 b23 = *reinterpret_cast<const float4*>(&W.xb[rr][gb + 2]);
+        const float2 xb[4] = {make_float2(b01.x, b01.y), make_float2(b01.z, b01.w), make_float2(b23.x, b23.y),
+                              make_float2(b23.z, b23.w)};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float2 x = cmul(xa, xb[v]);
+          if (!FOLD) {
+            const float f = W.bf[rr][rseg[v]];
+            x.x *= f;
+            x.y *= f;
+          }
+          xrv[v] = x.x;
+          xiv[v] = x.y;
+        }
+      }
       const float* kfr = bb.kf + bb.recb[n];
       float crv[4];
       float s1r = 0.f, s1i = 0.f;
