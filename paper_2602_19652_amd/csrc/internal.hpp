@@ -230,6 +230,7 @@ struct SynthWS {
   float* lc;
   float* ld;
   float* lp;                 // [Bk] log2 I_p (passive component)
+  float* lmax;               // [3 Q + 1] per material: max log2 k, min lobe coefficient, max log2 I_d; max log2 I_p
   float* plk;                // [cap][Bk] path-product reading: log2 k over each record's path (or log2 I_d)
   float* plc;                // [cap][Bk] path-product reading: each record's lobe coefficient
 };
@@ -318,7 +319,7 @@ struct SynthBatchWS {
   void* sort_tmp;
   int64_t* tab;                 // chunk tables (forward, adjoint)
   void* jobs;                   // device job table
-  float* tables;                // [J][4][Q][Bk] band tables
+  float* tables;                // [J][4 Q Bk + 3 Q + 1] band tables and their per-material bounds
 };
 bool synth_batch_factorised(int32_t J, const et_job* jobs, bool adjoint);
 size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const BatchTune& tune, bool adjoint,

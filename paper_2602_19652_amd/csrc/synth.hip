@@ -64,6 +64,8 @@ struct SynthArgs {
   const float* ld;         // [Q][Bk] log2 I_d
   const float* pcoef;      // [Bk] passive source magnitude I_p (NULL without the passive component)
   const float* lp;         // [Bk] log2 I_p
+  const float* lmax;       // [3 Q + 1] per material: max_b log2 k, min_b lobe coefficient, max_b log2 I_d;
+                           // then max_b log2 I_p (bounds on the band factors, used with rec_rows 0)
   int32_t rec_rows;        // 1 (path-product reading): lk, lc, ld have a row per record and a
                            // record's `mat` in the kernels is its index; 0: a row per material
   const uint64_t* rxv;     // per-receiver line of sight [records] (NULL: the records' visible bit)
@@ -87,6 +89,7 @@ SynthArgs make_args(const et_sim_desc* sim, int32_t P) {
   a.kbase = -(a.A0 + a.A1 * a.f_lo) / 20.0 * LOG2_10;
   a.kslope = -a.A1 * a.df / 20.0 * LOG2_10;
   a.pcoef = (sim->flags & ET_PASSIVE) ? sim->passive_coef : nullptr;
+  a.lk = a.lc = a.ld = a.lp = a.lmax = nullptr;
   a.rec_rows = 0;
   a.rxv = nullptr;
   return a;
@@ -212,8 +215,31 @@ __device__ inline void band_table_entry(const SynthArgs& a, int i, float* lk, fl
   if (i < a.Bk) lp[i] = a.pcoef ? log2f(a.pcoef[i]) : -INFINITY;
 }
 
-__global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld, float* lp) {
+// Per-material bounds of material q (and, for q = 0, of the passive factors) from the same
+// expressions as the table entries, so that each bound equals the extreme of its entries.
+__device__ inline void band_bound_entry(const SynthArgs& a, int q, float* lmax) {
+  float mk = -INFINITY, mc = INFINITY, md = -INFINITY;
+  for (int b = 0; b < a.Bk; ++b) {
+    const int i = q * a.Bk + b;
+    const float bt = a.beta[i];
+    mk = fmaxf(mk, log2f(a.refl_k[i]));
+    mc = fminf(mc, LOG2E_F / (2.0f * bt * bt));
+    md = fmaxf(md, log2f(a.dcoef[i]));
+  }
+  lmax[q] = mk;
+  lmax[a.Q + q] = mc;
+  lmax[2 * a.Q + q] = md;
+  if (q == 0) {
+    float mp = -INFINITY;
+    if (a.pcoef)
+      for (int b = 0; b < a.Bk; ++b) mp = fmaxf(mp, log2f(a.pcoef[b]));
+    lmax[3 * a.Q] = mp;
+  }
+}
+
+__global__ void k_band_tables(SynthArgs a, float* lk, float* lc, float* ld, float* lp, float* lmax) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.Q) band_bound_entry(a, i, lmax);
   if (i >= a.Q * a.Bk) return;
   band_table_entry(a, i, lk, lc, ld, lp);
 }
@@ -414,8 +440,17 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
       q.vx = -ux; q.vy = -uy; q.vz = -uz;
     }
   }
+  // bound on the record's log2 band factor over every band: from the per-material bounds (at
+  // least the largest factor: k and the lobe's coefficient may peak on different bands), or by
+  // taking every band with per-record tables
   float bm = -INFINITY;
-  for (int b = 0; b < a.Bk; ++b) bm = fmaxf(bm, band_log2_v<GRAD>(a, q.kind, q.mat, q.gamma, b));
+  if (!a.rec_rows) {
+    bm = q.kind == 0   ? (GRAD ? 0.f : a.lmax[q.mat]) - q.gamma * q.gamma * a.lmax[a.Q + q.mat]
+         : q.kind == 1 ? a.lmax[2 * a.Q + q.mat]
+                       : a.lmax[3 * a.Q];
+  } else {
+    for (int b = 0; b < a.Bk; ++b) bm = fmaxf(bm, band_log2_v<GRAD>(a, q.kind, q.mat, q.gamma, b));
+  }
   q.lbm = bm + dmax;
   if (q.lbm == -INFINITY) {   // every band factor is zero: nothing to add (lbm stays finite)
     q.base = -INFINITY;
@@ -1590,8 +1625,9 @@ void build_tables(SynthArgs& a, const SynthWS& ws, hipStream_t s) {
   a.lc = ws.lc;
   a.ld = ws.ld;
   a.lp = ws.lp;
+  a.lmax = ws.lmax;
   const int n = a.Q * a.Bk;
-  k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld, ws.lp);
+  k_band_tables<<<(n + 255) / 256, 256, 0, s>>>(a, ws.lk, ws.lc, ws.ld, ws.lp, ws.lmax);
 }
 
 // Path-product reading: band tables with a row per record.  Specular record n: the sum of
@@ -1650,6 +1686,8 @@ size_t table_ws(const et_sim_desc* sim, char* base, size_t off, SynthWS& w) {
   off += al(sizeof(float) * n);
   w.lp = (float*)(base ? base + off : nullptr);
   off += al(sizeof(float) * sim->Bk);
+  w.lmax = (float*)(base ? base + off : nullptr);
+  off += al(sizeof(float) * (3 * (size_t)sim->Q + 1));
   return off;
 }
 
@@ -1681,6 +1719,7 @@ __global__ void k_band_tables_batch(const SynthArgs* __restrict__ jobs) {
   for (int i = threadIdx.x; i < a.Q * a.Bk; i += blockDim.x)
     band_table_entry(a, i, const_cast<float*>(a.lk), const_cast<float*>(a.lc), const_cast<float*>(a.ld),
                      const_cast<float*>(a.lp));
+  for (int q = threadIdx.x; q < a.Q; q += blockDim.x) band_bound_entry(a, q, const_cast<float*>(a.lmax));
 }
 
 // sort key of each visible record: its job (the ray field of a batch record)
@@ -2030,7 +2069,7 @@ size_t synth_batch_ws_layout(int32_t J, const et_job* jobs, int64_t cap, const B
   w.sort_tmp = take(sort_temp_bytes(cap, 8));
   w.tab = (int64_t*)take(sizeof(int64_t) * (size_t)(3 * J + 2) * 2);
   w.jobs = take(sizeof(SynthArgs) * (size_t)J);
-  w.tables = (float*)take(sizeof(float) * 4 * (size_t)J * s0->Q * s0->Bk);
+  w.tables = (float*)take(sizeof(float) * (size_t)J * (4 * (size_t)s0->Q * s0->Bk + 3 * s0->Q + 1));
   if (ws) *ws = w;
   return off;
 }
@@ -2053,10 +2092,11 @@ int synth_batch_run(int32_t J, const et_job* jobs, const et_paths* paths, const 
   SynthJobPack pk{};
   for (int32_t i = 0; i < J; ++i) {
     SynthArgs a = make_args(jobs[i].sim, 0);
-    a.lk = w.tables + (size_t)i * 4 * QB;
+    a.lk = w.tables + (size_t)i * (4 * QB + 3 * s0->Q + 1);
     a.lc = a.lk + QB;
     a.ld = a.lc + QB;
     a.lp = a.ld + QB;
+    a.lmax = a.lp + QB;
     pk.j[pk.n++] = a;
     if (pk.n == SJOB_PACK || i + 1 == J) {
       k_put_synth_jobs<<<1, SJOB_PACK, 0, s>>>(pk, dj);
