@@ -747,9 +747,9 @@ __device__ inline float wave_max(float v) {
 }
 
 // Upper bound on log2 |X[k1] Y[k2]| over the tile for the record set up in q (-inf for none):
-// the amplitude at the tile's first or last row, the record's band bound lbm (largest band
-// factor with its lobe, plus the receiver's largest log2 directivity gain), and what |Y| can
-// exceed 1 by.
+// the amplitude at the tile's first or last row, the record's band bound lbm (at least its
+// largest band factor with its lobe, plus the receiver's largest log2 directivity gain), and
+// what |Y| can exceed 1 by.
 __device__ inline float record_bound(const PairLean& q, int k1_0, int nk1) {
   if (q.base == -INFINITY) return -INFINITY;
   const float s64 = (float)K2 * q.slope;
