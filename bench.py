@@ -340,6 +340,7 @@ def main():
     ctx.set_counting(False)
 
     dynamic = None if args.no_extra_legs else dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps)
+    pipelined = None if args.no_extra_legs else pipelined_leg(ctx, et, sc, s, P, ws, out, reps)
     other_configs = None if args.no_extra_legs else configs_leg(ctx, et, W, reps)
 
     adj_tflops = terms * ADJ_FLOP_PER_TERM / (ms_adj_kernel * 1e-3) / 1e12
@@ -380,6 +381,7 @@ def main():
                     "kernel_tflops_algorithmic": adj_tflops, "roofline": adj_roof},
         "bvh": {"nodes": info.n_nodes, "depth": info.depth, "sah_cost": info.sah_cost, "build_ms": info.build_ms},
         "dynamic_scene": dynamic,
+        "pipelined_poses": pipelined,
         "other_configs": other_configs,
         "traversal": {"nodes_per_segment": (cnt.nodes_closest) / max(cnt.rays_closest, 1),
                       "tris_per_segment": cnt.tris_closest / max(cnt.rays_closest, 1),
@@ -533,6 +535,39 @@ def dynamic_leg(ctx, et, W, scene, sim, sc, s, P, ws, out, reps):
             "sah_refit": refit_sah, "sah_rebuilt": fi.sah_cost,
             "step_ms_refitted": ms_refitted, "step_ms_rebuilt": ms_fresh,
             "frame_ms_refit": dev_ms / n + ms_refitted, "frame_ms_rebuild": fi.build_ms + ms_fresh}
+
+
+def pipelined_leg(ctx, et, sc, s, P, ws, out, reps):
+    """Room poses handed alternately to two contexts, each on a stream of its own (default
+    priority): the calls are asynchronous and the contexts share only the scene, so one pose's
+    synthesis runs while the next pose's trace does.  Wall time per pose over 2 reps poses,
+    against the same loop on one context and stream."""
+    import torch
+    ctx2 = et.Context(0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ctxs = [ctx, ctx2]
+    Ps = [P, et.Paths(s.capacity())]
+    wss = [ws, et.Workspace()]
+    outs = [out, torch.empty_like(out)]
+
+    def run(n, two):
+        for i in range(n):
+            k = i % 2 if two else 0
+            with torch.cuda.stream(streams[k]):
+                et.simulate(ctxs[k], sc, s, paths=Ps[k], ws=wss[k], out=outs[k])
+
+    def per_pose(two):
+        run(2, two)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(2 * reps, two)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / (2 * reps)
+
+    one, two = per_pose(False), per_pose(True)
+    del ctx2
+    return {"workload": "room step per pose, poses alternating between two contexts on two streams",
+            "ms_per_pose_one_stream": one, "ms_per_pose_two_streams": two}
 
 
 def batched_leg(ctx, args):

@@ -541,3 +541,33 @@ def test_d_full_instance_directional_derivatives(et, ctx, d_instance):
         an = float(np.sum(gk * dk.astype(np.float64)))
         print(f"D full, coefficient direction {t}: adjoint {an:.6e}, exact {ex:.6e}")
         assert abs(an - ex) <= 1e-4 * abs(ex)
+
+
+def test_two_contexts_on_two_streams(et, ctx):
+    """Two contexts, each on a stream of its own, run alternate poses of the room concurrently
+    (one pose's synthesis beside the other's trace): every call's spectra equal, bit for bit,
+    those of the same pose run alone on one context."""
+    import torch
+    scene, sim = W.room_scene(n_rays=1 << 16, M=4, F=1024, diff_K=4096)
+    simB = dict(sim, emitter_pos=np.asarray(sim["emitter_pos"]) + np.array([0.3, 0.0, 0.0]))
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    sims = [et.Sim(sim), et.Sim(simB)]
+    ref = [et.simulate(ctx, sc, s).clone() for s in sims]
+    torch.cuda.synchronize()
+    assert not torch.equal(ref[0], ref[1])
+    ctxs = [ctx, et.Context(0)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    paths = [et.Paths(s.capacity()) for s in sims]
+    wss = [et.Workspace(), et.Workspace()]
+    outs = [torch.empty(s.M, s.F, 2, dtype=torch.float32, device="cuda") for s in sims]
+    for k in range(2):   # workspaces sized before the concurrent calls
+        et.simulate(ctxs[k], sc, sims[k], paths=paths[k], ws=wss[k], out=outs[k])
+    torch.cuda.synchronize()
+    for rep in range(4):
+        got = []
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                got.append(et.simulate(ctxs[k], sc, sims[k], paths=paths[k], ws=wss[k], out=outs[k]))
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert torch.equal(got[k], ref[k]), (rep, k)
