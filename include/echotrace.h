@@ -16,12 +16,14 @@
  *    et_last_error() gives a message for the last failing call on a context.
  *  - Pointers documented as "device" are HIP device pointers (e.g. torch CUDA tensors on
  *    ROCm); "host" pointers are read during the call only.  The caller owns every buffer:
- *    scene blob, scratch, workspace, inputs and outputs.  Apart from one small control
- *    block per context (counters and error word, allocated by et_create, freed by
+ *    scene blob, scratch, workspace, inputs and outputs.  Apart from two small control
+ *    blocks per context (counters and error word, allocated by et_create, freed by
  *    et_destroy) the library allocates no device memory.
  *  - Calls enqueue work on the context's stream and return; outputs are valid once the
  *    stream has completed the work (the Python binding uses torch's current stream).
- *    et_get_stats() synchronises the stream.
+ *    et_get_stats() synchronises the stream.  A fused batch of several job waves also uses a
+ *    second stream of the context's own (default priority, created by et_create), forked
+ *    from and joined back into the context's stream within the call.
  *  - A context is used by one host thread at a time.  Scenes are immutable after build
  *    and may be shared by contexts on the same device.
  *  - Host-side validation (shapes, null pointers, ranges of scalar parameters) runs
@@ -271,8 +273,9 @@ typedef struct {
 } et_job;
 
 /* Workspace for a batch: fused (specular-only) batches run in job waves (et_tuning.wave_rays) and
- * need one wave's rays, records and synthesis scratch; other batches run job after job and need
- * the largest job's scratch plus every job's records. */
+ * need one wave's rays and synthesis scratch and, with several waves, two waves' records (the
+ * next wave traces into one buffer while the synthesis reads the other); other batches run job
+ * after job and need the largest job's scratch plus every job's records. */
 int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* bytes);
 
 /* Traces and synthesises J jobs (poses and scenes may all differ; M, F, Q and Bk are shared).
@@ -280,8 +283,13 @@ int et_batch_workspace_size(et_ctx* ctx, int32_t J, const et_job* jobs, size_t* 
  * rays and each bounce is one launch over all of them (every ray reads its scene and pose
  * from a device job table); the visible records of all jobs are sorted by job (stably) and
  * cut into chunks that never mix jobs, so one synthesis launch (and one adjoint launch)
- * covers the batch, followed by a per-job reduction in a fixed order.  Launch shapes come
- * from the context's tuning (et_autotune_batch).  Batches with diffraction jobs run job after
+ * covers the batch, followed by a per-job reduction in a fixed order.  With several job waves
+ * the traces run on the context's second stream, each wave's synthesis (and adjoint) on the
+ * context's stream once its trace is done, so that a wave's synthesis runs beside the next
+ * wave's trace; the waves alternate between two record buffers and two control blocks, and
+ * the call's work ends on the context's stream (not when the stream is being captured into a
+ * graph: then the waves run in order on that stream).  Launch shapes come from the context's
+ * tuning (et_autotune_batch).  Batches with diffraction jobs run job after
  * job.  spectra is device float [J][M][F][2].  grad_spectra (optional, same shape, dL/dconj(H)
  * per job) makes the call also write every job's adjoint into grad_k [J][Q][Bk] and
  * grad_rx [J][M][3] (device double).  Results are bit-reproducible for a given tuning. */

@@ -16,7 +16,10 @@ struct et_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  Ctl* ctl = nullptr;                 // device control block (the only library allocation)
+  Ctl* ctl = nullptr;                 // device control block (with ctl2, the only library allocations)
+  Ctl* ctl2 = nullptr;                // control block of the odd job waves of a pipelined batch
+  hipStream_t aux = nullptr;          // a batch's trace stream (default priority) beside `stream`
+  hipEvent_t pev[5] = {};             // pipelined batch: fork, trace done (2), synthesis done (2)
   bool counting = false;
   int32_t stack_cap = TRAV_STACK;     // per-lane traversal stack entries (et_set_stack_limit)
   hipEvent_t ev[12] = {};
@@ -215,7 +218,9 @@ FusedPlan fused_plan(et_ctx* ctx, int32_t J, const et_job* jobs) {
   }
   f.tw = al(trace_ws_layout(f.N, 0, 0, 0, nullptr, nullptr, TUNE_MAX_TRACE_BLOCKS));
   f.pp = al(paths_bytes(f.cap));
-  f.total = f.tj + f.tw + f.pp + f.sy;
+  // with several waves, two record buffers: the next wave's trace fills one while the
+  // synthesis reads the other
+  f.total = f.tj + f.tw + (f.waves.size() > 1 ? 2 : 1) * f.pp + f.sy;
   return f;
 }
 
@@ -295,6 +300,20 @@ __global__ void k_set_nrec(Ctl* ctl, const int64_t* count, int64_t cap) {
   ctl->n_rec = n < cap ? n : cap;
 }
 
+// A pipelined batch's second control block starts without a deferred error.
+__global__ void k_ctl_clear_err(Ctl* c) { c->err = 0; }
+
+// The odd waves' statistics and deferred errors join the even waves' (every field the
+// statistics read that a batch accumulates).
+__global__ void k_ctl_merge(Ctl* a, const Ctl* b) {
+  a->err |= b->err;
+  a->rec_prev += b->rec_prev + b->rec_base;
+  a->seg += b->seg;
+  a->shadow += b->shadow;
+  a->overflow += b->overflow;
+  for (int i = 0; i < 6; ++i) a->cnt[i] += b->cnt[i];
+}
+
 }  // namespace
 
 extern "C" {
@@ -326,10 +345,14 @@ int et_create(int device, void* hip_stream, et_ctx** out) {
     ET_HIP(hipSetDevice(device));
     ET_HIP(hipMalloc(&c->ctl, sizeof(Ctl)));
     ET_HIP(hipMemset(c->ctl, 0, sizeof(Ctl)));
+    ET_HIP(hipMalloc(&c->ctl2, sizeof(Ctl)));
+    ET_HIP(hipMemset(c->ctl2, 0, sizeof(Ctl)));
+    ET_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     for (auto& e : c->ev) ET_HIP(hipEventCreate(&e));
+    for (auto& e : c->pev) ET_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     noalloc_init(device);   // this device's address of the allocation-free calls' scratch
   } catch (const Error& e) {
-    delete c;
+    et_destroy(c);
     return e.code;
   }
   *out = c;
@@ -344,6 +367,10 @@ int et_destroy(et_ctx* ctx) {
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->wave_ev) (void)hipEventDestroy(e);
+  for (auto& e : ctx->pev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+  if (ctx->ctl2) (void)hipFree(ctx->ctl2);
   if (ctx->ctl) (void)hipFree(ctx->ctl);
   delete ctx;
   return ET_OK;
@@ -572,17 +599,17 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
   ctx->last_count = nullptr;
   if (batch_fused(J, jobs)) {
     const FusedPlan f = fused_plan(ctx, J, jobs);
+    const size_t nw = f.waves.size();
     char* base = (char*)ws;
     void* dj = base;
     base += f.tj;
     char* twb = base;
     base += f.tw;
     char* ppb = base;
-    base += f.pp;
+    base += (nw > 1 ? 2 : 1) * f.pp;
     char* syb = base;
     const size_t MF2 = (size_t)s0->M * s0->F * 2;
     const size_t QB = (size_t)s0->Q * s0->Bk;
-    const size_t nw = f.waves.size();
     // timed: three event pairs per wave (trace, synthesis kernel, adjoint kernel)
     if (timed)
       while (ctx->wave_ev.size() < 6 * nw) {
@@ -590,33 +617,58 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
         ET_HIP(hipEventCreate(&e));
         ctx->wave_ev.push_back(e);
       }
+    // Pipelined waves (several waves, and the stream not being captured into a graph): the
+    // traces run on the context's second stream, each wave's synthesis on the caller's stream
+    // once its trace is done, so that wave w's synthesis runs beside wave w + 1's trace.  Waves
+    // alternate between two record buffers and two control blocks; a trace waits until the
+    // synthesis that last read its buffer is done, and the caller's stream ends after both.
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    ET_HIP(hipStreamIsCapturing(ctx->stream, &cap_status));
+    const bool pipe = nw > 1 && cap_status == hipStreamCaptureStatusNone;
+    hipStream_t ts = pipe ? ctx->aux : ctx->stream;   // trace stream
+    if (pipe) {
+      ET_HIP(hipEventRecord(ctx->pev[0], ctx->stream));
+      ET_HIP(hipStreamWaitEvent(ts, ctx->pev[0], 0));
+      k_ctl_clear_err<<<1, 1, 0, ts>>>(ctx->ctl2);
+    }
     for (size_t wi = 0; wi < nw; ++wi) {
       const Wave& wv = f.waves[wi];
       const et_job* wj = jobs + wv.j0;
       const int64_t cap = std::max<int64_t>(wv.cap, 1);
+      const int k = pipe ? (int)(wi & 1) : 0;   // record buffer and control block of this wave
+      Ctl* ctl = k ? ctx->ctl2 : ctx->ctl;
       TraceWS tw;
       trace_ws_layout(wv.N, 0, 0, 0, twb, &tw, TUNE_MAX_TRACE_BLOCKS);
       tw.stack_cap = ctx->stack_cap;
-      char* pp = ppb;
+      char* pp = ppb + k * f.pp;
       et_paths P = carve_paths(pp, cap);
       SynthBatchWS sw;
       synth_batch_ws_layout(wv.n, wj, cap, ctx->tune, true, syb, &sw);
       hipEvent_t* ev = timed ? ctx->wave_ev.data() + 6 * wi : nullptr;
-      if (ev) ET_HIP(hipEventRecord(ev[0], ctx->stream));
-      trace_batch_run(wv.n, wj, dj, &P, tw, ctx->ctl, ctx->counting, ctx->tune.trace_blocks, ctx->stream, wi > 0);
-      if (ev) ET_HIP(hipEventRecord(ev[1], ctx->stream));
-      k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctx->ctl, P.count, P.capacity);
+      if (pipe && wi >= 2) ET_HIP(hipStreamWaitEvent(ts, ctx->pev[3 + k], 0));   // buffer k read by wave wi - 2
+      if (ev) ET_HIP(hipEventRecord(ev[0], ts));
+      // a control block carries its statistics from its earlier waves
+      trace_batch_run(wv.n, wj, dj, &P, tw, ctl, ctx->counting, ctx->tune.trace_blocks, ts,
+                      pipe ? wi >= 2 : wi > 0);
+      if (ev) ET_HIP(hipEventRecord(ev[1], ts));
+      if (pipe) {
+        ET_HIP(hipEventRecord(ctx->pev[1 + k], ts));
+        ET_HIP(hipStreamWaitEvent(ctx->stream, ctx->pev[1 + k], 0));
+      }
+      k_set_nrec<<<1, 1, 0, ctx->stream>>>(ctl, P.count, P.capacity);
       int ak = 0;
       const hipEvent_t kev[4] = {ev ? ev[2] : nullptr, ev ? ev[3] : nullptr, ev ? ev[4] : nullptr,
                                  ev ? ev[5] : nullptr};
       ctx->synth_kernel =
-          synth_batch_run(wv.n, wj, &P, sw, ctx->ctl, spectra + (size_t)wv.j0 * MF2,
+          synth_batch_run(wv.n, wj, &P, sw, ctl, spectra + (size_t)wv.j0 * MF2,
                           grad_spectra ? grad_spectra + (size_t)wv.j0 * MF2 : nullptr,
                           grad_spectra ? grad_k + (size_t)wv.j0 * QB : nullptr,
                           grad_spectra ? grad_rx + (size_t)wv.j0 * s0->M * 3 : nullptr, &ak, ev ? kev : nullptr,
                           ctx->stream);
       if (grad_spectra) ctx->adjoint_kernel = ak;
+      if (pipe) ET_HIP(hipEventRecord(ctx->pev[3 + k], ctx->stream));
     }
+    if (pipe) k_ctl_merge<<<1, 1, 0, ctx->stream>>>(ctx->ctl, ctx->ctl2);
     ctx->waves_timed = timed ? (int32_t)nw : 0;
     ctx->timed = timed ? (TM_WAVES | TM_TRACE | TM_SYNTH_K | (grad_spectra ? TM_ADJ_K : 0u)) : 0u;
     return;
