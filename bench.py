@@ -631,7 +631,10 @@ def batched_leg(ctx, args):
     ws_gb = batch.ws.numel() / 1e9
     tuned = {"synth_wgs": tune.synth_wgs, "adjoint_wgs": tune.adjoint_wgs, "trace_blocks": tune.trace_blocks,
              "batched_fwd_ms": ms_fwd_t, "batched_fwd_adj_ms": ms_fwd_adj_t,
-             "phase_ms": {"trace": st.ms_trace, "synth_kernel": st.ms_synth_kernel, "adjoint_kernel": st.ms_adjoint_kernel},
+             "phase_ms": {"trace": tune.ms_trace, "synth_kernel": tune.ms_synth, "adjoint_kernel": tune.ms_adjoint},
+             "phase_ms_note": "each phase alone (the autotuner's runs take the job waves in order)",
+             "phase_ms_pipelined": {"trace": st.ms_trace, "synth_kernel": st.ms_synth_kernel,
+                                    "adjoint_kernel": st.ms_adjoint_kernel},
              "ratio_batched_fwd_adj_vs_plain_fwd": ms_plain / ms_fwd_adj_t}
     return {"jobs": J, "poses": args.batch_poses, "scenes": args.batch_scenes, "rays_per_job": args.batch_rays,
             "receivers": sims[0].M, "bins": sims[0].F, "scene_triangles": [int(len(sc["tris"])) for sc in b.scenes],

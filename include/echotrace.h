@@ -22,8 +22,9 @@
  *  - Calls enqueue work on the context's stream and return; outputs are valid once the
  *    stream has completed the work (the Python binding uses torch's current stream).
  *    et_get_stats() synchronises the stream.  A fused batch of several job waves also uses a
- *    second stream of the context's own (default priority, created by et_create), forked
- *    from and joined back into the context's stream within the call.
+ *    second stream of the context's own (default priority, created by the first such call,
+ *    destroyed by et_destroy), forked from and joined back into the context's stream within
+ *    the call.
  *  - A context is used by one host thread at a time.  Scenes are immutable after build
  *    and may be shared by contexts on the same device.
  *  - Host-side validation (shapes, null pointers, ranges of scalar parameters) runs
@@ -387,8 +388,9 @@ int et_set_tuning(et_ctx* ctx, const et_tuning* t);   /* ET_E_INVALID outside th
  * is given) once per candidate shape (synthesis and adjoint workgroups 1024, 2048, 4096, 8192,
  * 16384; bounce grids 1024, 2048, 4096, 6144, 8192 blocks), times the trace phase, the synthesis
  * kernel and the adjoint kernel with events, keeps for each knob its fastest candidate in
- * the context (the phases do not interact) and returns the choice with its times.  The
- * outputs hold the results of the last run.  ET_E_UNSUPPORTED for batches that do not run
+ * the context (its runs take the job waves in order on the context's stream, so that the
+ * phases do not interact) and returns the choice with its times.  The outputs hold the
+ * results of the last run.  ET_E_UNSUPPORTED for batches that do not run
  * fused (jobs with diffraction). */
 int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_bytes, float* spectra,
                       const float* grad_spectra, double* grad_k, double* grad_rx, et_tuning* out);
@@ -402,7 +404,8 @@ typedef struct {
   int64_t dropped;                                   /* records beyond capacity */
   int32_t synth_kernel;                              /* 1 factorised MFMA, 2 direct per-term */
   int32_t status;                                    /* deferred device-side status */
-  double ms_trace, ms_diffraction, ms_synth;         /* event-timed phases of the last calls */
+  double ms_trace, ms_diffraction, ms_synth;         /* event-timed phases of the last calls (summed
+                                                        over job waves; pipelined waves overlap) */
   double ms_adjoint;                                 /* event-timed et_synthesize_backward */
   double ms_synth_kernel, ms_adjoint_kernel;         /* the main synthesis / adjoint kernel alone */
   int32_t adjoint_kernel;                            /* 1 factorised MFMA, 2 direct per-term */

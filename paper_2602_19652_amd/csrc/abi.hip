@@ -18,8 +18,10 @@ struct et_ctx {
   std::string last_error;
   Ctl* ctl = nullptr;                 // device control block (with ctl2, the only library allocations)
   Ctl* ctl2 = nullptr;                // control block of the odd job waves of a pipelined batch
-  hipStream_t aux = nullptr;          // a batch's trace stream (default priority) beside `stream`
+  hipStream_t aux = nullptr;          // a batch's trace stream (default priority) beside `stream`,
+                                      // created by the first pipelined batch
   hipEvent_t pev[5] = {};             // pipelined batch: fork, trace done (2), synthesis done (2)
+  bool serial_waves = false;          // the autotuner's runs: job waves in order on one stream
   bool counting = false;
   int32_t stack_cap = TRAV_STACK;     // per-lane traversal stack entries (et_set_stack_limit)
   hipEvent_t ev[12] = {};
@@ -347,7 +349,6 @@ int et_create(int device, void* hip_stream, et_ctx** out) {
     ET_HIP(hipMemset(c->ctl, 0, sizeof(Ctl)));
     ET_HIP(hipMalloc(&c->ctl2, sizeof(Ctl)));
     ET_HIP(hipMemset(c->ctl2, 0, sizeof(Ctl)));
-    ET_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     for (auto& e : c->ev) ET_HIP(hipEventCreate(&e));
     for (auto& e : c->pev) ET_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     noalloc_init(device);   // this device's address of the allocation-free calls' scratch
@@ -624,7 +625,8 @@ void batch_impl(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size_t ws_
     // synthesis that last read its buffer is done, and the caller's stream ends after both.
     hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
     ET_HIP(hipStreamIsCapturing(ctx->stream, &cap_status));
-    const bool pipe = nw > 1 && cap_status == hipStreamCaptureStatusNone;
+    const bool pipe = nw > 1 && cap_status == hipStreamCaptureStatusNone && !ctx->serial_waves;
+    if (pipe && !ctx->aux) ET_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
     hipStream_t ts = pipe ? ctx->aux : ctx->stream;   // trace stream
     if (pipe) {
       ET_HIP(hipEventRecord(ctx->pev[0], ctx->stream));
@@ -996,6 +998,12 @@ int et_autotune_batch(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws, size
     ET_CHECK(batch_fused(J, jobs), ET_E_UNSUPPORTED, "autotuning applies to fused (specular-only) batches");
     const int32_t cw[5] = {1024, 2048, 4096, 8192, 16384};
     const int32_t cb[5] = {1024, 2048, 4096, 6144, 8192};
+    // each phase is timed alone: the job waves run in order, not pipelined over two streams
+    struct Serial {
+      et_ctx* c;
+      ~Serial() { c->serial_waves = false; }
+    } serial{ctx};
+    ctx->serial_waves = true;
     auto run = [&](double* t) {
       batch_impl(ctx, J, jobs, ws, ws_bytes, spectra, grad_spectra, grad_k, grad_rx, true);
       ET_HIP(hipStreamSynchronize(ctx->stream));
