@@ -122,6 +122,14 @@ def test_batch_fused_matches_plain_and_graph(et, ctx, batch_small):
         assert stw.segments == seg and stw.records == st.records
         assert bw.ws.numel() < batch.ws.numel()
         assert max(ew) <= 1e-5
+        # several waves run pipelined over two streams; repeated runs and a captured graph (whose
+        # waves run in order on one stream) give the same bits
+        assert np.array_equal(bw.run().cpu().numpy(), Hw), "pipelined waves not deterministic"
+        sw = torch.cuda.Stream()
+        with torch.cuda.stream(sw):
+            Hwg = bw.run(graph=True).cpu().numpy()
+            torch.cuda.synchronize()
+        assert np.array_equal(Hwg, Hw), "pipelined waves differ from the waves in order"
     finally:
         ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 0)
     assert np.array_equal(batch.run().cpu().numpy(), Hb), "fused batch not deterministic"
