@@ -735,6 +735,7 @@ int et_simulate_batch_graph(et_ctx* ctx, int32_t J, const et_job* jobs, void* ws
     key.push_back(((uint64_t)(uint32_t)ctx->tune.synth_wgs << 32) | (uint32_t)ctx->tune.adjoint_wgs);
     key.push_back((uint64_t)(uint32_t)ctx->tune.trace_blocks);
     key.push_back((uint64_t)ctx->tune.wave_rays);
+    key.push_back(((uint64_t)(uint32_t)ctx->stack_cap << 1) | (ctx->counting ? 1u : 0u));
     for (int j = 0; j < J; ++j) {
       key.push_back((uint64_t)(uintptr_t)jobs[j].scene);
       const uint64_t* w = reinterpret_cast<const uint64_t*>(jobs[j].sim);

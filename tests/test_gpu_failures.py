@@ -101,3 +101,43 @@ def test_stack_overflow_is_reported(et, ctx):
     et.trace(ctx, sc, s)
     st = ctx.stats()
     assert st.stack_overflows == 0 and st.segments > 0
+
+
+def test_stack_overflow_in_pipelined_batch(et, ctx):
+    """A fused batch in four job waves (pipelined over two streams, two control blocks) with a
+    3-entry traversal stack: the overflows of every wave reach et_get_stats (ET_E_INTERNAL), as
+    many as when the same batch runs its waves in order (a captured graph); with the full stack
+    again the replay is clean (the graph is keyed on the stack limit)."""
+    import torch
+    scene, sim = W.room_scene(n_rays=1 << 16, M=2, F=256, diff_K=0)
+    sc = et.Scene(ctx, scene, area_ref=sim["area_ref"])
+    sims = [et.Sim(dict(sim, emitter_pos=np.asarray(sim["emitter_pos"]) + np.array([0.1 * i, 0.0, 0.0])),
+                   flags=et.ET_SPECULAR) for i in range(4)]
+    t0 = ctx.tuning()
+    ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 1 << 16)   # one job per wave
+    side = torch.cuda.Stream()
+    try:
+        batch = et.Batch(ctx, [(sc, s) for s in sims])
+        ctx.set_stack_limit(3)
+        batch.run()
+        with pytest.raises(et.EchoError) as e:
+            ctx.stats()
+        assert e.value.status == -6
+        n_pipe = e.value.stats.stack_overflows
+        with torch.cuda.stream(side):
+            batch.run(graph=True)
+            torch.cuda.synchronize()
+        with pytest.raises(et.EchoError) as e2:
+            ctx.stats()
+        print(f"4 waves, stack limit 3: {n_pipe} dropped pushes pipelined, {e2.value.stats.stack_overflows} in order")
+        assert n_pipe > 0 and e2.value.stats.stack_overflows == n_pipe
+        ctx.set_stack_limit(0)
+        with torch.cuda.stream(side):
+            batch.run(graph=True)
+            torch.cuda.synchronize()
+        assert ctx.stats().stack_overflows == 0
+        batch.run()
+        assert ctx.stats().stack_overflows == 0
+    finally:
+        ctx.set_stack_limit(0)
+        ctx.set_tuning(t0.synth_wgs, t0.adjoint_wgs, t0.trace_blocks, 0)
