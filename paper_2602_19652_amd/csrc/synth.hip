@@ -1598,13 +1598,13 @@ __global__ __launch_bounds__(RED_T) void k_bwd_reduce(const double* __restrict__
 inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
 
 int choose_P(const et_sim_desc* sim, int64_t cap, bool mfma) {
-  // matrix-core kernels: about twelve workgroups per CU over the launch (three run at a time,
-  // so four even rounds; measured on the room's 32 x 4096 synthesis: 1024 workgroups, 1.33
-  // rounds, 25.4 ms; 3072, 23.6 ms; 6144, 23.5 ms).  Chunk count a multiple of 8 so that every
-  // receiver's workgroups of one chunk share an XCD's L2.
+  // matrix-core kernels: about sixteen workgroups per CU over the launch (measured on the
+  // room's 32 x 4096 forward and adjoint: 2048 workgroups 11.20 / 20.16 ms, 3072 10.90 / 20.05,
+  // 4096 10.76 / 19.87, 6144 10.75 / 19.98, 8192 10.73 / 19.92 ms).  Chunk count a multiple of 8
+  // so that every receiver's workgroups of one chunk share an XCD's L2.
   const int64_t tiles = mfma ? (int64_t)sim->M * std::max<int64_t>(1, (sim->F / K2 + KT1 - 1) / KT1)
                              : (int64_t)sim->M * ((sim->F + DTILE - 1) / DTILE);
-  const int64_t target = mfma ? 3072 : 2048;
+  const int64_t target = mfma ? 4096 : 2048;
   int64_t P = std::max<int64_t>(1, (target + tiles - 1) / tiles);
   if (P >= 8) P = (P + 7) / 8 * 8;
   P = std::min<int64_t>(P, std::max<int64_t>(1, cap / 64));
