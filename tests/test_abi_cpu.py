@@ -66,3 +66,14 @@ def test_binding_structs_match_header_field_order():
         names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*(?:\[\d+\])?\s*[,;]", body)
         names = [n for n in names if n not in ("int32_t", "int64_t", "double", "float", "uint64_t", "uint32_t", "uint8_t")]
         assert [f[0] for f in cls._fields_] == names, cname
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits (status 2) with a message, before
+    importing torch or touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
