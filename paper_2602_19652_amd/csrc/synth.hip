@@ -500,6 +500,24 @@ __device__ inline void split8(const float (&v)[8], halfx8& h, halfx8& l) {
   l = L.h8;
 }
 
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
+// split8 for four values
+__device__ inline void split4(const float (&v)[4], halfx4& h, halfx4& l) {
+  union { halfx4 h4; uint32_t u[2]; } H, L;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const uint32_t xu = __builtin_bit_cast(uint32_t, __builtin_convertvector((float2v){v[2 * i], v[2 * i + 1]}, half2v));
+    uint32_t lo;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(xu), "v"(v[2 * i]));
+    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(lo) : "v"(xu), "v"(v[2 * i + 1]));
+    H.u[i] = xu;
+    L.u[i] = lo;
+  }
+  h = H.h4;
+  l = L.h4;
+}
+
 // Two-level generation: X[8a+b] = Xa[a] Xb[b] bf[seg(8a+b)] and Y[8a+b] = Ya[a] Yb[b]:
 // 32 exp2/sin/cos factors per record instead of 128 values, plus one real band factor
 // bf = 2^(band + directivity log2) per segment of outer indices with equal bands.
@@ -661,10 +679,58 @@ __device__ inline void xy_value(const WaveScratch& W, int rr, int lane, int myse
   }
 }
 
+// X of record rr at outer index `row` (as in xy_value; seg: the row's band segment)
+template <int FOLD>
+__device__ inline float2 x_value(const WaveScratch& W, int rr, int row, int seg) {
+  const int ka = row >> 3, kb = row & 7;
+  if (FOLD == 8) return cmul(W.xa[rr][ka], W.xb[rr][kb]);
+  if (FOLD == 4) return cmul(kb < 4 ? W.xa[rr][ka] : W.xh[rr][ka], W.xb[rr][kb]);
+  float2 x = cmul(W.xa[rr][ka], W.xb[rr][kb]);
+  const float f = W.bf[rr][seg];
+  x.x *= f;
+  x.y *= f;
+  return x;
+}
+
 // The sub-stage's records as f16 halves: X of this lane's outer index into A, Y of its inner
-// index into B, chunk wv (the wave's 8 records of the stage).
+// index into B, chunk wv (the wave's 8 records of the stage).  With a tile of at most 32 rows
+// (SPLIT) every lane forms X: lane (row = lane % 32, h = lane / 32) for records 4 h .. 4 h + 3,
+// writing its half of the row's 8-record chunk; segx is the band segment of row lane % 32.
 template <bool SPLIT, int FOLD>
-__device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, H16Buf<SPLIT>& buf) {
+__device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int myseg, int segx, H16Buf<SPLIT>& buf) {
+  if constexpr (SPLIT) {
+    const int row = lane & 31, hh = lane >> 5;
+    float xr[4], xi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float2 x = x_value<FOLD>(W, 4 * hh + i, row, segx);
+      xr[i] = x.x;
+      xi[i] = x.y;
+    }
+    halfx4 h4, l4;
+    split4(xr, h4, l4);
+    reinterpret_cast<halfx4*>(&buf.A[0][row][wv])[hh] = h4;
+    reinterpret_cast<halfx4*>(&buf.A[1][row][wv])[hh] = l4;
+    split4(xi, h4, l4);
+    reinterpret_cast<halfx4*>(&buf.A[2][row][wv])[hh] = h4;
+    reinterpret_cast<halfx4*>(&buf.A[3][row][wv])[hh] = l4;
+    const int ka = lane >> 3, kb = lane & 7;
+    float yr[RPW], yi[RPW];
+#pragma unroll
+    for (int rr = 0; rr < RPW; ++rr) {
+      const float2 y = cmul(W.ya[rr][ka], W.yb[rr][kb]);
+      yr[rr] = y.x;
+      yi[rr] = y.y;
+    }
+    halfx8 h, l;
+    split8(yr, h, l);
+    buf.B[0][lane][wv] = h;
+    buf.B[1][lane][wv] = l;
+    split8(yi, h, l);
+    buf.B[2][lane][wv] = h;
+    buf.B[3][lane][wv] = l;
+    return;
+  }
   float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
 #pragma unroll
   for (int rr = 0; rr < RPW; ++rr) {
@@ -798,6 +864,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
   seg_init(a, k1_0, nk1, tid, st, nseg, myseg);
   // segments of the two half groups of row group lane % 8 (FOLD)
   const int segl = min(__shfl(myseg, 8 * (lane & 7)), nseg - 1), segh = min(__shfl(myseg, 8 * (lane & 7) + 4), nseg - 1);
+  const int segx = __shfl(myseg, lane & 31);   // (SPLIT: the band segment of row lane % 32)
   const float dmax = dir_log2_max(a, m, tid, red);
   const int64_t nst = (hi - lo + 8 * RB - 1) / (8 * RB) * 8;   // whole groups of 8 stages (256 records)
   floatx4 acc[3][2][2];
@@ -833,7 +900,7 @@ __global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0,
     }
     gen_factors<false, FOLD>(a, q, t, m, k1_0, nk1, lane, nseg, st, E != -INFINITY ? XTOP - E : 0.f, wscr[wv], segl,
                              segh);
-    write_h16<SPLIT, FOLD>(wscr[wv], lane, wv, myseg, buf);
+    write_h16<SPLIT, FOLD>(wscr[wv], lane, wv, myseg, segx, buf);
     __syncthreads();
     contract_h16<SPLIT>(buf, wv, lane, acc);
     __syncthreads();
