@@ -472,11 +472,17 @@ __device__ inline void pair_lean(const SynthArgs& a, const et_paths& P, const in
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 constexpr int HROW = 5;          // halfx8 per LDS row: 4 chunks of 8 records and a pad
 constexpr float XTOP = 12.f;     // log2 of the largest scaled |X| (|Y| <= 1 for non-negative absorption)
+// With SPLIT the Y rows hold no pad: chunk c of row k sits at slot c ^ ((k / 4) % 4), which puts
+// 16 lanes reading or writing one chunk of 16 consecutive rows on distinct banks, and the
+// workgroup's LDS (about 37 KB) lets four workgroups share a CU.
 template <bool SPLIT>
 struct H16Buf {
   static constexpr int NA = SPLIT ? KT1 / 2 : KT1;   // rows of X (a tile of at most 32 with SPLIT)
+  static constexpr int BROW = SPLIT ? 4 : HROW;
   halfx8 A[4][NA][HROW];         // X halves: [re hi, re lo, im hi, im lo][k1][record chunk]
-  halfx8 B[4][K2][HROW];         // Y halves: [re hi, re lo, im hi, im lo][k2][record chunk]
+  halfx8 B[4][K2][BROW];         // Y halves: [re hi, re lo, im hi, im lo][k2][record chunk slot]
+  // slot of record chunk c in Y row k
+  static __device__ __forceinline__ int bslot(int k, int c) { return SPLIT ? c ^ ((k >> 2) & 3) : c; }
 };
 
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
@@ -723,12 +729,13 @@ __device__ inline void write_h16(const WaveScratch& W, int lane, int wv, int mys
       yi[rr] = y.y;
     }
     halfx8 h, l;
+    const int sl = H16Buf<SPLIT>::bslot(lane, wv);
     split8(yr, h, l);
-    buf.B[0][lane][wv] = h;
-    buf.B[1][lane][wv] = l;
+    buf.B[0][lane][sl] = h;
+    buf.B[1][lane][sl] = l;
     split8(yi, h, l);
-    buf.B[2][lane][wv] = h;
-    buf.B[3][lane][wv] = l;
+    buf.B[2][lane][sl] = h;
+    buf.B[3][lane][sl] = l;
     return;
   }
   float xr[RPW], xi[RPW], yr[RPW], yi[RPW];
@@ -778,7 +785,10 @@ __device__ inline void contract_h16(const H16Buf<SPLIT>& buf, int wv, int lane, 
 #pragma unroll
   for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-    for (int f = 0; f < 4; ++f) b[jj][f] = buf.B[f][16 * (cb0 + jj) + r16][ch];
+    for (int f = 0; f < 4; ++f) {
+      const int k2 = 16 * (cb0 + jj) + r16;
+      b[jj][f] = buf.B[f][k2][H16Buf<SPLIT>::bslot(k2, ch)];
+    }
 #pragma unroll
   for (int i = 0; i < NRB; ++i) {
     halfx8 av[4];
@@ -846,7 +856,7 @@ __device__ inline float dir_log2_max(const SynthArgs& a, int m, int tid, float* 
 // FOLD 4 (8): every band edge falls on a multiple of 4 (8) rows and the grid holds whole groups of
 // that many rows (bins a multiple of 256, 512): the band factor rides on Xa.
 template <bool BATCH, bool SPLIT, int FOLD>
-__global__ __launch_bounds__(256, SPLIT ? 3 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
+__global__ __launch_bounds__(256, SPLIT ? 4 : 2) void k_synth_mfma(SynthArgs a0, const SynthArgs* __restrict__ jobs,
                                                                    ChunkTab ct, et_paths P,
                                                                    const int32_t* __restrict__ idx, const Ctl* ctl,
                                                                    float* __restrict__ part) {
