@@ -591,18 +591,31 @@ __global__ void k_obj_fov(SceneDev S, DiffArgs a, uint8_t* oel) {
 
 // Largest C_i over the field-of-view objects: positive doubles order as their bit patterns, so
 // a wave takes the maximum of the bits by shuffles and issues one atomic.
-__global__ void k_cmax(SceneDev S, const uint8_t* __restrict__ oel, Ctl* ctl) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Largest C_i over the triangles of eligible objects, as the bit pattern of a non-negative double
+// (ordered like the value): a grid-strided maximum per thread, then per wave and per block, and
+// one atomic per block (one per wave left the room's 193,212 triangles waiting on about 3000 atomics).
+__global__ __launch_bounds__(BS) void k_cmax(SceneDev S, const uint8_t* __restrict__ oel, Ctl* ctl) {
+  __shared__ long long wmax[BS / 64];
   long long v = 0;
-  if (t < S.T && oel[S.obj[t]]) {
-    const double c = S.C[t];
-    if (c > 0.0) v = __double_as_longlong(c);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < S.T; t += (int64_t)gridDim.x * blockDim.x) {
+    if (oel[S.obj[t]]) {
+      const double c = S.C[t];
+      if (c > 0.0) {
+        const long long b = __double_as_longlong(c);
+        v = b > v ? b : v;
+      }
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     const long long o = __shfl_xor(v, off);
     v = o > v ? o : v;
   }
-  if ((threadIdx.x & 63) == 0 && v > 0) atomicMax((unsigned long long*)&ctl->cmax_bits, (unsigned long long)v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < BS / 64; ++i) v = wmax[i] > v ? wmax[i] : v;
+    if (v > 0) atomicMax((unsigned long long*)&ctl->cmax_bits, (unsigned long long)v);
+  }
 }
 
 __global__ void k_qweight(SceneDev S, DiffArgs a, const uint8_t* __restrict__ oel, const Ctl* ctl,
@@ -1037,7 +1050,7 @@ void trace_run(const SceneDev& S, const et_sim_desc* sim, const et_paths* paths,
     int obj_bits = 1;
     while (obj_bits < 31 && ((int64_t)1 << obj_bits) < S.n_obj) ++obj_bits;
     k_obj_fov<<<nblk_full(S.n_obj), BS, 0, s>>>(S, d, w.oel);
-    k_cmax<<<nblk_full(S.T), BS, 0, s>>>(S, w.oel, ctl);
+    k_cmax<<<(unsigned)std::min<int64_t>(nblk_full(S.T), 256), BS, 0, s>>>(S, w.oel, ctl);
     k_qweight<<<nblk_full(S.T), BS, 0, s>>>(S, d, w.oel, ctl, w.dq, w.dflags);
     scan_exclusive_u64(w.dflags, w.doffs, S.T, nullptr, S.T, &ctl->tot[1], w.scan_tmp, s);
     k_elig_keys<<<nblk_full(S.T), BS, 0, s>>>(S, d.per_mesh, w.dq, w.dflags, w.doffs, w.dkeys, w.dvals);
